@@ -1,0 +1,133 @@
+"""Seeded synthetic workloads (descriptors only).
+
+This module is shared by the tests, the benchmark and the CPU reference as
+the single source of inputs.  It enumerates probe descriptors (N, s, passes,
+j0, base) and cache-model descriptors (C, b, a, policy, seed); it contains no
+replay, no trace arithmetic and no scoring.  Sizes follow the paper's sweeps:
+N ramps a line at a time across the capacity (Section 4.2 steps 2-3,
+Section 4.3 texture L1 ramp 12 KB -> 12.5 KB), strides run from an element to
+a few lines (Section 4.1, Eqs. (1)-(2)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LRU, FIFO, PLRU, RANDOM = 0, 1, 2, 3
+POLICY_NAMES = {LRU: "LRU", FIFO: "FIFO", PLRU: "PLRU", RANDOM: "RANDOM"}
+
+MODEL_DT = np.dtype([("C", "<u8"), ("b", "<u8"), ("a", "<u8"), ("policy", "<u8"),
+                     ("set_shift", "<u8"), ("seed", "<u8")])
+PROBE_DT = np.dtype([("N", "<u8"), ("s", "<u8"), ("base", "<u8"), ("j0", "<u8"),
+                     ("elem", "<u8"), ("passes", "<u8")])
+
+
+def models(rows) -> np.ndarray:
+    """rows: iterable of (C, b, a, policy[, set_shift[, seed]])."""
+    out = np.zeros(len(rows), dtype=MODEL_DT)
+    for i, r in enumerate(rows):
+        r = tuple(r) + (0,) * (6 - len(r))
+        out[i] = r
+    return out
+
+
+def probes(rows) -> np.ndarray:
+    """rows: iterable of (N, s[, passes[, j0[, base]]]); elem is 4 bytes (int32)."""
+    out = np.zeros(len(rows), dtype=PROBE_DT)
+    for i, r in enumerate(rows):
+        N, s = r[0], r[1]
+        passes = r[2] if len(r) > 2 else 2
+        j0 = r[3] if len(r) > 3 else 0
+        base = r[4] if len(r) > 4 else 0
+        out[i] = (N, s, base, j0, 4, passes)
+    return out
+
+
+# --------------------------------------------------------------------------
+# One LRU model, a P-chase sweep around its capacity (4 KB, 32 B lines,
+# 4 ways): N = 2 KB .. 8 KB in 32 B steps, s in {32, 64, 128} B, 2 passes.
+# --------------------------------------------------------------------------
+def plain_sweep():
+    model = models([(4096, 32, 4, LRU)])
+    rows = [(N, s, 2) for s in (32, 64, 128) for N in range(2048, 8192 + 1, 32)]
+    return model, probes(rows)
+
+
+# --------------------------------------------------------------------------
+# Candidate grid for the exhaustive search: C in {8..64 KB, powers of two and
+# 1.5x}, b in {32, 64, 128} B, a in {1..64}, policy in {LRU, FIFO, PLRU};
+# kept only when a*b divides C.  Canonical order: C, b, a, policy ascending.
+# --------------------------------------------------------------------------
+GRID_C = (8192, 12288, 16384, 24576, 32768, 49152, 65536)
+GRID_B = (32, 64, 128)
+GRID_A = (1, 2, 4, 8, 16, 32, 64)
+GRID_POLICIES = (LRU, FIFO, PLRU)
+
+
+def candidate_grid(Cs=GRID_C, bs=GRID_B, As=GRID_A, policies=GRID_POLICIES) -> np.ndarray:
+    rows = []
+    for C in Cs:
+        for b in bs:
+            for a in As:
+                if C % (a * b) != 0:
+                    continue
+                for pol in policies:
+                    rows.append((C, b, a, pol))
+    return models(rows)
+
+
+def own_sweep_rows(C: int, b: int, passes: int = 2):
+    """The probes a candidate (C, b) replays: N = C/2 .. 2C step b, s in {b/2, b, 2b}."""
+    return [(N, s, passes) for s in (b // 2, b, 2 * b) for N in range(C // 2, 2 * C + 1, b)]
+
+
+def sweep_union(cands: np.ndarray, passes: int = 2) -> np.ndarray:
+    """Distinct probes over every candidate's own sweep, sorted by (s, N)."""
+    seen = set()
+    for C, b in {(int(c["C"]), int(c["b"])) for c in cands}:
+        for N, s, p in own_sweep_rows(C, b, passes):
+            seen.add((s, N))
+    rows = [(N, s, passes) for (s, N) in sorted(seen)]
+    return probes(rows)
+
+
+def pick_target(n_cands: int, seed: int = 1509) -> int:
+    """The synthetic observed cache: one candidate drawn uniformly."""
+    return int(np.random.default_rng(seed).integers(n_cands))
+
+
+def inference_sweep(seed: int = 1509, Cs=GRID_C, bs=GRID_B, As=GRID_A, policies=GRID_POLICIES):
+    cands = candidate_grid(Cs, bs, As, policies)
+    return cands, sweep_union(cands), pick_target(len(cands), seed)
+
+
+# --------------------------------------------------------------------------
+# Large batch: (model, trace) pairs of uneven length, log-uniform on
+# [lo, hi] accesses, realised as uniform-stride P-chases (s divides N so one
+# pass is N/s accesses), models C in {2^k, 1.5*2^k} up to 4 MB, a up to 128,
+# all four policies (RANDOM keyed by a per-model seed).
+# --------------------------------------------------------------------------
+def large_batch(n_pairs: int, seed: int = 4711, len_lo: int = 1000, len_hi: int = 100_000,
+                c_lo: int = 8192, c_hi: int = 4 << 20, a_max: int = 128):
+    rng = np.random.default_rng(seed)
+    caps = []
+    c = c_lo
+    while c <= c_hi:
+        caps.append(c)
+        if c + c // 2 <= c_hi:
+            caps.append(c + c // 2)
+        c *= 2
+    ways = [a for a in (1, 2, 4, 8, 16, 32, 64, 128) if a <= a_max]
+    valid = [(C, b, a) for C in caps for b in (32, 64, 128) for a in ways if C % (a * b) == 0]
+    pick = rng.integers(len(valid), size=n_pairs)
+    pol = rng.integers(4, size=n_pairs)
+    seeds = rng.integers(0, 2**63, size=n_pairs, dtype=np.int64).astype(np.uint64)
+    mrows = [(valid[i][0], valid[i][1], valid[i][2], int(p), 0, int(sd))
+             for i, p, sd in zip(pick, pol, seeds)]
+    lens = np.exp(rng.uniform(np.log(len_lo), np.log(len_hi), size=n_pairs))
+    strides = 4 << rng.integers(7, size=n_pairs)          # 4 B .. 256 B
+    passes = rng.integers(1, 5, size=n_pairs)
+    prow = []
+    for L, s, p in zip(lens, strides, passes):
+        per_pass = max(1, int(round(L / p)))
+        prow.append((int(per_pass * s), int(s), int(p)))
+    return models(mrows), probes(prow)
