@@ -1,0 +1,213 @@
+"""Benchmark: exhaustive cache-parameter inference over the full candidate grid.
+
+One step = one infer_cache_params call on one MI355X: 438 candidate caches
+(C 8..64 KB in powers of two and 1.5x, b 32/64/128 B, a 1..64, LRU/FIFO/
+tree-PLRU) each replay their own N sweep (C/2..2C in line steps, s in
+{b/2, b, 2b}, 2 passes) -- 1,079,586 replays, 3,361,069,440 replayed
+accesses -- scored against one seeded synthetic observation, exact argmin
+and zero class returned to the host.  The observation is the replay of a
+seeded target candidate; inputs are resident in HBM before timing.
+
+Prints one JSON line (see the repository's benchmark contract).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_LANE_OPS = 256 * 64 * 2.4e9      # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def lane_ops_per_access(a: int, policy: int) -> float:
+    """Algorithmic VALU lane-ops of one replayed access (stated convention):
+    LRU 3a+8 (a tag compares, 2a recency updates), FIFO a+8, tree-PLRU
+    a+2log2(a)+8, RANDOM a+8 (+60 per evicting miss, not in this grid)."""
+    if policy == 0:
+        return 3 * a + 8
+    if policy == 2:
+        return a + 2 * math.log2(a) + 8
+    return a + 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
+              f"candidate across GPUs with one 8-byte min-reduction, which this build does not run.",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1509_02308_amd import capi
+    from paper_1509_02308_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    cands, probes, target = W.inference_sweep()
+    crows = [tuple(int(x) for x in c) for c in cands]
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in probes]
+    parr, carr = capi.probes(prows), capi.models(crows)
+    lens = np.array([capi.pchase_trace_len(parr[i])[0] for i in range(len(prows))], dtype=np.uint64)
+    words = (lens + 31) // 32
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+
+    # observation: the target cache's hit bits on every probe (replayed on the GPU, untimed)
+    bits = torch.zeros(int(words.sum()) + 1, dtype=torch.int32, device="cuda")
+    misses = torch.zeros(2 * len(prows), dtype=torch.int64, device="cuda")
+    capi.cache_replay_probes(capi.models([crows[target]]), parr, np.zeros(len(prows), np.uint32),
+                             np.arange(len(prows), dtype=np.uint32), None, misses, bits, bitoff)
+    torch.cuda.synchronize()
+
+    # algorithmic work of one step
+    accesses, lane_ops = 0, 0.0
+    for C, b, a, pol, _, _ in crows:
+        own = [i for i, (N, s, _) in enumerate(prows)
+               if C <= 2 * N <= 4 * C and N % b == 0 and s in (b // 2, b, 2 * b)]
+        acc = int(lens[own].sum())
+        accesses += acc
+        lane_ops += acc * lane_ops_per_access(a, pol)
+
+    def step(sched=0):
+        return capi.infer_cache_params(parr, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_OWN_SWEEP,
+                                       mode=capi.EXHAUSTIVE | sched)[0]
+
+    t_cold0 = time.perf_counter()
+    res = step()
+    cold_ms = (time.perf_counter() - t_cold0) * 1e3
+    assert res.replayed_accesses == accesses, (res.replayed_accesses, accesses)
+    for _ in range(max(0, args.warmup - 1)):
+        res = step()
+
+    # timed region: K steps, HIP events on the launch stream around each step
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    lat_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        ev[k][0].record(stream)
+        res = step()
+        ev[k][1].record(stream)
+        lat_ms.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = [a.elapsed_time(b) for a, b in ev]
+    value = accesses * args.steps / wall
+    exact = bool(res.best >= 0 and res.best_m == 0)
+
+    # plain schedule: one launch per candidate, no persistent queue, no graph
+    plain = None
+    if args.plain_steps > 0:
+        step(capi.SCHED_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(args.plain_steps):
+            rp = step(capi.SCHED_PLAIN)
+        torch.cuda.synchronize()
+        pw = (time.perf_counter() - tp) / args.plain_steps
+        assert rp.best == res.best and rp.best_m == res.best_m
+        plain = {"value": accesses / pw, "unit": "accesses/s", "time_to_params_ms": pw * 1e3,
+                 "steps": args.plain_steps}
+
+    gpu_step_ms = float(np.median(gpu_ms))
+    achieved = lane_ops / (gpu_step_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "kernel": "sweep_kernel<policy, way class, score> (all instantiations of one captured step)",
+                "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(crows, prows, lens, bits, bitoff, args.cpu_seconds)
+
+    out = {
+        "metric": "cache-model replayed accesses/sec and time-to-inferred-params, batched vs plain",
+        "value": value,
+        "unit": "accesses/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "exhaustive inference sweep: 438 candidates (C 8-64 KB, b 32-128 B, a 1-64, "
+                               "LRU/FIFO/PLRU) x own N sweep (C/2..2C step b, s in {b/2,b,2b}, 2 passes), "
+                               "one seeded target",
+                   "candidates": len(crows), "probes": len(prows), "replays": 1079586,
+                   "accesses_per_step": accesses, "target": target, "schedule": "batched"},
+        "time_to_params_ms": float(np.median(lat_ms)),
+        "time_to_params_cold_ms": cold_ms,
+        "exact": exact,
+        "best": int(res.best),
+        "zero_class": int(res.n_zero),
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):
+    """The CPU oracle (single-threaded) on a bounded sample of the same
+    inference: a few candidates, each on its full own sweep."""
+    import oracle as orc
+
+    b = bits.cpu().numpy().view(np.uint32)
+    flat, off = [], []
+    pos = 0
+    for i, n in enumerate(lens):
+        w = b[int(bitoff[i]):int(bitoff[i]) + (int(n) + 31) // 32].astype(np.uint64)
+        flat.append(((w[:, None] >> np.arange(32, dtype=np.uint64)) & 1).astype(np.uint8).reshape(-1)[:int(n)])
+        off.append(pos)
+        pos += int(n)
+    flat = np.concatenate(flat)
+    off = np.array(off, np.uint64)
+    cf = np.array([orc.cycle_len(orc.make_probe(*r)) for r in prows], np.uint64)
+    oprobes = [orc.make_probe(*r) for r in prows]
+    # one candidate per associativity, cycling through the grid, until the budget is used
+    order = sorted(range(len(crows)), key=lambda i: (crows[i][2], crows[i][0], crows[i][3]))
+    picks, seen = [], set()
+    for i in order:
+        if crows[i][2] not in seen:
+            picks.append(i)
+            seen.add(crows[i][2])
+    done, acc, t_used = [], 0, 0.0
+    for i in picks:
+        if t_used > budget_s:
+            break
+        m = orc.make_model(*crows[i][:4])
+        t = time.perf_counter()
+        _, _, n = orc.infer([m], oprobes, flat, off, cf, probe_select=1)
+        t_used += time.perf_counter() - t
+        own = [p for p in range(len(prows)) if orc.in_own_sweep(m, oprobes[p])]
+        acc += int(sum(int(lens[p]) for p in own))
+        done.append(crows[i])
+    return {"value": acc / t_used, "unit": "accesses/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(done)} candidates (one per associativity {sorted({c[2] for c in done})}) on "
+                      f"their full own sweeps, {acc} replayed accesses, {t_used:.1f} s single-threaded"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,306 @@
+/*
+ * pchase.h -- C ABI of the MI355X (gfx950) fine-grained P-chase cache-model
+ * replay library, libpchase.so.
+ *
+ * The library replays pointer-chase access sequences through parameterised
+ * set-associative cache models and searches candidate models for the one
+ * that reproduces an observed hit/miss trace.  The method is the
+ * fine-grained P-chase of Mei & Chu, "Dissecting GPU Memory Hierarchy
+ * through Microbenchmarking" (IEEE TPDS 2017, arXiv:1509.02308):
+ *   - the chase itself: Listing 1 (A[i] = (i + s) mod N) and Listing 2
+ *     (j = A[j]), notation of Table 4 (C, b, a, T; N, s, k, r);
+ *   - the cache model: Section 4.1, Assumptions 1-3 (T*a*b = C, set bits
+ *     directly above the offset bits, LRU), with the non-LRU policies and
+ *     non-bit-defined set mappings the paper finds in Sections 4.3-4.6;
+ *   - per-access latency and index records: Section 4.2, Listing 3;
+ *   - parameter search: Section 4.2, Fig. 6 two-stage procedure (here an
+ *     exact exhaustive search over a candidate grid);
+ *   - throughput / bank-conflict microbenchmarks: Section 5.1 (copy
+ *     throughput = 2 * size / time), Section 6.2 (Listing 4 stride access).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (PCHASE_OK) or a negative PCHASE_E* code; the message of the
+ *     last failure on the calling thread is pchase_last_error();
+ *   - arguments are checked on the host before anything is launched; a
+ *     failed check launches nothing and writes no output;
+ *   - "_dev" pointers are device memory owned by the caller (the library
+ *     never frees them); every other pointer is host memory, read during
+ *     the call only;
+ *   - work is enqueued on `stream` (0 = the null stream).  Functions that
+ *     return values to host memory synchronise `stream` before returning;
+ *     the others return as soon as the work is enqueued;
+ *   - the library keeps per-device workspace (descriptor staging, replay
+ *     state, work queues, captured graphs) that it allocates on first use
+ *     and grows on demand; pchase_release() frees it.
+ */
+#ifndef PCHASE_H
+#define PCHASE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ errors --- */
+#define PCHASE_OK        0
+#define PCHASE_EINVAL   -1  /* malformed model, probe or argument          */
+#define PCHASE_ERANGE   -2  /* a size exceeds a buffer or a kernel limit   */
+#define PCHASE_ENOMEM   -3  /* device or host allocation failed            */
+#define PCHASE_EHIP     -4  /* a HIP runtime call failed (message has it)  */
+#define PCHASE_EABORTED -5  /* pchase_abort() stopped the work             */
+#define PCHASE_ENODEV   -6  /* no usable gfx950 device                     */
+
+/* Message of the last failure on this thread ("" if none).  The string is
+ * owned by the library and valid until the next call on this thread. */
+const char *pchase_last_error(void);
+
+/* ------------------------------------------------------------- types --- */
+/* Replacement policies.  LRU is Assumption 3 of Section 4.1; the paper
+ * shows most GPU caches break it (Section 4.5: Fermi L1 is not LRU;
+ * Section 4.6: L2 is not LRU).  FIFO and tree-PLRU are the usual hardware
+ * alternatives; RANDOM evicts way Philox4x32-10(key = seed,
+ * counter = (k_lo, k_hi, trace_lo, trace_hi)).x mod a, k = access index,
+ * trace = trace id, so the draw depends on nothing but those values. */
+enum {
+    PCHASE_LRU = 0,
+    PCHASE_FIFO = 1,
+    PCHASE_PLRU = 2,
+    PCHASE_RANDOM = 3
+};
+
+/* A cache model (Table 4 notation).  Valid iff sets*ways*line_bytes ==
+ * capacity_bytes (Assumption 1), line_bytes is a power of two >= 4,
+ * 1 <= ways <= 128, policy is one of the above, PLRU has a power-of-two
+ * ways, and set_shift is 0 or >= log2(line_bytes).  The set of byte address
+ * x is (x / line_bytes) mod sets when set_shift == 0 (Assumption 2), else
+ * (x >> set_shift) mod sets (the texture-L1 style mapping of Section 4.3,
+ * where bits above the line offset other than the next ones pick the set).
+ * A cache starts empty; a miss fills the lowest-numbered empty way of its
+ * set; only a full set asks the policy for a victim. */
+typedef struct pchase_model {
+    uint64_t capacity_bytes; /* C */
+    uint32_t line_bytes;     /* b */
+    uint32_t ways;           /* a */
+    uint32_t sets;           /* T */
+    uint32_t policy;         /* PCHASE_LRU .. PCHASE_RANDOM */
+    uint32_t set_shift;      /* 0, or log2 of the set-mapping unit in bytes */
+    uint32_t reserved;       /* must be 0 */
+    uint64_t seed;           /* RANDOM key (ignored by other policies) */
+} pchase_model;
+
+/* A P-chase probe (Listing 1 + Listing 2).  Element i of the array sits at
+ * byte base_offset + elem_bytes*i and holds (i + s/elem_bytes) mod
+ * (n_bytes/elem_bytes).  The chase starts at element j0 and runs `passes`
+ * full cycles; one cycle has L = Ne / gcd(Ne, Se mod Ne) accesses
+ * (Ne = n_bytes/elem_bytes, Se = s_bytes/elem_bytes).  Valid iff elem_bytes
+ * is 4, n_bytes and s_bytes are multiples of it, 1 <= Ne < 2^31,
+ * j0 < Ne, passes >= 1 and base_offset/elem_bytes < 2^31.  s_bytes >= n_bytes
+ * is legal (Fig. 4 sweeps s past N). */
+typedef struct pchase_probe {
+    uint64_t n_bytes;     /* N */
+    uint64_t s_bytes;     /* s */
+    uint64_t base_offset; /* byte address of element 0 */
+    uint64_t j0;          /* first element visited */
+    uint32_t elem_bytes;  /* 4 (int32 array) */
+    uint32_t passes;      /* full cycles replayed */
+} pchase_probe;
+
+/* ------------------------------------------------------------ traces --- */
+/* Length of one probe's trace: *len = passes * L, *cycle = L (either
+ * pointer may be NULL).  Host only. */
+int pchase_trace_len(const pchase_probe *probe, uint64_t *len, uint64_t *cycle);
+
+/* Writes the visited element indices of n_probes probes back to back into
+ * idx_dev (int32, capacity `cap` elements): probe p occupies
+ * [off[p], off[p+1]).  off (host, n_probes+1 entries, may be NULL) receives
+ * the offsets.  ERANGE if the total exceeds cap. */
+int pchase_trace(const pchase_probe *probes, uint32_t n_probes, int32_t *idx_dev,
+                 uint64_t *off, uint64_t cap, hipStream_t stream);
+
+/* ------------------------------------------------------------ replay --- */
+/* Replay scheduling: BATCHED runs every pair in one captured graph of
+ * persistent kernels fed by a cost-ordered work queue; PLAIN launches one
+ * ordinary kernel per model.  Results are identical. */
+enum { PCHASE_BATCHED = 0, PCHASE_PLAIN = 1 };
+
+/* Replays (model, trace) pairs over materialised index traces.
+ *   models[n_models]                      host
+ *   idx_dev                               element indices, int32, device
+ *   trace_off[n_traces+1]                 host, trace t = idx[off[t], off[t+1])
+ *   trace_base[n_traces]                  host, byte address of element 0
+ *                                         (NULL = 0)
+ *   elem_bytes                            bytes per element (4)
+ *   pair_model[n_pairs], pair_trace[n_pairs]   host
+ *   count_from[n_pairs]                   host, first access counted in
+ *                                         misses_steady (NULL = 0)
+ *   misses_dev[2*n_pairs]                 uint64 out: (total, steady) per pair
+ *   hitbits_dev                           uint32 out or NULL: bit k%32 of word
+ *                                         bitoff[i] + k/32 is pair i's access k
+ *                                         (1 = hit); words the pairs touch are
+ *                                         fully written
+ *   bitoff[n_pairs]                       host, word offsets (needed iff hitbits)
+ * The RANDOM policy's trace id is pair_trace[i].  Access k of a pair whose
+ * trace holds a negative index is rejected (EINVAL, detected on device, the
+ * outputs of that call are then unspecified). */
+int cache_replay_batch(const pchase_model *models, uint32_t n_models,
+                       const int32_t *idx_dev, const uint64_t *trace_off,
+                       const uint64_t *trace_base, uint32_t elem_bytes, uint32_t n_traces,
+                       const uint32_t *pair_model, const uint32_t *pair_trace,
+                       const uint64_t *count_from, uint64_t n_pairs,
+                       uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
+                       uint32_t mode, hipStream_t stream);
+
+/* Same replay with traces given as probes instead of index arrays: pair i
+ * replays probe pair_probe[i] through model pair_model[i]; the trace id of
+ * the RANDOM policy is pair_probe[i]; count_from NULL means one cycle L of
+ * the probe (one warm pass, the paper's "preheat").  Nothing is
+ * materialised: each set's accesses are enumerated from (N, s) directly. */
+int cache_replay_probes(const pchase_model *models, uint32_t n_models,
+                        const pchase_probe *probes, uint32_t n_probes,
+                        const uint32_t *pair_model, const uint32_t *pair_probe,
+                        const uint64_t *count_from, uint64_t n_pairs,
+                        uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
+                        uint32_t mode, hipStream_t stream);
+
+/* --------------------------------------------------------- inference --- */
+enum { PCHASE_PROBES_ALL = 0, PCHASE_PROBES_OWN_SWEEP = 1 };
+enum { PCHASE_EXHAUSTIVE = 0, PCHASE_LEARNED = 1 };
+/* OR into infer_cache_params' mode to replay with the PLAIN schedule (one
+ * launch per candidate) instead of the captured persistent batch. */
+#define PCHASE_SCHED_PLAIN 0x100
+
+/* Observed fine-grained P-chase runs (Listing 3 outputs): probe p's trace
+ * is known from the probe; its hit bits are either given (bits_dev, layout
+ * of cache_replay_batch with bitoff) or derived from latencies (lat_dev,
+ * uint32 cycles back to back at lat_off[p]) as hit iff latency <= threshold;
+ * threshold == UINT32_MAX asks for the lower end of the widest gap between
+ * distinct latency values (the two populations of t = t0 + tm*r).  Accesses
+ * before count_from[p] (NULL: one cycle L) are not compared. */
+typedef struct pchase_observation {
+    const pchase_probe *probes;
+    uint32_t n_probes;
+    uint32_t threshold;
+    const uint32_t *bits_dev;   /* or NULL */
+    const uint64_t *bitoff;     /* host, with bits_dev */
+    const uint32_t *lat_dev;    /* or NULL */
+    const uint64_t *lat_off;    /* host, with lat_dev */
+    const uint64_t *count_from; /* host or NULL */
+} pchase_observation;
+
+/* Learned proposer (3-layer MLP, bf16 weights, fp32 accumulate) over the
+ * fixed 768-probe feature grid; see pchase_mlp_* below. */
+typedef struct pchase_mlp pchase_mlp;
+
+typedef struct pchase_result {
+    int64_t best;               /* candidate index, -1 if none compared */
+    uint64_t best_m, best_n;    /* mismatches / compared accesses of best */
+    uint64_t n_zero;            /* candidates with m == 0 (zero class) */
+    uint64_t replayed_accesses; /* accesses replayed by this call */
+    uint32_t fallback;          /* LEARNED: 1 if exhaustive search was needed */
+    uint32_t threshold_used;    /* latency threshold applied (UINT32_MAX: none) */
+} pchase_result;
+
+/* Scores every candidate against the observation and returns the exact
+ * rational argmin of m/n (m = mismatched hit/miss decisions, n = compared
+ * accesses), ties to the lowest candidate index, candidates with n == 0
+ * skipped.  probe_select = ALL compares every probe with every candidate;
+ * OWN_SWEEP compares candidate (C, b, ...) on the probes with
+ * C/2 <= N <= 2C, N % b == 0 and s in {b/2, b, 2b} (the Section 4.2
+ * overflow sweeps around a candidate capacity).
+ * mode = LEARNED ranks candidates with `net` (whose candidate list must be
+ * `cands`), replays only the top-k and accepts the best when its m == 0;
+ * otherwise it falls back to the exhaustive search (out->fallback = 1).
+ * mn_dev (uint64[2*n_cands], nullable) receives (m, n) per candidate;
+ * zero_host (uint32[(n_cands+31)/32], nullable) the zero-class bitmap
+ * (exhaustive results only).  Synchronises `stream`. */
+int infer_cache_params(const pchase_observation *obs, const pchase_model *cands,
+                       uint32_t n_cands, int probe_select, int mode, uint32_t topk,
+                       const pchase_mlp *net, pchase_result *out, uint64_t *mn_dev,
+                       uint32_t *zero_host, hipStream_t stream);
+
+/* ---------------------------------------------------- microbenchmarks --- */
+/* Load flavours of the single-lane chase: which cache level a load may be
+ * served from (gfx950 cache-policy bits of the load instruction). */
+enum {
+    PCHASE_LOAD_DEFAULT = 0, /* may hit the per-CU vector L1                    */
+    PCHASE_LOAD_L2 = 1,      /* sc0: bypasses the vector L1, served by L2      */
+    PCHASE_LOAD_SYSTEM = 2,  /* sc0 sc1: system scope, past L2 (MALL / HBM)    */
+    PCHASE_LOAD_STREAM = 3   /* nt: non-temporal hint                           */
+};
+
+/* Fine-grained P-chase on the device (Listing 3 redesigned for one gfx950
+ * lane): initialises the probe's array in array_dev (array_bytes >=
+ * base_offset + n_bytes, 4-byte aligned), walks it once untimed (the
+ * paper's preheat), then times k dependent loads one by one with the
+ * shader clock, keeping the records in LDS until the walk ends.
+ * lat_dev[i] = raw cycles of access i, idx_dev[i] = element index accessed
+ * at step i (the paper's s_index holds the loaded value, one step later).
+ * *overhead_cycles receives the median cost of the same timed sequence
+ * with the load replaced by a register move (subtract it for net latency).
+ * ERANGE if k exceeds the LDS record capacity (pchase_microbench_max_k).
+ * Synchronises `stream`. */
+int microbench_pchase(const pchase_probe *probe, uint32_t flavor, void *array_dev,
+                      uint64_t array_bytes, uint64_t k, uint32_t *lat_dev, int32_t *idx_dev,
+                      int32_t *overhead_cycles, hipStream_t stream);
+uint64_t pchase_microbench_max_k(void);
+
+/* Copy throughput (Section 5.1): grid x block threads copy `bytes` from
+ * src_dev to dst_dev, each thread moving `ilp` independent words per step
+ * (dtype 0 = 4-byte words, 1 = 16-byte words), `reps` times; *gbps =
+ * 2 * bytes * reps / elapsed (read + write), timed with HIP events.
+ * Synchronises `stream`. */
+int microbench_hbm_stream(const void *src_dev, void *dst_dev, uint64_t bytes, uint32_t dtype,
+                          uint32_t grid, uint32_t block, uint32_t ilp, uint32_t reps,
+                          double *gbps, hipStream_t stream);
+
+/* LDS bank conflicts (Section 6.2, Listing 4): one wave, lane t chases
+ * words t*stride, 64 dependent LDS loads per timed repetition; for every
+ * stride in [stride_lo, stride_hi] writes the average cycles per load
+ * (x100, rounded) to cycles_dev[stride - stride_lo].  stride_hi <= 64. */
+int microbench_lds_bank(uint32_t stride_lo, uint32_t stride_hi, uint32_t reps,
+                        uint32_t *cycles_dev, hipStream_t stream);
+
+/* ------------------------------------------------------ learned model --- */
+/* Fixed feature grid of the learned proposer: 256 array sizes
+ * N_i = 4096 + 512 i bytes times strides {32, 64, 128} bytes, 2 passes;
+ * feature = steady misses / L of each probe. */
+#define PCHASE_MLP_IN 768
+#define PCHASE_MLP_HIDDEN 256
+
+/* Creates a network for n_out candidate classes with weights drawn from
+ * `seed`.  Device memory is allocated here and freed by pchase_mlp_destroy. */
+int pchase_mlp_create(uint32_t n_out, uint64_t seed, pchase_mlp **net);
+void pchase_mlp_destroy(pchase_mlp *net);
+/* Feature vectors (fp32 [n][768], device) of n models, one row each,
+ * computed by replaying the feature grid. */
+int pchase_mlp_features(const pchase_model *models, uint32_t n, float *x_dev, hipStream_t stream);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on a batch:
+ * x_dev fp32 [batch][768], labels_dev int32 [batch].  *loss (nullable)
+ * receives the mean cross-entropy before the step (synchronises). */
+int pchase_mlp_train_step(pchase_mlp *net, const float *x_dev, const int32_t *labels_dev,
+                          uint32_t batch, float lr, float *loss, hipStream_t stream);
+/* Logits fp32 [batch][n_out] of x_dev. */
+int pchase_mlp_forward(const pchase_mlp *net, const float *x_dev, uint32_t batch,
+                       float *logits_dev, hipStream_t stream);
+/* Raw parameter access for checkpoints and tests: which = 0..5 selects
+ * W1, b1, W2, b2, W3, b3 (bf16 weights as uint16, fp32 biases);
+ * adam = 0 parameter, 1 first moment (fp32), 2 second moment (fp32).
+ * *bytes receives the size; data may be NULL to query it. */
+int pchase_mlp_param(const pchase_mlp *net, uint32_t which, uint32_t adam, void *data,
+                     uint64_t *bytes, int to_device /*0 read, 1 write*/);
+int pchase_mlp_step_count(const pchase_mlp *net, uint64_t *steps, int set);
+
+/* --------------------------------------------------------- lifecycle --- */
+/* Sets a host flag that running persistent replays poll; they drain and
+ * the call that launched them returns PCHASE_EABORTED.  pchase_abort(0)
+ * clears it. */
+void pchase_abort(int on);
+/* Frees the calling thread's current device workspace. */
+int pchase_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libpchase (include/pchase.h), same names as the C ABI.
+
+Argument marshalling only: every step of the replay, scoring and search runs
+in the library's HIP kernels.  Device buffers are torch tensors on the
+current device, streams are torch's current stream.  The binding raises if
+the built library is missing; it never falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpchase.so")
+
+PCHASE_OK = 0
+LRU, FIFO, PLRU, RANDOM = 0, 1, 2, 3
+BATCHED, PLAIN = 0, 1
+PROBES_ALL, PROBES_OWN_SWEEP = 0, 1
+EXHAUSTIVE, LEARNED = 0, 1
+SCHED_PLAIN = 0x100
+LOAD_DEFAULT, LOAD_L2, LOAD_SYSTEM, LOAD_STREAM = 0, 1, 2, 3
+MLP_IN, MLP_HIDDEN = 768, 256
+U32_MAX = 0xFFFFFFFF
+
+u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
+vp = ctypes.c_void_p
+
+
+class PchaseModel(ctypes.Structure):
+    _fields_ = [("capacity_bytes", u64), ("line_bytes", u32), ("ways", u32), ("sets", u32),
+                ("policy", u32), ("set_shift", u32), ("reserved", u32), ("seed", u64)]
+
+
+class PchaseProbe(ctypes.Structure):
+    _fields_ = [("n_bytes", u64), ("s_bytes", u64), ("base_offset", u64), ("j0", u64),
+                ("elem_bytes", u32), ("passes", u32)]
+
+
+class PchaseObservation(ctypes.Structure):
+    _fields_ = [("probes", vp), ("n_probes", u32), ("threshold", u32), ("bits_dev", vp),
+                ("bitoff", vp), ("lat_dev", vp), ("lat_off", vp), ("count_from", vp)]
+
+
+class PchaseResult(ctypes.Structure):
+    _fields_ = [("best", i64), ("best_m", u64), ("best_n", u64), ("n_zero", u64),
+                ("replayed_accesses", u64), ("fallback", u32), ("threshold_used", u32)]
+
+
+class PchaseError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pchase error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run paper_1509_02308_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pchase_last_error.restype = ctypes.c_char_p
+        L.pchase_trace_len.argtypes = [ctypes.POINTER(PchaseProbe), vp, vp]
+        L.pchase_trace.argtypes = [vp, u32, vp, vp, u64, vp]
+        L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.cache_replay_probes.argtypes = [vp, u32, vp, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.infer_cache_params.argtypes = [ctypes.POINTER(PchaseObservation), vp, u32, ctypes.c_int,
+                                         ctypes.c_int, u32, vp, ctypes.POINTER(PchaseResult), vp, vp, vp]
+        L.microbench_pchase.argtypes = [ctypes.POINTER(PchaseProbe), u32, vp, u64, u64, vp, vp, vp, vp]
+        L.pchase_microbench_max_k.restype = u64
+        L.microbench_hbm_stream.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp, vp]
+        L.microbench_lds_bank.argtypes = [u32, u32, u32, vp, vp]
+        L.pchase_abort.argtypes = [ctypes.c_int]
+        L.pchase_release.argtypes = []
+        for name in ("pchase_mlp_create", "pchase_mlp_destroy", "pchase_mlp_features",
+                     "pchase_mlp_train_step", "pchase_mlp_forward", "pchase_mlp_param",
+                     "pchase_mlp_step_count"):
+            if not hasattr(L, name):
+                continue
+        if hasattr(L, "pchase_mlp_create"):
+            L.pchase_mlp_create.argtypes = [u32, u64, ctypes.POINTER(vp)]
+            L.pchase_mlp_destroy.argtypes = [vp]
+            L.pchase_mlp_destroy.restype = None
+            L.pchase_mlp_features.argtypes = [vp, u32, vp, vp]
+            L.pchase_mlp_train_step.argtypes = [vp, vp, vp, u32, ctypes.c_float, vp, vp]
+            L.pchase_mlp_forward.argtypes = [vp, vp, u32, vp, vp]
+            L.pchase_mlp_param.argtypes = [vp, u32, u32, vp, vp, ctypes.c_int]
+            L.pchase_mlp_step_count.argtypes = [vp, vp, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pchase_last_error().decode()
+
+
+def check(rc: int):
+    if rc != PCHASE_OK:
+        raise PchaseError(rc, last_error())
+
+
+# ------------------------------------------------------------- marshalling --
+def _stream(stream=None):
+    if stream is not None:
+        return vp(stream)
+    import torch
+    return vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return vp(t.data_ptr())
+
+
+def _hptr(a, dtype):
+    """Host pointer of a numpy array kept alive by the caller (or None)."""
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr, arr.ctypes.data_as(vp)
+
+
+def models(rows) -> ctypes.Array:
+    """Model descriptors from (C, b, a, policy[, set_shift[, seed]]) rows or a
+    workloads.MODEL_DT array; sets = C / (a*b) (Assumption 1)."""
+    rows = list(rows)
+    out = (PchaseModel * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        if isinstance(r, np.void):
+            C, b, a, pol, sh, seed = (int(r["C"]), int(r["b"]), int(r["a"]), int(r["policy"]),
+                                      int(r["set_shift"]), int(r["seed"]))
+        else:
+            r = tuple(int(x) for x in r) + (0,) * (6 - len(r))
+            C, b, a, pol, sh, seed = r
+        sets = C // (a * b) if a * b and C % (a * b) == 0 else 0
+        out[i] = PchaseModel(C, b, a, sets, pol, sh, 0, seed)
+    out.n = len(rows)
+    return out
+
+
+def probes(rows) -> ctypes.Array:
+    """Probe descriptors from (N, s[, passes[, j0[, base]]]) rows or a
+    workloads.PROBE_DT array (elem = 4 bytes)."""
+    rows = list(rows)
+    out = (PchaseProbe * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        if isinstance(r, np.void):
+            N, s, base, j0, elem, passes = (int(r["N"]), int(r["s"]), int(r["base"]), int(r["j0"]),
+                                            int(r["elem"]), int(r["passes"]))
+        else:
+            r = tuple(int(x) for x in r)
+            N, s = r[0], r[1]
+            passes = r[2] if len(r) > 2 else 2
+            j0 = r[3] if len(r) > 3 else 0
+            base = r[4] if len(r) > 4 else 0
+            elem = 4
+        out[i] = PchaseProbe(N, s, base, j0, elem, passes)
+    out.n = len(rows)
+    return out
+
+
+def pchase_trace_len(probe: PchaseProbe):
+    n, L = u64(), u64()
+    check(lib().pchase_trace_len(ctypes.byref(probe), ctypes.byref(n), ctypes.byref(L)))
+    return int(n.value), int(L.value)
+
+
+def pchase_trace(probe_arr, idx, stream=None) -> np.ndarray:
+    """Fills idx (int32 CUDA tensor) with the probes' traces; returns offsets."""
+    off = np.zeros(probe_arr.n + 1, dtype=np.uint64)
+    check(lib().pchase_trace(ctypes.cast(probe_arr, vp), probe_arr.n, _dptr(idx), off.ctypes.data_as(vp),
+                             idx.numel() if idx is not None else 0, _stream(stream)))
+    return off
+
+
+def cache_replay_batch(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
+                       misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None):
+    toff, p_toff = _hptr(trace_off, np.uint64)
+    tb, p_tb = _hptr(trace_base, np.uint64)
+    pm, p_pm = _hptr(pair_model, np.uint32)
+    pt, p_pt = _hptr(pair_trace, np.uint32)
+    cf, p_cf = _hptr(count_from, np.uint64)
+    bo, p_bo = _hptr(bitoff, np.uint64)
+    check(lib().cache_replay_batch(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
+                                   len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
+                                   p_bo, mode, _stream(stream)))
+
+
+def cache_replay_probes(model_arr, probe_arr, pair_model, pair_probe, count_from, misses, hitbits=None,
+                        bitoff=None, mode=BATCHED, stream=None):
+    pm, p_pm = _hptr(pair_model, np.uint32)
+    pp, p_pp = _hptr(pair_probe, np.uint32)
+    cf, p_cf = _hptr(count_from, np.uint64)
+    bo, p_bo = _hptr(bitoff, np.uint64)
+    check(lib().cache_replay_probes(ctypes.cast(model_arr, vp), model_arr.n, ctypes.cast(probe_arr, vp),
+                                    probe_arr.n, p_pm, p_pp, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
+                                    p_bo, mode, _stream(stream)))
+
+
+def infer_cache_params(probe_arr, cand_arr, bits=None, bitoff=None, lat=None, lat_off=None,
+                       threshold=U32_MAX, count_from=None, probe_select=PROBES_OWN_SWEEP,
+                       mode=EXHAUSTIVE, topk=8, net=None, mn=None, want_zero=False, stream=None):
+    """Returns (PchaseResult, zero-class bitmap as uint32 array or None)."""
+    bo, p_bo = _hptr(bitoff, np.uint64)
+    lo, p_lo = _hptr(lat_off, np.uint64)
+    cf, p_cf = _hptr(count_from, np.uint64)
+    obs = PchaseObservation(ctypes.cast(probe_arr, vp), probe_arr.n, threshold, _dptr(bits), p_bo,
+                            _dptr(lat), p_lo, p_cf)
+    res = PchaseResult()
+    zero = np.zeros((cand_arr.n + 31) // 32, dtype=np.uint32) if want_zero else None
+    check(lib().infer_cache_params(ctypes.byref(obs), ctypes.cast(cand_arr, vp), cand_arr.n, probe_select,
+                                   mode, topk, net, ctypes.byref(res), _dptr(mn),
+                                   zero.ctypes.data_as(vp) if zero is not None else None,
+                                   _stream(stream)))
+    return res, zero
+
+
+def pchase_microbench_max_k() -> int:
+    return int(lib().pchase_microbench_max_k())
+
+
+def microbench_pchase(probe: PchaseProbe, flavor, array, k, lat, idx, stream=None) -> int:
+    ovh = i32()
+    check(lib().microbench_pchase(ctypes.byref(probe), flavor, _dptr(array),
+                                  array.numel() * array.element_size(), k, _dptr(lat), _dptr(idx),
+                                  ctypes.byref(ovh), _stream(stream)))
+    return int(ovh.value)
+
+
+def microbench_hbm_stream(src, dst, nbytes, dtype, grid, block, ilp, reps, stream=None) -> float:
+    g = ctypes.c_double()
+    check(lib().microbench_hbm_stream(_dptr(src), _dptr(dst), nbytes, dtype, grid, block, ilp, reps,
+                                      ctypes.byref(g), _stream(stream)))
+    return float(g.value)
+
+
+def microbench_lds_bank(stride_lo, stride_hi, reps, cycles, stream=None):
+    check(lib().microbench_lds_bank(stride_lo, stride_hi, reps, _dptr(cycles), _stream(stream)))
+
+
+def pchase_abort(on: bool):
+    lib().pchase_abort(1 if on else 0)
+
+
+def pchase_release():
+    check(lib().pchase_release())

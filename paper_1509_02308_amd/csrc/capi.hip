@@ -1,0 +1,490 @@
+// capi.hip -- C-ABI entry points: trace generation, replay of probes and of
+// materialised traces, exhaustive and learned inference.
+#include <algorithm>
+#include <cstring>
+
+#include "plan.h"
+
+namespace pc {
+
+
+
+static int validate_models(const pchase_model* models, uint32_t n, std::vector<DevModel>* out) {
+    if (n && !models) return set_error(PCHASE_EINVAL, "models is NULL");
+    out->resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        int rc = check_model(models[i], &(*out)[i], i);
+        if (rc) return rc;
+    }
+    return PCHASE_OK;
+}
+
+static int validate_probes(const pchase_probe* probes, uint32_t n, std::vector<DevProbe>* out,
+                           std::vector<uint64_t>* len) {
+    if (n && !probes) return set_error(PCHASE_EINVAL, "probes is NULL");
+    out->resize(n);
+    len->resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        int rc = check_probe(probes[i], &(*out)[i], &(*len)[i], i);
+        if (rc) return rc;
+    }
+    return PCHASE_OK;
+}
+
+static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
+    const uint64_t C = c.capacity_bytes, b = c.line_bytes, N = p.n_bytes, s = p.s_bytes;
+    if (2 * N < C || N > 2 * C) return false;
+    if (N % b) return false;
+    return 2 * s == b || s == b || s == 2 * b;
+}
+
+}  // namespace pc
+
+using namespace pc;
+
+// ------------------------------------------------------------- traces ---
+extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32_t* idx_dev, uint64_t* off,
+                            uint64_t cap, hipStream_t stream) {
+    std::vector<DevProbe> dp;
+    std::vector<uint64_t> len;
+    int rc = validate_probes(probes, n_probes, &dp, &len);
+    if (rc) return rc;
+    std::vector<uint64_t> o(n_probes + 1, 0);
+    uint64_t maxlen = 0;
+    for (uint32_t i = 0; i < n_probes; ++i) {
+        o[i + 1] = o[i] + len[i];
+        maxlen = std::max(maxlen, len[i]);
+    }
+    if (o[n_probes] > cap)
+        return set_error(PCHASE_ERANGE, "trace needs %llu elements, capacity is %llu",
+                         (unsigned long long)o[n_probes], (unsigned long long)cap);
+    if (o[n_probes] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
+    if (off) std::memcpy(off, o.data(), o.size() * sizeof(uint64_t));
+    if (n_probes == 0 || o[n_probes] == 0) return PCHASE_OK;
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    const size_t bytes = dp.size() * sizeof(DevProbe) + o.size() * sizeof(uint64_t);
+    hipError_t e = ws->stage.ensure(bytes);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    DevProbe* d_p = ws->stage.as<DevProbe>();
+    uint64_t* d_o = reinterpret_cast<uint64_t*>(ws->stage.as<uint8_t>() + dp.size() * sizeof(DevProbe));
+    PC_HIP(hipMemcpyAsync(d_p, dp.data(), dp.size() * sizeof(DevProbe), hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_o, o.data(), o.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_trace(d_p, d_o, n_probes, maxlen, idx_dev, stream));
+    // the staging buffer is reused by the next call: finish before releasing it
+    PC_HIP(hipStreamSynchronize(stream));
+    return PCHASE_OK;
+}
+
+// -------------------------------------------------------- probe replay ---
+extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models, const pchase_probe* probes,
+                                   uint32_t n_probes, const uint32_t* pair_model, const uint32_t* pair_probe,
+                                   const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
+                                   uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode,
+                                   hipStream_t stream) {
+    if (mode > PCHASE_PLAIN) return set_error(PCHASE_EINVAL, "unknown mode %u", mode);
+    std::vector<DevModel> dm;
+    std::vector<DevProbe> dp;
+    std::vector<uint64_t> len;
+    int rc = validate_models(models, n_models, &dm);
+    if (rc) return rc;
+    rc = validate_probes(probes, n_probes, &dp, &len);
+    if (rc) return rc;
+    if (n_pairs == 0) return PCHASE_OK;
+    if (!pair_model || !pair_probe) return set_error(PCHASE_EINVAL, "pair arrays are NULL");
+    if (!misses_dev) return set_error(PCHASE_EINVAL, "misses_dev is NULL");
+    if (hitbits_dev && !bitoff) return set_error(PCHASE_EINVAL, "hitbits_dev needs bitoff");
+    if (n_pairs >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many pairs");
+    std::vector<uint32_t> order(n_pairs);
+    for (uint64_t i = 0; i < n_pairs; ++i) {
+        if (pair_model[i] >= n_models) return set_error(PCHASE_EINVAL, "pair %llu: model index out of range", (unsigned long long)i);
+        if (pair_probe[i] >= n_probes) return set_error(PCHASE_EINVAL, "pair %llu: probe index out of range", (unsigned long long)i);
+        order[i] = (uint32_t)i;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return pair_model[x] < pair_model[y]; });
+    std::vector<SweepJob> jobs(n_pairs);
+    for (uint64_t q = 0; q < n_pairs; ++q) {
+        const uint32_t i = order[q];
+        SweepJob& j = jobs[q];
+        j.model = pair_model[i];
+        j.probe = pair_probe[i];
+        j.out = i;
+        j.trace_id = pair_probe[i];
+        j.count_from = count_from ? count_from[i] : dp[pair_probe[i]].L;
+        j.bitoff = bitoff ? bitoff[i] : 0;
+    }
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    SweepPlan plan;
+    rc = build_sweep_plan(&plan, dm, dp, len, jobs, hitbits_dev != nullptr);
+    if (rc) return rc;
+    rc = run_sweep_plan(ws, &plan, false, misses_dev, 2 * n_pairs, hitbits_dev, hitbits_dev != nullptr, mode,
+                        stream, {}, "");
+    if (rc) return rc;
+    PC_HIP(hipStreamSynchronize(stream));
+    uint32_t status = 0;
+    PC_HIP(hipMemcpy(&status, plan.d_queues + plan.batched.size(), sizeof status, hipMemcpyDeviceToHost));
+    if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
+    return PCHASE_OK;
+}
+
+// -------------------------------------------------- trace-array replay ---
+extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models, const int32_t* idx_dev,
+                                  const uint64_t* trace_off, const uint64_t* trace_base, uint32_t elem_bytes,
+                                  uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
+                                  const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
+                                  uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode,
+                                  hipStream_t stream) {
+    if (mode > PCHASE_PLAIN) return set_error(PCHASE_EINVAL, "unknown mode %u", mode);
+    if (elem_bytes != 4) return set_error(PCHASE_EINVAL, "elem_bytes must be 4");
+    std::vector<DevModel> dm;
+    int rc = validate_models(models, n_models, &dm);
+    if (rc) return rc;
+    if (n_pairs == 0) return PCHASE_OK;
+    if (!trace_off || !pair_model || !pair_trace) return set_error(PCHASE_EINVAL, "trace or pair arrays are NULL");
+    if (!misses_dev) return set_error(PCHASE_EINVAL, "misses_dev is NULL");
+    if (hitbits_dev && !bitoff) return set_error(PCHASE_EINVAL, "hitbits_dev needs bitoff");
+    if (n_pairs >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many pairs");
+    for (uint32_t t = 0; t < n_traces; ++t) {
+        if (trace_off[t + 1] < trace_off[t]) return set_error(PCHASE_EINVAL, "trace_off is not monotone at %u", t);
+        if (trace_base && (trace_base[t] >= (1ull << 33) || trace_base[t] % 4))
+            return set_error(PCHASE_EINVAL, "trace %u: base must be a multiple of 4 below 2^33", t);
+    }
+    if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
+
+    // bucket pairs by (policy, group width), longest first inside a bucket
+    struct Item {
+        int key;
+        uint64_t len;
+        uint32_t i;
+    };
+    std::vector<Item> items(n_pairs);
+    uint64_t max_state = 0;
+    for (uint64_t i = 0; i < n_pairs; ++i) {
+        if (pair_model[i] >= n_models) return set_error(PCHASE_EINVAL, "pair %llu: model index out of range", (unsigned long long)i);
+        if (pair_trace[i] >= n_traces) return set_error(PCHASE_EINVAL, "pair %llu: trace index out of range", (unsigned long long)i);
+        const DevModel& m = dm[pair_model[i]];
+        uint32_t w = 1;
+        while (w < m.ways && w < 64) w *= 2;
+        int wl = 0;
+        while ((1u << wl) < w) ++wl;
+        const uint64_t len = trace_off[pair_trace[i] + 1] - trace_off[pair_trace[i]];
+        items[i] = Item{(int)m.policy * 8 + wl, len, (uint32_t)i};
+        max_state = std::max<uint64_t>(max_state, (uint64_t)m.sets * 32 + (uint64_t)m.sets * m.ways * 8);
+    }
+    std::sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+        if (x.key != y.key) return x.key < y.key;
+        if (x.len != y.len) return x.len > y.len;
+        return x.i < y.i;
+    });
+    std::vector<StreamPair> pairs(n_pairs);
+    for (uint64_t q = 0; q < n_pairs; ++q) {
+        const uint32_t i = items[q].i;
+        StreamPair& p = pairs[q];
+        p.start = trace_off[pair_trace[i]];
+        p.len = items[q].len;
+        p.base = trace_base ? trace_base[pair_trace[i]] : 0;
+        p.count_from = count_from ? count_from[i] : 0;
+        p.bitoff = bitoff ? bitoff[i] : 0;
+        p.model = pair_model[i];
+        p.trace_id = pair_trace[i];
+        p.out = i;
+        p.pad = 0;
+    }
+
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    // descriptors
+    const size_t o_models = 0;
+    const size_t o_pairs = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
+    const size_t o_status = o_pairs + (pairs.size() * sizeof(StreamPair) + 255) / 256 * 256;
+    const size_t total = o_status + 256;
+    hipError_t e = ws->stage.ensure(total);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    uint8_t* sb = ws->stage.as<uint8_t>();
+    DevModel* d_models = reinterpret_cast<DevModel*>(sb + o_models);
+    StreamPair* d_pairs = reinterpret_cast<StreamPair*>(sb + o_pairs);
+    uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + o_status);
+    PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(StreamPair), hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_fill_u32(d_status, 64, 0, stream));
+
+    // state slabs: one per resident group, bounded by a 4 GiB pool
+    const uint64_t slab_bytes = (max_state + 255) / 256 * 256;
+    const uint64_t pool_cap = 4ull << 30;
+    uint64_t groups_max = pool_cap / slab_bytes;
+    if (groups_max < 1) return set_error(PCHASE_ERANGE, "model state of %llu bytes exceeds the slab pool",
+                                         (unsigned long long)slab_bytes);
+
+    // epochs are unique per pair across calls; on wrap the pool is cleared
+    if ((uint64_t)ws->epoch + n_pairs + 1 >= 0xFFFFFFFFull) {
+        ws->epoch = 0;
+        ws->slab_clean = 0;
+    }
+    size_t qi = 0;
+    uint64_t q = 0;
+    while (q < n_pairs) {
+        const int key = items[q].key;
+        uint64_t e2 = q;
+        while (e2 < n_pairs && items[e2].key == key) ++e2;
+        const int pol = key / 8, wl = key % 8, W = 1 << wl;
+        int occ = ws->occ_stream[pol][wl];
+        if (occ == 0) {
+            hipError_t eo = stream_occupancy(pol, W, &occ);
+            if (eo != hipSuccess) return hip_fail(eo, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            if (occ < 1) occ = 1;
+            ws->occ_stream[pol][wl] = occ;
+        }
+        const uint64_t gpb = 4ull * (64 / W);  // groups per 256-thread block
+        uint64_t blocks = (uint64_t)occ * ws->cus;
+        const uint64_t need = (e2 - q + gpb - 1) / gpb;
+        if (mode == PCHASE_PLAIN) blocks = need;  // one group per pair, no reuse beyond the queue
+        blocks = std::min(blocks, need);
+        blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, groups_max / gpb));
+        const uint64_t slab_total = blocks * gpb * slab_bytes;
+        if (slab_total > ws->slab.cap) {
+            e = ws->slab.ensure(slab_total);
+            if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "slab pool of %llu bytes: %s",
+                                                  (unsigned long long)slab_total, hipGetErrorString(e));
+            ws->slab_clean = 0;
+        }
+        if (ws->slab_clean < ws->slab.cap) {
+            PC_HIP(hipMemsetAsync(ws->slab.p, 0, ws->slab.cap, stream));
+            ws->slab_clean = ws->slab.cap;
+        }
+        StreamArgs a;
+        a.pairs = d_pairs + q;
+        a.n_pairs = (uint32_t)(e2 - q);
+        a.queue = d_status + 2 + qi;
+        a.models = d_models;
+        a.idx = idx_dev;
+        a.misses = misses_dev;
+        a.bits = hitbits_dev;
+        a.slab = ws->slab.as<uint8_t>();
+        a.slab_bytes = slab_bytes;
+        a.epoch_base = ws->epoch + (uint32_t)q;
+        a.elem_shift = 2;
+        a.abort_flag = abort_flag_dev();
+        a.status = d_status;
+        PC_HIP(launch_stream(pol, W, a, (uint32_t)blocks, stream));
+        ++qi;
+        q = e2;
+        if (qi >= 60) {
+            // more buckets than status words: drain before reusing queues
+            PC_HIP(hipStreamSynchronize(stream));
+            PC_HIP(launch_fill_u32(d_status + 2, 62, 0, stream));
+            qi = 0;
+        }
+    }
+    ws->epoch += (uint32_t)n_pairs + 1;
+    PC_HIP(hipStreamSynchronize(stream));
+    uint32_t status = 0;
+    PC_HIP(hipMemcpy(&status, d_status, sizeof status, hipMemcpyDeviceToHost));
+    if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
+    if (status & 2u) return set_error(PCHASE_EINVAL, "a trace holds a negative element index");
+    return PCHASE_OK;
+}
+
+// ----------------------------------------------------------- inference ---
+static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const pchase_model* cands,
+                            uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
+                            const std::vector<uint64_t>& len, const std::vector<uint64_t>& cf,
+                            const std::vector<uint64_t>& bitoff, const uint32_t* bits, int probe_select,
+                            const std::vector<uint8_t>* allow, pchase_result* out, uint64_t* mn_dev,
+                            uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched) {
+    // plan cache key: everything that shapes the schedule
+    Digest dg;
+    dg.add(&n_cands, sizeof n_cands);
+    dg.add(cands, n_cands * sizeof(pchase_model));
+    dg.add(obs->probes, obs->n_probes * sizeof(pchase_probe));
+    dg.add(cf.data(), cf.size() * sizeof(uint64_t));
+    dg.add(bitoff.data(), bitoff.size() * sizeof(uint64_t));
+    dg.add(&probe_select, sizeof probe_select);
+    if (allow) dg.add(allow->data(), allow->size());
+    const std::string key = dg.str();
+    auto it = ws->plans.find(key);
+    InferPlan* ip;
+    if (it == ws->plans.end()) {
+        std::unique_ptr<InferPlan> np(new InferPlan());
+        np->n_cands = n_cands;
+        np->n_host.assign(n_cands, 0);
+        std::vector<SweepJob> jobs;
+        for (uint32_t c = 0; c < n_cands; ++c) {
+            if (allow && !(*allow)[c]) continue;
+            for (uint32_t p = 0; p < obs->n_probes; ++p) {
+                if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
+                SweepJob j;
+                j.model = c;
+                j.probe = p;
+                j.out = c;
+                j.trace_id = p;
+                j.count_from = cf[p];
+                j.bitoff = bitoff[p];
+                jobs.push_back(j);
+                if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
+            }
+        }
+        int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false);
+        if (rc) return rc;
+        const size_t zw = (n_cands + 31) / 32;
+        const size_t bytes = 2 * n_cands * sizeof(uint64_t) + zw * 4 + 256 + sizeof(ArgminOut);
+        hipError_t e = np->dev.ensure(bytes);
+        if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "inference plan: %s", hipGetErrorString(e));
+        uint8_t* b = np->dev.as<uint8_t>();
+        np->d_m = reinterpret_cast<uint64_t*>(b);
+        np->d_n = np->d_m + n_cands;
+        np->d_zero = reinterpret_cast<uint32_t*>(np->d_n + n_cands);
+        np->d_out = reinterpret_cast<ArgminOut*>(b + (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256);
+        PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
+        if (ws->plans.size() > 16) ws->plans.clear();
+        ip = np.get();
+        ws->plans[key] = std::move(np);
+    } else {
+        ip = it->second.get();
+    }
+    const size_t zw = (n_cands + 31) / 32;
+    InferPlan* pp = ip;
+    auto tail = [pp, zw](hipStream_t s) -> hipError_t {
+        hipError_t e = launch_fill_u32(pp->d_zero, zw, 0, s);
+        if (e != hipSuccess) return e;
+        return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
+    };
+    int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,
+                            sched, stream, tail, "argmin");
+    if (rc) return rc;
+    ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
+    PC_HIP(hipMemcpyAsync(hr, ip->d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));
+    if (zero_host) PC_HIP(hipMemcpyAsync(static_cast<uint8_t*>(ws->host_res) + 256, ip->d_zero, zw * 4,
+                                         hipMemcpyDeviceToHost, stream));
+    if (mn_dev) {
+        PC_HIP(hipMemcpy2DAsync(mn_dev, 16, ip->d_m, 8, 8, n_cands, hipMemcpyDeviceToDevice, stream));
+        PC_HIP(hipMemcpy2DAsync(mn_dev + 1, 16, ip->d_n, 8, 8, n_cands, hipMemcpyDeviceToDevice, stream));
+    }
+    PC_HIP(hipStreamSynchronize(stream));
+    uint32_t status = 0;
+    PC_HIP(hipMemcpy(&status, ip->sweep.d_queues + ip->sweep.batched.size(), sizeof status, hipMemcpyDeviceToHost));
+    if (status & 1u) return set_error(PCHASE_EABORTED, "inference aborted by pchase_abort");
+    out->best = hr->best;
+    out->best_m = hr->m;
+    out->best_n = hr->n;
+    out->n_zero = hr->n_zero;
+    if (zero_host && zw * 4 <= 4096 - 256) std::memcpy(zero_host, static_cast<uint8_t*>(ws->host_res) + 256, zw * 4);
+    *replayed = ip->sweep.accesses;
+    return PCHASE_OK;
+}
+
+
+extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
+                                  int probe_select, int mode, uint32_t topk, const pchase_mlp* net,
+                                  pchase_result* out, uint64_t* mn_dev, uint32_t* zero_host,
+                                  hipStream_t stream) {
+    if (!obs || !out) return set_error(PCHASE_EINVAL, "obs and out must not be NULL");
+    if (probe_select != PCHASE_PROBES_ALL && probe_select != PCHASE_PROBES_OWN_SWEEP)
+        return set_error(PCHASE_EINVAL, "unknown probe_select %d", probe_select);
+    const uint32_t sched = (mode & PCHASE_SCHED_PLAIN) ? PCHASE_PLAIN : PCHASE_BATCHED;
+    mode &= ~PCHASE_SCHED_PLAIN;
+    if (mode != PCHASE_EXHAUSTIVE && mode != PCHASE_LEARNED) return set_error(PCHASE_EINVAL, "unknown mode %d", mode);
+    if (mode == PCHASE_LEARNED && (!net || topk == 0)) return set_error(PCHASE_EINVAL, "LEARNED needs a network and topk >= 1");
+    if (n_cands == 0) return set_error(PCHASE_EINVAL, "no candidates");
+    if (zero_host && (n_cands + 31) / 32 * 4 > 4096 - 256) return set_error(PCHASE_ERANGE, "zero-class bitmap too large");
+    std::vector<DevModel> dm;
+    std::vector<DevProbe> dp;
+    std::vector<uint64_t> len;
+    int rc = validate_models(cands, n_cands, &dm);
+    if (rc) return rc;
+    rc = validate_probes(obs->probes, obs->n_probes, &dp, &len);
+    if (rc) return rc;
+    if (obs->n_probes == 0) return set_error(PCHASE_EINVAL, "no observed probes");
+    const bool have_bits = obs->bits_dev != nullptr, have_lat = obs->lat_dev != nullptr;
+    if (have_bits == have_lat) return set_error(PCHASE_EINVAL, "give exactly one of bits_dev and lat_dev");
+    if (have_bits && !obs->bitoff) return set_error(PCHASE_EINVAL, "bits_dev needs bitoff");
+    if (have_lat && !obs->lat_off) return set_error(PCHASE_EINVAL, "lat_dev needs lat_off");
+    std::vector<uint64_t> cf(obs->n_probes), bitoff(obs->n_probes);
+    uint64_t words = 0, maxlen = 0;
+    for (uint32_t p = 0; p < obs->n_probes; ++p) {
+        cf[p] = obs->count_from ? obs->count_from[p] : dp[p].L;
+        maxlen = std::max(maxlen, len[p]);
+        if (have_bits) {
+            bitoff[p] = obs->bitoff[p];
+        } else {
+            if (obs->lat_off[p + 1] - obs->lat_off[p] != len[p])
+                return set_error(PCHASE_EINVAL, "probe %u: %llu latencies for a trace of %llu accesses", p,
+                                 (unsigned long long)(obs->lat_off[p + 1] - obs->lat_off[p]),
+                                 (unsigned long long)len[p]);
+            bitoff[p] = words;
+            words += (len[p] + 31) / 32;
+        }
+    }
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    const uint32_t* bits = obs->bits_dev;
+    out->threshold_used = 0xFFFFFFFFu;
+    if (have_lat) {
+        // latency -> hit bits on the device
+        const uint64_t n_lat = obs->lat_off[obs->n_probes] - obs->lat_off[0];
+        const size_t o_bits = 0;
+        const size_t o_off = (words * 4 + 255) / 256 * 256;
+        const size_t o_mm = o_off + ((2 * (size_t)obs->n_probes + 1) * 8 + 255) / 256 * 256;
+        const size_t o_present = o_mm + 256;
+        const uint64_t present_words = (1ull << 26) / 32;
+        size_t total = o_present + (obs->threshold == 0xFFFFFFFFu ? present_words * 4 : 0);
+        hipError_t e = ws->obs.ensure(total);
+        if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "observation scratch: %s", hipGetErrorString(e));
+        uint8_t* b = ws->obs.as<uint8_t>();
+        uint32_t* d_bits = reinterpret_cast<uint32_t*>(b + o_bits);
+        uint64_t* d_latoff = reinterpret_cast<uint64_t*>(b + o_off);
+        uint64_t* d_bitoff = d_latoff + obs->n_probes + 1;
+        uint32_t* d_mm = reinterpret_cast<uint32_t*>(b + o_mm);
+        PC_HIP(hipMemcpyAsync(d_latoff, obs->lat_off, (obs->n_probes + 1) * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(hipMemcpyAsync(d_bitoff, bitoff.data(), obs->n_probes * 8, hipMemcpyHostToDevice, stream));
+        uint32_t mm_init[4] = {0xFFFFFFFFu, 0u, obs->threshold, 0u};
+        PC_HIP(hipMemcpyAsync(d_mm, mm_init, sizeof mm_init, hipMemcpyHostToDevice, stream));
+        if (obs->threshold == 0xFFFFFFFFu) {
+            PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(b + o_present), present_words, 0, stream));
+            // the presence bitmap covers 2^26 distinct values above the minimum
+            uint32_t mmh[3];
+            PC_HIP(launch_auto_threshold(obs->lat_dev + obs->lat_off[0], n_lat, d_mm,
+                                         reinterpret_cast<uint32_t*>(b + o_present), present_words * 32,
+                                         d_mm + 2, stream));
+            PC_HIP(hipMemcpyAsync(mmh, d_mm, sizeof mmh, hipMemcpyDeviceToHost, stream));
+            PC_HIP(hipStreamSynchronize(stream));
+            if ((uint64_t)mmh[1] - mmh[0] >= present_words * 32 || mmh[2] == 0xFFFFFFFFu)
+                return set_error(PCHASE_ERANGE, "latency range %u..%u too wide for the automatic threshold", mmh[0], mmh[1]);
+        }
+        PC_HIP(launch_classify(obs->lat_dev, d_latoff, d_bitoff, obs->n_probes, maxlen, d_mm + 2, d_bits, stream));
+        uint32_t th = 0;
+        PC_HIP(hipMemcpyAsync(&th, d_mm + 2, 4, hipMemcpyDeviceToHost, stream));
+        PC_HIP(hipStreamSynchronize(stream));
+        out->threshold_used = th;
+        bits = d_bits;
+    }
+
+    out->fallback = 0;
+    uint64_t replayed = 0;
+    if (mode == PCHASE_LEARNED) {
+        std::vector<uint8_t> allow;
+        rc = infer_learned(ws, obs, cands, n_cands, dp, len, cf, bitoff, bits, topk, net, &allow, stream);
+        if (rc) return rc;
+        rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, &allow, out,
+                              nullptr, nullptr, stream, &replayed, sched);
+        if (rc) return rc;
+        out->replayed_accesses = replayed;
+        if (out->best >= 0 && out->best_m == 0) return PCHASE_OK;
+        out->fallback = 1;
+    }
+    rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, nullptr, out, mn_dev,
+                          zero_host, stream, &replayed, sched);
+    if (rc) return rc;
+    out->replayed_accesses += replayed;
+    if (mode == PCHASE_EXHAUSTIVE) out->replayed_accesses = replayed;
+    return PCHASE_OK;
+}

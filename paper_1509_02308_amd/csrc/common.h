@@ -1,0 +1,187 @@
+// common.h -- internal definitions shared by the HIP kernels and the host
+// side of libpchase (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pchase.h"
+
+namespace pc {
+
+// ---------------------------------------------------------------- limits --
+constexpr uint32_t kMaxWays = 128;
+constexpr uint32_t kInvalidTag = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+
+// Replay classes: ways held in registers (unrolled up to the class bound) or
+// in an LDS column per lane for the large associativities.
+enum WayClass : int { kA1 = 0, kA2, kA4, kA8, kA16, kALds, kNumClasses };
+__host__ __device__ inline int way_class(uint32_t a) {
+    return a <= 1 ? kA1 : a <= 2 ? kA2 : a <= 4 ? kA4 : a <= 8 ? kA8 : a <= 16 ? kA16 : kALds;
+}
+
+// ------------------------------------------------------ device descriptors --
+// A model as the kernels see it (derived on the host from pchase_model).
+struct DevModel {
+    uint32_t line_shift;  // log2(b)
+    uint32_t unit_shift;  // log2 of the set-mapping unit (== line_shift by default)
+    uint32_t sets;        // T
+    uint32_t ways;        // a
+    uint32_t policy;
+    uint32_t log2_ways;   // PLRU tree depth
+    uint32_t seed_lo, seed_hi;
+};
+
+// A probe as the kernels see it: element indices, one cycle = L accesses.
+struct DevProbe {
+    uint64_t base;        // byte address of element 0
+    uint32_t ne;          // N / elem
+    uint32_t se;          // (s / elem) mod ne
+    uint32_t L;           // cycle length
+    uint32_t j0;
+    uint32_t passes;
+    uint32_t elem_shift;  // log2(elem)
+};
+
+// One replay job of the probe kernels: model x probe.
+struct SweepJob {
+    uint32_t model;
+    uint32_t probe;
+    uint32_t out;         // counter slot (pair index, or candidate index when scoring)
+    uint32_t trace_id;    // RANDOM counter high word
+    uint64_t count_from;
+    uint64_t bitoff;      // word offset of the output / observed bitmap
+};
+
+// A wave's worth of (job, set) items: items item0 .. item0+n-1 of the run of
+// jobs that starts at `job` (all with the same model); item i is set i % T of
+// job job + i / T.
+struct SweepTask {
+    uint32_t job;
+    uint32_t item0;
+    uint32_t n;
+    uint32_t model;
+};
+
+// Materialised-trace pair.
+struct StreamPair {
+    uint64_t start;       // first index of the trace in idx
+    uint64_t len;
+    uint64_t base;        // byte address of element 0
+    uint64_t count_from;
+    uint64_t bitoff;
+    uint32_t model;
+    uint32_t trace_id;
+    uint32_t out;
+    uint32_t pad;
+};
+
+
+// ------------------------------------------------------- kernel arguments --
+struct SweepArgs {
+    const SweepTask* tasks;
+    uint32_t n_tasks;
+    uint32_t persistent;      // 1: waves pull tasks from *queue
+    uint32_t* queue;
+    const SweepJob* jobs;
+    const DevModel* models;
+    const DevProbe* probes;
+    uint64_t* counters;       // replay: (total, steady) per out; score: m per out
+    uint32_t* bits;           // replay: output bitmap or null; score: observed bitmap
+    const volatile uint32_t* abort_flag;
+    uint32_t* aborted;
+};
+
+struct StreamArgs {
+    const StreamPair* pairs;
+    uint32_t n_pairs;
+    uint32_t* queue;
+    const DevModel* models;
+    const int32_t* idx;
+    uint64_t* misses;
+    uint32_t* bits;
+    uint8_t* slab;
+    uint64_t slab_bytes;     // per group
+    uint32_t epoch_base;
+    uint32_t elem_shift;
+    const volatile uint32_t* abort_flag;
+    uint32_t* status;        // bit 0: aborted, bit 1: negative index seen
+};
+
+struct ArgminOut {
+    int64_t best;
+    uint64_t m, n;
+    uint64_t n_zero;
+};
+
+// ------------------------------------------------------------ launchers --
+hipError_t launch_sweep(bool score, int pol, int cls, const SweepArgs& args, uint32_t blocks,
+                        hipStream_t stream);
+hipError_t sweep_occupancy(bool score, int pol, int cls, int* blocks_per_cu);
+void sweep_geometry(int cls, uint32_t* threads, size_t* lds);
+hipError_t sweep_prepare_lds();
+hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream);
+hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu);
+hipError_t launch_trace(const DevProbe* probes, const uint64_t* off, uint32_t n_probes, uint64_t maxlen,
+                        int32_t* idx, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_argmin(const uint64_t* m, const uint64_t* n, uint32_t nc, uint32_t* zero_bits,
+                         ArgminOut* out, hipStream_t stream);
+hipError_t launch_auto_threshold(const uint32_t* lat, uint64_t n, uint32_t* mm, uint32_t* present,
+                                 uint64_t max_bits, uint32_t* theta, hipStream_t stream);
+hipError_t launch_classify(const uint32_t* lat, const uint64_t* lat_off, const uint64_t* bitoff,
+                           uint32_t n_probes, uint64_t maxlen, const uint32_t* theta, uint32_t* bits,
+                           hipStream_t stream);
+hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t n, hipStream_t stream);
+
+// ------------------------------------------------------------ Philox ----
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32 multiplies; the high halves are xored into the other two words with
+// the round key, which advances by the Weyl increments between rounds.
+__device__ __forceinline__ uint32_t philox_x(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t h0 = __umulhi(m0, c0), l0 = m0 * c0;
+        uint32_t h1 = __umulhi(m1, c2), l1 = m1 * c2;
+        uint32_t n0 = h1 ^ c1 ^ k0;
+        uint32_t n2 = h0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = l1;
+        c2 = n2;
+        c3 = l0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0;
+}
+
+// ------------------------------------------------------------- helpers ---
+__device__ __forceinline__ uint64_t udiv64(uint64_t x, uint64_t d) {
+    if ((x >> 32) == 0 && (d >> 32) == 0) return (uint32_t)x / (uint32_t)d;
+    return x / d;
+}
+__device__ __forceinline__ uint64_t umod64(uint64_t x, uint64_t d) {
+    if ((x >> 32) == 0 && (d >> 32) == 0) return (uint32_t)x % (uint32_t)d;
+    return x % d;
+}
+
+}  // namespace pc
+
+// ------------------------------------------------------ host-side errors --
+namespace pc {
+int set_error(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+}  // namespace pc
+
+#define PC_HIP(call)                                          \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return pc::hip_fail(e_, #call); \
+    } while (0)
+
+static_assert(sizeof(pchase_model) == 40, "pchase_model layout");
+static_assert(sizeof(pchase_probe) == 40, "pchase_probe layout");
+static_assert(sizeof(pchase_result) == 48, "pchase_result layout");

@@ -1,0 +1,57 @@
+// host_common.h -- host-side declarations shared by the C-ABI translation
+// units of libpchase (workspace, validation, kernel launchers).
+#pragma once
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace pc {
+
+// ----------------------------------------------------------- validation --
+int check_model(const pchase_model& m, DevModel* d, uint64_t index);
+int check_probe(const pchase_probe& p, DevProbe* d, uint64_t* len, uint64_t index);
+
+// ----------------------------------------------------------- workspace ---
+// Growable device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n);
+    void release();
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct InferPlan;
+
+struct Workspace {
+    int device = -1;
+    int cus = 0;
+    std::mutex mu;
+    DevBuf stage;      // per-call descriptors
+    DevBuf aux;        // per-call device scratch (counters, queues, results)
+    DevBuf obs;        // derived observed bitmaps
+    DevBuf slab;       // stream-replay set state
+    size_t slab_clean = 0;  // bytes of `slab` known to hold epoch 0 or older epochs
+    uint32_t epoch = 0;
+    void* host_res = nullptr;  // pinned result staging
+    int occ_sweep[2][4][kNumClasses] = {};
+    int occ_stream[4][7] = {};
+    bool lds_ready = false;
+    std::map<std::string, std::unique_ptr<InferPlan>> plans;
+    ~Workspace();
+};
+
+// Locks and returns the calling thread's current device's workspace.
+int workspace(Workspace** ws, std::unique_lock<std::mutex>* lock);
+const volatile uint32_t* abort_flag_dev();
+uint32_t abort_flag_host();
+
+int persistent_blocks(Workspace* ws, bool score, int pol, int cls, uint32_t* blocks);
+
+}  // namespace pc

@@ -1,0 +1,323 @@
+// microbench.hip -- the paper's microbenchmarks redesigned for one gfx950
+// GPU.
+//
+// * microbench_pchase: the fine-grained P-chase (Section 4.2, Listing 3).
+//   One lane initialises nothing itself; an init kernel writes the chase
+//   array (Listing 1), then a single active lane walks it once untimed (the
+//   preheat) and times k dependent loads one by one.  Each timed segment is
+//   "read shader clock, load, wait for the load, read shader clock" in one
+//   asm block, so the compiler cannot move work into or out of it; the
+//   explicit wait for the load plays the role of the paper's dependent
+//   s_index store.  Records stay in LDS until the walk ends, so recording
+//   does not touch the caches under test.
+// * microbench_hbm_stream: copy throughput over a grid x block x ILP sweep
+//   (Section 5.1), throughput = 2 * size / time.
+// * microbench_lds_bank: Listing 4 on one wave; lane t chases word t*stride
+//   64 times, the average cycles per load show the bank-conflict degree
+//   (Section 6.2).
+#include <algorithm>
+#include <vector>
+
+#include "host_common.h"
+
+namespace pc {
+
+// ----------------------------------------------------------- P-chase ----
+__global__ void pchase_init_kernel(int32_t* a, uint32_t ne, uint32_t se) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t v = i + se;
+        if (v >= ne) v -= ne;
+        a[i] = (int32_t)v;
+    }
+}
+
+template <int FLAVOR>
+__device__ __forceinline__ void timed_load(const int32_t* addr, int32_t& j, uint64_t& t0, uint64_t& t1) {
+    if constexpr (FLAVOR == PCHASE_LOAD_DEFAULT) {
+        asm volatile(
+            "s_memtime %0\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "global_load_dword %2, %3, off\n\t"
+            "s_waitcnt vmcnt(0)\n\t"
+            "s_memtime %1\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&s"(t0), "=&s"(t1), "=&v"(j)
+            : "v"(addr)
+            : "memory");
+    } else if constexpr (FLAVOR == PCHASE_LOAD_L2) {
+        asm volatile(
+            "s_memtime %0\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "global_load_dword %2, %3, off sc0\n\t"
+            "s_waitcnt vmcnt(0)\n\t"
+            "s_memtime %1\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&s"(t0), "=&s"(t1), "=&v"(j)
+            : "v"(addr)
+            : "memory");
+    } else if constexpr (FLAVOR == PCHASE_LOAD_SYSTEM) {
+        asm volatile(
+            "s_memtime %0\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "global_load_dword %2, %3, off sc0 sc1\n\t"
+            "s_waitcnt vmcnt(0)\n\t"
+            "s_memtime %1\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&s"(t0), "=&s"(t1), "=&v"(j)
+            : "v"(addr)
+            : "memory");
+    } else {
+        asm volatile(
+            "s_memtime %0\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "global_load_dword %2, %3, off nt\n\t"
+            "s_waitcnt vmcnt(0)\n\t"
+            "s_memtime %1\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&s"(t0), "=&s"(t1), "=&v"(j)
+            : "v"(addr)
+            : "memory");
+    }
+}
+
+// the same segment with the load replaced by a register move
+__device__ __forceinline__ void timed_nothing(int32_t& j, uint64_t& t0, uint64_t& t1) {
+    asm volatile(
+        "s_memtime %0\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mov_b32 %2, 0\n\t"
+        "s_memtime %1\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&s"(t0), "=&s"(t1), "=&v"(j)
+        :
+        : "memory");
+}
+
+template <int FLAVOR>
+__global__ void __launch_bounds__(64) pchase_walk_kernel(const int32_t* arr, uint32_t j0, uint64_t warm, uint64_t k,
+                                                         uint32_t* lat_out, int32_t* idx_out, int32_t* ovh_out) {
+    extern __shared__ uint32_t rec[];  // [k] latencies then [k] indices
+    if (threadIdx.x != 0) return;
+    int32_t j = (int32_t)j0;
+    // preheat: one untimed walk over the cycle
+    for (uint64_t i = 0; i < warm; ++i) {
+        uint64_t t0, t1;
+        int32_t nj;
+        timed_load<FLAVOR>(arr + j, nj, t0, t1);
+        j = nj;
+    }
+    j = (int32_t)j0;
+    for (uint64_t i = 0; i < k; ++i) {
+        uint64_t t0, t1;
+        int32_t nj;
+        timed_load<FLAVOR>(arr + j, nj, t0, t1);
+        rec[i] = (uint32_t)(t1 - t0);
+        rec[k + i] = (uint32_t)j;
+        j = nj;
+    }
+    // timer overhead: median of 63 empty segments
+    uint32_t o[63];
+    for (int r = 0; r < 63; ++r) {
+        uint64_t t0, t1;
+        int32_t z;
+        timed_nothing(z, t0, t1);
+        o[r] = (uint32_t)(t1 - t0) + (uint32_t)(z & 0);
+    }
+    for (int a = 1; a < 63; ++a)
+        for (int b = a; b > 0 && o[b - 1] > o[b]; --b) {
+            uint32_t t = o[b];
+            o[b] = o[b - 1];
+            o[b - 1] = t;
+        }
+    *ovh_out = (int32_t)o[31];
+    for (uint64_t i = 0; i < k; ++i) {
+        lat_out[i] = rec[i];
+        idx_out[i] = (int32_t)rec[k + i];
+    }
+}
+
+using WalkFn = void (*)(const int32_t*, uint32_t, uint64_t, uint64_t, uint32_t*, int32_t*, int32_t*);
+static WalkFn walk_fn(uint32_t flavor) {
+    switch (flavor) {
+        case PCHASE_LOAD_DEFAULT: return pchase_walk_kernel<PCHASE_LOAD_DEFAULT>;
+        case PCHASE_LOAD_L2: return pchase_walk_kernel<PCHASE_LOAD_L2>;
+        case PCHASE_LOAD_SYSTEM: return pchase_walk_kernel<PCHASE_LOAD_SYSTEM>;
+        default: return pchase_walk_kernel<PCHASE_LOAD_STREAM>;
+    }
+}
+
+static uint64_t lds_record_bytes() {
+    static uint64_t cached = 0;
+    if (cached) return cached;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 64 * 1024;
+    uint64_t lim = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                         : prop.sharedMemPerBlock;
+    lim = std::min<uint64_t>(lim, 160 * 1024);
+    cached = lim - 1024;  // leave room for static LDS
+    return cached;
+}
+
+// --------------------------------------------------------- HBM stream ----
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <class V, int ILP>
+__global__ void __launch_bounds__(1024) copy_kernel(const V* __restrict__ src, V* __restrict__ dst, uint64_t n) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = tid; base < n; base += nthreads * ILP) {
+        V v[ILP];
+#pragma unroll
+        for (int i = 0; i < ILP; ++i) {
+            const uint64_t x = base + (uint64_t)i * nthreads;
+            if (x < n) v[i] = __builtin_nontemporal_load(src + x);
+        }
+#pragma unroll
+        for (int i = 0; i < ILP; ++i) {
+            const uint64_t x = base + (uint64_t)i * nthreads;
+            if (x < n) __builtin_nontemporal_store(v[i], dst + x);
+        }
+    }
+}
+
+template <class V>
+static hipError_t launch_copy(const void* s, void* d, uint64_t n, uint32_t grid, uint32_t block, uint32_t ilp,
+                              hipStream_t stream) {
+    const V* src = static_cast<const V*>(s);
+    V* dst = static_cast<V*>(d);
+    switch (ilp) {
+        case 1: hipLaunchKernelGGL((copy_kernel<V, 1>), dim3(grid), dim3(block), 0, stream, src, dst, n); break;
+        case 2: hipLaunchKernelGGL((copy_kernel<V, 2>), dim3(grid), dim3(block), 0, stream, src, dst, n); break;
+        case 4: hipLaunchKernelGGL((copy_kernel<V, 4>), dim3(grid), dim3(block), 0, stream, src, dst, n); break;
+        default: hipLaunchKernelGGL((copy_kernel<V, 8>), dim3(grid), dim3(block), 0, stream, src, dst, n); break;
+    }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- LDS bank ----
+// Lane t starts at word t*stride; the array holds its own word addresses
+// (in bytes), so "data = sdata[data]" revisits the same word 64 times.
+__global__ void __launch_bounds__(64) lds_bank_kernel(uint32_t stride, uint32_t reps, uint32_t* out) {
+    __shared__ uint32_t sdata[64 * 64 + 64];
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t*)sdata;
+    for (uint32_t i = threadIdx.x; i < 64 * 64 + 64; i += 64) sdata[i] = lds_base + i * 4u;
+    __syncthreads();
+    uint32_t data = lds_base + threadIdx.x * stride * 4u;
+    uint64_t best = ~0ull;
+    for (uint32_t r = 0; r <= reps; ++r) {
+        uint64_t t0, t1;
+        uint32_t d = data;
+        asm volatile(
+            "s_memtime %0\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            ".rept 64\n\t"
+            "ds_read_b32 %2, %2\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            ".endr\n\t"
+            "s_memtime %1\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&s"(t0), "=&s"(t1), "+v"(d)
+            :
+            : "memory");
+        if (r > 0) best = min(best, t1 - t0);  // r == 0 warms the instruction cache
+        data = d;
+    }
+    if (threadIdx.x == 0) *out = (uint32_t)((best * 100 + 32) / 64);
+}
+
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" uint64_t pchase_microbench_max_k(void) { return lds_record_bytes() / 8; }
+
+extern "C" int microbench_pchase(const pchase_probe* probe, uint32_t flavor, void* array_dev, uint64_t array_bytes,
+                                 uint64_t k, uint32_t* lat_dev, int32_t* idx_dev, int32_t* overhead_cycles,
+                                 hipStream_t stream) {
+    if (!probe || !array_dev || !lat_dev || !idx_dev || !overhead_cycles)
+        return set_error(PCHASE_EINVAL, "NULL argument");
+    if (flavor > PCHASE_LOAD_STREAM) return set_error(PCHASE_EINVAL, "unknown load flavour %u", flavor);
+    DevProbe dp;
+    uint64_t len = 0;
+    int rc = check_probe(*probe, &dp, &len, 0);
+    if (rc) return rc;
+    if (probe->base_offset + probe->n_bytes > array_bytes)
+        return set_error(PCHASE_ERANGE, "array of %llu bytes is smaller than base_offset + N",
+                         (unsigned long long)array_bytes);
+    if ((uintptr_t)array_dev % 4) return set_error(PCHASE_EINVAL, "array_dev must be 4-byte aligned");
+    const uint64_t maxk = pchase_microbench_max_k();
+    if (k == 0 || k > maxk)
+        return set_error(PCHASE_ERANGE, "k = %llu outside [1, %llu] (LDS record capacity)", (unsigned long long)k,
+                         (unsigned long long)maxk);
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    int32_t* arr = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(array_dev) + probe->base_offset);
+    hipLaunchKernelGGL(pchase_init_kernel, dim3(1024), dim3(256), 0, stream, arr, dp.ne, dp.se);
+    PC_HIP(hipGetLastError());
+    const size_t lds = (size_t)k * 8;
+    WalkFn fn = walk_fn(flavor);
+    PC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_record_bytes()));
+    hipError_t e = ws->aux.ensure(256);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "aux: %s", hipGetErrorString(e));
+    int32_t* d_ovh = ws->aux.as<int32_t>();
+    const uint64_t warm = dp.L < k ? (uint64_t)dp.L : k;
+    hipLaunchKernelGGL(fn, dim3(1), dim3(64), lds, stream, arr, dp.j0, warm, k, lat_dev, idx_dev, d_ovh);
+    PC_HIP(hipGetLastError());
+    PC_HIP(hipMemcpyAsync(overhead_cycles, d_ovh, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    PC_HIP(hipStreamSynchronize(stream));
+    return PCHASE_OK;
+}
+
+extern "C" int microbench_hbm_stream(const void* src_dev, void* dst_dev, uint64_t bytes, uint32_t dtype,
+                                     uint32_t grid, uint32_t block, uint32_t ilp, uint32_t reps, double* gbps,
+                                     hipStream_t stream) {
+    if (!src_dev || !dst_dev || !gbps) return set_error(PCHASE_EINVAL, "NULL argument");
+    if (dtype > 1) return set_error(PCHASE_EINVAL, "dtype must be 0 (4-byte) or 1 (16-byte)");
+    const uint64_t w = dtype ? 16 : 4;
+    if (bytes == 0 || bytes % w) return set_error(PCHASE_EINVAL, "bytes must be a positive multiple of %llu",
+                                                  (unsigned long long)w);
+    if (grid == 0 || block == 0 || block > 1024 || block % 64) return set_error(PCHASE_EINVAL, "bad grid/block");
+    if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8) return set_error(PCHASE_EINVAL, "ilp must be 1, 2, 4 or 8");
+    if (reps == 0) return set_error(PCHASE_EINVAL, "reps must be >= 1");
+    const uint64_t n = bytes / w;
+    // warm-up launch (first-touch, code load)
+    hipError_t e = dtype ? launch_copy<f32x4>(src_dev, dst_dev, n, grid, block, ilp, stream)
+                         : launch_copy<float>(src_dev, dst_dev, n, grid, block, ilp, stream);
+    if (e != hipSuccess) return hip_fail(e, "copy kernel");
+    hipEvent_t a, b;
+    PC_HIP(hipEventCreate(&a));
+    PC_HIP(hipEventCreate(&b));
+    PC_HIP(hipEventRecord(a, stream));
+    for (uint32_t r = 0; r < reps; ++r) {
+        e = dtype ? launch_copy<f32x4>(src_dev, dst_dev, n, grid, block, ilp, stream)
+                  : launch_copy<float>(src_dev, dst_dev, n, grid, block, ilp, stream);
+        if (e != hipSuccess) break;
+    }
+    PC_HIP(hipEventRecord(b, stream));
+    PC_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    PC_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "copy kernel");
+    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return PCHASE_OK;
+}
+
+extern "C" int microbench_lds_bank(uint32_t stride_lo, uint32_t stride_hi, uint32_t reps, uint32_t* cycles_dev,
+                                   hipStream_t stream) {
+    if (!cycles_dev) return set_error(PCHASE_EINVAL, "cycles_dev is NULL");
+    if (stride_lo == 0 || stride_hi < stride_lo || stride_hi > 64)
+        return set_error(PCHASE_EINVAL, "strides must satisfy 1 <= lo <= hi <= 64");
+    if (reps == 0) return set_error(PCHASE_EINVAL, "reps must be >= 1");
+    for (uint32_t s = stride_lo; s <= stride_hi; ++s) {
+        hipLaunchKernelGGL(lds_bank_kernel, dim3(1), dim3(64), 0, stream, s, reps, cycles_dev + (s - stride_lo));
+        PC_HIP(hipGetLastError());
+    }
+    PC_HIP(hipStreamSynchronize(stream));
+    return PCHASE_OK;
+}

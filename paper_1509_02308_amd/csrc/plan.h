@@ -1,0 +1,79 @@
+// plan.h -- schedules of the probe-replay kernels: jobs (model x probe)
+// split into wave tasks, grouped by (policy, way class), ordered longest
+// first for the persistent batched launch, and the captured graph that
+// replays a schedule.
+#pragma once
+
+#include <functional>
+
+#include "host_common.h"
+
+namespace pc {
+
+struct Bucket {
+    int pol;
+    int cls;
+    uint32_t first;   // into the task array
+    uint32_t count;
+};
+
+struct SweepPlan {
+    uint32_t n_models = 0, n_probes = 0;
+    uint64_t n_jobs = 0, n_tasks = 0;
+    uint64_t accesses = 0;           // replayed accesses of one run
+    std::vector<Bucket> batched;     // task ranges of the cost-ordered array
+    std::vector<Bucket> plain;       // one range per model in the natural array
+    std::vector<uint64_t> clear;     // (word, count) ranges of the output bitmap
+    DevBuf dev;
+    DevModel* d_models = nullptr;
+    DevProbe* d_probes = nullptr;
+    SweepJob* d_jobs = nullptr;
+    SweepTask* d_lpt = nullptr;
+    SweepTask* d_plain = nullptr;
+    uint32_t* d_queues = nullptr;    // one per batched bucket, + status word
+    uint64_t* d_clear = nullptr;
+    // captured batched run
+    hipGraphExec_t gexec = nullptr;
+    std::string gkey;
+    ~SweepPlan();
+};
+
+// jobs must be grouped by model (each model's jobs contiguous).
+int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models,
+                     const std::vector<DevProbe>& probes, const std::vector<uint64_t>& probe_len,
+                     const std::vector<SweepJob>& jobs, bool want_clear);
+
+// Runs the plan: zeroes `counters` (n_counters words) and the bitmap ranges
+// (when clear_bits), then replays every job.  `tail` (may be empty) is
+// enqueued after the replay, inside the same graph.
+int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
+                   uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
+                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key);
+
+// Cached schedule + score buffers of one inference problem.
+struct InferPlan {
+    SweepPlan sweep;
+    std::vector<uint64_t> n_host;   // compared accesses per candidate
+    DevBuf dev;                     // m | n | zero bits | argmin out
+    uint64_t* d_m = nullptr;
+    uint64_t* d_n = nullptr;
+    uint32_t* d_zero = nullptr;
+    ArgminOut* d_out = nullptr;
+    uint32_t n_cands = 0;
+};
+
+// Learned proposer: marks in *allow the top-k candidates of the network for
+// the observation (defined with the MLP kernels).
+int infer_learned(Workspace* ws, const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
+                  const std::vector<DevProbe>& dp, const std::vector<uint64_t>& len,
+                  const std::vector<uint64_t>& cf, const std::vector<uint64_t>& bitoff, const uint32_t* bits,
+                  uint32_t topk, const pchase_mlp* net, std::vector<uint8_t>* allow, hipStream_t stream);
+
+// 128-bit FNV-style digest of byte ranges (plan cache keys).
+struct Digest {
+    uint64_t a = 1469598103934665603ull, b = 0x9E3779B97F4A7C15ull;
+    void add(const void* p, size_t n);
+    std::string str() const;
+};
+
+}  // namespace pc

@@ -1,0 +1,262 @@
+// plan.hip -- building and running probe-replay schedules.
+//
+// A job is one replay (model, probe).  A model with T sets gives each job
+// G = min(T, 64) lanes (lane g owns sets g, g+G, ...); a task is 64
+// consecutive (job, lane) items of one model.  Tasks are grouped by
+// (policy, way class) because each group is one kernel instantiation.
+//
+// PLAIN runs one ordinary launch per model, tasks in natural order.
+// BATCHED runs one persistent launch per group, each wave pulling tasks
+// from an atomic queue in longest-first order (a counting sort on a
+// log-scale cost estimate), with the whole sequence captured once into a
+// graph and replayed afterwards.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "plan.h"
+
+namespace pc {
+
+void Digest::add(const void* p, size_t n) {
+    const uint8_t* c = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        a = (a ^ c[i]) * 1099511628211ull;
+        b = (b + c[i] + 1) * 0xFF51AFD7ED558CCDull;
+        b ^= b >> 29;
+    }
+    a ^= n;
+}
+
+std::string Digest::str() const {
+    char buf[40];
+    snprintf(buf, sizeof buf, "%016llx%016llx", (unsigned long long)a, (unsigned long long)b);
+    return buf;
+}
+
+SweepPlan::~SweepPlan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    dev.release();
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const std::vector<DevProbe>& probes,
+                     const std::vector<uint64_t>& probe_len, const std::vector<SweepJob>& jobs,
+                     bool want_clear) {
+    plan->n_models = (uint32_t)models.size();
+    plan->n_probes = (uint32_t)probes.size();
+    plan->n_jobs = jobs.size();
+
+    // --- natural task order: per model run of jobs, 64 items per task
+    std::vector<SweepTask> tasks;
+    std::vector<float> cost;
+    plan->plain.clear();
+    plan->accesses = 0;
+    size_t j = 0;
+    while (j < jobs.size()) {
+        const uint32_t mi = jobs[j].model;
+        size_t e = j;
+        while (e < jobs.size() && jobs[e].model == mi) ++e;
+        const DevModel& m = models[mi];
+        const uint64_t G = m.sets < (uint32_t)kWave ? m.sets : (uint64_t)kWave;
+        const uint64_t items = (e - j) * G;
+        const double per_set = std::ceil((double)m.sets / (double)G) / (double)m.sets;
+        const double wcost = m.ways > 16 ? (double)m.ways : 1.0;
+        const uint32_t first = (uint32_t)tasks.size();
+        for (uint64_t it = 0; it < items; it += kWave) {
+            SweepTask t;
+            t.job = (uint32_t)j;
+            t.item0 = (uint32_t)it;
+            t.n = (uint32_t)std::min<uint64_t>(kWave, items - it);
+            t.model = mi;
+            const uint64_t jlo = j + it / G, jhi = j + (it + t.n - 1) / G;
+            uint64_t ml = 0;
+            for (uint64_t q = jlo; q <= jhi; ++q) ml = std::max(ml, probe_len[jobs[q].probe]);
+            tasks.push_back(t);
+            cost.push_back((float)((double)ml * per_set * wcost + 64.0));
+        }
+        for (size_t q = j; q < e; ++q) plan->accesses += probe_len[jobs[q].probe];
+        plan->plain.push_back(Bucket{(int)m.policy, way_class(m.ways), first, (uint32_t)(tasks.size() - first)});
+        j = e;
+    }
+    plan->n_tasks = tasks.size();
+
+    // --- batched order: group by (policy, class), longest first within a group
+    std::vector<uint32_t> order(tasks.size());
+    {
+        // key = group * 256 + (255 - log-cost bucket); counting sort
+        const int nkeys = 4 * kNumClasses * 256;
+        std::vector<uint32_t> cnt(nkeys + 1, 0);
+        std::vector<uint32_t> key(tasks.size());
+        for (size_t i = 0; i < tasks.size(); ++i) {
+            const DevModel& m = models[tasks[i].model];
+            const int grp = (int)m.policy * kNumClasses + way_class(m.ways);
+            int cb = (int)std::floor(std::log2((double)cost[i] + 1.0) * 8.0);
+            cb = std::max(0, std::min(255, cb));
+            key[i] = (uint32_t)(grp * 256 + (255 - cb));
+            ++cnt[key[i] + 1];
+        }
+        for (int k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
+        for (size_t i = 0; i < tasks.size(); ++i) order[cnt[key[i]]++] = (uint32_t)i;
+    }
+    std::vector<SweepTask> lpt(tasks.size());
+    plan->batched.clear();
+    for (size_t i = 0; i < order.size(); ++i) {
+        lpt[i] = tasks[order[i]];
+        const DevModel& m = models[lpt[i].model];
+        const int pol = (int)m.policy, cls = way_class(m.ways);
+        if (plan->batched.empty() || plan->batched.back().pol != pol || plan->batched.back().cls != cls)
+            plan->batched.push_back(Bucket{pol, cls, (uint32_t)i, 0});
+        plan->batched.back().count++;
+    }
+
+    // --- bitmap ranges each job writes
+    plan->clear.clear();
+    if (want_clear) {
+        for (const SweepJob& jb : jobs) {
+            plan->clear.push_back(jb.bitoff);
+            plan->clear.push_back((probe_len[jb.probe] + 31) / 32);
+        }
+    }
+
+    // --- one device allocation for everything
+    size_t off = 0;
+    const size_t o_models = off; off = align_up(off + models.size() * sizeof(DevModel), 256);
+    const size_t o_probes = off; off = align_up(off + probes.size() * sizeof(DevProbe), 256);
+    const size_t o_jobs = off; off = align_up(off + jobs.size() * sizeof(SweepJob), 256);
+    const size_t o_lpt = off; off = align_up(off + lpt.size() * sizeof(SweepTask), 256);
+    const size_t o_plain = off; off = align_up(off + tasks.size() * sizeof(SweepTask), 256);
+    const size_t o_queues = off; off = align_up(off + (plan->batched.size() + 2) * sizeof(uint32_t), 256);
+    const size_t o_clear = off; off = align_up(off + plan->clear.size() * sizeof(uint64_t), 256);
+    hipError_t e = plan->dev.ensure(off);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "plan allocation of %zu bytes: %s", off, hipGetErrorString(e));
+    uint8_t* base = plan->dev.as<uint8_t>();
+    plan->d_models = reinterpret_cast<DevModel*>(base + o_models);
+    plan->d_probes = reinterpret_cast<DevProbe*>(base + o_probes);
+    plan->d_jobs = reinterpret_cast<SweepJob*>(base + o_jobs);
+    plan->d_lpt = reinterpret_cast<SweepTask*>(base + o_lpt);
+    plan->d_plain = reinterpret_cast<SweepTask*>(base + o_plain);
+    plan->d_queues = reinterpret_cast<uint32_t*>(base + o_queues);
+    plan->d_clear = reinterpret_cast<uint64_t*>(base + o_clear);
+    auto up = [](void* dst, const void* src, size_t n) -> hipError_t {
+        return n ? hipMemcpy(dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    PC_HIP(up(plan->d_models, models.data(), models.size() * sizeof(DevModel)));
+    PC_HIP(up(plan->d_probes, probes.data(), probes.size() * sizeof(DevProbe)));
+    PC_HIP(up(plan->d_jobs, jobs.data(), jobs.size() * sizeof(SweepJob)));
+    PC_HIP(up(plan->d_lpt, lpt.data(), lpt.size() * sizeof(SweepTask)));
+    PC_HIP(up(plan->d_plain, tasks.data(), tasks.size() * sizeof(SweepTask)));
+    PC_HIP(up(plan->d_clear, plan->clear.data(), plan->clear.size() * sizeof(uint64_t)));
+    return PCHASE_OK;
+}
+
+// Enqueues the batched sequence on `s` (used both eagerly and under capture).
+static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters,
+                           uint64_t n_counters, uint32_t* bits, bool clear_bits, hipStream_t s,
+                           const std::function<hipError_t(hipStream_t)>& tail) {
+    const uint32_t nq = (uint32_t)plan->batched.size() + 2;
+    PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, s));
+    PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
+    if (clear_bits && bits)
+        PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
+    for (size_t b = 0; b < plan->batched.size(); ++b) {
+        const Bucket& bk = plan->batched[b];
+        SweepArgs a;
+        a.tasks = plan->d_lpt + bk.first;
+        a.n_tasks = bk.count;
+        a.persistent = 1;
+        a.queue = plan->d_queues + b;
+        a.jobs = plan->d_jobs;
+        a.models = plan->d_models;
+        a.probes = plan->d_probes;
+        a.counters = counters;
+        a.bits = bits;
+        a.abort_flag = abort_flag_dev();
+        a.aborted = plan->d_queues + plan->batched.size();
+        uint32_t blocks;
+        int rc = persistent_blocks(ws, score, bk.pol, bk.cls, &blocks);
+        if (rc) return rc;
+        uint32_t threads;
+        size_t lds;
+        sweep_geometry(bk.cls, &threads, &lds);
+        const uint32_t wpb = threads / kWave;
+        const uint32_t need = (bk.count + wpb - 1) / wpb;
+        if (need < blocks) blocks = need;
+        PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, blocks, s));
+    }
+    if (tail) PC_HIP(tail(s));
+    return PCHASE_OK;
+}
+
+int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
+                   uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
+                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key) {
+    if (mode == PCHASE_PLAIN) {
+        const uint32_t nq = (uint32_t)plan->batched.size() + 2;
+        PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, stream));
+        PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, stream));
+        if (clear_bits && bits)
+            PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), stream));
+        for (const Bucket& bk : plan->plain) {
+            if (bk.count == 0) continue;
+            SweepArgs a;
+            a.tasks = plan->d_plain + bk.first;
+            a.n_tasks = bk.count;
+            a.persistent = 0;
+            a.queue = nullptr;
+            a.jobs = plan->d_jobs;
+            a.models = plan->d_models;
+            a.probes = plan->d_probes;
+            a.counters = counters;
+            a.bits = bits;
+            a.abort_flag = nullptr;
+            a.aborted = nullptr;
+            uint32_t threads;
+            size_t lds;
+            sweep_geometry(bk.cls, &threads, &lds);
+            const uint32_t wpb = threads / kWave;
+            PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, (bk.count + wpb - 1) / wpb, stream));
+        }
+        if (tail) PC_HIP(tail(stream));
+        return PCHASE_OK;
+    }
+
+    // batched: capture once per (outputs, tail) and replay the graph
+    char kb[160];
+    snprintf(kb, sizeof kb, "%d|%p|%llu|%p|%d|", (int)score, (void*)counters, (unsigned long long)n_counters,
+             (void*)bits, (int)clear_bits);
+    const std::string key = std::string(kb) + tail_key;
+    if (plan->gexec == nullptr || plan->gkey != key) {
+        if (plan->gexec) {
+            (void)hipGraphExecDestroy(plan->gexec);
+            plan->gexec = nullptr;
+        }
+        hipStream_t cs;
+        PC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = PCHASE_OK;
+        if (e == hipSuccess) rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, cs, tail);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            plan->gexec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        plan->gkey = key;
+    }
+    PC_HIP(hipGraphLaunch(plan->gexec, stream));
+    return PCHASE_OK;
+}
+
+}  // namespace pc

@@ -1,0 +1,259 @@
+// stream_kernels.hip -- replay of materialised index traces (any access
+// sequence, e.g. a recorded fine-grained P-chase) through set-associative
+// cache models (Mei & Chu, Section 4.1, Assumptions 1-3, with the non-LRU
+// policies of Sections 4.5-4.6).
+//
+// A group of W lanes (W = associativity rounded up to a power of two, at
+// most 64) replays one (model, trace) pair: lane w holds way w (and way
+// w+64 when a > 64) of whichever set the current access maps to, so a tag
+// lookup is one compare per lane and a ballot.  Accesses are processed in
+// trace order; the trace is streamed from HBM W indices at a time and
+// broadcast through cross-lane shuffles.
+//
+// The cache state of a pair lives in a slab of device memory owned by its
+// group: per set a 32-byte header (epoch, FIFO pointer, PLRU bits) that only
+// the group's first lane reads and writes, and per way an 8-byte entry
+// (tag, LRU rank) that only the owning lane reads and writes, so every
+// memory dependence stays within one lane.  A set whose header epoch is not
+// the current pair's is empty; its first access rewrites every entry.
+#include "common.h"
+
+namespace pc {
+
+struct SetHeader {
+    uint32_t epoch;
+    uint32_t ptr;
+    uint64_t lo;
+    uint64_t hi;
+    uint64_t pad;
+};
+
+
+
+__device__ __forceinline__ uint32_t plru_get(uint64_t lo, uint64_t hi, uint32_t n) {
+    return n < 64 ? (uint32_t)(lo >> n) & 1u : (uint32_t)(hi >> (n - 64)) & 1u;
+}
+__device__ __forceinline__ void plru_put(uint64_t& lo, uint64_t& hi, uint32_t n, uint32_t v) {
+    if (n < 64) lo = (lo & ~(1ull << n)) | ((uint64_t)v << n);
+    else hi = (hi & ~(1ull << (n - 64))) | ((uint64_t)v << (n - 64));
+}
+
+template <int POL, int W>
+__device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32_t pair_index,
+                            int gl, int gbase, uint8_t* slab) {
+    const DevModel m = args.models[pr.model];
+    const uint32_t a = m.ways;
+    const uint32_t T = m.sets;
+    const uint32_t epoch = args.epoch_base + pair_index + 1;
+    SetHeader* hdr = reinterpret_cast<SetHeader*>(slab);
+    uint2* ent = reinterpret_cast<uint2*>(slab + (size_t)T * sizeof(SetHeader));
+    const uint64_t gmask = (W == 64) ? ~0ull : (((1ull << (W & 63)) - 1ull) << gbase);
+    const bool two = (W == 64) && (a > 64);
+    const bool own0 = (uint32_t)gl < a;
+    const bool own1 = two && (uint32_t)(gl + 64) < a;
+
+    uint64_t mt = 0, ms = 0;
+    uint32_t word = 0;
+    uint32_t* bits = args.bits ? args.bits + pr.bitoff : nullptr;
+    bool bad = false;
+
+    for (uint64_t k0 = 0; k0 < pr.len; k0 += W) {
+        int32_t mine = 0;
+        if (k0 + gl < pr.len) mine = args.idx[pr.start + k0 + gl];
+        const uint32_t nstep = (pr.len - k0 < (uint64_t)W) ? (uint32_t)(pr.len - k0) : (uint32_t)W;
+        for (uint32_t i = 0; i < nstep; ++i) {
+            const uint64_t k = k0 + i;
+            const int32_t j = __shfl(mine, gbase + (int)i, kWave);
+            bad |= j < 0;
+            const uint64_t xa = pr.base + ((uint64_t)(uint32_t)(j < 0 ? 0 : j) << args.elem_shift);
+            const uint32_t line = (uint32_t)(xa >> m.line_shift);
+            const uint32_t set = (uint32_t)umod64(xa >> m.unit_shift, T);
+
+            // header: first lane of the group only
+            uint32_t h_ep = 0, h_ptr = 0;
+            uint64_t h_lo = 0, h_hi = 0;
+            if (gl == 0) {
+                const SetHeader h = hdr[set];
+                h_ep = h.epoch;
+                h_ptr = h.ptr;
+                h_lo = h.lo;
+                h_hi = h.hi;
+            }
+            h_ep = __shfl(h_ep, gbase, kWave);
+            const bool fresh = h_ep != epoch;
+            if (fresh) {
+                h_ptr = 0;
+                h_lo = 0;
+                h_hi = 0;
+            } else {
+                h_ptr = __shfl(h_ptr, gbase, kWave);
+                h_lo = __shfl(h_lo, gbase, kWave);
+                h_hi = __shfl(h_hi, gbase, kWave);
+            }
+
+            uint2 e0 = make_uint2(kInvalidTag, 0xFFu), e1 = make_uint2(kInvalidTag, 0xFFu);
+            const uint64_t eb = (uint64_t)set * a;
+            if (!fresh) {
+                if (own0) e0 = ent[eb + gl];
+                if (own1) e1 = ent[eb + gl + 64];
+            }
+            const uint64_t hm0 = __ballot(own0 && e0.x == line) & gmask;
+            const uint64_t hm1 = __ballot(own1 && e1.x == line) & gmask;
+            const uint64_t vm0 = __ballot(own0 && e0.x != kInvalidTag) & gmask;
+            const uint64_t vm1 = __ballot(own1 && e1.x != kInvalidTag) & gmask;
+            const uint32_t nvalid = (uint32_t)(__popcll(vm0) + __popcll(vm1));
+            const bool hit = (hm0 | hm1) != 0;
+            uint32_t hw = 0;
+            if (hm0) hw = (uint32_t)(__ffsll((long long)hm0) - 1 - gbase);
+            else if (hm1) hw = (uint32_t)(__ffsll((long long)hm1) - 1 - gbase) + 64;
+
+            uint32_t x;  // way used by this access
+            bool hdr_dirty = fresh;
+            if (POL == PCHASE_LRU) {
+                uint32_t ax;
+                if (hit) {
+                    x = hw;
+                    const uint32_t src = hw & 63u;
+                    const uint32_t g0 = __shfl(e0.y, gbase + (int)src, kWave);
+                    const uint32_t g1 = __shfl(e1.y, gbase + (int)src, kWave);
+                    ax = hw < 64 ? g0 : g1;
+                } else if (nvalid < a) {
+                    x = nvalid;
+                    ax = nvalid;
+                } else {
+                    const uint64_t o0 = __ballot(own0 && e0.y == a - 1) & gmask;
+                    const uint64_t o1 = __ballot(own1 && e1.y == a - 1) & gmask;
+                    x = o0 ? (uint32_t)(__ffsll((long long)o0) - 1 - gbase)
+                           : (uint32_t)(__ffsll((long long)o1) - 1 - gbase) + 64;
+                    ax = a - 1;
+                }
+                if (own0 && e0.y < ax) e0.y += 1;
+                if (own1 && e1.y < ax) e1.y += 1;
+            } else if (POL == PCHASE_FIFO) {
+                x = hit ? hw : h_ptr;
+                if (!hit) {
+                    h_ptr = (h_ptr + 1 == a) ? 0 : h_ptr + 1;
+                    hdr_dirty = true;
+                }
+            } else if (POL == PCHASE_PLRU) {
+                if (hit) x = hw;
+                else if (nvalid < a) x = nvalid;
+                else {
+                    uint32_t node = 0;
+                    for (uint32_t d = 0; d < m.log2_ways; ++d) node = 2 * node + 1 + plru_get(h_lo, h_hi, node);
+                    x = node - (a - 1);
+                }
+                uint32_t node = 0;
+                for (uint32_t d = 0; d < m.log2_ways; ++d) {
+                    const uint32_t dir = (x >> (m.log2_ways - 1 - d)) & 1u;
+                    plru_put(h_lo, h_hi, node, dir ^ 1u);
+                    node = 2 * node + 1 + dir;
+                }
+                hdr_dirty = true;
+            } else {
+                if (hit) x = hw;
+                else if (nvalid < a) x = nvalid;
+                else x = philox_x((uint32_t)k, (uint32_t)(k >> 32), pr.trace_id, 0u, m.seed_lo,
+                                  m.seed_hi) % a;
+            }
+            bool dirty0 = fresh, dirty1 = fresh;
+            if (POL == PCHASE_LRU) {
+                dirty0 = dirty1 = true;
+            }
+            if ((uint32_t)gl == x) {
+                e0.x = line;
+                e0.y = 0;
+                dirty0 = true;
+            }
+            if ((uint32_t)gl + 64 == x) {
+                e1.x = line;
+                e1.y = 0;
+                dirty1 = true;
+            }
+            if (own0 && dirty0) ent[eb + gl] = e0;
+            if (own1 && dirty1) ent[eb + gl + 64] = e1;
+            if (gl == 0 && hdr_dirty) {
+                SetHeader h;
+                h.epoch = epoch;
+                h.ptr = h_ptr;
+                h.lo = h_lo;
+                h.hi = h_hi;
+                h.pad = 0;
+                hdr[set] = h;
+            }
+
+            if (!hit) {
+                ++mt;
+                ms += (k >= pr.count_from) ? 1u : 0u;
+            }
+            word |= (hit ? 1u : 0u) << (k & 31);
+            if (((k & 31) == 31) || k + 1 == pr.len) {
+                if (bits != nullptr && gl == 0) bits[k >> 5] = word;
+                word = 0;
+            }
+        }
+    }
+    if (gl == 0) {
+        args.misses[2 * (uint64_t)pr.out] = mt;
+        args.misses[2 * (uint64_t)pr.out + 1] = ms;
+        if (bad) atomicOr(args.status, 2u);
+    }
+}
+
+template <int POL, int W>
+__global__ void __launch_bounds__(256) stream_kernel(StreamArgs args) {
+    constexpr int G = kWave / W;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gl = lane % W;
+    const int gbase = lane - gl;
+    const uint64_t group = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * G +
+                           (uint64_t)(lane / W);
+    uint8_t* slab = args.slab + group * args.slab_bytes;
+    for (uint32_t iter = 0;; ++iter) {
+        uint32_t t = 0;
+        if (gl == 0) {
+            t = atomicAdd(args.queue, 1u);
+            if ((iter & 15) == 15 && args.abort_flag != nullptr && *args.abort_flag != 0) {
+                atomicOr(args.status, 1u);
+                t = args.n_pairs;
+            }
+        }
+        t = __shfl(t, gbase, kWave);
+        if (t >= args.n_pairs) break;
+        stream_pair<POL, W>(args, args.pairs[t], t, gl, gbase, slab);
+    }
+}
+
+using StreamFn = void (*)(StreamArgs);
+
+static StreamFn pick_stream(int pol, int w) {
+#define PC_W(P)                                   \
+    switch (w) {                                  \
+        case 1: return stream_kernel<P, 1>;       \
+        case 2: return stream_kernel<P, 2>;       \
+        case 4: return stream_kernel<P, 4>;       \
+        case 8: return stream_kernel<P, 8>;       \
+        case 16: return stream_kernel<P, 16>;     \
+        case 32: return stream_kernel<P, 32>;     \
+        default: return stream_kernel<P, 64>;     \
+    }
+    switch (pol) {
+        case PCHASE_LRU: PC_W(PCHASE_LRU)
+        case PCHASE_FIFO: PC_W(PCHASE_FIFO)
+        case PCHASE_PLRU: PC_W(PCHASE_PLRU)
+        default: PC_W(PCHASE_RANDOM)
+    }
+#undef PC_W
+}
+
+hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream) {
+    hipLaunchKernelGGL(pick_stream(pol, w), dim3(blocks), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}
+
+hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)pick_stream(pol, w),
+                                                        256, 0);
+}
+
+}  // namespace pc

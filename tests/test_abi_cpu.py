@@ -1,0 +1,145 @@
+"""C-ABI checks that need no GPU: every symbol declared in include/pchase.h
+is exported by the built library, and malformed arguments are rejected on
+the host (before anything would touch a device) with the documented codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pchase.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted({n for n in names if not n.startswith("sizeof")})
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_1509_02308_amd import capi as C
+    if not os.path.exists(C.LIB_PATH):
+        pytest.fail("libpchase.so is not built (run __graft_entry__.build())")
+    C.lib()
+    return C
+
+
+def test_header_functions_exported(capi):
+    names = _declared_functions()
+    assert {"pchase_trace", "cache_replay_batch", "infer_cache_params", "microbench_pchase",
+            "microbench_hbm_stream", "microbench_lds_bank"} <= set(names)
+    L = capi.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header(capi):
+    assert ctypes.sizeof(capi.PchaseModel) == 40
+    assert ctypes.sizeof(capi.PchaseProbe) == 40
+    assert ctypes.sizeof(capi.PchaseResult) == 48
+
+
+def _rc(capi, rc):
+    return rc, capi.last_error()
+
+
+def test_trace_len_validation(capi):
+    L = capi.lib()
+    n, c = ctypes.c_uint64(), ctypes.c_uint64()
+    ok = capi.PchaseProbe(52, 4, 0, 0, 4, 6)        # Fig. 3 array, 13 words
+    assert L.pchase_trace_len(ctypes.byref(ok), ctypes.byref(n), ctypes.byref(c)) == 0
+    assert (n.value, c.value) == (78, 13)
+    for bad in (capi.PchaseProbe(10, 4, 0, 0, 4, 1),        # N not a multiple of elem
+                capi.PchaseProbe(16, 6, 0, 0, 4, 1),        # s not a multiple of elem
+                capi.PchaseProbe(16, 4, 0, 4, 4, 1),        # j0 outside
+                capi.PchaseProbe(16, 4, 0, 0, 4, 0),        # no passes
+                capi.PchaseProbe(16, 4, 0, 0, 8, 1),        # elem != 4
+                capi.PchaseProbe(16, 4, 2, 0, 4, 1),        # misaligned base
+                capi.PchaseProbe(1 << 33, 4, 0, 0, 4, 1)):  # N/elem >= 2^31
+        rc = L.pchase_trace_len(ctypes.byref(bad), None, None)
+        assert rc == -1, capi.last_error()
+        assert capi.last_error()
+
+
+@pytest.mark.parametrize("row,code", [
+    ((4096, 32, 4, 4, 0, 0, 0), -1),      # unknown policy
+    ((4096, 32, 3, 0, 0, 0, 0), -1),      # T*a*b != C
+    ((4096, 24, 4, 0, 0, 0, 0), -1),      # line not a power of two
+    ((6144, 32, 6, 2, 0, 0, 0), -1),      # PLRU with 6 ways
+    ((4096, 32, 4, 0, 3, 0, 0), -1),      # set unit smaller than a line
+    ((4096, 32, 4, 0, 0, 1, 0), -1),      # reserved field
+    ((8192 * 32, 32, 256, 0, 0, 0, 0), -2),  # ways above 128
+])
+def test_model_validation_before_launch(capi, row, code):
+    C, b, a, pol, sh, res, seed = row
+    T = C // (a * b) if C % (a * b) == 0 else 1
+    m = (capi.PchaseModel * 1)(capi.PchaseModel(C, b, a, T, pol, sh, res, seed))
+    p = capi.probes([(4096, 32, 2)])
+    pm = (ctypes.c_uint32 * 1)(0)
+    pp = (ctypes.c_uint32 * 1)(0)
+    rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
+                                        pm, pp, None, 1, ctypes.c_void_p(16), None, None, 0, None)
+    assert rc == code, capi.last_error()
+
+
+def test_pair_index_validation(capi):
+    m = capi.models([(4096, 32, 4, 0)])
+    p = capi.probes([(4096, 32, 2)])
+    pm = (ctypes.c_uint32 * 1)(1)                       # model index out of range
+    pp = (ctypes.c_uint32 * 1)(0)
+    rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
+                                        pm, pp, None, 1, ctypes.c_void_p(16), None, None, 0, None)
+    assert rc == -1 and "out of range" in capi.last_error()
+    rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
+                                        pp, pp, None, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0, None)
+    assert rc == -1 and "bitoff" in capi.last_error()
+    rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
+                                        pp, pp, None, 1, ctypes.c_void_p(16), None, None, 7, None)
+    assert rc == -1 and "mode" in capi.last_error()
+
+
+def test_trace_capacity_checked(capi):
+    p = capi.probes([(4096, 4, 2)])                      # 2048 accesses
+    off = (ctypes.c_uint64 * 2)()
+    rc = capi.lib().pchase_trace(ctypes.cast(p, ctypes.c_void_p), 1, ctypes.c_void_p(16), off, 100, None)
+    assert rc == -2 and "capacity" in capi.last_error()
+
+
+def test_infer_argument_checks(capi):
+    cands = capi.models([(4096, 32, 4, 0)])
+    probes = capi.probes([(4096, 32, 2)])
+    obs = capi.PchaseObservation(ctypes.cast(probes, ctypes.c_void_p), 1, capi.U32_MAX, None, None, None,
+                                 None, None)
+    res = capi.PchaseResult()
+    L = capi.lib()
+    # neither bits nor latencies
+    rc = L.infer_cache_params(ctypes.byref(obs), ctypes.cast(cands, ctypes.c_void_p), 1, 1, 0, 8, None,
+                              ctypes.byref(res), None, None, None)
+    assert rc == -1 and "exactly one" in capi.last_error()
+    # learned without a network
+    rc = L.infer_cache_params(ctypes.byref(obs), ctypes.cast(cands, ctypes.c_void_p), 1, 1, 1, 8, None,
+                              ctypes.byref(res), None, None, None)
+    assert rc == -1
+    rc = L.infer_cache_params(ctypes.byref(obs), ctypes.cast(cands, ctypes.c_void_p), 0, 1, 0, 8, None,
+                              ctypes.byref(res), None, None, None)
+    assert rc == -1 and "candidates" in capi.last_error()
+
+
+def test_microbench_argument_checks(capi):
+    L = capi.lib()
+    assert L.microbench_lds_bank(0, 4, 1, ctypes.c_void_p(16), None) == -1
+    assert L.microbench_lds_bank(4, 65, 1, ctypes.c_void_p(16), None) == -1
+    g = ctypes.c_double()
+    assert L.microbench_hbm_stream(ctypes.c_void_p(16), ctypes.c_void_p(16), 100, 1, 1, 64, 1, 1,
+                                   ctypes.byref(g), None) == -1          # not a multiple of 16
+    assert L.microbench_hbm_stream(ctypes.c_void_p(16), ctypes.c_void_p(16), 128, 0, 1, 64, 3, 1,
+                                   ctypes.byref(g), None) == -1          # ilp 3
+    p = capi.PchaseProbe(4096, 4, 0, 0, 4, 1)
+    ovh = ctypes.c_int32()
+    assert L.microbench_pchase(ctypes.byref(p), 0, ctypes.c_void_p(16), 1024, 10, ctypes.c_void_p(16),
+                               ctypes.c_void_p(16), ctypes.byref(ovh), None) == -2   # array too small
+    assert L.microbench_pchase(ctypes.byref(p), 9, ctypes.c_void_p(16), 8192, 10, ctypes.c_void_p(16),
+                               ctypes.c_void_p(16), ctypes.byref(ovh), None) == -1   # flavour

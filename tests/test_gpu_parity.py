@@ -1,0 +1,365 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU
+oracle on the same seeded inputs.  Hit/miss decisions, counts, argmins and
+zero classes are integer results and must match bit for bit."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1509_02308_amd import workloads as W
+from tests.gpu_common import need_gpu, orc_model, orc_probe, pack_bits, say, unpack_bits
+
+pytestmark = pytest.mark.gpu
+
+
+# ------------------------------------------------------------ fixtures ---
+# Models covering every way class (registers 1..16, LDS up to 128), every
+# policy, non-power-of-two set counts and associativities, line sizes from
+# 4 to 128 bytes and texture-style set mappings (set_shift).
+MODELS = [
+    (4096, 32, 4, W.LRU), (4096, 32, 4, W.FIFO), (4096, 32, 4, W.PLRU), (4096, 32, 4, W.RANDOM, 0, 77),
+    (48, 8, 2, W.LRU),                       # Fig. 3 cache: 12 words, 2 ways, 3 sets
+    (3072, 32, 1, W.LRU), (3072, 32, 1, W.RANDOM, 0, 5),
+    (6144, 64, 2, W.PLRU), (6144, 64, 3, W.FIFO), (6144, 32, 12, W.LRU),
+    (8192, 128, 8, W.PLRU), (8192, 32, 8, W.RANDOM, 0, 2**40 + 3),
+    (12288, 32, 96, W.LRU), (12288, 32, 96, W.FIFO), (12288, 32, 96, W.RANDOM, 0, 9),  # texture-L1 shape
+    (12288, 32, 96, W.LRU, 7),               # set picked by address bits 7-8
+    (16384, 128, 4, W.LRU), (16384, 128, 4, W.PLRU),  # Fermi-L1 shape
+    (16384, 64, 16, W.LRU), (16384, 64, 16, W.PLRU), (16384, 64, 16, W.FIFO),
+    (24576, 32, 24, W.LRU), (32768, 32, 32, W.PLRU), (32768, 64, 64, W.LRU),
+    (32768, 64, 64, W.PLRU), (65536, 64, 128, W.LRU), (65536, 64, 128, W.PLRU),
+    (65536, 128, 128, W.RANDOM, 0, 1234), (8192, 4, 16, W.LRU), (1024, 8, 2, W.FIFO, 6),
+]
+
+PROBES = [
+    (4096, 32, 2), (4128, 32, 3), (4096 + 4, 4, 2), (8192, 64, 2), (2048, 16, 2),
+    (13 * 4, 4, 4),                          # Fig. 3 array
+    (6144, 96, 2), (12544, 32, 2), (16512, 128, 3), (20000, 200, 2),
+    (65536 + 512, 128, 1), (4096, 4096, 3),   # s == N: the chase stays put
+    (4096, 8192 + 64, 2),                     # s > N
+    (30000, 4, 1, 123), (8192, 36, 2, 5, 64),  # j0 and base offsets
+    (1 << 20, 65536, 2), (1 << 18, 2048, 2), (40960, 4092, 2), (128, 4, 3),
+]
+
+
+def _expected_pair(mrow, prow, trace_id, count_from=None):
+    om, op = orc_model(mrow), orc_probe(prow)
+    idx = orc.trace(op)
+    cf = orc.cycle_len(op) if count_from is None else count_from
+    hits, mt, ms = orc.replay(om, idx, base=op.base, trace_id=trace_id, count_from=cf)
+    return hits, mt, ms
+
+
+# --------------------------------------------------------------- traces ---
+def test_trace_matches_oracle():
+    torch, capi = need_gpu()
+    rows = [(N, s, 2) for s in (32, 64, 128) for N in range(2048, 8192 + 1, 32)] + PROBES
+    parr = capi.probes(rows)
+    total = sum(orc.trace_len(orc_probe(r)) for r in rows)
+    idx = torch.full((total + 7,), -7, dtype=torch.int32, device="cuda")
+    say(f"pchase_trace: {len(rows)} probes, {total} accesses")
+    off = capi.pchase_trace(parr, idx)
+    torch.cuda.synchronize()
+    got = idx.cpu().numpy()
+    for i, r in enumerate(rows):
+        exp = orc.trace(orc_probe(r))
+        assert np.array_equal(got[off[i]:off[i + 1]], exp), r
+    assert (got[total:] == -7).all()
+
+
+# ------------------------------------------------------- probe replay ---
+def _run_probe_pairs(torch, capi, mrows, prows, pairs, mode, with_bits=True, count_from=None):
+    marr, parr = capi.models(mrows), capi.probes(prows)
+    lens = [orc.trace_len(orc_probe(prows[p])) for _, p in pairs]
+    words = [(n + 31) // 32 for n in lens]
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.full((int(sum(words)) + 1,), 0x5A5A5A5A, dtype=torch.int32, device="cuda") if with_bits else None
+    misses = torch.full((2 * len(pairs),), -1, dtype=torch.int64, device="cuda")
+    pm = np.array([m for m, _ in pairs], dtype=np.uint32)
+    pp = np.array([p for _, p in pairs], dtype=np.uint32)
+    capi.cache_replay_probes(marr, parr, pm, pp, count_from, misses, bits, bitoff if with_bits else None, mode)
+    torch.cuda.synchronize()
+    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    b = bits.cpu().numpy().view(np.uint32) if with_bits else None
+    return mis, b, bitoff, lens
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_plain_sweep_lru_bit_exact(mode):
+    """One LRU model (4 KB, 32 B, 4 ways) over N = 2..8 KB step 32 B, s in
+    {32, 64, 128}, 2 passes: per-access hit bits and miss counts."""
+    torch, capi = need_gpu()
+    model, probes = W.plain_sweep()
+    mrows = [tuple(int(x) for x in model[0])]
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in probes]
+    pairs = [(0, i) for i in range(len(prows))]
+    say(f"cache_replay_probes plain sweep mode={mode}: {len(pairs)} pairs")
+    mis, bits, bitoff, lens = _run_probe_pairs(torch, capi, mrows, prows, pairs, mode)
+    for i, (m, p) in enumerate(pairs):
+        hits, mt, ms = _expected_pair(mrows[m], prows[p], p)
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms), prows[p]
+        assert np.array_equal(unpack_bits(bits[bitoff[i]:], lens[i]), hits), prows[p]
+        # words a pair touches are fully defined: padding bits are zero
+        tail = int(bits[bitoff[i] + (lens[i] - 1) // 32])
+        assert tail >> ((lens[i] - 1) % 32) >> 1 == 0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_probe_replay_all_classes_and_policies(mode):
+    torch, capi = need_gpu()
+    pairs = [(m, p) for m in range(len(MODELS)) for p in range(len(PROBES))]
+    say(f"cache_replay_probes classes mode={mode}: {len(pairs)} pairs")
+    mis, bits, bitoff, lens = _run_probe_pairs(torch, capi, MODELS, PROBES, pairs, mode)
+    for i, (m, p) in enumerate(pairs):
+        hits, mt, ms = _expected_pair(MODELS[m], PROBES[p], p)
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms), (MODELS[m], PROBES[p])
+        assert np.array_equal(unpack_bits(bits[bitoff[i]:], lens[i]), hits), (MODELS[m], PROBES[p])
+
+
+def test_probe_replay_count_from_and_no_bits():
+    torch, capi = need_gpu()
+    pairs = [(m, p) for m in (0, 2, 9, 12, 25) for p in range(len(PROBES))]
+    cf = np.array([(7 * i) % 50 for i in range(len(pairs))], dtype=np.uint64)
+    say("cache_replay_probes explicit count_from, no bitmap")
+    mis, _, _, _ = _run_probe_pairs(torch, capi, MODELS, PROBES, pairs, 0, with_bits=False, count_from=cf)
+    for i, (m, p) in enumerate(pairs):
+        _, mt, ms = _expected_pair(MODELS[m], PROBES[p], p, count_from=int(cf[i]))
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms)
+
+
+# -------------------------------------------------- trace-array replay ---
+def _random_traces(rng, n, maxlen, span):
+    out = []
+    for _ in range(n):
+        L = int(rng.integers(0, maxlen))
+        kind = rng.integers(3)
+        if kind == 0:
+            out.append(rng.integers(0, span, size=L).astype(np.int32))
+        elif kind == 1:    # a few hot lines plus noise: exercises hits under every policy
+            hot = rng.integers(0, span, size=int(rng.integers(2, 40)))
+            out.append(rng.choice(hot, size=L).astype(np.int32))
+        else:              # a P-chase trace
+            N = int(rng.integers(64, 40000)) * 4
+            s = int(rng.integers(1, 80)) * 4
+            out.append(orc.trace(orc.make_probe(N, s, passes=2))[:max(L, 1)])
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_trace_array_replay_matches_oracle(mode):
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(2024)
+    traces = _random_traces(rng, 24, 3000, 5000)
+    bases = [int(rng.integers(0, 64)) * 4 for _ in traces]
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    pairs = [(m, t) for m in range(len(MODELS)) for t in range(len(traces))]
+    pm = np.array([m for m, _ in pairs], dtype=np.uint32)
+    pt = np.array([t for _, t in pairs], dtype=np.uint32)
+    cf = np.array([len(traces[t]) // 3 for _, t in pairs], dtype=np.uint64)
+    words = [(len(traces[t]) + 31) // 32 for _, t in pairs]
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.full((int(sum(words)) + 1,), 0x33, dtype=torch.int32, device="cuda")
+    misses = torch.full((2 * len(pairs),), -1, dtype=torch.int64, device="cuda")
+    say(f"cache_replay_batch mode={mode}: {len(pairs)} pairs")
+    capi.cache_replay_batch(capi.models(MODELS), idx, off, bases, pm, pt, cf, misses, bits, bitoff, mode)
+    torch.cuda.synchronize()
+    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    b = bits.cpu().numpy().view(np.uint32)
+    for i, (m, t) in enumerate(pairs):
+        hits, mt, ms = orc.replay(orc_model(MODELS[m]), traces[t], base=bases[t], trace_id=t,
+                                  count_from=int(cf[i]))
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms), (MODELS[m], t)
+        assert np.array_equal(unpack_bits(b[bitoff[i]:], len(traces[t])), hits), (MODELS[m], t)
+
+
+def test_trace_array_replay_repeated_calls_reuse_state():
+    """Second call with other pairs on the same (reused) state slabs."""
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(77)
+    for call in range(3):
+        traces = _random_traces(rng, 6, 2000, 3000)
+        off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+        idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+        pairs = [(m, t) for m in (0, 9, 12, 25) for t in range(len(traces))]
+        misses = torch.zeros(2 * len(pairs), dtype=torch.int64, device="cuda")
+        say(f"cache_replay_batch call {call}")
+        capi.cache_replay_batch(capi.models(MODELS), idx, off, None,
+                                np.array([m for m, _ in pairs], np.uint32),
+                                np.array([t for _, t in pairs], np.uint32), None, misses)
+        torch.cuda.synchronize()
+        mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        for i, (m, t) in enumerate(pairs):
+            _, mt, ms = orc.replay(orc_model(MODELS[m]), traces[t], trace_id=t)
+            assert (mis[i, 0], mis[i, 1]) == (mt, ms)
+
+
+# ---------------------------------------------------------- inference ---
+def _obs_from_oracle(target_row, prows):
+    """Observed hit bits of the target cache on every probe (oracle replay)."""
+    om = orc_model(target_row)
+    hits_all, off, cfs = [], [], []
+    pos = 0
+    for i, r in enumerate(prows):
+        op = orc_probe(r)
+        idx = orc.trace(op)
+        h, _, _ = orc.replay(om, idx, base=op.base, trace_id=i)
+        hits_all.append(h)
+        off.append(pos)
+        pos += len(h)
+        cfs.append(orc.cycle_len(op))
+    return hits_all, np.array(off, np.uint64), np.array(cfs, np.uint64)
+
+
+def _bits_layout(hits_all):
+    words = [(len(h) + 31) // 32 for h in hits_all]
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    packed = np.concatenate([pack_bits(h) for h in hits_all] + [np.zeros(1, np.uint32)])
+    return packed, bitoff
+
+
+@pytest.mark.parametrize("target", [0, 5, 20, 47])
+def test_inference_small_grid_matches_oracle(target):
+    torch, capi = need_gpu()
+    cands = W.candidate_grid(Cs=(4096, 6144, 8192), bs=(32, 64), As=(1, 2, 4, 8), policies=(0, 1, 2))
+    crows = [tuple(int(x) for x in c) for c in cands]
+    probes = W.sweep_union(cands)
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in probes]
+    hits_all, off, cfs = _obs_from_oracle(crows[target], prows)
+    best, m, n = orc.infer([orc_model(r) for r in crows], [orc_probe(r) for r in prows],
+                           np.concatenate(hits_all), off, cfs, probe_select=1)
+    packed, bitoff = _bits_layout(hits_all)
+    bits = torch.from_numpy(packed.view(np.int32)).cuda()
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+    say(f"infer_cache_params small grid target={target}: {len(crows)} cands, {len(prows)} probes")
+    res, zero = capi.infer_cache_params(capi.probes(prows), capi.models(crows), bits=bits, bitoff=bitoff,
+                                        probe_select=1, mn=mn, want_zero=True)
+    got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    assert np.array_equal(got[:, 0], m) and np.array_equal(got[:, 1], n)
+    assert res.best == best and res.best_m == m[best] and res.best_n == n[best]
+    zc = set(orc.zero_class(m[n > 0]).tolist()) if False else {i for i in range(len(m)) if m[i] == 0 and n[i] > 0}
+    assert res.n_zero == len(zc)
+    got_zero = {i for i in range(len(crows)) if (int(zero[i // 32]) >> (i % 32)) & 1}
+    assert got_zero == zc and target in zc
+
+
+def test_inference_from_latencies_auto_threshold():
+    """Observation given as latencies (two populations, Section 4.1
+    t = t0 + tm*r, GTX780 levels of Section 5.2); the device threshold must
+    equal the oracle's and give the same inference."""
+    torch, capi = need_gpu()
+    cands = W.candidate_grid(Cs=(4096, 8192), bs=(32, 64), As=(2, 4), policies=(0, 2))
+    crows = [tuple(int(x) for x in c) for c in cands]
+    probes = W.sweep_union(cands)
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in probes]
+    hits_all, off, cfs = _obs_from_oracle(crows[3], prows)
+    rng = np.random.default_rng(99)
+    flat = np.concatenate(hits_all)
+    lat = np.where(flat == 1, 198 + rng.integers(0, 14, size=len(flat)),
+                   339 + rng.integers(0, 40, size=len(flat))).astype(np.uint32)
+    theta = orc.auto_threshold(lat)
+    assert (orc.classify(lat, theta) == flat).all()
+    best, m, n = orc.infer([orc_model(r) for r in crows], [orc_probe(r) for r in prows], flat, off, cfs, 1)
+    lat_off = np.concatenate([off, [len(flat)]]).astype(np.uint64)
+    say("infer_cache_params from latencies")
+    res, _ = capi.infer_cache_params(capi.probes(prows), capi.models(crows),
+                                     lat=torch.from_numpy(lat.view(np.int32)).cuda(), lat_off=lat_off,
+                                     probe_select=1)
+    assert res.threshold_used == theta
+    assert res.best == best and res.best_m == m[best]
+    say("infer_cache_params from latencies, given threshold")
+    res2, _ = capi.infer_cache_params(capi.probes(prows), capi.models(crows),
+                                      lat=torch.from_numpy(lat.view(np.int32)).cuda(), lat_off=lat_off,
+                                      threshold=250, probe_select=1)
+    assert res2.threshold_used == 250 and res2.best == best
+
+
+def test_inference_all_probes_mode():
+    torch, capi = need_gpu()
+    cands = W.candidate_grid(Cs=(4096, 8192), bs=(32, 64), As=(1, 4), policies=(0, 1, 2))
+    crows = [tuple(int(x) for x in c) for c in cands] + [(4096, 32, 4, W.RANDOM, 0, 11)]
+    prows = [(N, s, 2) for s in (16, 32, 64) for N in range(2048, 12288, 512)]
+    hits_all, off, cfs = _obs_from_oracle(crows[2], prows)
+    best, m, n = orc.infer([orc_model(r) for r in crows], [orc_probe(r) for r in prows],
+                           np.concatenate(hits_all), off, cfs, probe_select=0)
+    packed, bitoff = _bits_layout(hits_all)
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+    say("infer_cache_params ALL probes")
+    res, _ = capi.infer_cache_params(capi.probes(prows), capi.models(crows),
+                                     bits=torch.from_numpy(packed.view(np.int32)).cuda(), bitoff=bitoff,
+                                     probe_select=0, mn=mn)
+    got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    assert np.array_equal(got[:, 0], m) and np.array_equal(got[:, 1], n)
+    assert res.best == best
+
+
+def test_inference_full_candidate_grid_sampled():
+    """The full search: 438 candidates (C 8..64 KB, b 32..128 B, a 1..64,
+    LRU/FIFO/PLRU), each on its own N sweep at s in {b/2, b, 2b}, against one
+    seeded target; 1,079,586 replays.  The oracle recomputes the scores of
+    a sample of candidates (plus the target and the reported best)."""
+    torch, capi = need_gpu()
+    cands, probes, target = W.inference_sweep()
+    crows = [tuple(int(x) for x in c) for c in cands]
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in probes]
+    say(f"oracle observation for target {target}")
+    hits_all, off, cfs = _obs_from_oracle(crows[target], prows)
+    packed, bitoff = _bits_layout(hits_all)
+    bits = torch.from_numpy(packed.view(np.int32)).cuda()
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+    say("infer_cache_params full grid")
+    res, zero = capi.infer_cache_params(capi.probes(prows), capi.models(crows), bits=bits, bitoff=bitoff,
+                                        probe_select=1, mn=mn, want_zero=True)
+    got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    assert res.replayed_accesses == 3361069440
+    assert got[target, 0] == 0
+    zc = [i for i in range(len(crows)) if got[i, 0] == 0 and got[i, 1] > 0]
+    assert res.best == min(zc) and res.n_zero == len(zc)
+    rng = np.random.default_rng(5)
+    sample = sorted(set(rng.choice(len(crows), size=5, replace=False).tolist()) | {target, int(res.best)})
+    flat = np.concatenate(hits_all)
+    for c in sample:
+        say(f"oracle scores candidate {c}")
+        _, m, n = orc.infer([orc_model(crows[c])], [orc_probe(r) for r in prows], flat, off, cfs, 1)
+        assert (got[c, 0], got[c, 1]) == (m[0], n[0]), crows[c]
+
+
+# -------------------------------------------------------- microbenches ---
+def test_microbench_pchase_records_the_chase():
+    torch, capi = need_gpu()
+    N, s = 16384, 64
+    p = capi.PchaseProbe(N, s, 256, 3, 4, 1)
+    arr = torch.zeros((N + 256) // 4 + 16, dtype=torch.int32, device="cuda")
+    k = 1000
+    lat = torch.zeros(k, dtype=torch.int32, device="cuda")
+    idx = torch.zeros(k, dtype=torch.int32, device="cuda")
+    say("microbench_pchase 16 KB / 64 B")
+    ovh = capi.microbench_pchase(p, 0, arr, k, lat, idx)
+    op = orc.make_probe(N, s, passes=k // (N // s) + 1, j0=3, base=256)
+    exp = orc.trace(op)[:k]
+    assert np.array_equal(idx.cpu().numpy(), exp)
+    a = arr.cpu().numpy()[64:64 + N // 4]
+    assert np.array_equal(a, (np.arange(N // 4) + s // 4) % (N // 4))   # Listing 1
+    l = lat.cpu().numpy().view(np.uint32)
+    assert ovh > 0 and (l > 0).all() and np.median(l) > ovh
+
+
+def test_microbench_lds_bank_conflicts_grow_with_even_strides():
+    torch, capi = need_gpu()
+    cyc = torch.zeros(64, dtype=torch.int32, device="cuda")
+    say("microbench_lds_bank 1..64")
+    capi.microbench_lds_bank(1, 64, 8, cyc)
+    c = cyc.cpu().numpy()
+    assert (c > 0).all()
+    assert c[63] > c[0]          # stride 64: every lane in one bank
+    assert c[2] <= c[1] * 1.5    # odd stride 3 no worse than a little above stride 2
+
+
+def test_microbench_hbm_stream_positive():
+    torch, capi = need_gpu()
+    n = 64 << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    say("microbench_hbm_stream 64 MB")
+    g = capi.microbench_hbm_stream(src, dst, n, 1, 1024, 256, 4, 3)
+    assert g > 10.0
+    assert torch.equal(src, dst)
