@@ -400,7 +400,10 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
             }
         }
     }
-    const bool head = (lane == 0) || (__shfl_up(key, 1, kWave) != key);
+    // every lane takes part in the shuffle (a shuffle from an inactive lane
+    // is undefined, so it must not sit behind the lane == 0 test)
+    const uint32_t key_up = __shfl_up(key, 1, kWave);
+    const bool head = (lane == 0) || (key_up != key);
     if (SCORE) {
         mm = seg_sum(mm, key, lane);
         if (head && key != kInvalidTag && mm) atomicAdd((unsigned long long*)&args.counters[key], mm);
