@@ -16,7 +16,10 @@ constexpr int kWave = 64;
 
 // Replay classes: ways held in registers (unrolled up to the class bound) or
 // in an LDS column per lane for the large associativities.
-enum WayClass : int { kA1 = 0, kA2, kA4, kA8, kA16, kALds, kNumClasses };
+// Large associativities use an LDS map (when the set's lines fit it) or an
+// LDS scan.
+enum WayClass : int { kA1 = 0, kA2, kA4, kA8, kA16, kAMap, kALds, kNumClasses };
+constexpr uint32_t kMapMaxEntries = 512;   // map rows + ways <= 256 dwords per lane
 __host__ __device__ inline int way_class(uint32_t a) {
     return a <= 1 ? kA1 : a <= 2 ? kA2 : a <= 4 ? kA4 : a <= 8 ? kA8 : a <= 16 ? kA16 : kALds;
 }
@@ -33,6 +36,28 @@ struct DevModel {
     uint32_t seed_lo, seed_hi;
 };
 
+// Exact floor(n / d) for 32-bit n through a multiply-high (Granlund &
+// Montgomery, "Division by invariant integers using multiplication", 1994,
+// Fig. 4.1): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// t = mulhi(m, n) and q = (t + ((n - t) >> min(l,1))) >> max(l-1, 0).
+struct UDiv32 {
+    uint32_t m, s1, s2;
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+        return (t + ((n - t) >> s1)) >> s2;
+    }
+};
+
+inline UDiv32 make_udiv32(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    UDiv32 u;
+    u.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+    u.s1 = l < 1 ? l : 1;
+    u.s2 = l > 1 ? l - 1 : 0;
+    return u;
+}
+
 // A probe as the kernels see it: element indices, one cycle = L accesses.
 struct DevProbe {
     uint64_t base;        // byte address of element 0
@@ -42,6 +67,8 @@ struct DevProbe {
     uint32_t j0;
     uint32_t passes;
     uint32_t elem_shift;  // log2(elem)
+    UDiv32 sb_div;        // division by the stride in bytes, se << elem_shift
+    uint32_t sb_fast;     // 1 if that stride fits 32 bits (sb_div valid)
 };
 
 // One replay job of the probe kernels: model x probe.
@@ -91,6 +118,8 @@ struct SweepArgs {
     uint32_t* bits;           // replay: output bitmap or null; score: observed bitmap
     const volatile uint32_t* abort_flag;
     uint32_t* aborted;
+    uint32_t lds_rows;        // LDS classes: dwords per lane column
+    uint32_t map_rows;        // map class: dwords of the map in a column
 };
 
 struct StreamArgs {
@@ -118,8 +147,8 @@ struct ArgminOut {
 // ------------------------------------------------------------ launchers --
 hipError_t launch_sweep(bool score, int pol, int cls, const SweepArgs& args, uint32_t blocks,
                         hipStream_t stream);
-hipError_t sweep_occupancy(bool score, int pol, int cls, int* blocks_per_cu);
-void sweep_geometry(int cls, uint32_t* threads, size_t* lds);
+hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, int* blocks_per_cu);
+void sweep_geometry(int cls, uint32_t lds_rows, uint32_t* threads, size_t* lds);
 hipError_t sweep_prepare_lds();
 hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream);
 hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu);

@@ -40,7 +40,6 @@ struct Workspace {
     size_t slab_clean = 0;  // bytes of `slab` known to hold epoch 0 or older epochs
     uint32_t epoch = 0;
     void* host_res = nullptr;  // pinned result staging
-    int occ_sweep[2][4][kNumClasses] = {};
     int occ_stream[4][7] = {};
     bool lds_ready = false;
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
@@ -52,6 +51,5 @@ int workspace(Workspace** ws, std::unique_lock<std::mutex>* lock);
 const volatile uint32_t* abort_flag_dev();
 uint32_t abort_flag_host();
 
-int persistent_blocks(Workspace* ws, bool score, int pol, int cls, uint32_t* blocks);
 
 }  // namespace pc

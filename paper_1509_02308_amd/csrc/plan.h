@@ -13,8 +13,10 @@ namespace pc {
 struct Bucket {
     int pol;
     int cls;
-    uint32_t first;   // into the task array
+    uint32_t first;     // into the task array
     uint32_t count;
+    uint32_t lds_rows;  // LDS classes: dwords per lane column
+    uint32_t map_rows;  // map class: dwords of the map
 };
 
 struct SweepPlan {

@@ -16,6 +16,7 @@
 #include <cstring>
 
 #include "plan.h"
+#include "sweep_lane.h"
 
 namespace pc {
 
@@ -52,6 +53,8 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     // --- natural task order: per model run of jobs, 64 items per task
     std::vector<SweepTask> tasks;
     std::vector<float> cost;
+    std::vector<uint8_t> tcls;
+    std::vector<uint16_t> tmap;   // map dwords a map-class task needs
     plan->plain.clear();
     plan->accesses = 0;
     size_t j = 0;
@@ -63,8 +66,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         const uint64_t G = m.sets < (uint32_t)kWave ? m.sets : (uint64_t)kWave;
         const uint64_t items = (e - j) * G;
         const double per_set = std::ceil((double)m.sets / (double)G) / (double)m.sets;
-        const double wcost = m.ways > 16 ? (double)m.ways : 1.0;
-        const uint32_t first = (uint32_t)tasks.size();
+        const int base_cls = way_class(m.ways);
         for (uint64_t it = 0; it < items; it += kWave) {
             SweepTask t;
             t.job = (uint32_t)j;
@@ -72,16 +74,57 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
             t.n = (uint32_t)std::min<uint64_t>(kWave, items - it);
             t.model = mi;
             const uint64_t jlo = j + it / G, jhi = j + (it + t.n - 1) / G;
-            uint64_t ml = 0;
-            for (uint64_t q = jlo; q <= jhi; ++q) ml = std::max(ml, probe_len[jobs[q].probe]);
+            uint64_t ml = 0, me = 0;
+            for (uint64_t q = jlo; q <= jhi; ++q) {
+                ml = std::max(ml, probe_len[jobs[q].probe]);
+                if (base_cls == kALds) me = std::max(me, map_entries(probes[jobs[q].probe], m));
+            }
+            int cls = base_cls;
+            double wcost = 1.0;
+            if (base_cls == kALds) {
+                if (me <= kMapMaxEntries) cls = kAMap;
+                else wcost = (double)m.ways;
+            }
             tasks.push_back(t);
+            tcls.push_back((uint8_t)cls);
+            tmap.push_back((uint16_t)(cls == kAMap ? (me + 3) / 4 : 0));
             cost.push_back((float)((double)ml * per_set * wcost + 64.0));
         }
         for (size_t q = j; q < e; ++q) plan->accesses += probe_len[jobs[q].probe];
-        plan->plain.push_back(Bucket{(int)m.policy, way_class(m.ways), first, (uint32_t)(tasks.size() - first)});
         j = e;
     }
     plan->n_tasks = tasks.size();
+
+    auto rows_of = [&](size_t i, uint32_t* lds_rows, uint32_t* map_rows) {
+        const DevModel& m = models[tasks[i].model];
+        if (tcls[i] == kAMap) {
+            *map_rows = tmap[i];
+            *lds_rows = tmap[i] + m.ways;
+        } else if (tcls[i] == kALds) {
+            *map_rows = 0;
+            *lds_rows = 2 * m.ways;
+        } else {
+            *map_rows = *lds_rows = 0;
+        }
+    };
+    // plain launches: runs of tasks with one model and one class
+    for (size_t i = 0; i < tasks.size(); ++i) {
+        const DevModel& m = models[tasks[i].model];
+        uint32_t lr, mr;
+        rows_of(i, &lr, &mr);
+        if (plan->plain.empty() || tasks[plan->plain.back().first].model != tasks[i].model ||
+            plan->plain.back().cls != tcls[i])
+            plan->plain.push_back(Bucket{(int)m.policy, (int)tcls[i], (uint32_t)i, 0, 0, 0});
+        Bucket& b = plan->plain.back();
+        b.count++;
+        b.map_rows = std::max(b.map_rows, mr);
+    }
+    for (Bucket& b : plan->plain)
+        if (b.cls == kAMap || b.cls == kALds) {
+            uint32_t amax = 0;
+            for (uint32_t i = b.first; i < b.first + b.count; ++i) amax = std::max(amax, models[tasks[i].model].ways);
+            b.lds_rows = b.cls == kAMap ? b.map_rows + amax : 2 * amax;
+        }
 
     // --- batched order: group by (policy, class), longest first within a group
     std::vector<uint32_t> order(tasks.size());
@@ -92,7 +135,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         std::vector<uint32_t> key(tasks.size());
         for (size_t i = 0; i < tasks.size(); ++i) {
             const DevModel& m = models[tasks[i].model];
-            const int grp = (int)m.policy * kNumClasses + way_class(m.ways);
+            const int grp = (int)m.policy * kNumClasses + tcls[i];
             int cb = (int)std::floor(std::log2((double)cost[i] + 1.0) * 8.0);
             cb = std::max(0, std::min(255, cb));
             key[i] = (uint32_t)(grp * 256 + (255 - cb));
@@ -103,13 +146,26 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     }
     std::vector<SweepTask> lpt(tasks.size());
     plan->batched.clear();
+    std::vector<uint32_t> bucket_amax;
     for (size_t i = 0; i < order.size(); ++i) {
         lpt[i] = tasks[order[i]];
         const DevModel& m = models[lpt[i].model];
-        const int pol = (int)m.policy, cls = way_class(m.ways);
-        if (plan->batched.empty() || plan->batched.back().pol != pol || plan->batched.back().cls != cls)
-            plan->batched.push_back(Bucket{pol, cls, (uint32_t)i, 0});
-        plan->batched.back().count++;
+        const int pol = (int)m.policy, cls = tcls[order[i]];
+        if (plan->batched.empty() || plan->batched.back().pol != pol || plan->batched.back().cls != cls) {
+            plan->batched.push_back(Bucket{pol, cls, (uint32_t)i, 0, 0, 0});
+            bucket_amax.push_back(0);
+        }
+        Bucket& b = plan->batched.back();
+        b.count++;
+        uint32_t lr, mr;
+        rows_of(order[i], &lr, &mr);
+        b.map_rows = std::max(b.map_rows, mr);
+        bucket_amax.back() = std::max(bucket_amax.back(), m.ways);
+    }
+    for (size_t k = 0; k < plan->batched.size(); ++k) {
+        Bucket& b = plan->batched[k];
+        if (b.cls == kAMap) b.lds_rows = b.map_rows + bucket_amax[k];
+        else if (b.cls == kALds) b.lds_rows = 2 * bucket_amax[k];
     }
 
     // --- bitmap ranges each job writes
@@ -175,12 +231,14 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         a.bits = bits;
         a.abort_flag = abort_flag_dev();
         a.aborted = plan->d_queues + plan->batched.size();
-        uint32_t blocks;
-        int rc = persistent_blocks(ws, score, bk.pol, bk.cls, &blocks);
-        if (rc) return rc;
+        a.lds_rows = bk.lds_rows;
+        a.map_rows = bk.map_rows;
+        int occ = 0;
+        PC_HIP(sweep_occupancy(score, bk.pol, bk.cls, bk.lds_rows, &occ));
+        uint32_t blocks = (uint32_t)std::max(occ, 1) * (uint32_t)ws->cus;
         uint32_t threads;
         size_t lds;
-        sweep_geometry(bk.cls, &threads, &lds);
+        sweep_geometry(bk.cls, bk.lds_rows, &threads, &lds);
         const uint32_t wpb = threads / kWave;
         const uint32_t need = (bk.count + wpb - 1) / wpb;
         if (need < blocks) blocks = need;
@@ -213,9 +271,11 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             a.bits = bits;
             a.abort_flag = nullptr;
             a.aborted = nullptr;
+            a.lds_rows = bk.lds_rows;
+            a.map_rows = bk.map_rows;
             uint32_t threads;
             size_t lds;
-            sweep_geometry(bk.cls, &threads, &lds);
+            sweep_geometry(bk.cls, bk.lds_rows, &threads, &lds);
             const uint32_t wpb = threads / kWave;
             PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, (bk.count + wpb - 1) / wpb, stream));
         }

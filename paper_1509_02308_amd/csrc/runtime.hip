@@ -93,6 +93,9 @@ int check_probe(const pchase_probe& p, DevProbe* d, uint64_t* len, uint64_t i) {
         d->j0 = (uint32_t)p.j0;
         d->passes = p.passes;
         d->elem_shift = 2;
+        const uint64_t sb = se * 4;
+        d->sb_fast = (sb > 0 && sb < (1ull << 32)) ? 1u : 0u;
+        d->sb_div = make_udiv32(d->sb_fast ? (uint32_t)sb : 1u);
     }
     return PCHASE_OK;
 }
@@ -193,17 +196,6 @@ const volatile uint32_t* abort_flag_dev() {
 }
 
 uint32_t abort_flag_host() { return g_abort_host ? *g_abort_host : 0; }
-
-int persistent_blocks(Workspace* ws, bool score, int pol, int cls, uint32_t* blocks) {
-    int& occ = ws->occ_sweep[score ? 1 : 0][pol][cls];
-    if (occ == 0) {
-        hipError_t e = sweep_occupancy(score, pol, cls, &occ);
-        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-        if (occ < 1) occ = 1;
-    }
-    *blocks = (uint32_t)occ * (uint32_t)ws->cus;
-    return PCHASE_OK;
-}
 
 }  // namespace pc
 

@@ -1,0 +1,459 @@
+// sweep_lane.h -- per-lane part of the probe replay: the state of one cache
+// set and the enumeration of that set's accesses, in trace order, straight
+// from the probe (N, s, j0, base, passes).
+//
+// Method (Mei & Chu, Section 4.1, Assumptions 1-3; Section 4.2): access k of
+// a probe visits element (j0 + k*s) mod N (Listing 1 + Listing 2) and falls
+// in set (address >> unit) mod T; only that set's a ways are involved, so
+// the hit/miss decision of an access depends only on the earlier accesses of
+// its own set.  Within one increasing sweep of the chase the accesses of a
+// set are those inside units t, t+T, t+2T, ..., and the accesses inside one
+// line are consecutive in the trace: only the first of such a run can miss,
+// the others hit and leave every policy's state unchanged.
+//
+// Three ways to hold the a ways of a set:
+//   RegSet   ways in registers, loops unrolled to the class bound (a <= 16);
+//   MapSet   an LDS column per lane: a map from the line's index within the
+//            set to its way, plus per way its line index and LRU links, so
+//            every access costs O(1) LDS operations whatever a is (used
+//            when the set's lines in the probe fit the map);
+//   ScanSet  an LDS column per lane with tags and LRU ranks, scanned per
+//            access (any a <= 128, any probe).
+// LDS columns are laid out row-major over the 64 lanes of a wave (row r of
+// lane l at dword r*64 + l), so lanes never share a bank.
+#pragma once
+
+#include "common.h"
+
+namespace pc {
+
+// ------------------------------------------------------------ PLRU tree --
+// a-1 node bits in heap order (children of n: 2n+1 left, 2n+2 right; leaf of
+// way w is a-1+w); a 0 bit sends the victim search left.
+struct PlruBits {
+    uint64_t lo = 0, hi = 0;
+    __device__ __forceinline__ uint32_t get(uint32_t n) const {
+        return n < 64 ? (uint32_t)(lo >> n) & 1u : (uint32_t)(hi >> (n - 64)) & 1u;
+    }
+    __device__ __forceinline__ void put(uint32_t n, uint32_t v) {
+        if (n < 64) lo = (lo & ~(1ull << n)) | ((uint64_t)v << n);
+        else hi = (hi & ~(1ull << (n - 64))) | ((uint64_t)v << (n - 64));
+    }
+    // a use of way x makes every node on its path point to the other child
+    __device__ __forceinline__ void touch(uint32_t x, uint32_t depth) {
+        uint32_t node = 0;
+        for (uint32_t d = 0; d < depth; ++d) {
+            uint32_t dir = (x >> (depth - 1 - d)) & 1u;
+            put(node, dir ^ 1u);
+            node = 2 * node + 1 + dir;
+        }
+    }
+    __device__ __forceinline__ uint32_t victim(uint32_t depth, uint32_t a) const {
+        uint32_t node = 0;
+        for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + get(node);
+        return node - (a - 1);
+    }
+};
+
+__device__ __forceinline__ uint32_t random_way(const DevModel& m, uint64_t k, uint32_t trace_id) {
+    return philox_x((uint32_t)k, (uint32_t)(k >> 32), trace_id, 0u, m.seed_lo, m.seed_hi) % m.ways;
+}
+
+// ----------------------------------------------- set state in registers --
+template <int POL, int A>
+struct RegSet {
+    uint32_t tag[A];
+    uint32_t age[A];  // LRU recency rank (0 = most recent); 0xFF = empty way
+    uint32_t nvalid;  // ways fill in index order, so ways < nvalid are valid
+    uint32_t ptr;     // FIFO: next way to replace
+    PlruBits bits;
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int w = 0; w < A; ++w) {
+            tag[w] = kInvalidTag;
+            age[w] = 0xFFu;
+        }
+        nvalid = 0;
+        ptr = 0;
+        bits = PlruBits();
+    }
+
+    __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint64_t k,
+                                           uint32_t trace_id) {
+        const uint32_t a = m.ways;
+        int hw = -1;
+        uint32_t vic = 0;
+#pragma unroll
+        for (int w = 0; w < A; ++w) {
+            if (w < (int)a) {
+                if (tag[w] == line) hw = w;
+                if constexpr (POL == PCHASE_LRU) {
+                    if (age[w] == a - 1) vic = (uint32_t)w;
+                }
+            }
+        }
+        const bool hit = hw >= 0;
+        if constexpr (POL == PCHASE_LRU) {
+            uint32_t x, ax = 0;
+#pragma unroll
+            for (int w = 0; w < A; ++w)
+                if (w == hw) ax = age[w];
+            if (hit) {
+                x = (uint32_t)hw;
+            } else if (nvalid < a) {
+                x = nvalid;
+                ax = nvalid;
+                ++nvalid;
+            } else {
+                x = vic;
+                ax = a - 1;
+            }
+#pragma unroll
+            for (int w = 0; w < A; ++w) {
+                if (w < (int)a) {
+                    uint32_t g = age[w];
+                    g += (g < ax) ? 1u : 0u;
+                    if ((uint32_t)w == x) {
+                        g = 0;
+                        tag[w] = line;
+                    }
+                    age[w] = g;
+                }
+            }
+        } else if constexpr (POL == PCHASE_FIFO) {
+            if (!hit) {
+                uint32_t x = ptr;
+                ptr = (ptr + 1 == a) ? 0 : ptr + 1;
+#pragma unroll
+                for (int w = 0; w < A; ++w)
+                    if ((uint32_t)w == x) tag[w] = line;
+            }
+        } else if constexpr (POL == PCHASE_PLRU) {
+            uint32_t x;
+            if (hit) x = (uint32_t)hw;
+            else if (nvalid < a) x = nvalid++;
+            else x = bits.victim(m.log2_ways, a);
+            bits.touch(x, m.log2_ways);
+            if (!hit) {
+#pragma unroll
+                for (int w = 0; w < A; ++w)
+                    if ((uint32_t)w == x) tag[w] = line;
+            }
+        } else {  // RANDOM
+            if (!hit) {
+                uint32_t x;
+                if (nvalid < a) x = nvalid++;
+                else x = random_way(m, k, trace_id);
+#pragma unroll
+                for (int w = 0; w < A; ++w)
+                    if ((uint32_t)w == x) tag[w] = line;
+            }
+        }
+        return hit;
+    }
+};
+
+// --------------------------------------- set state in an LDS column: map --
+// Rows [0, mapw): the map, four 8-bit entries per dword, entry q = way of the
+// set's line with index q, 0xFF if absent.  Rows [mapw, mapw + a): per way
+// its line index (bits 0-15) and, for LRU, the previous / next way in
+// recency order (bits 16-23 / 24-31, 0xFF = none).
+template <int POL>
+struct MapSet {
+    static constexpr uint32_t kNil = 0xFFu;
+    uint32_t* col;
+    uint32_t mapw;
+    uint32_t nvalid, ptr, head, tail;
+    PlruBits bits;
+
+    __device__ __forceinline__ uint32_t& row(uint32_t r) { return col[(size_t)r * kWave]; }
+    __device__ __forceinline__ uint32_t map_get(uint32_t q) { return (row(q >> 2) >> ((q & 3) * 8)) & 0xFFu; }
+    __device__ __forceinline__ void map_put(uint32_t q, uint32_t w) {
+        uint32_t& d = row(q >> 2);
+        const uint32_t sh = (q & 3) * 8;
+        d = (d & ~(0xFFu << sh)) | (w << sh);
+    }
+    __device__ __forceinline__ uint32_t& info(uint32_t w) { return row(mapw + w); }
+    __device__ __forceinline__ uint32_t prev_of(uint32_t w) { return (info(w) >> 16) & 0xFFu; }
+    __device__ __forceinline__ uint32_t next_of(uint32_t w) { return info(w) >> 24; }
+    __device__ __forceinline__ void set_prev(uint32_t w, uint32_t p) {
+        uint32_t& d = info(w);
+        d = (d & 0xFF00FFFFu) | (p << 16);
+    }
+    __device__ __forceinline__ void set_next(uint32_t w, uint32_t n) {
+        uint32_t& d = info(w);
+        d = (d & 0x00FFFFFFu) | (n << 24);
+    }
+
+    __device__ __forceinline__ void init(uint32_t* c, uint32_t map_rows) {
+        col = c;
+        mapw = map_rows;
+        for (uint32_t r = 0; r < mapw; ++r) row(r) = 0xFFFFFFFFu;
+        nvalid = 0;
+        ptr = 0;
+        head = tail = kNil;
+        bits = PlruBits();
+    }
+
+    __device__ __forceinline__ void unlink(uint32_t x) {
+        const uint32_t p = prev_of(x), n = next_of(x);
+        if (p != kNil) set_next(p, n);
+        else head = n;
+        if (n != kNil) set_prev(n, p);
+        else tail = p;
+    }
+    __device__ __forceinline__ void push_front(uint32_t x) {
+        uint32_t& d = info(x);
+        d = (d & 0xFFFFu) | (kNil << 16) | (head << 24);
+        if (head != kNil) set_prev(head, x);
+        head = x;
+        if (tail == kNil) tail = x;
+    }
+
+    __device__ __forceinline__ bool access(uint32_t, uint32_t q, const DevModel& m, uint64_t k,
+                                           uint32_t trace_id) {
+        const uint32_t a = m.ways;
+        const uint32_t w = map_get(q);
+        const bool hit = w != kNil;
+        if constexpr (POL == PCHASE_LRU) {
+            if (hit) {
+                if (head != w) {
+                    unlink(w);
+                    push_front(w);
+                }
+                return true;
+            }
+            uint32_t x;
+            if (nvalid < a) {
+                x = nvalid++;
+            } else {
+                x = tail;
+                map_put(info(x) & 0xFFFFu, kNil);
+                unlink(x);
+            }
+            info(x) = q;
+            map_put(q, x);
+            push_front(x);
+            return false;
+        } else {
+            if constexpr (POL == PCHASE_PLRU) {
+                if (hit) {
+                    bits.touch(w, m.log2_ways);
+                    return true;
+                }
+            } else {
+                if (hit) return true;
+            }
+            uint32_t x;
+            if constexpr (POL == PCHASE_FIFO) {
+                x = ptr;
+                ptr = (ptr + 1 == a) ? 0 : ptr + 1;
+            } else if constexpr (POL == PCHASE_PLRU) {
+                x = nvalid < a ? nvalid : bits.victim(m.log2_ways, a);
+            } else {
+                x = nvalid < a ? nvalid : random_way(m, k, trace_id);
+            }
+            if (nvalid < a) ++nvalid;
+            else map_put(info(x) & 0xFFFFu, kNil);
+            info(x) = q;
+            map_put(q, x);
+            if constexpr (POL == PCHASE_PLRU) bits.touch(x, m.log2_ways);
+            return false;
+        }
+    }
+};
+
+// -------------------------------------- set state in an LDS column: scan --
+// Rows [0, a): tags; rows [a, 2a): LRU ranks (0xFF = empty way).
+template <int POL>
+struct ScanSet {
+    uint32_t* col;
+    uint32_t nvalid, ptr;
+    PlruBits bits;
+
+    __device__ __forceinline__ uint32_t& tag(uint32_t w) { return col[(size_t)w * kWave]; }
+    __device__ __forceinline__ uint32_t& age(uint32_t w, uint32_t a) { return col[(size_t)(a + w) * kWave]; }
+
+    __device__ __forceinline__ void init(uint32_t* c, uint32_t a) {
+        col = c;
+        nvalid = 0;
+        ptr = 0;
+        bits = PlruBits();
+        for (uint32_t w = 0; w < a; ++w) {
+            tag(w) = kInvalidTag;
+            if (POL == PCHASE_LRU) age(w, a) = 0xFFu;
+        }
+    }
+
+    __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint64_t k,
+                                           uint32_t trace_id) {
+        const uint32_t a = m.ways;
+        uint32_t hw = kInvalidTag;
+        for (uint32_t w = 0; w < a; ++w)
+            if (tag(w) == line) hw = w;
+        const bool hit = hw != kInvalidTag;
+        uint32_t x;
+        if constexpr (POL == PCHASE_LRU) {
+            uint32_t ax;
+            if (hit) {
+                x = hw;
+                ax = age(hw, a);
+            } else if (nvalid < a) {
+                x = nvalid;
+                ax = nvalid;
+                ++nvalid;
+            } else {
+                ax = a - 1;
+                x = 0;
+                for (uint32_t w = 0; w < a; ++w)
+                    if (age(w, a) == a - 1) x = w;
+            }
+            for (uint32_t w = 0; w < a; ++w) {
+                const uint32_t g = age(w, a);
+                if (g < ax) age(w, a) = g + 1;
+            }
+            age(x, a) = 0;
+            if (!hit) tag(x) = line;
+        } else if constexpr (POL == PCHASE_FIFO) {
+            if (!hit) {
+                x = ptr;
+                ptr = (ptr + 1 == a) ? 0 : ptr + 1;
+                tag(x) = line;
+            }
+        } else if constexpr (POL == PCHASE_PLRU) {
+            if (hit) x = hw;
+            else if (nvalid < a) x = nvalid++;
+            else x = bits.victim(m.log2_ways, a);
+            bits.touch(x, m.log2_ways);
+            if (!hit) tag(x) = line;
+        } else {
+            if (!hit) {
+                x = nvalid < a ? nvalid++ : random_way(m, k, trace_id);
+                tag(x) = line;
+            }
+        }
+        return hit;
+    }
+};
+
+// ------------------------------------------------- access enumeration ----
+// Calls visit(line, q, k0, r) for every run of r consecutive accesses
+// k0 .. k0+r-1 of the probe inside one line of set `set`, in trace order.
+// q is the line's index among the set's lines of the probe:
+// (floor(u/T) - floor(u_lo/T)) * R + (line mod R), with u the line's unit,
+// u_lo the probe's lowest unit and R lines per unit.
+template <class Visit>
+__device__ __forceinline__ void sweep_runs(uint64_t xf, uint64_t sb, uint64_t cnt, uint64_t kstart,
+                                           const DevModel& m, const DevProbe& p, uint32_t set, uint64_t qlo,
+                                           Visit& visit) {
+    const uint32_t T = m.sets;
+    const uint32_t us = m.unit_shift, ls = m.line_shift;
+    const uint32_t rsh = us - ls;
+    const uint64_t U = 1ull << us;
+    if (sb < U * T) {
+        // walk the units of this set inside the sweep's address range
+        const uint64_t xl = xf + (cnt - 1) * sb;
+        const uint64_t uf = xf >> us, ul = xl >> us;
+        const uint64_t rem = umod64(uf, T);
+        uint64_t u = uf + (set >= rem ? set - rem : set + T - rem);
+        uint64_t Q = udiv64(u, T) - qlo;
+        // offsets inside the sweep fit 32 bits on the common path: divide by
+        // the stride through its precomputed multiplier
+        const bool fast = p.sb_fast && (xl - xf) + U + sb < (1ull << 32);
+        for (; u <= ul; u += T, ++Q) {
+            const uint64_t lo = u << us;
+            uint64_t ilo, ihi;
+            if (fast) {
+                ilo = lo <= xf ? 0 : p.sb_div.div((uint32_t)(lo - xf + sb - 1));
+                ihi = p.sb_div.div((uint32_t)(lo + U - 1 - xf));
+            } else {
+                ilo = lo <= xf ? 0 : udiv64(lo - xf + sb - 1, sb);
+                ihi = udiv64(lo + U - 1 - xf, sb);
+            }
+            if (ihi > cnt - 1) ihi = cnt - 1;
+            if (ilo > ihi) continue;
+            if (rsh == 0) {
+                visit((uint32_t)u, (uint32_t)Q, kstart + ilo, ihi - ilo + 1);
+            } else {
+                uint64_t i = ilo;
+                while (i <= ihi) {
+                    const uint64_t line = (xf + i * sb) >> ls;
+                    const uint64_t lend = (line + 1) << ls;
+                    uint64_t inext = udiv64(lend - xf + sb - 1, sb);
+                    if (inext > ihi + 1) inext = ihi + 1;
+                    visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kstart + i,
+                          inext - i);
+                    i = inext;
+                }
+            }
+        }
+    } else {
+        // stride of at least T units: walk the accesses, tracking the set
+        // and the unit's quotient by T incrementally (the unit advances by
+        // d or d+1 per access, d = sb >> unit)
+        uint64_t x = xf, u = xf >> us;
+        uint32_t st = (uint32_t)umod64(u, T);
+        uint64_t Q = udiv64(u, T) - qlo;
+        const uint64_t d0 = sb >> us;
+        const uint64_t dq0 = udiv64(d0, T), dq1 = udiv64(d0 + 1, T);
+        const uint32_t dm0 = (uint32_t)(d0 - dq0 * T), dm1 = (uint32_t)(d0 + 1 - dq1 * T);
+        for (uint64_t i = 0; i < cnt; ++i) {
+            if (st == set) {
+                const uint64_t line = x >> ls;
+                visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kstart + i, 1);
+            }
+            const uint64_t xn = x + sb, un = xn >> us;
+            const bool one = (un - u == d0);
+            st += one ? dm0 : dm1;
+            Q += one ? dq0 : dq1;
+            if (st >= T) {
+                st -= T;
+                ++Q;
+            }
+            x = xn;
+            u = un;
+        }
+    }
+}
+
+template <class Visit>
+__device__ __forceinline__ void probe_runs(const DevProbe& p, const DevModel& m, uint32_t set, Visit& visit) {
+    const uint32_t es = p.elem_shift;
+    const uint64_t sb = (uint64_t)p.se << es;
+    const uint64_t qlo = udiv64(p.base >> m.unit_shift, m.sets);
+    for (uint32_t pass = 0; pass < p.passes; ++pass) {
+        const uint64_t kpass = (uint64_t)pass * p.L;
+        if (p.se == 0) {  // s is a multiple of N: the chase stays on j0
+            const uint64_t x = p.base + ((uint64_t)p.j0 << es);
+            const uint64_t u = x >> m.unit_shift;
+            if (umod64(u, m.sets) == set) {
+                const uint64_t line = x >> m.line_shift;
+                const uint32_t rsh = m.unit_shift - m.line_shift;
+                const uint64_t Q = udiv64(u, m.sets) - qlo;
+                visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kpass, 1);
+            }
+            continue;
+        }
+        uint64_t r = p.j0, kpos = 0;
+        while (kpos < p.L) {
+            // one increasing sweep: r, r+se, ... < ne
+            uint64_t cnt = (p.ne - r + p.se - 1) / p.se;
+            if (cnt > p.L - kpos) cnt = p.L - kpos;
+            sweep_runs(p.base + (r << es), sb, cnt, kpass + kpos, m, p, set, qlo, visit);
+            kpos += cnt;
+            r = r + cnt * p.se - p.ne;
+        }
+    }
+}
+
+// Capacity a MapSet needs for probe p under model m: number of distinct line
+// indices q any set can see.
+inline uint64_t map_entries(const DevProbe& p, const DevModel& m) {
+    const uint64_t xlo = p.base, xhi = p.base + ((uint64_t)(p.ne - 1) << p.elem_shift);
+    const uint64_t ulo = xlo >> m.unit_shift, uhi = xhi >> m.unit_shift;
+    const uint64_t qspan = uhi / m.sets - ulo / m.sets + 1;
+    return qspan << (m.unit_shift - m.line_shift);
+}
+
+}  // namespace pc
