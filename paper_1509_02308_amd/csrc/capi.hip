@@ -256,7 +256,7 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
             ws->slab_clean = 0;
         }
         if (ws->slab_clean < ws->slab.cap) {
-            PC_HIP(hipMemsetAsync(ws->slab.p, 0, ws->slab.cap, stream));
+            PC_HIP(launch_fill_u32(ws->slab.as<uint32_t>(), ws->slab.cap / 4, 0, stream));
             ws->slab_clean = ws->slab.cap;
         }
         StreamArgs a;

@@ -19,7 +19,7 @@ constexpr int kWave = 64;
 // Large associativities use an LDS map (when the set's lines fit it) or an
 // LDS scan.
 enum WayClass : int { kA1 = 0, kA2, kA4, kA8, kA16, kAMap, kALds, kNumClasses };
-constexpr uint32_t kMapMaxEntries = 512;   // map rows + ways <= 256 dwords per lane
+constexpr uint32_t kMapMaxEntries = 448;   // map rows + ways <= 240 dwords per lane
 __host__ __device__ inline int way_class(uint32_t a) {
     return a <= 1 ? kA1 : a <= 2 ? kA2 : a <= 4 ? kA4 : a <= 8 ? kA8 : a <= 16 ? kA16 : kALds;
 }
@@ -79,16 +79,21 @@ struct SweepJob {
     uint32_t trace_id;    // RANDOM counter high word
     uint64_t count_from;
     uint64_t bitoff;      // word offset of the output / observed bitmap
+    uint32_t bm_off;      // word offset of the job's bits in its task's LDS bitmap
+    uint32_t pad;
 };
 
 // A wave's worth of (job, set) items: items item0 .. item0+n-1 of the run of
-// jobs that starts at `job` (all with the same model); item i is set i % T of
+// jobs that starts at `job` (all with the same model; a task holds whole
+// jobs only); item i is set group i % G of
 // job job + i / T.
 struct SweepTask {
     uint32_t job;
     uint32_t item0;
     uint32_t n;
     uint32_t model;
+    uint32_t bm_words;    // LDS bitmap words of the task's jobs (0: bits go straight to memory)
+    uint32_t pad;
 };
 
 // Materialised-trace pair.
@@ -120,7 +125,12 @@ struct SweepArgs {
     uint32_t* aborted;
     uint32_t lds_rows;        // LDS classes: dwords per lane column
     uint32_t map_rows;        // map class: dwords of the map in a column
+    uint32_t bm_words;        // dwords of the per-wave LDS hit bitmap
 };
+
+// Largest per-wave LDS hit bitmap (dwords); tasks needing more write their
+// bits to memory directly.
+constexpr uint32_t kBmMaxWords = 1024;
 
 struct StreamArgs {
     const StreamPair* pairs;
@@ -147,8 +157,8 @@ struct ArgminOut {
 // ------------------------------------------------------------ launchers --
 hipError_t launch_sweep(bool score, int pol, int cls, const SweepArgs& args, uint32_t blocks,
                         hipStream_t stream);
-hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, int* blocks_per_cu);
-void sweep_geometry(int cls, uint32_t lds_rows, uint32_t* threads, size_t* lds);
+hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, uint32_t bm_words, int* blocks_per_cu);
+void sweep_geometry(int cls, uint32_t lds_rows, uint32_t bm_words, uint32_t* threads, size_t* lds);
 hipError_t sweep_prepare_lds();
 hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream);
 hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu);

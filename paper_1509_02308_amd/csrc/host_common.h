@@ -29,6 +29,9 @@ struct DevBuf {
 
 struct InferPlan;
 
+// Parallel graph branches of a batched replay.
+constexpr int kBranches = 4;
+
 struct Workspace {
     int device = -1;
     int cus = 0;
@@ -42,6 +45,8 @@ struct Workspace {
     void* host_res = nullptr;  // pinned result staging
     int occ_stream[4][7] = {};
     bool lds_ready = false;
+    hipStream_t branch[kBranches] = {};   // capture-side streams (default priority)
+    hipEvent_t fork = nullptr, join[kBranches] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
     ~Workspace();
 };

@@ -17,6 +17,8 @@ struct Bucket {
     uint32_t count;
     uint32_t lds_rows;  // LDS classes: dwords per lane column
     uint32_t map_rows;  // map class: dwords of the map
+    double cost;        // estimated lane work of the bucket
+    uint32_t bm_words;  // per-wave LDS hit bitmap dwords
 };
 
 struct SweepPlan {

@@ -44,13 +44,15 @@ SweepPlan::~SweepPlan() {
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const std::vector<DevProbe>& probes,
-                     const std::vector<uint64_t>& probe_len, const std::vector<SweepJob>& jobs,
+                     const std::vector<uint64_t>& probe_len, const std::vector<SweepJob>& jobs_in,
                      bool want_clear) {
     plan->n_models = (uint32_t)models.size();
     plan->n_probes = (uint32_t)probes.size();
-    plan->n_jobs = jobs.size();
+    plan->n_jobs = jobs_in.size();
+    std::vector<SweepJob> jobs(jobs_in);
 
-    // --- natural task order: per model run of jobs, 64 items per task
+    // --- natural task order: per model run of jobs; a task holds whole jobs
+    // (floor(64 / T) of them when T < 64, else one job over 64 lanes)
     std::vector<SweepTask> tasks;
     std::vector<float> cost;
     std::vector<uint8_t> tcls;
@@ -64,21 +66,26 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         while (e < jobs.size() && jobs[e].model == mi) ++e;
         const DevModel& m = models[mi];
         const uint64_t G = m.sets < (uint32_t)kWave ? m.sets : (uint64_t)kWave;
-        const uint64_t items = (e - j) * G;
+        const uint64_t jpt = std::max<uint64_t>(1, kWave / G);  // jobs per task
         const double per_set = std::ceil((double)m.sets / (double)G) / (double)m.sets;
         const int base_cls = way_class(m.ways);
-        for (uint64_t it = 0; it < items; it += kWave) {
+        for (uint64_t q0 = j; q0 < e; q0 += jpt) {
+            const uint64_t q1 = std::min<uint64_t>(e, q0 + jpt);
             SweepTask t;
             t.job = (uint32_t)j;
-            t.item0 = (uint32_t)it;
-            t.n = (uint32_t)std::min<uint64_t>(kWave, items - it);
+            t.item0 = (uint32_t)((q0 - j) * G);
+            t.n = (uint32_t)((q1 - q0) * G);
             t.model = mi;
-            const uint64_t jlo = j + it / G, jhi = j + (it + t.n - 1) / G;
-            uint64_t ml = 0, me = 0;
-            for (uint64_t q = jlo; q <= jhi; ++q) {
-                ml = std::max(ml, probe_len[jobs[q].probe]);
+            t.pad = 0;
+            uint64_t ml = 0, me = 0, words = 0;
+            for (uint64_t q = q0; q < q1; ++q) {
+                const uint64_t len = probe_len[jobs[q].probe];
+                ml = std::max(ml, len);
                 if (base_cls == kALds) me = std::max(me, map_entries(probes[jobs[q].probe], m));
+                jobs[q].bm_off = (uint32_t)words;
+                words += (len + 31) / 32;
             }
+            t.bm_words = words <= kBmMaxWords ? (uint32_t)words : 0u;
             int cls = base_cls;
             double wcost = 1.0;
             if (base_cls == kALds) {
@@ -102,7 +109,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
             *lds_rows = tmap[i] + m.ways;
         } else if (tcls[i] == kALds) {
             *map_rows = 0;
-            *lds_rows = 2 * m.ways;
+            *lds_rows = m.ways + (m.ways + 3) / 4;
         } else {
             *map_rows = *lds_rows = 0;
         }
@@ -114,16 +121,17 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         rows_of(i, &lr, &mr);
         if (plan->plain.empty() || tasks[plan->plain.back().first].model != tasks[i].model ||
             plan->plain.back().cls != tcls[i])
-            plan->plain.push_back(Bucket{(int)m.policy, (int)tcls[i], (uint32_t)i, 0, 0, 0});
+            plan->plain.push_back(Bucket{(int)m.policy, (int)tcls[i], (uint32_t)i, 0, 0, 0, 0.0, 0});
         Bucket& b = plan->plain.back();
         b.count++;
         b.map_rows = std::max(b.map_rows, mr);
+        b.bm_words = std::max(b.bm_words, tasks[i].bm_words);
     }
     for (Bucket& b : plan->plain)
         if (b.cls == kAMap || b.cls == kALds) {
             uint32_t amax = 0;
             for (uint32_t i = b.first; i < b.first + b.count; ++i) amax = std::max(amax, models[tasks[i].model].ways);
-            b.lds_rows = b.cls == kAMap ? b.map_rows + amax : 2 * amax;
+            b.lds_rows = b.cls == kAMap ? b.map_rows + amax : amax + (amax + 3) / 4;
         }
 
     // --- batched order: group by (policy, class), longest first within a group
@@ -152,11 +160,13 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         const DevModel& m = models[lpt[i].model];
         const int pol = (int)m.policy, cls = tcls[order[i]];
         if (plan->batched.empty() || plan->batched.back().pol != pol || plan->batched.back().cls != cls) {
-            plan->batched.push_back(Bucket{pol, cls, (uint32_t)i, 0, 0, 0});
+            plan->batched.push_back(Bucket{pol, cls, (uint32_t)i, 0, 0, 0, 0.0, 0});
             bucket_amax.push_back(0);
         }
         Bucket& b = plan->batched.back();
         b.count++;
+        b.cost += cost[order[i]];
+        b.bm_words = std::max(b.bm_words, lpt[i].bm_words);
         uint32_t lr, mr;
         rows_of(order[i], &lr, &mr);
         b.map_rows = std::max(b.map_rows, mr);
@@ -165,7 +175,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     for (size_t k = 0; k < plan->batched.size(); ++k) {
         Bucket& b = plan->batched[k];
         if (b.cls == kAMap) b.lds_rows = b.map_rows + bucket_amax[k];
-        else if (b.cls == kALds) b.lds_rows = 2 * bucket_amax[k];
+        else if (b.cls == kALds) b.lds_rows = bucket_amax[k] + (bucket_amax[k] + 3) / 4;
     }
 
     // --- bitmap ranges each job writes
@@ -208,7 +218,10 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     return PCHASE_OK;
 }
 
-// Enqueues the batched sequence on `s` (used both eagerly and under capture).
+// Enqueues the batched sequence on `s` (under capture): the buckets, one
+// persistent kernel each, are spread over parallel branches (least-loaded
+// branch first, largest bucket first) so that one bucket's tail overlaps the
+// next bucket's work; the branches join before the tail.
 static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters,
                            uint64_t n_counters, uint32_t* bits, bool clear_bits, hipStream_t s,
                            const std::function<hipError_t(hipStream_t)>& tail) {
@@ -217,13 +230,27 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
     PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
     if (clear_bits && bits)
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
-    for (size_t b = 0; b < plan->batched.size(); ++b) {
-        const Bucket& bk = plan->batched[b];
+    const int nb = (int)std::min<size_t>(kBranches, plan->batched.size());
+    if (nb > 1) {
+        PC_HIP(hipEventRecord(ws->fork, s));
+        for (int b = 0; b < nb; ++b) PC_HIP(hipStreamWaitEvent(ws->branch[b], ws->fork, 0));
+    }
+    std::vector<size_t> idx(plan->batched.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return plan->batched[x].cost > plan->batched[y].cost; });
+    std::vector<double> load(nb > 1 ? nb : 1, 0.0);
+    for (size_t qi : idx) {
+        const Bucket& bk = plan->batched[qi];
+        int br = 0;
+        for (int b = 1; b < (int)load.size(); ++b)
+            if (load[b] < load[br]) br = b;
+        load[br] += bk.cost;
+        hipStream_t bs = nb > 1 ? ws->branch[br] : s;
         SweepArgs a;
         a.tasks = plan->d_lpt + bk.first;
         a.n_tasks = bk.count;
         a.persistent = 1;
-        a.queue = plan->d_queues + b;
+        a.queue = plan->d_queues + qi;
         a.jobs = plan->d_jobs;
         a.models = plan->d_models;
         a.probes = plan->d_probes;
@@ -233,16 +260,23 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         a.aborted = plan->d_queues + plan->batched.size();
         a.lds_rows = bk.lds_rows;
         a.map_rows = bk.map_rows;
+        a.bm_words = bk.bm_words;
         int occ = 0;
-        PC_HIP(sweep_occupancy(score, bk.pol, bk.cls, bk.lds_rows, &occ));
+        PC_HIP(sweep_occupancy(score, bk.pol, bk.cls, bk.lds_rows, bk.bm_words, &occ));
         uint32_t blocks = (uint32_t)std::max(occ, 1) * (uint32_t)ws->cus;
         uint32_t threads;
         size_t lds;
-        sweep_geometry(bk.cls, bk.lds_rows, &threads, &lds);
+        sweep_geometry(bk.cls, bk.lds_rows, bk.bm_words, &threads, &lds);
         const uint32_t wpb = threads / kWave;
         const uint32_t need = (bk.count + wpb - 1) / wpb;
         if (need < blocks) blocks = need;
-        PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, blocks, s));
+        PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, blocks, bs));
+    }
+    if (nb > 1) {
+        for (int b = 0; b < nb; ++b) {
+            PC_HIP(hipEventRecord(ws->join[b], ws->branch[b]));
+            PC_HIP(hipStreamWaitEvent(s, ws->join[b], 0));
+        }
     }
     if (tail) PC_HIP(tail(s));
     return PCHASE_OK;
@@ -273,9 +307,10 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             a.aborted = nullptr;
             a.lds_rows = bk.lds_rows;
             a.map_rows = bk.map_rows;
+            a.bm_words = bk.bm_words;
             uint32_t threads;
             size_t lds;
-            sweep_geometry(bk.cls, bk.lds_rows, &threads, &lds);
+            sweep_geometry(bk.cls, bk.lds_rows, bk.bm_words, &threads, &lds);
             const uint32_t wpb = threads / kWave;
             PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, (bk.count + wpb - 1) / wpb, stream));
         }

@@ -127,6 +127,11 @@ void DevBuf::release() {
 }
 
 Workspace::~Workspace() {
+    for (int b = 0; b < kBranches; ++b) {
+        if (branch[b]) (void)hipStreamDestroy(branch[b]);
+        if (join[b]) (void)hipEventDestroy(join[b]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
     stage.release();
     aux.release();
     obs.release();
@@ -170,6 +175,14 @@ int workspace(Workspace** out, std::unique_lock<std::mutex>* lock) {
     if (!ws->lds_ready) {
         e = sweep_prepare_lds();
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+        for (int b = 0; b < kBranches; ++b) {
+            e = hipStreamCreateWithFlags(&ws->branch[b], hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+            e = hipEventCreateWithFlags(&ws->join[b], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+        }
+        e = hipEventCreateWithFlags(&ws->fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
         ws->lds_ready = true;
     }
     *out = ws;

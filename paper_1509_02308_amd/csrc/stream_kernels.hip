@@ -16,17 +16,21 @@
 // (tag, LRU rank) that only the owning lane reads and writes, so every
 // memory dependence stays within one lane.  A set whose header epoch is not
 // the current pair's is empty; its first access rewrites every entry.
+// A group's slab serves pair after pair with different set counts, so a
+// header slot may hold an old entry word (tag, rank) of an earlier pair; the
+// header's epoch word carries all-ones in its high half, which no entry word
+// (rank <= 0xFF) can, so such leftovers never pass for a current header.
 #include "common.h"
 
 namespace pc {
 
 struct SetHeader {
-    uint32_t epoch;
-    uint32_t ptr;
-    uint64_t lo;
-    uint64_t hi;
-    uint64_t pad;
+    uint64_t epoch;  // kEpochTag | pair epoch
+    uint64_t lo;     // PLRU node bits 0-63
+    uint64_t hi;     // PLRU node bits 64-126
+    uint64_t ptr;    // FIFO: next way to replace
 };
+constexpr uint64_t kEpochTag = 0xFFFFFFFF00000000ull;
 
 
 
@@ -74,8 +78,8 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
             uint64_t h_lo = 0, h_hi = 0;
             if (gl == 0) {
                 const SetHeader h = hdr[set];
-                h_ep = h.epoch;
-                h_ptr = h.ptr;
+                h_ep = (h.epoch == (kEpochTag | epoch)) ? epoch : 0u;
+                h_ptr = (uint32_t)h.ptr;
                 h_lo = h.lo;
                 h_hi = h.hi;
             }
@@ -174,11 +178,10 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
             if (own1 && dirty1) ent[eb + gl + 64] = e1;
             if (gl == 0 && hdr_dirty) {
                 SetHeader h;
-                h.epoch = epoch;
-                h.ptr = h_ptr;
+                h.epoch = kEpochTag | epoch;
                 h.lo = h_lo;
                 h.hi = h_hi;
-                h.pad = 0;
+                h.ptr = h_ptr;
                 hdr[set] = h;
             }
 

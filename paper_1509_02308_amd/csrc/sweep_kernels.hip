@@ -52,13 +52,18 @@ __device__ __forceinline__ uint64_t ones_in(const uint32_t* w, uint64_t lo, uint
 // ---------------------------------------------------------------- kernel --
 
 
+// Per-run bookkeeping of one lane.  With an LDS bitmap (bm != nullptr) the
+// run's hit bits are or-ed into it and compared or written out by the whole
+// wave afterwards; otherwise they are compared with the observation or or-ed
+// into the output bitmap in memory run by run.
 template <class S, bool SCORE>
 struct Visitor {
     S* st;
     const DevModel* m;
     uint32_t trace_id;
     uint64_t cf;
-    uint32_t* bits;
+    uint32_t* bits;   // memory bitmap of the job (observed or output), or null
+    uint32_t* bm;     // LDS bitmap of the job, or null
     uint64_t mt = 0, ms = 0, mm = 0;
     __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint64_t k0, uint64_t r) {
         const bool hit = st->access(line, q, *m, k0, trace_id);
@@ -66,7 +71,9 @@ struct Visitor {
             ++mt;
             ms += (k0 >= cf) ? 1u : 0u;
         }
-        if constexpr (SCORE) {
+        if (bm != nullptr) {
+            or_bits(bm, hit ? k0 : k0 + 1, k0 + r);
+        } else if constexpr (SCORE) {
             if (k0 >= cf) {
                 const uint32_t ob = (bits[k0 >> 5] >> (k0 & 31)) & 1u;
                 mm += (ob != (hit ? 1u : 0u)) ? 1u : 0u;
@@ -92,45 +99,84 @@ __device__ __forceinline__ uint64_t seg_sum(uint64_t v, uint32_t key, int lane) 
 // Way classes of the kernel template: 1..16 are register classes.
 constexpr int kClassMap = 1000;
 constexpr int kClassScan = 2000;
-constexpr uint32_t kMaxLdsRows = 256;  // 64 KB per one-wave block at most
+constexpr uint32_t kMaxLdsRows = 240;  // with the bitmap, 64 KB per one-wave block at most
 
 template <int POL, int A, bool SCORE>
-__device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask& task, int lane, uint32_t* col) {
+__device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask& task, int lane, uint32_t* col,
+                                         uint32_t* bm) {
     const DevModel m = args.models[task.model];
     const bool active = (uint32_t)lane < task.n;
+    const bool use_bm = task.bm_words != 0 && (SCORE || args.bits != nullptr);
+    const uint32_t T = m.sets;
+    const uint32_t G = T < (uint32_t)kWave ? T : (uint32_t)kWave;
+    if (use_bm) {
+        for (uint32_t w = (uint32_t)lane; w < task.bm_words; w += kWave) bm[w] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     uint32_t key = kInvalidTag;
     uint64_t mt = 0, ms = 0, mm = 0;
     if (active) {
         // G = min(T, 64) lanes per replay; lane g of a replay owns the sets
         // g, g+G, g+2G, ... and replays them one after the other
-        const uint32_t T = m.sets;
-        const uint32_t G = T < (uint32_t)kWave ? T : (uint32_t)kWave;
         const uint32_t item = task.item0 + (uint32_t)lane;
         const uint32_t jrel = item / G;
         const uint32_t g = item - jrel * G;
         const SweepJob job = args.jobs[task.job + jrel];
         const DevProbe p = args.probes[job.probe];
         key = job.out;
-        uint32_t* bits = args.bits == nullptr ? nullptr : args.bits + job.bitoff;
+        uint32_t* bits = (args.bits == nullptr || use_bm) ? nullptr : args.bits + job.bitoff;
+        uint32_t* jbm = use_bm ? bm + job.bm_off : nullptr;
+        SweepCache sc;
+        sweep_cache(sc, p, m);
         for (uint32_t set = g; set < T; set += G) {
             if constexpr (A == kClassMap) {
                 MapSet<POL> st;
                 st.init(col, args.map_rows);
-                Visitor<MapSet<POL>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits};
-                probe_runs(p, m, set, v);
+                Visitor<MapSet<POL>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits, jbm};
+                cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;
             } else if constexpr (A == kClassScan) {
                 ScanSet<POL> st;
                 st.init(col, m.ways);
-                Visitor<ScanSet<POL>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits};
-                probe_runs(p, m, set, v);
+                Visitor<ScanSet<POL>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits, jbm};
+                cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;
             } else {
                 RegSet<POL, A> st;
                 st.init();
-                Visitor<RegSet<POL, A>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits};
-                probe_runs(p, m, set, v);
+                Visitor<RegSet<POL, A>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits, jbm};
+                cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;
+            }
+        }
+    }
+    if (use_bm) {
+        // every lane's runs are in the LDS bitmap: compare it with the
+        // observation (score) or store it (replay), word by word, coalesced
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t jlo = task.item0 / G, jhi = (task.item0 + task.n - 1) / G;
+        for (uint32_t jr = jlo; jr <= jhi; ++jr) {
+            const SweepJob job = args.jobs[task.job + jr];
+            const DevProbe p = args.probes[job.probe];
+            const uint64_t len = (uint64_t)p.L * p.passes;
+            const uint64_t words = (len + 31) / 32;
+            if constexpr (SCORE) {
+                key = job.out;  // one candidate per task when scoring
+                const uint64_t cf = job.count_from;
+                for (uint64_t w = (cf >> 5) + (uint64_t)lane; w < words; w += kWave) {
+                    uint32_t mask = 0xFFFFFFFFu;
+                    if (w == (cf >> 5)) mask &= ~((1u << (cf & 31)) - 1u);
+                    if (w == words - 1 && (len & 31)) mask &= (1u << (len & 31)) - 1u;
+                    const uint32_t diff = (bm[job.bm_off + w] ^ args.bits[job.bitoff + w]) & mask;
+                    mm += __popc(diff);
+                }
+            } else {
+                for (uint64_t w = (uint64_t)lane; w < words; w += kWave)
+                    args.bits[job.bitoff + w] = bm[job.bm_off + w];
             }
         }
     }
@@ -149,6 +195,12 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
             if (ms) atomicAdd((unsigned long long*)&args.counters[2 * (uint64_t)key + 1], ms);
         }
     }
+    if (use_bm) {
+        // the next task reuses the bitmap: every lane must be done reading it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 template <int POL, int A, bool SCORE>
@@ -156,11 +208,13 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs args) {
     extern __shared__ uint32_t lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    uint32_t* col = nullptr;
-    if constexpr (A == kClassMap || A == kClassScan) col = lds + (size_t)wave * args.lds_rows * kWave + lane;
+    // per wave: the hit bitmap, then (LDS classes) one column per lane
+    uint32_t* base = lds + (size_t)wave * (args.bm_words + (size_t)args.lds_rows * kWave);
+    uint32_t* bm = base;
+    uint32_t* col = base + args.bm_words + lane;
     if (!args.persistent) {
         const uint32_t t = blockIdx.x * (blockDim.x / kWave) + wave;
-        if (t < args.n_tasks) run_task<POL, A, SCORE>(args, args.tasks[t], lane, col);
+        if (t < args.n_tasks) run_task<POL, A, SCORE>(args, args.tasks[t], lane, col, bm);
         return;
     }
     for (uint32_t iter = 0;; ++iter) {
@@ -174,7 +228,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs args) {
         }
         t = __shfl(t, 0, kWave);
         if (t >= args.n_tasks) break;
-        run_task<POL, A, SCORE>(args, args.tasks[t], lane, col);
+        run_task<POL, A, SCORE>(args, args.tasks[t], lane, col, bm);
     }
 }
 
@@ -205,13 +259,13 @@ static SweepFn pick(int pol, int cls) {
 // Launch geometry of one (policy, class) sweep kernel: register classes run
 // 4 waves per block without LDS; LDS classes run one wave per block with
 // lds_rows dwords per lane.
-void sweep_geometry(int cls, uint32_t lds_rows, uint32_t* threads, size_t* lds) {
+void sweep_geometry(int cls, uint32_t lds_rows, uint32_t bm_words, uint32_t* threads, size_t* lds) {
     if (cls == kAMap || cls == kALds) {
         *threads = kWave;
-        *lds = (size_t)lds_rows * kWave * 4;
+        *lds = ((size_t)lds_rows * kWave + bm_words) * 4;
     } else {
         *threads = 256;
-        *lds = 0;
+        *lds = (size_t)4 * bm_words * 4;
     }
 }
 
@@ -219,17 +273,17 @@ hipError_t launch_sweep(bool score, int pol, int cls, const SweepArgs& args, uin
                         hipStream_t stream) {
     uint32_t threads;
     size_t lds;
-    sweep_geometry(cls, args.lds_rows, &threads, &lds);
+    sweep_geometry(cls, args.lds_rows, args.bm_words, &threads, &lds);
     SweepFn fn = score ? pick<true>(pol, cls) : pick<false>(pol, cls);
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, stream, args);
     return hipGetLastError();
 }
 
 // Resident blocks per CU of a sweep kernel (for persistent grids).
-hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, int* blocks_per_cu) {
+hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, uint32_t bm_words, int* blocks_per_cu) {
     uint32_t threads;
     size_t lds;
-    sweep_geometry(cls, lds_rows, &threads, &lds);
+    sweep_geometry(cls, lds_rows, bm_words, &threads, &lds);
     SweepFn fn = score ? pick<true>(pol, cls) : pick<false>(pol, cls);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)fn, threads, lds);
 }
@@ -241,7 +295,7 @@ hipError_t sweep_prepare_lds() {
             for (int cls : {(int)kAMap, (int)kALds}) {
                 SweepFn fn = s ? pick<true>(pol, cls) : pick<false>(pol, cls);
                 hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)(kMaxLdsRows * kWave * 4));
+                                                   (int)((kMaxLdsRows * kWave + kBmMaxWords) * 4));
                 if (e != hipSuccess) return e;
             }
     return hipSuccess;

@@ -41,6 +41,20 @@ struct PlruBits {
     }
     // a use of way x makes every node on its path point to the other child
     __device__ __forceinline__ void touch(uint32_t x, uint32_t depth) {
+        if (depth <= 6) {
+            // all a-1 <= 63 nodes sit in `lo`: build the path's mask and
+            // values, then merge them in one step
+            uint64_t mask = 0, val = 0;
+            uint32_t node = 0;
+            for (uint32_t d = 0; d < depth; ++d) {
+                const uint32_t dir = (x >> (depth - 1 - d)) & 1u;
+                mask |= 1ull << node;
+                val |= (uint64_t)(dir ^ 1u) << node;
+                node = 2 * node + 1 + dir;
+            }
+            lo = (lo & ~mask) | val;
+            return;
+        }
         uint32_t node = 0;
         for (uint32_t d = 0; d < depth; ++d) {
             uint32_t dir = (x >> (depth - 1 - d)) & 1u;
@@ -50,7 +64,11 @@ struct PlruBits {
     }
     __device__ __forceinline__ uint32_t victim(uint32_t depth, uint32_t a) const {
         uint32_t node = 0;
-        for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + get(node);
+        if (depth <= 6) {
+            for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + ((uint32_t)(lo >> node) & 1u);
+        } else {
+            for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + get(node);
+        }
         return node - (a - 1);
     }
 };
@@ -265,30 +283,37 @@ struct MapSet {
 };
 
 // -------------------------------------- set state in an LDS column: scan --
-// Rows [0, a): tags; rows [a, 2a): LRU ranks (0xFF = empty way).
+// Rows [0, a): tags; rows [a, a + ceil(a/4)): LRU ranks, four 8-bit ranks per
+// dword (0xFF = empty way).
 template <int POL>
 struct ScanSet {
     uint32_t* col;
+    uint32_t a;
     uint32_t nvalid, ptr;
     PlruBits bits;
 
     __device__ __forceinline__ uint32_t& tag(uint32_t w) { return col[(size_t)w * kWave]; }
-    __device__ __forceinline__ uint32_t& age(uint32_t w, uint32_t a) { return col[(size_t)(a + w) * kWave]; }
+    __device__ __forceinline__ uint32_t& rank_word(uint32_t w) { return col[(size_t)(a + (w >> 2)) * kWave]; }
+    __device__ __forceinline__ uint32_t rank(uint32_t w) { return (rank_word(w) >> ((w & 3) * 8)) & 0xFFu; }
+    __device__ __forceinline__ void set_rank(uint32_t w, uint32_t v) {
+        uint32_t& d = rank_word(w);
+        const uint32_t sh = (w & 3) * 8;
+        d = (d & ~(0xFFu << sh)) | (v << sh);
+    }
 
-    __device__ __forceinline__ void init(uint32_t* c, uint32_t a) {
+    __device__ __forceinline__ void init(uint32_t* c, uint32_t ways) {
         col = c;
+        a = ways;
         nvalid = 0;
         ptr = 0;
         bits = PlruBits();
-        for (uint32_t w = 0; w < a; ++w) {
-            tag(w) = kInvalidTag;
-            if (POL == PCHASE_LRU) age(w, a) = 0xFFu;
-        }
+        for (uint32_t w = 0; w < a; ++w) tag(w) = kInvalidTag;
+        if (POL == PCHASE_LRU)
+            for (uint32_t w = 0; w < a; w += 4) rank_word(w) = 0xFFFFFFFFu;
     }
 
     __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint64_t k,
                                            uint32_t trace_id) {
-        const uint32_t a = m.ways;
         uint32_t hw = kInvalidTag;
         for (uint32_t w = 0; w < a; ++w)
             if (tag(w) == line) hw = w;
@@ -298,7 +323,7 @@ struct ScanSet {
             uint32_t ax;
             if (hit) {
                 x = hw;
-                ax = age(hw, a);
+                ax = rank(hw);
             } else if (nvalid < a) {
                 x = nvalid;
                 ax = nvalid;
@@ -307,13 +332,22 @@ struct ScanSet {
                 ax = a - 1;
                 x = 0;
                 for (uint32_t w = 0; w < a; ++w)
-                    if (age(w, a) == a - 1) x = w;
+                    if (rank(w) == a - 1) x = w;
             }
-            for (uint32_t w = 0; w < a; ++w) {
-                const uint32_t g = age(w, a);
-                if (g < ax) age(w, a) = g + 1;
+            // ranks below ax move up by one; way x becomes the most recent
+            for (uint32_t w = 0; w < a; w += 4) {
+                uint32_t d = rank_word(w), o = 0;
+#pragma unroll
+                for (uint32_t b = 0; b < 4; ++b) {
+                    uint32_t g = (d >> (8 * b)) & 0xFFu;
+                    if (w + b < a) {
+                        if (g < ax) ++g;
+                        if (w + b == x) g = 0;
+                    }
+                    o |= g << (8 * b);
+                }
+                rank_word(w) = o;
             }
-            age(x, a) = 0;
             if (!hit) tag(x) = line;
         } else if constexpr (POL == PCHASE_FIFO) {
             if (!hit) {
@@ -338,33 +372,56 @@ struct ScanSet {
 };
 
 // ------------------------------------------------- access enumeration ----
+// One increasing sweep of a pass: elements r, r+se, ... (cnt of them) at
+// byte addresses xf, xf+sb, ...; everything here is independent of the set,
+// so a lane computes it once and walks each of its sets from it.
+struct Sweep {
+    uint64_t xf;     // address of the first access
+    uint64_t cnt;    // accesses in the sweep
+    uint64_t kin;    // index of the first access within the pass
+    uint64_t uf, ul; // first and last unit touched
+    uint64_t qf;     // floor(uf / T)
+    uint32_t rem;    // uf mod T
+    uint32_t unit_mode;  // 1: walk units (stride below T units), 0: walk accesses
+    uint32_t fast;   // unit mode: offsets fit 32 bits, divide by the stride's multiplier
+};
+
+__device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, uint64_t cnt, uint64_t kin,
+                                          const DevModel& m, const DevProbe& p) {
+    const uint32_t us = m.unit_shift;
+    const uint64_t U = 1ull << us;
+    w.xf = xf;
+    w.cnt = cnt;
+    w.kin = kin;
+    w.uf = xf >> us;
+    w.ul = (xf + (cnt - 1) * sb) >> us;
+    w.qf = udiv64(w.uf, m.sets);
+    w.rem = (uint32_t)(w.uf - w.qf * m.sets);
+    w.unit_mode = (sb > 0 && sb < U * m.sets) ? 1u : 0u;
+    w.fast = (w.unit_mode && p.sb_fast && (cnt - 1) * sb + U + sb < (1ull << 32)) ? 1u : 0u;
+}
+
 // Calls visit(line, q, k0, r) for every run of r consecutive accesses
-// k0 .. k0+r-1 of the probe inside one line of set `set`, in trace order.
+// k0 .. k0+r-1 of one sweep inside one line of set `set`, in trace order.
 // q is the line's index among the set's lines of the probe:
 // (floor(u/T) - floor(u_lo/T)) * R + (line mod R), with u the line's unit,
 // u_lo the probe's lowest unit and R lines per unit.
 template <class Visit>
-__device__ __forceinline__ void sweep_runs(uint64_t xf, uint64_t sb, uint64_t cnt, uint64_t kstart,
-                                           const DevModel& m, const DevProbe& p, uint32_t set, uint64_t qlo,
-                                           Visit& visit) {
+__device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint64_t sb, const DevModel& m,
+                                           const DevProbe& p, uint32_t set, uint64_t qlo, Visit& visit) {
     const uint32_t T = m.sets;
     const uint32_t us = m.unit_shift, ls = m.line_shift;
     const uint32_t rsh = us - ls;
     const uint64_t U = 1ull << us;
-    if (sb < U * T) {
-        // walk the units of this set inside the sweep's address range
-        const uint64_t xl = xf + (cnt - 1) * sb;
-        const uint64_t uf = xf >> us, ul = xl >> us;
-        const uint64_t rem = umod64(uf, T);
-        uint64_t u = uf + (set >= rem ? set - rem : set + T - rem);
-        uint64_t Q = udiv64(u, T) - qlo;
-        // offsets inside the sweep fit 32 bits on the common path: divide by
-        // the stride through its precomputed multiplier
-        const bool fast = p.sb_fast && (xl - xf) + U + sb < (1ull << 32);
-        for (; u <= ul; u += T, ++Q) {
+    const uint64_t xf = w.xf, cnt = w.cnt, kstart = kpass + w.kin;
+    if (w.unit_mode) {
+        // the first unit of this set at or after uf, and its quotient by T
+        uint64_t u = w.uf + (set >= w.rem ? set - w.rem : set + T - w.rem);
+        uint64_t Q = w.qf + (set < w.rem ? 1u : 0u) - qlo;
+        for (; u <= w.ul; u += T, ++Q) {
             const uint64_t lo = u << us;
             uint64_t ilo, ihi;
-            if (fast) {
+            if (w.fast) {
                 ilo = lo <= xf ? 0 : p.sb_div.div((uint32_t)(lo - xf + sb - 1));
                 ihi = p.sb_div.div((uint32_t)(lo + U - 1 - xf));
             } else {
@@ -389,12 +446,12 @@ __device__ __forceinline__ void sweep_runs(uint64_t xf, uint64_t sb, uint64_t cn
             }
         }
     } else {
-        // stride of at least T units: walk the accesses, tracking the set
-        // and the unit's quotient by T incrementally (the unit advances by
-        // d or d+1 per access, d = sb >> unit)
-        uint64_t x = xf, u = xf >> us;
-        uint32_t st = (uint32_t)umod64(u, T);
-        uint64_t Q = udiv64(u, T) - qlo;
+        // stride of at least T units (or a single access): walk the
+        // accesses, tracking the set and the unit's quotient by T
+        // incrementally (the unit advances by d or d+1 per access)
+        uint64_t x = xf, u = w.uf;
+        uint32_t st = w.rem;
+        uint64_t Q = w.qf - qlo;
         const uint64_t d0 = sb >> us;
         const uint64_t dq0 = udiv64(d0, T), dq1 = udiv64(d0 + 1, T);
         const uint32_t dm0 = (uint32_t)(d0 - dq0 * T), dm1 = (uint32_t)(d0 + 1 - dq1 * T);
@@ -403,6 +460,7 @@ __device__ __forceinline__ void sweep_runs(uint64_t xf, uint64_t sb, uint64_t cn
                 const uint64_t line = x >> ls;
                 visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kstart + i, 1);
             }
+            if (i + 1 == cnt) break;
             const uint64_t xn = x + sb, un = xn >> us;
             const bool one = (un - u == d0);
             st += one ? dm0 : dm1;
@@ -417,33 +475,76 @@ __device__ __forceinline__ void sweep_runs(uint64_t xf, uint64_t sb, uint64_t cn
     }
 }
 
-template <class Visit>
-__device__ __forceinline__ void probe_runs(const DevProbe& p, const DevModel& m, uint32_t set, Visit& visit) {
+// Sweeps of one pass, in order: calls f(sweep) for each.
+template <class F>
+__device__ __forceinline__ void pass_sweeps(const DevProbe& p, const DevModel& m, F& f) {
     const uint32_t es = p.elem_shift;
     const uint64_t sb = (uint64_t)p.se << es;
-    const uint64_t qlo = udiv64(p.base >> m.unit_shift, m.sets);
+    Sweep w;
+    if (p.se == 0) {  // s is a multiple of N: the chase stays on j0
+        sweep_geo(w, p.base + ((uint64_t)p.j0 << es), 0, 1, 0, m, p);
+        f(w);
+        return;
+    }
+    uint64_t r = p.j0, kpos = 0;
+    while (kpos < p.L) {
+        // one increasing sweep: r, r+se, ... < ne
+        uint64_t cnt = (p.ne - r + p.se - 1) / p.se;
+        if (cnt > p.L - kpos) cnt = p.L - kpos;
+        sweep_geo(w, p.base + (r << es), sb, cnt, kpos, m, p);
+        f(w);
+        kpos += cnt;
+        r = r + cnt * p.se - p.ne;
+    }
+}
+
+__device__ __forceinline__ uint64_t probe_qlo(const DevProbe& p, const DevModel& m) {
+    return udiv64(p.base >> m.unit_shift, m.sets);
+}
+
+// All runs of set `set` over the whole probe (every pass), in trace order.
+template <class Visit>
+__device__ __forceinline__ void probe_runs(const DevProbe& p, const DevModel& m, uint32_t set, Visit& visit) {
+    const uint64_t sb = (uint64_t)p.se << p.elem_shift;
+    const uint64_t qlo = probe_qlo(p, m);
     for (uint32_t pass = 0; pass < p.passes; ++pass) {
         const uint64_t kpass = (uint64_t)pass * p.L;
-        if (p.se == 0) {  // s is a multiple of N: the chase stays on j0
-            const uint64_t x = p.base + ((uint64_t)p.j0 << es);
-            const uint64_t u = x >> m.unit_shift;
-            if (umod64(u, m.sets) == set) {
-                const uint64_t line = x >> m.line_shift;
-                const uint32_t rsh = m.unit_shift - m.line_shift;
-                const uint64_t Q = udiv64(u, m.sets) - qlo;
-                visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kpass, 1);
-            }
-            continue;
-        }
-        uint64_t r = p.j0, kpos = 0;
-        while (kpos < p.L) {
-            // one increasing sweep: r, r+se, ... < ne
-            uint64_t cnt = (p.ne - r + p.se - 1) / p.se;
-            if (cnt > p.L - kpos) cnt = p.L - kpos;
-            sweep_runs(p.base + (r << es), sb, cnt, kpass + kpos, m, p, set, qlo, visit);
-            kpos += cnt;
-            r = r + cnt * p.se - p.ne;
-        }
+        auto f = [&](const Sweep& w) { sweep_walk(w, kpass, sb, m, p, set, qlo, visit); };
+        pass_sweeps(p, m, f);
+    }
+}
+
+// Sweeps of one pass precomputed for a lane that replays many sets of the
+// same probe; probes with more than kCachedSweeps sweeps per pass fall back
+// to probe_runs.
+constexpr int kCachedSweeps = 2;
+struct SweepCache {
+    Sweep w[kCachedSweeps];
+    uint32_t n;   // sweeps per pass, or kCachedSweeps + 1 if they do not fit
+    uint64_t qlo, sb;
+};
+
+__device__ __forceinline__ void sweep_cache(SweepCache& c, const DevProbe& p, const DevModel& m) {
+    c.n = 0;
+    c.qlo = probe_qlo(p, m);
+    c.sb = (uint64_t)p.se << p.elem_shift;
+    auto f = [&](const Sweep& w) {
+        if (c.n < kCachedSweeps) c.w[c.n] = w;
+        ++c.n;
+    };
+    pass_sweeps(p, m, f);
+}
+
+template <class Visit>
+__device__ __forceinline__ void cached_runs(const SweepCache& c, const DevProbe& p, const DevModel& m, uint32_t set,
+                                            Visit& visit) {
+    if (c.n > kCachedSweeps) {
+        probe_runs(p, m, set, visit);
+        return;
+    }
+    for (uint32_t pass = 0; pass < p.passes; ++pass) {
+        const uint64_t kpass = (uint64_t)pass * p.L;
+        for (uint32_t i = 0; i < c.n; ++i) sweep_walk(c.w[i], kpass, c.sb, m, p, set, c.qlo, visit);
     }
 }
 

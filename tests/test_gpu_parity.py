@@ -363,3 +363,31 @@ def test_microbench_hbm_stream_positive():
     g = capi.microbench_hbm_stream(src, dst, n, 1, 1024, 256, 4, 3)
     assert g > 10.0
     assert torch.equal(src, dst)
+
+
+def test_trace_array_replay_mixed_set_counts_reusing_slabs():
+    """Regression: one lane group replays pair after pair of models with the
+    same way-group width but different set counts, so its state slab is
+    re-laid-out between pairs; leftovers of an earlier pair must never pass
+    for current state.  Line numbers are kept small so that stale tags take
+    values an epoch counter also takes."""
+    torch, capi = need_gpu()
+    models = [(64 * 4 * 4, 4, 4, W.LRU), (4 * 4 * 4, 4, 4, W.LRU), (256 * 4 * 3, 4, 3, W.FIFO),
+              (2 * 4 * 3, 4, 3, W.FIFO), (128 * 4 * 4, 4, 4, W.PLRU), (4 * 4 * 4, 4, 4, W.PLRU)]
+    rng = np.random.default_rng(404)
+    traces = [rng.integers(0, int(rng.integers(8, 900)), size=int(rng.integers(200, 1500))).astype(np.int32)
+              for _ in range(40)]
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    pairs = [(m, t) for t in range(len(traces)) for m in range(len(models))]
+    pm = np.array([m for m, _ in pairs], np.uint32)
+    pt = np.array([t for _, t in pairs], np.uint32)
+    exp = [orc.replay(orc_model(models[m]), traces[t], trace_id=t) for m, t in pairs]
+    for call in range(4):
+        misses = torch.zeros(2 * len(pairs), dtype=torch.int64, device="cuda")
+        say(f"cache_replay_batch mixed set counts, call {call}")
+        capi.cache_replay_batch(capi.models(models), idx, off, None, pm, pt, None, misses, mode=call % 2)
+        torch.cuda.synchronize()
+        mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        for i, (m, t) in enumerate(pairs):
+            assert (mis[i, 0], mis[i, 1]) == (exp[i][1], exp[i][2]), (call, models[m], t)
