@@ -84,6 +84,8 @@ int check_probe(const pchase_probe& p, DevProbe* d, uint64_t* len, uint64_t i) {
         return set_error(PCHASE_EINVAL, "probe %llu: base_offset must be a multiple of 4 below 2^33", (unsigned long long)i);
     const uint64_t se = (p.s_bytes / 4) % ne;
     const uint64_t L = ne / gcd64(ne, se);
+    if (L * (uint64_t)p.passes >= (1ull << 32))
+        return set_error(PCHASE_ERANGE, "probe %llu: passes * cycle length must stay below 2^32 accesses", (unsigned long long)i);
     if (len) *len = L * p.passes;
     if (d) {
         d->base = p.base_offset;

@@ -56,6 +56,25 @@ __device__ __forceinline__ uint64_t ones_in(const uint32_t* w, uint64_t lo, uint
 // run's hit bits are or-ed into it and compared or written out by the whole
 // wave afterwards; otherwise they are compared with the observation or or-ed
 // into the output bitmap in memory run by run.
+// Sets bits [k0 + (hit ? 0 : 1), k0 + r) of an LDS bitmap: the run's hit
+// bits.  Runs of up to 32 accesses touch at most two words.
+__device__ __forceinline__ void or_run(uint32_t* w, uint64_t k0, uint32_t r, bool hit) {
+    if (r <= 32) {
+        uint64_t mask = (r == 32) ? 0xFFFFFFFFull : ((1ull << r) - 1ull);
+        if (!hit) mask &= ~1ull;
+        mask <<= (k0 & 31);
+        const uint64_t word = k0 >> 5;
+        if ((uint32_t)mask) atomicOr(w + word, (uint32_t)mask);
+        if (mask >> 32) atomicOr(w + word + 1, (uint32_t)(mask >> 32));
+    } else {
+        or_bits(w, hit ? k0 : k0 + 1, k0 + r);
+    }
+}
+
+// Per-run bookkeeping of one lane.  With an LDS bitmap (bm != nullptr) the
+// run's hit bits are or-ed into it and compared or written out by the whole
+// wave afterwards; otherwise they are compared with the observation or or-ed
+// into the output bitmap in memory run by run.  Counts are per set (32 bits).
 template <class S, bool SCORE>
 struct Visitor {
     S* st;
@@ -64,15 +83,16 @@ struct Visitor {
     uint64_t cf;
     uint32_t* bits;   // memory bitmap of the job (observed or output), or null
     uint32_t* bm;     // LDS bitmap of the job, or null
-    uint64_t mt = 0, ms = 0, mm = 0;
-    __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint64_t k0, uint64_t r) {
+    uint32_t mt = 0, ms = 0;
+    uint64_t mm = 0;
+    __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint64_t k0, uint32_t r) {
         const bool hit = st->access(line, q, *m, k0, trace_id);
         if (!hit) {
             ++mt;
             ms += (k0 >= cf) ? 1u : 0u;
         }
         if (bm != nullptr) {
-            or_bits(bm, hit ? k0 : k0 + 1, k0 + r);
+            or_run(bm, k0, r, hit);
         } else if constexpr (SCORE) {
             if (k0 >= cf) {
                 const uint32_t ob = (bits[k0 >> 5] >> (k0 & 31)) & 1u;

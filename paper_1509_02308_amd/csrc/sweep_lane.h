@@ -384,6 +384,12 @@ struct Sweep {
     uint32_t rem;    // uf mod T
     uint32_t unit_mode;  // 1: walk units (stride below T units), 0: walk accesses
     uint32_t fast;   // unit mode: offsets fit 32 bits, divide by the stride's multiplier
+    // aligned unit mode (a unit is one line, the stride divides it and the
+    // sweep starts on a stride boundary): every full unit holds R accesses
+    // and the first access of unit uf + d is d*R - off0, no division needed
+    uint32_t aligned;
+    uint32_t R;
+    uint32_t off0;
 };
 
 __device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, uint64_t cnt, uint64_t kin,
@@ -399,6 +405,17 @@ __device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, ui
     w.rem = (uint32_t)(w.uf - w.qf * m.sets);
     w.unit_mode = (sb > 0 && sb < U * m.sets) ? 1u : 0u;
     w.fast = (w.unit_mode && p.sb_fast && (cnt - 1) * sb + U + sb < (1ull << 32)) ? 1u : 0u;
+    w.aligned = 0;
+    w.R = 0;
+    w.off0 = 0;
+    if (w.unit_mode && m.unit_shift == m.line_shift && sb <= U && (U % sb) == 0 && (xf % sb) == 0) {
+        const uint64_t R = U / sb;
+        if (cnt < (1ull << 30) && R * m.sets < (1ull << 30)) {
+            w.aligned = 1;
+            w.R = (uint32_t)R;
+            w.off0 = (uint32_t)((xf - (w.uf << us)) / sb);
+        }
+    }
 }
 
 // Calls visit(line, q, k0, r) for every run of r consecutive accesses
@@ -414,6 +431,22 @@ __device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint6
     const uint32_t rsh = us - ls;
     const uint64_t U = 1ull << us;
     const uint64_t xf = w.xf, cnt = w.cnt, kstart = kpass + w.kin;
+    if (w.aligned) {
+        // unit u = uf + d starts at access d*R - off0; units advance by T
+        const uint32_t d = set >= w.rem ? set - w.rem : set + T - w.rem;
+        uint32_t u = (uint32_t)(w.uf + d);
+        uint32_t Q = (uint32_t)(w.qf + (set < w.rem ? 1u : 0u) - qlo);
+        const int32_t R = (int32_t)w.R;
+        const int32_t step = (int32_t)(T * w.R);
+        const int32_t last = (int32_t)cnt - 1;
+        for (int32_t ilo_raw = (int32_t)(d * w.R) - (int32_t)w.off0; ilo_raw <= last;
+             ilo_raw += step, u += T, ++Q) {
+            const int32_t ilo = ilo_raw < 0 ? 0 : ilo_raw;
+            const int32_t ihi = ilo_raw + R - 1 < last ? ilo_raw + R - 1 : last;
+            visit(u, Q, kstart + (uint32_t)ilo, (uint32_t)(ihi - ilo + 1));
+        }
+        return;
+    }
     if (w.unit_mode) {
         // the first unit of this set at or after uf, and its quotient by T
         uint64_t u = w.uf + (set >= w.rem ? set - w.rem : set + T - w.rem);
@@ -431,7 +464,7 @@ __device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint6
             if (ihi > cnt - 1) ihi = cnt - 1;
             if (ilo > ihi) continue;
             if (rsh == 0) {
-                visit((uint32_t)u, (uint32_t)Q, kstart + ilo, ihi - ilo + 1);
+                visit((uint32_t)u, (uint32_t)Q, kstart + ilo, (uint32_t)(ihi - ilo + 1));
             } else {
                 uint64_t i = ilo;
                 while (i <= ihi) {
@@ -440,7 +473,7 @@ __device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint6
                     uint64_t inext = udiv64(lend - xf + sb - 1, sb);
                     if (inext > ihi + 1) inext = ihi + 1;
                     visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kstart + i,
-                          inext - i);
+                          (uint32_t)(inext - i));
                     i = inext;
                 }
             }
