@@ -46,6 +46,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--learned-samples", type=int, default=1_000_000)
+    ap.add_argument("--learned-epochs", type=int, default=2)
+    ap.add_argument("--learned-targets", type=int, default=200)
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -135,6 +139,10 @@ def main():
                 "kernel": "sweep_kernel<policy, way class, score> (all instantiations of one captured step)",
                 "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms}
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_leg(torch, capi, W, crows, args)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(crows, prows, lens, bits, bitoff, args.cpu_seconds)
@@ -163,10 +171,81 @@ def main():
         "best": int(res.best),
         "zero_class": int(res.n_zero),
         "plain": plain,
+        "learned": learned,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def learned_leg(torch, capi, W, crows, args):
+    """Learned proposer on the fixed 768-probe grid: canonical labels,
+    Philox-noised training samples, bf16-MFMA training, then learned
+    (top-8 + exact confirm) vs exhaustive time-to-params on held-out
+    seeded targets, both comparing every grid probe."""
+    carr = capi.models(crows)
+    n = len(crows)
+    t0 = time.perf_counter()
+    labels = capi.pchase_mlp_labels(carr)
+    t_labels = time.perf_counter() - t0
+    ns = args.learned_samples
+    x = torch.zeros(ns, 768, dtype=torch.float32, device="cuda")
+    y = torch.zeros(ns, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.pchase_mlp_samples(carr, labels, 0, ns, 1509, 1311, x, y)
+    t_samples = time.perf_counter() - t0
+    net = capi.Mlp(n, 2308)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = net.train(x, y, 1024, args.learned_epochs, 1e-3)
+    t_train = time.perf_counter() - t0
+    steps = (ns // 1024) * args.learned_epochs
+    del x, y
+
+    # observations of the held-out targets, replayed once (untimed)
+    g = capi.pchase_mlp_grid(0)
+    lens = np.array([capi.pchase_trace_len(g[i])[0] for i in range(768)], dtype=np.uint64)
+    words = (lens + 31) // 32
+    off = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    tw = int(words.sum()) + 1
+    targets = np.random.default_rng(4242).integers(0, n, args.learned_targets)
+    all_bits = torch.zeros(len(targets) * tw, dtype=torch.int32, device="cuda")
+    misses = torch.zeros(2 * 768 * len(targets), dtype=torch.int64, device="cuda")
+    pm = np.repeat(targets.astype(np.uint32), 768)
+    pp = np.tile(np.arange(768, dtype=np.uint32), len(targets))
+    bo = (np.repeat(np.arange(len(targets), dtype=np.uint64) * tw, 768) + np.tile(off, len(targets)))
+    capi.cache_replay_probes(carr, g, pm, pp, None, misses, all_bits, bo)
+    obs = torch.zeros(tw, dtype=torch.int32, device="cuda")
+    t_l, t_e, acc_l, acc_e, fb, exact, agree = [], [], 0, 0, 0, 0, 0
+    for k, t in enumerate(targets):
+        obs.copy_(all_bits[k * tw:(k + 1) * tw])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        rl, _ = capi.infer_cache_params(g, carr, bits=obs, bitoff=off, probe_select=capi.PROBES_ALL,
+                                        mode=capi.LEARNED, topk=8, net=net)
+        b = time.perf_counter()
+        re, zero = capi.infer_cache_params(g, carr, bits=obs, bitoff=off, probe_select=capi.PROBES_ALL,
+                                           mode=capi.EXHAUSTIVE, want_zero=True)
+        c = time.perf_counter()
+        t_l.append(b - a)
+        t_e.append(c - b)
+        acc_l += rl.replayed_accesses
+        acc_e += re.replayed_accesses
+        fb += rl.fallback != 0
+        exact += rl.best_m == 0 and bool((zero[rl.best // 32] >> (rl.best % 32)) & 1)
+        agree += rl.best == re.best
+    net.close()
+    return {"samples": ns, "epochs": args.learned_epochs, "batch": 1024, "train_steps": steps,
+            "labels_s": t_labels, "samples_s": t_samples, "train_s": t_train,
+            "train_samples_per_s": ns * args.learned_epochs / t_train,
+            "train_tflops": steps * 1024 * 2.25e6 / t_train / 1e12, "last_loss": loss,
+            "targets": len(targets), "fallback_rate": fb / len(targets), "exact_rate": exact / len(targets),
+            "same_best_as_exhaustive": agree / len(targets),
+            "time_to_params_ms": float(np.median(t_l) * 1e3),
+            "exhaustive_time_to_params_ms": float(np.median(t_e) * 1e3),
+            "replayed_accesses_per_target": acc_l / len(targets),
+            "exhaustive_replayed_accesses_per_target": acc_e / len(targets)}
 
 
 def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):

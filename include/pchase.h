@@ -198,7 +198,7 @@ typedef struct pchase_result {
     uint64_t best_m, best_n;    /* mismatches / compared accesses of best */
     uint64_t n_zero;            /* candidates with m == 0 (zero class) */
     uint64_t replayed_accesses; /* accesses replayed by this call */
-    uint32_t fallback;          /* LEARNED: 1 if exhaustive search was needed */
+    uint32_t fallback;          /* LEARNED: 1 no exact top-k match, 2 not the grid */
     uint32_t threshold_used;    /* latency threshold applied (UINT32_MAX: none) */
 } pchase_result;
 
@@ -209,9 +209,12 @@ typedef struct pchase_result {
  * OWN_SWEEP compares candidate (C, b, ...) on the probes with
  * C/2 <= N <= 2C, N % b == 0 and s in {b/2, b, 2b} (the Section 4.2
  * overflow sweeps around a candidate capacity).
- * mode = LEARNED ranks candidates with `net` (whose candidate list must be
- * `cands`), replays only the top-k and accepts the best when its m == 0;
- * otherwise it falls back to the exhaustive search (out->fallback = 1).
+ * mode = LEARNED (observation = the 768 grid probes, see pchase_mlp_*)
+ * computes the observation's features, ranks the candidates with `net`
+ * (n_out == n_cands, class c = candidate c), replays only the top-k and
+ * accepts the best of them when its m == 0; otherwise it runs the
+ * exhaustive search (out->fallback = 1), and when the observation is not
+ * the grid it runs the exhaustive search directly (out->fallback = 2).
  * mn_dev (uint64[2*n_cands], nullable) receives (m, n) per candidate;
  * zero_host (uint32[(n_cands+31)/32], nullable) the zero-class bitmap
  * (exhaustive results only).  Synchronises `stream`. */
@@ -263,33 +266,84 @@ int microbench_lds_bank(uint32_t stride_lo, uint32_t stride_hi, uint32_t reps,
                         uint32_t *cycles_dev, hipStream_t stream);
 
 /* ------------------------------------------------------ learned model --- */
-/* Fixed feature grid of the learned proposer: 256 array sizes
- * N_i = 4096 + 512 i bytes times strides {32, 64, 128} bytes, 2 passes;
- * feature = steady misses / L of each probe. */
+/* The learned proposer ranks candidates from a fixed set of fine-grained
+ * runs (the Section 4.2 procedure of Fig. 6 frozen into one grid: array
+ * sizes swept across the candidate capacities, strides around the line
+ * sizes) with a 3-layer perceptron, so that only its top-k candidates are
+ * replayed exactly.
+ *
+ * Feature grid: probe p = 256 * t + i has N = 4096 + 512 i bytes (i < 256),
+ * s = {32, 64, 128}[t] bytes, 2 passes, j0 = 0, 4-byte elements.  Feature p
+ * of a trace is its steady-pass miss ratio r (Section 4.1): misses over
+ * accesses [L, 2L) divided by L, rounded once to float.
+ * Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3 with
+ * W1 [256][768], W2 [256][256], W3 [n_out][256] row-major; products run on
+ * bf16 operands (weights rounded to nearest-even from fp32 masters,
+ * activations likewise) with fp32 accumulation; loss = mean softmax
+ * cross-entropy; Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected). */
 #define PCHASE_MLP_IN 768
 #define PCHASE_MLP_HIDDEN 256
 
-/* Creates a network for n_out candidate classes with weights drawn from
- * `seed`.  Device memory is allocated here and freed by pchase_mlp_destroy. */
+/* Writes the 768 grid probes (host array) with the given base offset. */
+int pchase_mlp_grid(pchase_probe *probes, uint64_t base_offset);
+
+/* Creates a network for n_out (1..4096) classes on the current device:
+ * weights uniform in [-1/sqrt(fan_in), 1/sqrt(fan_in)) from
+ * Philox4x32-10(key = seed, counter = (element, tensor, 0, 0x494E4954)),
+ * biases and Adam moments zero.  Device memory is owned by the network
+ * and freed by pchase_mlp_destroy.  A network is used by one thread at a
+ * time. */
 int pchase_mlp_create(uint32_t n_out, uint64_t seed, pchase_mlp **net);
 void pchase_mlp_destroy(pchase_mlp *net);
-/* Feature vectors (fp32 [n][768], device) of n models, one row each,
- * computed by replaying the feature grid. */
+
+/* Clean features (fp32 [n][768], device) of n models at base offset 0,
+ * by replaying the grid.  Synchronises `stream`. */
 int pchase_mlp_features(const pchase_model *models, uint32_t n, float *x_dev, hipStream_t stream);
-/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on a batch:
- * x_dev fp32 [batch][768], labels_dev int32 [batch].  *loss (nullable)
- * receives the mean cross-entropy before the step (synchronises). */
+
+/* Canonical labels (host int32 [n]): labels[i] = the lowest j whose
+ * steady-pass hit/miss bits on the whole grid (base 0) equal those of
+ * model i -- the representative of i's zero class when every grid probe
+ * is compared.  ERANGE above about 8,000 models.  Synchronises. */
+int pchase_mlp_labels(const pchase_model *models, uint32_t n, int32_t *labels, hipStream_t stream);
+
+/* Training samples first .. first+n-1 (x_dev fp32 [n][768], labels_dev
+ * int32 [n]).  Sample i draws (x, y, z, w) = Philox4x32-10(key = seed,
+ * counter = (i_lo, i_hi, 0, 0)): model = x mod n_models, base offset
+ * = 4 (y mod (b / 4)), flip threshold t = z mod (rho_q16 + 1).  The grid is
+ * replayed through that model at that base offset and steady bit k of probe
+ * p is flipped when 16-bit word (k mod 8) -- bits 16 (w mod 2).. of output
+ * word w div 2 -- of Philox4x32-10(key = seed, counter = (k div 8, p, i_lo,
+ * 2^31 | i_hi)) is below t; the label is class_of_model[model] (host).
+ * Lines must be at most 128 bytes.  Synchronises. */
+int pchase_mlp_samples(const pchase_model *models, uint32_t n_models, const int32_t *class_of_model,
+                       uint64_t first, uint32_t n, uint64_t seed, uint32_t rho_q16, float *x_dev,
+                       int32_t *labels_dev, hipStream_t stream);
+
+/* One Adam step at learning rate lr on a batch (1..65536 rows of x_dev
+ * fp32 [batch][768] with labels_dev int32 [batch]).  *loss (nullable)
+ * receives the batch's mean cross-entropy before the step (synchronises). */
 int pchase_mlp_train_step(pchase_mlp *net, const float *x_dev, const int32_t *labels_dev,
                           uint32_t batch, float lr, float *loss, hipStream_t stream);
-/* Logits fp32 [batch][n_out] of x_dev. */
+/* `epochs` passes of consecutive batches over n_samples rows (a trailing
+ * partial batch is skipped); *last_loss (nullable) = loss of the last
+ * batch.  Synchronises. */
+int pchase_mlp_train(pchase_mlp *net, const float *x_dev, const int32_t *labels_dev, uint64_t n_samples,
+                     uint32_t batch, uint32_t epochs, float lr, float *last_loss, hipStream_t stream);
+/* Logits fp32 [batch][n_out] of x_dev (device). */
 int pchase_mlp_forward(const pchase_mlp *net, const float *x_dev, uint32_t batch,
                        float *logits_dev, hipStream_t stream);
-/* Raw parameter access for checkpoints and tests: which = 0..5 selects
- * W1, b1, W2, b2, W3, b3 (bf16 weights as uint16, fp32 biases);
- * adam = 0 parameter, 1 first moment (fp32), 2 second moment (fp32).
- * *bytes receives the size; data may be NULL to query it. */
-int pchase_mlp_param(const pchase_mlp *net, uint32_t which, uint32_t adam, void *data,
-                     uint64_t *bytes, int to_device /*0 read, 1 write*/);
+/* Indices of the k largest logits of each row, largest first, ties to the
+ * lower index (idx_dev int32 [rows][k]; k <= 64, n_classes <= 4096). */
+int pchase_mlp_topk(const float *logits_dev, uint32_t rows, uint32_t n_classes, uint32_t k,
+                    int32_t *idx_dev, hipStream_t stream);
+/* Parameter access for checkpoints and tests (host buffers, fp32):
+ * which = 0..5 selects W1, b1, W2, b2, W3, b3; slot = 0 master parameter,
+ * 1 Adam first moment, 2 second moment, 3 gradient of the last step
+ * (read-only).  *bytes receives the size; data may be NULL to query it.
+ * Writing a weight master refreshes its bf16 copy.  Synchronises. */
+int pchase_mlp_param(const pchase_mlp *net, uint32_t which, uint32_t slot, void *data,
+                     uint64_t *bytes, int write);
+/* Adam step counter (for bias correction): read, or set when set != 0. */
 int pchase_mlp_step_count(const pchase_mlp *net, uint64_t *steps, int set);
 
 /* --------------------------------------------------------- lifecycle --- */

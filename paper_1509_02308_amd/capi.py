@@ -77,20 +77,19 @@ def lib():
         L.microbench_lds_bank.argtypes = [u32, u32, u32, vp, vp]
         L.pchase_abort.argtypes = [ctypes.c_int]
         L.pchase_release.argtypes = []
-        for name in ("pchase_mlp_create", "pchase_mlp_destroy", "pchase_mlp_features",
-                     "pchase_mlp_train_step", "pchase_mlp_forward", "pchase_mlp_param",
-                     "pchase_mlp_step_count"):
-            if not hasattr(L, name):
-                continue
-        if hasattr(L, "pchase_mlp_create"):
-            L.pchase_mlp_create.argtypes = [u32, u64, ctypes.POINTER(vp)]
-            L.pchase_mlp_destroy.argtypes = [vp]
-            L.pchase_mlp_destroy.restype = None
-            L.pchase_mlp_features.argtypes = [vp, u32, vp, vp]
-            L.pchase_mlp_train_step.argtypes = [vp, vp, vp, u32, ctypes.c_float, vp, vp]
-            L.pchase_mlp_forward.argtypes = [vp, vp, u32, vp, vp]
-            L.pchase_mlp_param.argtypes = [vp, u32, u32, vp, vp, ctypes.c_int]
-            L.pchase_mlp_step_count.argtypes = [vp, vp, ctypes.c_int]
+        L.pchase_mlp_grid.argtypes = [vp, u64]
+        L.pchase_mlp_create.argtypes = [u32, u64, ctypes.POINTER(vp)]
+        L.pchase_mlp_destroy.argtypes = [vp]
+        L.pchase_mlp_destroy.restype = None
+        L.pchase_mlp_features.argtypes = [vp, u32, vp, vp]
+        L.pchase_mlp_labels.argtypes = [vp, u32, vp, vp]
+        L.pchase_mlp_samples.argtypes = [vp, u32, vp, u64, u32, u64, u32, vp, vp, vp]
+        L.pchase_mlp_train_step.argtypes = [vp, vp, vp, u32, ctypes.c_float, vp, vp]
+        L.pchase_mlp_train.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.c_float, vp, vp]
+        L.pchase_mlp_forward.argtypes = [vp, vp, u32, vp, vp]
+        L.pchase_mlp_topk.argtypes = [vp, u32, u32, u32, vp, vp]
+        L.pchase_mlp_param.argtypes = [vp, u32, u32, vp, vp, ctypes.c_int]
+        L.pchase_mlp_step_count.argtypes = [vp, vp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -217,7 +216,7 @@ def infer_cache_params(probe_arr, cand_arr, bits=None, bitoff=None, lat=None, la
     res = PchaseResult()
     zero = np.zeros((cand_arr.n + 31) // 32, dtype=np.uint32) if want_zero else None
     check(lib().infer_cache_params(ctypes.byref(obs), ctypes.cast(cand_arr, vp), cand_arr.n, probe_select,
-                                   mode, topk, net, ctypes.byref(res), _dptr(mn),
+                                   mode, topk, net.handle if net is not None else None, ctypes.byref(res), _dptr(mn),
                                    zero.ctypes.data_as(vp) if zero is not None else None,
                                    _stream(stream)))
     return res, zero
@@ -252,3 +251,89 @@ def pchase_abort(on: bool):
 
 def pchase_release():
     check(lib().pchase_release())
+
+
+# ------------------------------------------------------------ learned model --
+def pchase_mlp_grid(base_offset=0) -> ctypes.Array:
+    """The 768 feature-grid probes (host descriptors)."""
+    arr = (PchaseProbe * MLP_IN)()
+    check(lib().pchase_mlp_grid(ctypes.cast(arr, vp), base_offset))
+    arr.n = MLP_IN
+    return arr
+
+
+def pchase_mlp_features(model_arr, x, stream=None):
+    check(lib().pchase_mlp_features(ctypes.cast(model_arr, vp), model_arr.n, _dptr(x), _stream(stream)))
+
+
+def pchase_mlp_labels(model_arr, stream=None) -> np.ndarray:
+    out = np.zeros(model_arr.n, dtype=np.int32)
+    check(lib().pchase_mlp_labels(ctypes.cast(model_arr, vp), model_arr.n, out.ctypes.data_as(vp),
+                                  _stream(stream)))
+    return out
+
+
+def pchase_mlp_samples(model_arr, class_of_model, first, n, seed, rho_q16, x, labels, stream=None):
+    cm, p_cm = _hptr(class_of_model, np.int32)
+    check(lib().pchase_mlp_samples(ctypes.cast(model_arr, vp), model_arr.n, p_cm, first, n, seed, rho_q16,
+                                   _dptr(x), _dptr(labels), _stream(stream)))
+
+
+def pchase_mlp_topk(logits, k, idx, stream=None):
+    rows, ncls = logits.shape
+    check(lib().pchase_mlp_topk(_dptr(logits), rows, ncls, k, _dptr(idx), _stream(stream)))
+
+
+class Mlp:
+    """Owning handle of a pchase_mlp network (pchase_mlp_create/destroy)."""
+
+    def __init__(self, n_out: int, seed: int):
+        h = vp()
+        check(lib().pchase_mlp_create(n_out, seed, ctypes.byref(h)))
+        self.handle = h
+        self.n_out = n_out
+
+    def close(self):
+        if self.handle:
+            lib().pchase_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train_step(self, x, labels, lr, want_loss=True, stream=None):
+        loss = ctypes.c_float()
+        check(lib().pchase_mlp_train_step(self.handle, _dptr(x), _dptr(labels), x.shape[0], lr,
+                                          ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return float(loss.value) if want_loss else None
+
+    def train(self, x, labels, batch, epochs, lr, stream=None):
+        loss = ctypes.c_float()
+        check(lib().pchase_mlp_train(self.handle, _dptr(x), _dptr(labels), x.shape[0], batch, epochs, lr,
+                                     ctypes.byref(loss), _stream(stream)))
+        return float(loss.value)
+
+    def forward(self, x, logits, stream=None):
+        check(lib().pchase_mlp_forward(self.handle, _dptr(x), x.shape[0], _dptr(logits), _stream(stream)))
+
+    def param(self, which, slot=0) -> np.ndarray:
+        nb = u64()
+        check(lib().pchase_mlp_param(self.handle, which, slot, None, ctypes.byref(nb), 0))
+        out = np.zeros(nb.value // 4, dtype=np.float32)
+        check(lib().pchase_mlp_param(self.handle, which, slot, out.ctypes.data_as(vp), ctypes.byref(nb), 0))
+        return out
+
+    def set_param(self, which, slot, values):
+        arr = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
+        nb = u64()
+        check(lib().pchase_mlp_param(self.handle, which, slot, None, ctypes.byref(nb), 0))
+        assert arr.nbytes == nb.value, (arr.nbytes, nb.value)
+        check(lib().pchase_mlp_param(self.handle, which, slot, arr.ctypes.data_as(vp), ctypes.byref(nb), 1))
+
+    def steps(self, value=None) -> int:
+        v = u64(0 if value is None else value)
+        check(lib().pchase_mlp_step_count(self.handle, ctypes.byref(v), 0 if value is None else 1))
+        return int(v.value)

@@ -38,6 +38,31 @@ static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     return 2 * s == b || s == b || s == 2 * b;
 }
 
+
+// Replays `jobs` (grouped by model) with hit bits into `bits` (cleared
+// first) and synchronises; the counters go to workspace scratch.
+int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
+                const std::vector<uint64_t>& len, const std::vector<SweepJob>& jobs, uint32_t* bits,
+                uint64_t bits_words, hipStream_t stream) {
+    if (jobs.empty()) return PCHASE_OK;
+    for (const SweepJob& j : jobs)
+        if (j.model >= dm.size() || j.probe >= dp.size() || j.bitoff + (len[j.probe] + 31) / 32 > bits_words)
+            return set_error(PCHASE_EINVAL, "internal replay job outside its model, probe or bitmap bounds");
+    hipError_t e = ws->aux.ensure(jobs.size() * 16);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "replay counters: %s", hipGetErrorString(e));
+    SweepPlan plan;
+    int rc = build_sweep_plan(&plan, dm, dp, len, jobs, true);
+    if (rc) return rc;
+    rc = run_sweep_plan(ws, &plan, false, ws->aux.as<uint64_t>(), 2 * jobs.size(), bits, true, PCHASE_BATCHED,
+                        stream, {}, "");
+    if (rc) return rc;
+    PC_HIP(hipStreamSynchronize(stream));
+    uint32_t status = 0;
+    PC_HIP(hipMemcpy(&status, plan.d_queues + plan.batched.size(), sizeof status, hipMemcpyDeviceToHost));
+    if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
+    return PCHASE_OK;
+}
+
 }  // namespace pc
 
 using namespace pc;
@@ -293,61 +318,82 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
 }
 
 // ----------------------------------------------------------- inference ---
+static int build_infer_plan(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
+                            const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
+                            const std::vector<uint64_t>& len, const std::vector<uint64_t>& cf,
+                            const std::vector<uint64_t>& bitoff, int probe_select,
+                            const std::vector<uint8_t>* allow, std::unique_ptr<InferPlan>* out) {
+    std::unique_ptr<InferPlan> np(new InferPlan());
+    np->n_cands = n_cands;
+    np->n_host.assign(n_cands, 0);
+    std::vector<SweepJob> jobs;
+    for (uint32_t c = 0; c < n_cands; ++c) {
+        if (allow && !(*allow)[c]) continue;
+        for (uint32_t p = 0; p < obs->n_probes; ++p) {
+            if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
+            SweepJob j;
+            j.model = c;
+            j.probe = p;
+            j.out = c;
+            j.trace_id = p;
+            j.count_from = cf[p];
+            j.bitoff = bitoff[p];
+            jobs.push_back(j);
+            if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
+        }
+    }
+    int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false);
+    if (rc) return rc;
+    const size_t zw = (n_cands + 31) / 32;
+    const size_t bytes = 2 * n_cands * sizeof(uint64_t) + zw * 4 + 256 + sizeof(ArgminOut);
+    hipError_t e = np->dev.ensure(bytes);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "inference plan: %s", hipGetErrorString(e));
+    uint8_t* b = np->dev.as<uint8_t>();
+    np->d_m = reinterpret_cast<uint64_t*>(b);
+    np->d_n = np->d_m + n_cands;
+    np->d_zero = reinterpret_cast<uint32_t*>(np->d_n + n_cands);
+    np->d_out = reinterpret_cast<ArgminOut*>(b + (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256);
+    PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
+    *out = std::move(np);
+    return PCHASE_OK;
+}
+
+// cache = false builds a one-off plan (the learned path's top-k subsets)
 static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const pchase_model* cands,
                             uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
                             const std::vector<uint64_t>& len, const std::vector<uint64_t>& cf,
                             const std::vector<uint64_t>& bitoff, const uint32_t* bits, int probe_select,
                             const std::vector<uint8_t>* allow, pchase_result* out, uint64_t* mn_dev,
-                            uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched) {
-    // plan cache key: everything that shapes the schedule
-    Digest dg;
-    dg.add(&n_cands, sizeof n_cands);
-    dg.add(cands, n_cands * sizeof(pchase_model));
-    dg.add(obs->probes, obs->n_probes * sizeof(pchase_probe));
-    dg.add(cf.data(), cf.size() * sizeof(uint64_t));
-    dg.add(bitoff.data(), bitoff.size() * sizeof(uint64_t));
-    dg.add(&probe_select, sizeof probe_select);
-    if (allow) dg.add(allow->data(), allow->size());
-    const std::string key = dg.str();
-    auto it = ws->plans.find(key);
+                            uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched,
+                            bool cache = true) {
     InferPlan* ip;
-    if (it == ws->plans.end()) {
-        std::unique_ptr<InferPlan> np(new InferPlan());
-        np->n_cands = n_cands;
-        np->n_host.assign(n_cands, 0);
-        std::vector<SweepJob> jobs;
-        for (uint32_t c = 0; c < n_cands; ++c) {
-            if (allow && !(*allow)[c]) continue;
-            for (uint32_t p = 0; p < obs->n_probes; ++p) {
-                if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
-                SweepJob j;
-                j.model = c;
-                j.probe = p;
-                j.out = c;
-                j.trace_id = p;
-                j.count_from = cf[p];
-                j.bitoff = bitoff[p];
-                jobs.push_back(j);
-                if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
-            }
-        }
-        int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false);
+    std::unique_ptr<InferPlan> once;
+    if (!cache) {
+        int rc = build_infer_plan(obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &once);
         if (rc) return rc;
-        const size_t zw = (n_cands + 31) / 32;
-        const size_t bytes = 2 * n_cands * sizeof(uint64_t) + zw * 4 + 256 + sizeof(ArgminOut);
-        hipError_t e = np->dev.ensure(bytes);
-        if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "inference plan: %s", hipGetErrorString(e));
-        uint8_t* b = np->dev.as<uint8_t>();
-        np->d_m = reinterpret_cast<uint64_t*>(b);
-        np->d_n = np->d_m + n_cands;
-        np->d_zero = reinterpret_cast<uint32_t*>(np->d_n + n_cands);
-        np->d_out = reinterpret_cast<ArgminOut*>(b + (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256);
-        PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
-        if (ws->plans.size() > 16) ws->plans.clear();
-        ip = np.get();
-        ws->plans[key] = std::move(np);
+        ip = once.get();
     } else {
-        ip = it->second.get();
+        // plan cache key: everything that shapes the schedule
+        Digest dg;
+        dg.add(&n_cands, sizeof n_cands);
+        dg.add(cands, n_cands * sizeof(pchase_model));
+        dg.add(obs->probes, obs->n_probes * sizeof(pchase_probe));
+        dg.add(cf.data(), cf.size() * sizeof(uint64_t));
+        dg.add(bitoff.data(), bitoff.size() * sizeof(uint64_t));
+        dg.add(&probe_select, sizeof probe_select);
+        if (allow) dg.add(allow->data(), allow->size());
+        const std::string key = dg.str();
+        auto it = ws->plans.find(key);
+        if (it == ws->plans.end()) {
+            std::unique_ptr<InferPlan> np;
+            int rc = build_infer_plan(obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &np);
+            if (rc) return rc;
+            if (ws->plans.size() > 16) ws->plans.clear();
+            ip = np.get();
+            ws->plans[key] = std::move(np);
+        } else {
+            ip = it->second.get();
+        }
     }
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
@@ -472,14 +518,20 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     uint64_t replayed = 0;
     if (mode == PCHASE_LEARNED) {
         std::vector<uint8_t> allow;
-        rc = infer_learned(ws, obs, cands, n_cands, dp, len, cf, bitoff, bits, topk, net, &allow, stream);
+        bool on_grid = false;
+        rc = infer_learned(ws, obs, cands, n_cands, dp, len, cf, bitoff, bits, topk, net, &allow, &on_grid, stream);
         if (rc) return rc;
-        rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, &allow, out,
-                              nullptr, nullptr, stream, &replayed, sched);
-        if (rc) return rc;
-        out->replayed_accesses = replayed;
-        if (out->best >= 0 && out->best_m == 0) return PCHASE_OK;
-        out->fallback = 1;
+        if (on_grid) {
+            // confirm the proposals exactly: one-off plan, eager launches
+            rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, &allow, out,
+                                  nullptr, nullptr, stream, &replayed, PCHASE_PLAIN, false);
+            if (rc) return rc;
+            out->replayed_accesses = replayed;
+            if (out->best >= 0 && out->best_m == 0) return PCHASE_OK;
+            out->fallback = 1;
+        } else {
+            out->fallback = 2;
+        }
     }
     rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, nullptr, out, mn_dev,
                           zero_host, stream, &replayed, sched);

@@ -40,6 +40,7 @@ struct Workspace {
     DevBuf aux;        // per-call device scratch (counters, queues, results)
     DevBuf obs;        // derived observed bitmaps
     DevBuf slab;       // stream-replay set state
+    DevBuf mlp;        // grid replay bank of the learned proposer
     size_t slab_clean = 0;  // bytes of `slab` known to hold epoch 0 or older epochs
     uint32_t epoch = 0;
     void* host_res = nullptr;  // pinned result staging

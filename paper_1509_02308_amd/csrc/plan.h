@@ -67,11 +67,19 @@ struct InferPlan {
 };
 
 // Learned proposer: marks in *allow the top-k candidates of the network for
-// the observation (defined with the MLP kernels).
+// the observation (defined with the MLP kernels); *on_grid is false (and
+// nothing is marked) when the observation is not the feature grid.
 int infer_learned(Workspace* ws, const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
                   const std::vector<DevProbe>& dp, const std::vector<uint64_t>& len,
                   const std::vector<uint64_t>& cf, const std::vector<uint64_t>& bitoff, const uint32_t* bits,
-                  uint32_t topk, const pchase_mlp* net, std::vector<uint8_t>* allow, hipStream_t stream);
+                  uint32_t topk, const pchase_mlp* net, std::vector<uint8_t>* allow, bool* on_grid,
+                  hipStream_t stream);
+
+// Replays jobs (grouped by model) into a cleared hit bitmap of bits_words
+// words (job bit offsets are word offsets) and waits.
+int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
+                const std::vector<uint64_t>& len, const std::vector<SweepJob>& jobs, uint32_t* bits,
+                uint64_t bits_words, hipStream_t stream);
 
 // 128-bit FNV-style digest of byte ranges (plan cache keys).
 struct Digest {

@@ -138,6 +138,7 @@ Workspace::~Workspace() {
     aux.release();
     obs.release();
     slab.release();
+    mlp.release();
     if (host_res) (void)hipHostFree(host_res);
 }
 

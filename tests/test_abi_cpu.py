@@ -143,3 +143,14 @@ def test_microbench_argument_checks(capi):
                                ctypes.c_void_p(16), ctypes.byref(ovh), None) == -2   # array too small
     assert L.microbench_pchase(ctypes.byref(p), 9, ctypes.c_void_p(16), 8192, 10, ctypes.c_void_p(16),
                                ctypes.c_void_p(16), ctypes.byref(ovh), None) == -1   # flavour
+
+
+def test_mlp_grid_matches_reference(capi):
+    """The library's feature grid is the reference grid (host-only call)."""
+    from oracle import mlp_ref
+    arr = capi.pchase_mlp_grid(64)
+    got = [(arr[i].n_bytes, arr[i].s_bytes, arr[i].passes) for i in range(768)]
+    assert got == mlp_ref.grid()
+    assert all(arr[i].base_offset == 64 and arr[i].j0 == 0 and arr[i].elem_bytes == 4 for i in range(768))
+    with pytest.raises(capi.PchaseError):
+        capi.pchase_mlp_grid(2)

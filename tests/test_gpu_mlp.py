@@ -1,0 +1,229 @@
+"""GPU parity of the learned proposer against oracle/mlp_ref.py: features,
+canonical labels and noised samples bit-exact; forward logits, gradients
+and the Adam update of the bf16-MFMA network within the stated tolerances;
+checkpoint/resume; and the learned inference, which must return exact
+(m = 0) answers while replaying far less than the exhaustive search."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from oracle import mlp_ref as R
+from paper_1509_02308_amd import workloads as W
+from tests.gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+# relative L2 error allowed between the bf16-operand network (fp32
+# accumulate, activations rounded to bf16 between layers) and the fp64
+# reference on the same bf16 weights and inputs: a handful of bf16 roundings
+# (2^-9 relative each) per element, averaged over the tensor.
+TOL_REL_L2 = 1e-2
+
+ROWS = [(8192, 32, 1, 0), (8192, 32, 1, 1), (8192, 32, 2, 2), (8192, 32, 4, 0), (8192, 32, 4, 1),
+        (12288, 64, 4, 2), (12288, 32, 3, 0), (16384, 128, 8, 3), (24576, 64, 64, 0), (65536, 64, 16, 2)]
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_features_match_oracle():
+    torch, capi = need_gpu()
+    say("features: 10 models")
+    x = torch.zeros(len(ROWS), 768, dtype=torch.float32, device="cuda")
+    capi.pchase_mlp_features(capi.models(ROWS), x)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy()
+    for i, r in enumerate(ROWS):
+        want = R.features(orc, r)
+        assert np.array_equal(got[i], want), (r, np.nonzero(got[i] != want)[0][:5])
+
+
+def test_labels_match_oracle():
+    torch, capi = need_gpu()
+    rows = ROWS + [(8192, 32, 2, 0), (8192, 32, 2, 1), (8192, 64, 4, 0), (8192, 64, 4, 1)]
+    say(f"labels: {len(rows)} models")
+    got = capi.pchase_mlp_labels(capi.models(rows))
+    assert got.tolist() == R.canonical_labels(orc, rows).tolist()
+
+
+def test_samples_match_oracle():
+    torch, capi = need_gpu()
+    rows = ROWS[:8]
+    labels = np.arange(100, 100 + len(rows), dtype=np.int32)
+    seed, rho = 0x1509_0000_0000_0002, 1311
+    first, n = (1 << 32) - 3, 6          # crosses the 32-bit boundary of the sample counter
+    say(f"samples: {n} from {first}")
+    x = torch.zeros(n, 768, dtype=torch.float32, device="cuda")
+    y = torch.zeros(n, dtype=torch.int32, device="cuda")
+    capi.pchase_mlp_samples(capi.models(rows), labels, first, n, seed, rho, x, y)
+    torch.cuda.synchronize()
+    gx, gy = x.cpu().numpy(), y.cpu().numpy()
+    for r in range(n):
+        wx, wy, draw = R.sample(orc, first + r, seed, rows, labels, rho)
+        assert gy[r] == wy, (r, draw)
+        assert np.array_equal(gx[r], wx), (r, draw, np.nonzero(gx[r] != wx)[0][:5])
+
+
+def _net_params(net):
+    return [net.param(i) for i in range(6)]
+
+
+def _ref_params(net, n_out):
+    p = _net_params(net)
+    shapes = [(256, 768), (256,), (256, 256), (256,), (n_out, 256), (n_out,)]
+    out = []
+    for i, (v, s) in enumerate(zip(p, shapes)):
+        v = v.reshape(s)
+        out.append(R.bf16_round(v) if i % 2 == 0 else v)
+    return out
+
+
+def test_forward_matches_reference():
+    torch, capi = need_gpu()
+    n_out, B = 438, 37
+    say(f"forward: n_out {n_out} batch {B}")
+    net = capi.Mlp(n_out, 2308)
+    rng = np.random.default_rng(1)
+    xh = rng.random((B, 768), dtype=np.float32)
+    x = torch.from_numpy(xh).cuda()
+    z = torch.zeros(B, n_out, dtype=torch.float32, device="cuda")
+    net.forward(x, z)
+    torch.cuda.synchronize()
+    want, _ = R.forward(_ref_params(net, n_out), R.bf16_round(xh))
+    assert _rel(z.cpu().numpy(), want) <= TOL_REL_L2
+    net.close()
+
+
+def test_train_step_gradients_and_adam():
+    torch, capi = need_gpu()
+    n_out, B, lr = 438, 100, 1e-3
+    say(f"train step: n_out {n_out} batch {B}")
+    net = capi.Mlp(n_out, 7)
+    rng = np.random.default_rng(2)
+    xh = rng.random((B, 768), dtype=np.float32)
+    yh = rng.integers(0, n_out, B).astype(np.int32)
+    before = _net_params(net)
+    ref = _ref_params(net, n_out)
+    loss = net.train_step(torch.from_numpy(xh).cuda(), torch.from_numpy(yh).cuda(), lr)
+    want_loss, want_g = R.loss_and_grads(ref, R.bf16_round(xh), yh)
+    assert abs(loss - want_loss) <= TOL_REL_L2 * abs(want_loss)
+    grads = [net.param(i, 3) for i in range(6)]
+    # gradients: against the reference that rounds product operands to bf16
+    # where the network does (the batch sums cancel, which magnifies the
+    # 2^-9 operand roundings against a fully fp64 evaluation)
+    _, want_r = R.loss_and_grads(ref, R.bf16_round(xh), yh, rnd=R.bf16_round)
+    errs = [_rel(grads[i], want_r[i]) for i in range(6)]
+    say(f"gradient rel L2 vs bf16-operand reference: {errs}; vs fp64: "
+        f"{[_rel(grads[i], want_g[i]) for i in range(6)]}")
+    for i in range(6):
+        assert errs[i] <= TOL_REL_L2, (i, errs[i])
+    # the update itself: Adam step 1 on the network's own gradients
+    after = _net_params(net)
+    upd, _, _ = R.adam_step(before, grads, [0 * g for g in grads], [0 * g for g in grads], 1, lr)
+    for i in range(6):
+        assert np.allclose(after[i], upd[i], rtol=1e-5, atol=1e-7), i
+    assert net.steps() == 1
+    net.close()
+
+
+def test_checkpoint_resume_is_exact():
+    torch, capi = need_gpu()
+    n_out, B = 50, 64
+    say("checkpoint/resume")
+    rng = np.random.default_rng(3)
+    xs = [torch.from_numpy(rng.random((B, 768), dtype=np.float32)).cuda() for _ in range(4)]
+    ys = [torch.from_numpy(rng.integers(0, n_out, B).astype(np.int32)).cuda() for _ in range(4)]
+    a = capi.Mlp(n_out, 11)
+    for k in range(3):
+        a.train_step(xs[k], ys[k], 1e-3, want_loss=False)
+    ckpt = {(w, s): a.param(w, s) for w in range(6) for s in range(3)}
+    steps = a.steps()
+    b = capi.Mlp(n_out, 12)
+    for (w, s), v in ckpt.items():
+        b.set_param(w, s, v)
+    b.steps(steps)
+    a.train_step(xs[3], ys[3], 1e-3, want_loss=False)
+    b.train_step(xs[3], ys[3], 1e-3, want_loss=False)
+    for w in range(6):
+        for s in range(3):
+            assert np.array_equal(a.param(w, s), b.param(w, s)), (w, s)
+    a.close()
+    b.close()
+
+
+def test_topk_ties_to_lower_index():
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(4)
+    rows, C, k = 5, 438, 8
+    z = np.round(rng.normal(0, 1, (rows, C)), 1).astype(np.float32)   # many ties
+    idx = torch.zeros(rows, k, dtype=torch.int32, device="cuda")
+    capi.pchase_mlp_topk(torch.from_numpy(z).cuda(), k, idx)
+    torch.cuda.synchronize()
+    want = np.argsort(-z, axis=1, kind="stable")[:, :k]
+    assert np.array_equal(idx.cpu().numpy(), want)
+
+
+def _grid_obs(torch, capi, cand_arr, t):
+    """Hit bits of candidate t on the grid (replayed on the GPU; the
+    exhaustive search below is checked to reproduce it exactly)."""
+    g = capi.pchase_mlp_grid(0)
+    lens = np.array([capi.pchase_trace_len(g[i])[0] for i in range(768)], dtype=np.uint64)
+    words = (lens + 31) // 32
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)   # word offsets
+    bits = torch.zeros(int(words.sum()) + 1, dtype=torch.int32, device="cuda")
+    misses = torch.zeros(2 * 768, dtype=torch.int64, device="cuda")
+    one = capi.models([tuple(int(v) for v in (cand_arr[t].capacity_bytes, cand_arr[t].line_bytes,
+                                              cand_arr[t].ways, cand_arr[t].policy))])
+    capi.cache_replay_probes(one, g, np.zeros(768, np.uint32), np.arange(768, dtype=np.uint32), None,
+                             misses, bits, bitoff)
+    return g, bits, bitoff
+
+
+def test_learned_inference_is_exact_and_cheaper():
+    torch, capi = need_gpu()
+    cands = W.candidate_grid()
+    crows = [tuple(int(v) for v in c) for c in cands]
+    carr = capi.models(crows)
+    n = len(crows)
+    say(f"learned: labels for {n} candidates")
+    labels = capi.pchase_mlp_labels(carr)
+    n_train, seed = 65536, 1509
+    say(f"learned: {n_train} samples")
+    x = torch.zeros(n_train, 768, dtype=torch.float32, device="cuda")
+    y = torch.zeros(n_train, dtype=torch.int32, device="cuda")
+    capi.pchase_mlp_samples(carr, labels, 0, n_train, seed, 1311, x, y)
+    net = capi.Mlp(n, 2308)
+    say("learned: training 4 epochs")
+    loss = net.train(x, y, 1024, 4, 1e-3)
+    say(f"learned: last loss {loss:.4f}")
+    assert loss < 1.0
+    targets = np.random.default_rng(4242).integers(0, n, 24)
+    t_l = t_e = 0.0
+    acc_l = acc_e = 0
+    fallbacks = 0
+    for t in targets:
+        g, bits, bitoff = _grid_obs(torch, capi, carr, int(t))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rl, _ = capi.infer_cache_params(g, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_ALL,
+                                        mode=capi.LEARNED, topk=8, net=net)
+        t1 = time.perf_counter()
+        re, zero = capi.infer_cache_params(g, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_ALL,
+                                           mode=capi.EXHAUSTIVE, want_zero=True)
+        t2 = time.perf_counter()
+        t_l += t1 - t0
+        t_e += t2 - t1
+        acc_l += rl.replayed_accesses
+        acc_e += re.replayed_accesses
+        fallbacks += rl.fallback != 0
+        assert re.best_m == 0 and labels[t] == re.best        # the target's class representative
+        assert rl.best_m == 0 and (zero[rl.best // 32] >> (rl.best % 32)) & 1, (t, rl.best, re.best)
+    say(f"learned: fallbacks {fallbacks}/{len(targets)}, accesses {acc_l} vs {acc_e}, "
+        f"time {t_l * 1e3:.1f} ms vs {t_e * 1e3:.1f} ms")
+    assert fallbacks <= len(targets) // 4
+    assert acc_l * 5 < acc_e
+    net.close()
