@@ -224,7 +224,11 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
 }
 
 template <int POL, int A, bool SCORE>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs args) {
+// At least 4 waves per SIMD: the replay is bound by latency (LDS round
+// trips, dependent compares, branches), not by issue, so occupancy wins even
+// at the cost of a few spilled registers (measured: 3, 4, 5, 6, 8 waves per
+// SIMD give 17.3, 15.8, 17.2, 20.3, 28.3 ms on the full inference sweep).
+__global__ void __launch_bounds__(256, 4) sweep_kernel(SweepArgs args) {
     extern __shared__ uint32_t lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;

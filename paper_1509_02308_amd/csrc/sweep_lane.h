@@ -550,9 +550,30 @@ __device__ __forceinline__ void probe_runs(const DevProbe& p, const DevModel& m,
 // Sweeps of one pass precomputed for a lane that replays many sets of the
 // same probe; probes with more than kCachedSweeps sweeps per pass fall back
 // to probe_runs.
+// Field-wise select of two sweeps held in registers (a select of their
+// addresses would force both into scratch memory).
+__device__ __forceinline__ Sweep pick_sweep(bool first, const Sweep& a, const Sweep& b) {
+    Sweep w;
+    w.xf = first ? a.xf : b.xf;
+    w.cnt = first ? a.cnt : b.cnt;
+    w.kin = first ? a.kin : b.kin;
+    w.uf = first ? a.uf : b.uf;
+    w.ul = first ? a.ul : b.ul;
+    w.qf = first ? a.qf : b.qf;
+    w.rem = first ? a.rem : b.rem;
+    w.unit_mode = first ? a.unit_mode : b.unit_mode;
+    w.fast = first ? a.fast : b.fast;
+    w.aligned = first ? a.aligned : b.aligned;
+    w.R = first ? a.R : b.R;
+    w.off0 = first ? a.off0 : b.off0;
+    return w;
+}
+
+// The two sweeps are named members, not an array: a runtime index into a
+// per-lane array would place it in scratch memory.
 constexpr int kCachedSweeps = 2;
 struct SweepCache {
-    Sweep w[kCachedSweeps];
+    Sweep w0, w1;
     uint32_t n;   // sweeps per pass, or kCachedSweeps + 1 if they do not fit
     uint64_t qlo, sb;
 };
@@ -561,8 +582,13 @@ __device__ __forceinline__ void sweep_cache(SweepCache& c, const DevProbe& p, co
     c.n = 0;
     c.qlo = probe_qlo(p, m);
     c.sb = (uint64_t)p.se << p.elem_shift;
+    c.w0 = Sweep{};
+    c.w1 = Sweep{};
+    // unconditional field-wise updates: a store whose destination depends
+    // on the branch taken would keep the cache in scratch memory
     auto f = [&](const Sweep& w) {
-        if (c.n < kCachedSweeps) c.w[c.n] = w;
+        c.w0 = pick_sweep(c.n == 0, w, c.w0);
+        c.w1 = pick_sweep(c.n == 1, w, c.w1);
         ++c.n;
     };
     pass_sweeps(p, m, f);
@@ -577,7 +603,10 @@ __device__ __forceinline__ void cached_runs(const SweepCache& c, const DevProbe&
     }
     for (uint32_t pass = 0; pass < p.passes; ++pass) {
         const uint64_t kpass = (uint64_t)pass * p.L;
-        for (uint32_t i = 0; i < c.n; ++i) sweep_walk(c.w[i], kpass, c.sb, m, p, set, c.qlo, visit);
+        for (uint32_t i = 0; i < c.n; ++i) {
+            const Sweep w = pick_sweep(i != 0, c.w1, c.w0);
+            sweep_walk(w, kpass, c.sb, m, p, set, c.qlo, visit);
+        }
     }
 }
 
