@@ -24,24 +24,25 @@
 namespace pc {
 
 // ------------------------------------------------------- bitmap helpers --
-__device__ __forceinline__ void or_bits(uint32_t* w, uint64_t lo, uint64_t hi) {
+// Trace indices are below 2^32 (traces are shorter than 2^32 accesses).
+__device__ __forceinline__ void or_bits(uint32_t* w, uint32_t lo, uint32_t hi) {
     // sets bits [lo, hi)
     while (lo < hi) {
-        const uint64_t word = lo >> 5;
-        const uint32_t b0 = (uint32_t)(lo & 31);
-        const uint64_t n = (hi - lo < 32 - b0) ? hi - lo : 32 - b0;
+        const uint32_t word = lo >> 5;
+        const uint32_t b0 = lo & 31;
+        const uint32_t n = (hi - lo < 32 - b0) ? hi - lo : 32 - b0;
         const uint32_t mask = (n == 32) ? 0xFFFFFFFFu : (((1u << n) - 1u) << b0);
         atomicOr(w + word, mask);
         lo += n;
     }
 }
 
-__device__ __forceinline__ uint64_t ones_in(const uint32_t* w, uint64_t lo, uint64_t hi) {
-    uint64_t c = 0;
+__device__ __forceinline__ uint32_t ones_in(const uint32_t* w, uint32_t lo, uint32_t hi) {
+    uint32_t c = 0;
     while (lo < hi) {
-        const uint64_t word = lo >> 5;
-        const uint32_t b0 = (uint32_t)(lo & 31);
-        const uint64_t n = (hi - lo < 32 - b0) ? hi - lo : 32 - b0;
+        const uint32_t word = lo >> 5;
+        const uint32_t b0 = lo & 31;
+        const uint32_t n = (hi - lo < 32 - b0) ? hi - lo : 32 - b0;
         const uint32_t mask = (n == 32) ? 0xFFFFFFFFu : (((1u << n) - 1u) << b0);
         c += __popc(w[word] & mask);
         lo += n;
@@ -58,12 +59,12 @@ __device__ __forceinline__ uint64_t ones_in(const uint32_t* w, uint64_t lo, uint
 // into the output bitmap in memory run by run.
 // Sets bits [k0 + (hit ? 0 : 1), k0 + r) of an LDS bitmap: the run's hit
 // bits.  Runs of up to 32 accesses touch at most two words.
-__device__ __forceinline__ void or_run(uint32_t* w, uint64_t k0, uint32_t r, bool hit) {
+__device__ __forceinline__ void or_run(uint32_t* w, uint32_t k0, uint32_t r, bool hit) {
     if (r <= 32) {
         uint64_t mask = (r == 32) ? 0xFFFFFFFFull : ((1ull << r) - 1ull);
         if (!hit) mask &= ~1ull;
         mask <<= (k0 & 31);
-        const uint64_t word = k0 >> 5;
+        const uint32_t word = k0 >> 5;
         if ((uint32_t)mask) atomicOr(w + word, (uint32_t)mask);
         if (mask >> 32) atomicOr(w + word + 1, (uint32_t)(mask >> 32));
     } else {
@@ -71,21 +72,16 @@ __device__ __forceinline__ void or_run(uint32_t* w, uint64_t k0, uint32_t r, boo
     }
 }
 
-// Per-run bookkeeping of one lane.  With an LDS bitmap (bm != nullptr) the
-// run's hit bits are or-ed into it and compared or written out by the whole
-// wave afterwards; otherwise they are compared with the observation or or-ed
-// into the output bitmap in memory run by run.  Counts are per set (32 bits).
 template <class S, bool SCORE>
 struct Visitor {
     S* st;
     const DevModel* m;
     uint32_t trace_id;
-    uint64_t cf;
+    uint32_t cf;
     uint32_t* bits;   // memory bitmap of the job (observed or output), or null
     uint32_t* bm;     // LDS bitmap of the job, or null
-    uint32_t mt = 0, ms = 0;
-    uint64_t mm = 0;
-    __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint64_t k0, uint32_t r) {
+    uint32_t mt = 0, ms = 0, mm = 0;
+    __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint32_t k0, uint32_t r) {
         const bool hit = st->access(line, q, *m, k0, trace_id);
         if (!hit) {
             ++mt;
@@ -98,7 +94,7 @@ struct Visitor {
                 const uint32_t ob = (bits[k0 >> 5] >> (k0 & 31)) & 1u;
                 mm += (ob != (hit ? 1u : 0u)) ? 1u : 0u;
             }
-            const uint64_t lo = (k0 + 1 > cf) ? k0 + 1 : cf, hi = k0 + r;
+            const uint32_t lo = (k0 + 1 > cf) ? k0 + 1 : cf, hi = k0 + r;
             if (lo < hi) mm += (hi - lo) - ones_in(bits, lo, hi);
         } else if (bits != nullptr) {
             or_bits(bits, hit ? k0 : k0 + 1, k0 + r);
@@ -136,7 +132,7 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     uint32_t key = kInvalidTag;
-    uint64_t mt = 0, ms = 0, mm = 0;
+    uint32_t mt = 0, ms = 0, mm = 0;   // per lane: below the trace length < 2^32
     if (active) {
         // G = min(T, 64) lanes per replay; lane g of a replay owns the sets
         // g, g+G, g+2G, ... and replays them one after the other
@@ -148,25 +144,27 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         key = job.out;
         uint32_t* bits = (args.bits == nullptr || use_bm) ? nullptr : args.bits + job.bitoff;
         uint32_t* jbm = use_bm ? bm + job.bm_off : nullptr;
+        const uint32_t len = p.L * p.passes;
+        const uint32_t cf = job.count_from < len ? (uint32_t)job.count_from : len;
         SweepCache sc;
         sweep_cache(sc, p, m);
         for (uint32_t set = g; set < T; set += G) {
             if constexpr (A == kClassMap) {
                 MapSet<POL> st;
                 st.init(col, args.map_rows);
-                Visitor<MapSet<POL>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits, jbm};
+                Visitor<MapSet<POL>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
                 cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;
             } else if constexpr (A == kClassScan) {
                 ScanSet<POL> st;
                 st.init(col, m.ways);
-                Visitor<ScanSet<POL>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits, jbm};
+                Visitor<ScanSet<POL>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
                 cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;
             } else {
                 RegSet<POL, A> st;
                 st.init();
-                Visitor<RegSet<POL, A>, SCORE> v{&st, &m, job.trace_id, job.count_from, bits, jbm};
+                Visitor<RegSet<POL, A>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
                 cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;
             }
@@ -182,12 +180,12 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         for (uint32_t jr = jlo; jr <= jhi; ++jr) {
             const SweepJob job = args.jobs[task.job + jr];
             const DevProbe p = args.probes[job.probe];
-            const uint64_t len = (uint64_t)p.L * p.passes;
-            const uint64_t words = (len + 31) / 32;
+            const uint32_t len = p.L * p.passes;
+            const uint32_t words = (len + 31) / 32;
             if constexpr (SCORE) {
                 key = job.out;  // one candidate per task when scoring
-                const uint64_t cf = job.count_from;
-                for (uint64_t w = (cf >> 5) + (uint64_t)lane; w < words; w += kWave) {
+                const uint32_t cf = job.count_from < len ? (uint32_t)job.count_from : len;
+                for (uint32_t w = (cf >> 5) + (uint32_t)lane; w < words; w += kWave) {
                     uint32_t mask = 0xFFFFFFFFu;
                     if (w == (cf >> 5)) mask &= ~((1u << (cf & 31)) - 1u);
                     if (w == words - 1 && (len & 31)) mask &= (1u << (len & 31)) - 1u;
@@ -195,7 +193,7 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
                     mm += __popc(diff);
                 }
             } else {
-                for (uint64_t w = (uint64_t)lane; w < words; w += kWave)
+                for (uint32_t w = (uint32_t)lane; w < words; w += kWave)
                     args.bits[job.bitoff + w] = bm[job.bm_off + w];
             }
         }
@@ -205,14 +203,14 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
     const uint32_t key_up = __shfl_up(key, 1, kWave);
     const bool head = (lane == 0) || (key_up != key);
     if (SCORE) {
-        mm = seg_sum(mm, key, lane);
-        if (head && key != kInvalidTag && mm) atomicAdd((unsigned long long*)&args.counters[key], mm);
+        const uint64_t sm = seg_sum(mm, key, lane);
+        if (head && key != kInvalidTag && sm) atomicAdd((unsigned long long*)&args.counters[key], sm);
     } else {
-        mt = seg_sum(mt, key, lane);
-        ms = seg_sum(ms, key, lane);
+        const uint64_t st = seg_sum(mt, key, lane);
+        const uint64_t ss = seg_sum(ms, key, lane);
         if (head && key != kInvalidTag) {
-            if (mt) atomicAdd((unsigned long long*)&args.counters[2 * (uint64_t)key], mt);
-            if (ms) atomicAdd((unsigned long long*)&args.counters[2 * (uint64_t)key + 1], ms);
+            if (st) atomicAdd((unsigned long long*)&args.counters[2 * (uint64_t)key], st);
+            if (ss) atomicAdd((unsigned long long*)&args.counters[2 * (uint64_t)key + 1], ss);
         }
     }
     if (use_bm) {

@@ -73,8 +73,10 @@ struct PlruBits {
     }
 };
 
-__device__ __forceinline__ uint32_t random_way(const DevModel& m, uint64_t k, uint32_t trace_id) {
-    return philox_x((uint32_t)k, (uint32_t)(k >> 32), trace_id, 0u, m.seed_lo, m.seed_hi) % m.ways;
+// k < 2^32 (traces are shorter than 2^32 accesses): the counter is
+// (k, 0, trace_id, 0)
+__device__ __forceinline__ uint32_t random_way(const DevModel& m, uint32_t k, uint32_t trace_id) {
+    return philox_x(k, 0u, trace_id, 0u, m.seed_lo, m.seed_hi) % m.ways;
 }
 
 // ----------------------------------------------- set state in registers --
@@ -97,7 +99,7 @@ struct RegSet {
         bits = PlruBits();
     }
 
-    __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint64_t k,
+    __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint32_t k,
                                            uint32_t trace_id) {
         const uint32_t a = m.ways;
         int hw = -1;
@@ -229,7 +231,7 @@ struct MapSet {
         if (tail == kNil) tail = x;
     }
 
-    __device__ __forceinline__ bool access(uint32_t, uint32_t q, const DevModel& m, uint64_t k,
+    __device__ __forceinline__ bool access(uint32_t, uint32_t q, const DevModel& m, uint32_t k,
                                            uint32_t trace_id) {
         const uint32_t a = m.ways;
         const uint32_t w = map_get(q);
@@ -312,7 +314,7 @@ struct ScanSet {
             for (uint32_t w = 0; w < a; w += 4) rank_word(w) = 0xFFFFFFFFu;
     }
 
-    __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint64_t k,
+    __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint32_t k,
                                            uint32_t trace_id) {
         uint32_t hw = kInvalidTag;
         for (uint32_t w = 0; w < a; ++w)
@@ -377,10 +379,10 @@ struct ScanSet {
 // so a lane computes it once and walks each of its sets from it.
 struct Sweep {
     uint64_t xf;     // address of the first access
-    uint64_t cnt;    // accesses in the sweep
-    uint64_t kin;    // index of the first access within the pass
-    uint64_t uf, ul; // first and last unit touched
-    uint64_t qf;     // floor(uf / T)
+    uint32_t cnt;    // accesses in the sweep
+    uint32_t kin;    // index of the first access within the pass
+    uint32_t uf, ul; // first and last unit touched (addresses < 2^34, units >= 4 bytes)
+    uint32_t qf;     // floor(uf / T)
     uint32_t rem;    // uf mod T
     uint32_t unit_mode;  // 1: walk units (stride below T units), 0: walk accesses
     uint32_t fast;   // unit mode: offsets fit 32 bits, divide by the stride's multiplier
@@ -392,28 +394,29 @@ struct Sweep {
     uint32_t off0;
 };
 
-__device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, uint64_t cnt, uint64_t kin,
+__device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, uint32_t cnt, uint32_t kin,
                                           const DevModel& m, const DevProbe& p) {
     const uint32_t us = m.unit_shift;
     const uint64_t U = 1ull << us;
     w.xf = xf;
     w.cnt = cnt;
     w.kin = kin;
-    w.uf = xf >> us;
-    w.ul = (xf + (cnt - 1) * sb) >> us;
-    w.qf = udiv64(w.uf, m.sets);
-    w.rem = (uint32_t)(w.uf - w.qf * m.sets);
+    const uint64_t uf = xf >> us;
+    w.uf = (uint32_t)uf;
+    w.ul = (uint32_t)((xf + (uint64_t)(cnt - 1) * sb) >> us);
+    w.qf = w.uf / m.sets;
+    w.rem = w.uf - w.qf * m.sets;
     w.unit_mode = (sb > 0 && sb < U * m.sets) ? 1u : 0u;
-    w.fast = (w.unit_mode && p.sb_fast && (cnt - 1) * sb + U + sb < (1ull << 32)) ? 1u : 0u;
+    w.fast = (w.unit_mode && p.sb_fast && (uint64_t)(cnt - 1) * sb + U + sb < (1ull << 32)) ? 1u : 0u;
     w.aligned = 0;
     w.R = 0;
     w.off0 = 0;
     if (w.unit_mode && m.unit_shift == m.line_shift && sb <= U && (U % sb) == 0 && (xf % sb) == 0) {
         const uint64_t R = U / sb;
-        if (cnt < (1ull << 30) && R * m.sets < (1ull << 30)) {
+        if (cnt < (1u << 30) && R * m.sets < (1ull << 30)) {
             w.aligned = 1;
             w.R = (uint32_t)R;
-            w.off0 = (uint32_t)((xf - (w.uf << us)) / sb);
+            w.off0 = (uint32_t)((xf - (uf << us)) / sb);
         }
     }
 }
@@ -424,18 +427,19 @@ __device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, ui
 // (floor(u/T) - floor(u_lo/T)) * R + (line mod R), with u the line's unit,
 // u_lo the probe's lowest unit and R lines per unit.
 template <class Visit>
-__device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint64_t sb, const DevModel& m,
-                                           const DevProbe& p, uint32_t set, uint64_t qlo, Visit& visit) {
+__device__ __forceinline__ void sweep_walk(const Sweep& w, uint32_t kpass, uint64_t sb, const DevModel& m,
+                                           const DevProbe& p, uint32_t set, uint32_t qlo, Visit& visit) {
     const uint32_t T = m.sets;
     const uint32_t us = m.unit_shift, ls = m.line_shift;
     const uint32_t rsh = us - ls;
     const uint64_t U = 1ull << us;
-    const uint64_t xf = w.xf, cnt = w.cnt, kstart = kpass + w.kin;
+    const uint64_t xf = w.xf;
+    const uint32_t cnt = w.cnt, kstart = kpass + w.kin;
     if (w.aligned) {
         // unit u = uf + d starts at access d*R - off0; units advance by T
         const uint32_t d = set >= w.rem ? set - w.rem : set + T - w.rem;
-        uint32_t u = (uint32_t)(w.uf + d);
-        uint32_t Q = (uint32_t)(w.qf + (set < w.rem ? 1u : 0u) - qlo);
+        uint32_t u = w.uf + d;
+        uint32_t Q = w.qf + (set < w.rem ? 1u : 0u) - qlo;
         const int32_t R = (int32_t)w.R;
         const int32_t step = (int32_t)(T * w.R);
         const int32_t last = (int32_t)cnt - 1;
@@ -448,33 +452,37 @@ __device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint6
         return;
     }
     if (w.unit_mode) {
-        // the first unit of this set at or after uf, and its quotient by T
-        uint64_t u = w.uf + (set >= w.rem ? set - w.rem : set + T - w.rem);
-        uint64_t Q = w.qf + (set < w.rem ? 1u : 0u) - qlo;
-        for (; u <= w.ul; u += T, ++Q) {
-            const uint64_t lo = u << us;
-            uint64_t ilo, ihi;
+        // the first unit of this set at or after uf, and its quotient by T;
+        // counted iterations, since u + T may pass 2^32 after the last unit
+        const uint64_t u0 = (uint64_t)w.uf + (set >= w.rem ? set - w.rem : set + T - w.rem);
+        if (u0 > w.ul) return;
+        const uint32_t n_units = (uint32_t)(w.ul - u0) / T + 1;
+        uint32_t u = (uint32_t)u0;
+        uint32_t Q = w.qf + (set < w.rem ? 1u : 0u) - qlo;
+        for (uint32_t it = 0; it < n_units; ++it, u += T, ++Q) {
+            const uint64_t lo = (uint64_t)u << us;
+            uint32_t ilo, ihi;
             if (w.fast) {
                 ilo = lo <= xf ? 0 : p.sb_div.div((uint32_t)(lo - xf + sb - 1));
                 ihi = p.sb_div.div((uint32_t)(lo + U - 1 - xf));
             } else {
-                ilo = lo <= xf ? 0 : udiv64(lo - xf + sb - 1, sb);
-                ihi = udiv64(lo + U - 1 - xf, sb);
+                ilo = lo <= xf ? 0 : (uint32_t)udiv64(lo - xf + sb - 1, sb);
+                const uint64_t h = udiv64(lo + U - 1 - xf, sb);
+                ihi = h > cnt - 1 ? cnt - 1 : (uint32_t)h;
             }
             if (ihi > cnt - 1) ihi = cnt - 1;
             if (ilo > ihi) continue;
             if (rsh == 0) {
-                visit((uint32_t)u, (uint32_t)Q, kstart + ilo, (uint32_t)(ihi - ilo + 1));
+                visit(u, Q, kstart + ilo, ihi - ilo + 1);
             } else {
-                uint64_t i = ilo;
+                uint32_t i = ilo;
                 while (i <= ihi) {
-                    const uint64_t line = (xf + i * sb) >> ls;
-                    const uint64_t lend = (line + 1) << ls;
+                    const uint32_t line = (uint32_t)((xf + (uint64_t)i * sb) >> ls);
+                    const uint64_t lend = (uint64_t)(line + 1) << ls;
                     uint64_t inext = udiv64(lend - xf + sb - 1, sb);
-                    if (inext > ihi + 1) inext = ihi + 1;
-                    visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kstart + i,
-                          (uint32_t)(inext - i));
-                    i = inext;
+                    if (inext > (uint64_t)ihi + 1) inext = (uint64_t)ihi + 1;
+                    visit(line, (Q << rsh) + (line & ((1u << rsh) - 1)), kstart + i, (uint32_t)inext - i);
+                    i = (uint32_t)inext;
                 }
             }
         }
@@ -482,22 +490,24 @@ __device__ __forceinline__ void sweep_walk(const Sweep& w, uint64_t kpass, uint6
         // stride of at least T units (or a single access): walk the
         // accesses, tracking the set and the unit's quotient by T
         // incrementally (the unit advances by d or d+1 per access)
-        uint64_t x = xf, u = w.uf;
+        uint64_t x = xf;
+        uint32_t u = w.uf;
         uint32_t st = w.rem;
-        uint64_t Q = w.qf - qlo;
+        uint32_t Q = w.qf - qlo;
         const uint64_t d0 = sb >> us;
         const uint64_t dq0 = udiv64(d0, T), dq1 = udiv64(d0 + 1, T);
         const uint32_t dm0 = (uint32_t)(d0 - dq0 * T), dm1 = (uint32_t)(d0 + 1 - dq1 * T);
-        for (uint64_t i = 0; i < cnt; ++i) {
+        for (uint32_t i = 0; i < cnt; ++i) {
             if (st == set) {
-                const uint64_t line = x >> ls;
-                visit((uint32_t)line, (uint32_t)((Q << rsh) + (line & ((1ull << rsh) - 1))), kstart + i, 1);
+                const uint32_t line = (uint32_t)(x >> ls);
+                visit(line, (Q << rsh) + (line & ((1u << rsh) - 1)), kstart + i, 1);
             }
             if (i + 1 == cnt) break;
-            const uint64_t xn = x + sb, un = xn >> us;
-            const bool one = (un - u == d0);
+            const uint64_t xn = x + sb;
+            const uint32_t un = (uint32_t)(xn >> us);
+            const bool one = ((uint64_t)(un - u) == d0);
             st += one ? dm0 : dm1;
-            Q += one ? dq0 : dq1;
+            Q += (uint32_t)(one ? dq0 : dq1);
             if (st >= T) {
                 st -= T;
                 ++Q;
@@ -519,29 +529,29 @@ __device__ __forceinline__ void pass_sweeps(const DevProbe& p, const DevModel& m
         f(w);
         return;
     }
-    uint64_t r = p.j0, kpos = 0;
+    uint32_t r = p.j0, kpos = 0;
     while (kpos < p.L) {
         // one increasing sweep: r, r+se, ... < ne
-        uint64_t cnt = (p.ne - r + p.se - 1) / p.se;
+        uint32_t cnt = (uint32_t)(((uint64_t)p.ne - r + p.se - 1) / p.se);
         if (cnt > p.L - kpos) cnt = p.L - kpos;
-        sweep_geo(w, p.base + (r << es), sb, cnt, kpos, m, p);
+        sweep_geo(w, p.base + ((uint64_t)r << es), sb, cnt, kpos, m, p);
         f(w);
         kpos += cnt;
-        r = r + cnt * p.se - p.ne;
+        r = (uint32_t)((uint64_t)r + (uint64_t)cnt * p.se - p.ne);
     }
 }
 
-__device__ __forceinline__ uint64_t probe_qlo(const DevProbe& p, const DevModel& m) {
-    return udiv64(p.base >> m.unit_shift, m.sets);
+__device__ __forceinline__ uint32_t probe_qlo(const DevProbe& p, const DevModel& m) {
+    return (uint32_t)(p.base >> m.unit_shift) / m.sets;
 }
 
 // All runs of set `set` over the whole probe (every pass), in trace order.
 template <class Visit>
 __device__ __forceinline__ void probe_runs(const DevProbe& p, const DevModel& m, uint32_t set, Visit& visit) {
     const uint64_t sb = (uint64_t)p.se << p.elem_shift;
-    const uint64_t qlo = probe_qlo(p, m);
+    const uint32_t qlo = probe_qlo(p, m);
     for (uint32_t pass = 0; pass < p.passes; ++pass) {
-        const uint64_t kpass = (uint64_t)pass * p.L;
+        const uint32_t kpass = pass * p.L;
         auto f = [&](const Sweep& w) { sweep_walk(w, kpass, sb, m, p, set, qlo, visit); };
         pass_sweeps(p, m, f);
     }
@@ -575,7 +585,8 @@ constexpr int kCachedSweeps = 2;
 struct SweepCache {
     Sweep w0, w1;
     uint32_t n;   // sweeps per pass, or kCachedSweeps + 1 if they do not fit
-    uint64_t qlo, sb;
+    uint32_t qlo;
+    uint64_t sb;
 };
 
 __device__ __forceinline__ void sweep_cache(SweepCache& c, const DevProbe& p, const DevModel& m) {
@@ -602,7 +613,7 @@ __device__ __forceinline__ void cached_runs(const SweepCache& c, const DevProbe&
         return;
     }
     for (uint32_t pass = 0; pass < p.passes; ++pass) {
-        const uint64_t kpass = (uint64_t)pass * p.L;
+        const uint32_t kpass = pass * p.L;
         for (uint32_t i = 0; i < c.n; ++i) {
             const Sweep w = pick_sweep(i != 0, c.w1, c.w0);
             sweep_walk(w, kpass, c.sb, m, p, set, c.qlo, visit);
