@@ -2,6 +2,7 @@
 // materialised traces, exhaustive and learned inference.
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "plan.h"
 
@@ -182,14 +183,21 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     }
     if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
 
-    // bucket pairs by (policy, group width), longest first inside a bucket
+    // bucket pairs by (policy, group width), longest first inside a bucket;
+    // a pair that is long, or whose state is large, is split by set into
+    // parts that run side by side: each part's serial chain of state updates
+    // and its state slab shrink by the number of parts
+    constexpr uint64_t kSplitLen = 8192, kPartState = 256 << 10;
     struct Item {
         int key;
         uint64_t len;
         uint32_t i;
+        uint32_t parts, part;
     };
-    std::vector<Item> items(n_pairs);
-    uint64_t max_state = 0;
+    std::vector<Item> items;
+    items.reserve(n_pairs);
+    std::map<int, uint64_t> bucket_state;   // largest model state of each (policy, width) bucket
+    std::vector<uint64_t> zero_cnt, zero_bits;   // (word, count) ranges merged into by split pairs
     for (uint64_t i = 0; i < n_pairs; ++i) {
         if (pair_model[i] >= n_models) return set_error(PCHASE_EINVAL, "pair %llu: model index out of range", (unsigned long long)i);
         if (pair_trace[i] >= n_traces) return set_error(PCHASE_EINVAL, "pair %llu: trace index out of range", (unsigned long long)i);
@@ -199,16 +207,36 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
         int wl = 0;
         while ((1u << wl) < w) ++wl;
         const uint64_t len = trace_off[pair_trace[i] + 1] - trace_off[pair_trace[i]];
-        items[i] = Item{(int)m.policy * 8 + wl, len, (uint32_t)i};
-        max_state = std::max<uint64_t>(max_state, (uint64_t)m.sets * 32 + (uint64_t)m.sets * m.ways * 8);
+        const int key = (int)m.policy * 8 + wl;
+        // parts: a power of two (at most 64 and at most T) until each part's
+        // chain is at most kSplitLen accesses and its state at most kPartState
+        const uint64_t per_set = 32 + (uint64_t)m.ways * 8;
+        uint32_t parts = 1;
+        while (parts < 64 && 2 * parts <= m.sets &&
+               ((uint64_t)parts * kSplitLen < len || ((m.sets + parts - 1) / parts) * per_set > kPartState))
+            parts *= 2;
+        uint64_t& bs = bucket_state[key];
+        bs = std::max<uint64_t>(bs, (uint64_t)((m.sets + parts - 1) / parts) * per_set);
+        for (uint32_t p = 0; p < parts; ++p) items.push_back(Item{key, len, (uint32_t)i, parts, p});
+        if (parts > 1) {
+            zero_cnt.push_back(4 * i);   // the pair's two 64-bit counters, as 32-bit words
+            zero_cnt.push_back(4);
+            if (hitbits_dev) {
+                zero_bits.push_back(bitoff[i]);
+                zero_bits.push_back((len + 31) / 32);
+            }
+        }
     }
+    if (items.size() >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many pairs");
     std::sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
         if (x.key != y.key) return x.key < y.key;
         if (x.len != y.len) return x.len > y.len;
-        return x.i < y.i;
+        if (x.i != y.i) return x.i < y.i;
+        return x.part < y.part;
     });
-    std::vector<StreamPair> pairs(n_pairs);
-    for (uint64_t q = 0; q < n_pairs; ++q) {
+    const uint64_t n_items = items.size();
+    std::vector<StreamPair> pairs(n_items);
+    for (uint64_t q = 0; q < n_items; ++q) {
         const uint32_t i = items[q].i;
         StreamPair& p = pairs[q];
         p.start = trace_off[pair_trace[i]];
@@ -219,7 +247,7 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
         p.model = pair_model[i];
         p.trace_id = pair_trace[i];
         p.out = i;
-        p.pad = 0;
+        p.pad = items[q].parts > 1 ? (items[q].parts << 16) | items[q].part : 0;
     }
 
     Workspace* ws;
@@ -230,7 +258,8 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     const size_t o_models = 0;
     const size_t o_pairs = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
     const size_t o_status = o_pairs + (pairs.size() * sizeof(StreamPair) + 255) / 256 * 256;
-    const size_t total = o_status + 256;
+    const size_t o_zero = o_status + 512;
+    const size_t total = o_zero + (zero_cnt.size() + zero_bits.size()) * sizeof(uint64_t) + 256;
     hipError_t e = ws->stage.ensure(total);
     if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
     uint8_t* sb = ws->stage.as<uint8_t>();
@@ -239,26 +268,52 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + o_status);
     PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(StreamPair), hipMemcpyHostToDevice, stream));
-    PC_HIP(launch_fill_u32(d_status, 64, 0, stream));
+    PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
+    if (!zero_cnt.empty()) {
+        // split pairs merge into their outputs: zero those first
+        uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + o_zero);
+        uint64_t* d_zb = d_zc + zero_cnt.size();
+        PC_HIP(hipMemcpyAsync(d_zc, zero_cnt.data(), zero_cnt.size() * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(launch_clear_ranges(reinterpret_cast<uint32_t*>(misses_dev), d_zc, (uint32_t)(zero_cnt.size() / 2),
+                                   stream));
+        if (!zero_bits.empty()) {
+            PC_HIP(hipMemcpyAsync(d_zb, zero_bits.data(), zero_bits.size() * 8, hipMemcpyHostToDevice, stream));
+            PC_HIP(launch_clear_ranges(hitbits_dev, d_zb, (uint32_t)(zero_bits.size() / 2), stream));
+        }
+    }
 
-    // state slabs: one per resident group, bounded by a 4 GiB pool
-    const uint64_t slab_bytes = (max_state + 255) / 256 * 256;
-    const uint64_t pool_cap = 4ull << 30;
-    uint64_t groups_max = pool_cap / slab_bytes;
-    if (groups_max < 1) return set_error(PCHASE_ERANGE, "model state of %llu bytes exceeds the slab pool",
-                                         (unsigned long long)slab_bytes);
+    // state slabs: one per resident group, sized per bucket; the pool may
+    // take half of the free device memory (at least 4 GiB, at most 64 GiB)
+    size_t mem_free = 0, mem_total = 0;
+    PC_HIP(hipMemGetInfo(&mem_free, &mem_total));
+    const uint64_t pool_cap = std::max<uint64_t>(4ull << 30, std::min<uint64_t>((mem_free + ws->slab.cap) / 2, 64ull << 30));
+    for (const auto& kv : bucket_state)
+        if ((kv.second + 255) / 256 * 256 > pool_cap)
+            return set_error(PCHASE_ERANGE, "model state of %llu bytes exceeds the slab pool",
+                             (unsigned long long)kv.second);
 
     // epochs are unique per pair across calls; on wrap the pool is cleared
-    if ((uint64_t)ws->epoch + n_pairs + 1 >= 0xFFFFFFFFull) {
+    if ((uint64_t)ws->epoch + n_items + 1 >= 0xFFFFFFFFull) {
         ws->epoch = 0;
         ws->slab_clean = 0;
     }
-    size_t qi = 0;
-    uint64_t q = 0;
-    while (q < n_pairs) {
+    // one launch per (policy, width) bucket; buckets run concurrently on
+    // the workspace's replay streams, each on its own region of the slab
+    // pool, so that one bucket's longest pair does not wait for another's
+    struct Launch {
+        int pol, W;
+        uint64_t q, e2, blocks, gpb, slab_bytes, region;
+        double cost;
+    };
+    std::vector<Launch> launches;
+    for (uint64_t q = 0; q < n_items;) {
         const int key = items[q].key;
         uint64_t e2 = q;
-        while (e2 < n_pairs && items[e2].key == key) ++e2;
+        double work = 0;
+        while (e2 < n_items && items[e2].key == key) {
+            work += (double)items[e2].len / items[e2].parts;
+            ++e2;
+        }
         const int pol = key / 8, wl = key % 8, W = 1 << wl;
         int occ = ws->occ_stream[pol][wl];
         if (occ == 0) {
@@ -267,48 +322,92 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
             if (occ < 1) occ = 1;
             ws->occ_stream[pol][wl] = occ;
         }
-        const uint64_t gpb = 4ull * (64 / W);  // groups per 256-thread block
-        uint64_t blocks = (uint64_t)occ * ws->cus;
-        const uint64_t need = (e2 - q + gpb - 1) / gpb;
-        if (mode == PCHASE_PLAIN) blocks = need;  // one group per pair, no reuse beyond the queue
-        blocks = std::min(blocks, need);
-        blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, groups_max / gpb));
-        const uint64_t slab_total = blocks * gpb * slab_bytes;
-        if (slab_total > ws->slab.cap) {
-            e = ws->slab.ensure(slab_total);
-            if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "slab pool of %llu bytes: %s",
-                                                  (unsigned long long)slab_total, hipGetErrorString(e));
-            ws->slab_clean = 0;
+        Launch L;
+        L.pol = pol;
+        L.W = W;
+        L.q = q;
+        L.e2 = e2;
+        L.gpb = 4ull * (64 / W);  // groups per 256-thread block
+        L.slab_bytes = (bucket_state[key] + 255) / 256 * 256;
+        const uint64_t need = (e2 - q + L.gpb - 1) / L.gpb;
+        L.blocks = mode == PCHASE_PLAIN ? need : std::min<uint64_t>((uint64_t)occ * ws->cus, need);
+        // the longest pair (first, pairs are longest first) or the bucket's share
+        L.cost = std::max((double)items[q].len / items[q].parts, work / (double)(L.blocks * L.gpb));
+        launches.push_back(L);
+        q = e2;
+    }
+    // concurrent when every bucket's claim fits the pool at once; otherwise
+    // one bucket after the other, each with the whole pool (a large batch
+    // is bound by resident groups, a small one by its longest pairs)
+    uint64_t claims = 0, largest = 0;
+    for (const Launch& L : launches) {
+        const uint64_t c = (L.blocks * L.gpb * L.slab_bytes + 255) / 256 * 256;
+        claims += c;
+        largest = std::max(largest, c);
+    }
+    const bool concurrent = claims <= pool_cap;
+    uint64_t pool = 0;
+    for (Launch& L : launches) {
+        if (!concurrent) {
+            L.blocks = std::max<uint64_t>(1, std::min<uint64_t>(L.blocks, pool_cap / (L.gpb * L.slab_bytes)));
+            L.region = 0;
+            pool = std::max<uint64_t>(pool, L.blocks * L.gpb * L.slab_bytes);
+        } else {
+            L.region = pool;
+            pool += (L.blocks * L.gpb * L.slab_bytes + 255) / 256 * 256;
         }
-        if (ws->slab_clean < ws->slab.cap) {
-            PC_HIP(launch_fill_u32(ws->slab.as<uint32_t>(), ws->slab.cap / 4, 0, stream));
-            ws->slab_clean = ws->slab.cap;
+    }
+    if (pool > ws->slab.cap) {
+        e = ws->slab.ensure(pool);
+        if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "slab pool of %llu bytes: %s", (unsigned long long)pool,
+                                              hipGetErrorString(e));
+        ws->slab_clean = 0;
+    }
+    if (ws->slab_clean < ws->slab.cap) {
+        PC_HIP(launch_fill_u32(ws->slab.as<uint32_t>(), ws->slab.cap / 4, 0, stream));
+        ws->slab_clean = ws->slab.cap;
+    }
+    // longest buckets first; concurrently onto the least-loaded stream
+    std::vector<size_t> order(launches.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return launches[x].cost > launches[y].cost; });
+    const int ns = concurrent ? (int)std::min<size_t>(kReplayStreams, launches.size()) : 0;
+    double load[kReplayStreams] = {};
+    if (ns) {
+        PC_HIP(hipEventRecord(ws->rfork, stream));
+        for (int b = 0; b < ns; ++b) PC_HIP(hipStreamWaitEvent(ws->rstream[b], ws->rfork, 0));
+    }
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const Launch& L = launches[order[oi]];
+        hipStream_t st = stream;
+        if (ns) {
+            int b = 0;
+            for (int c = 1; c < ns; ++c)
+                if (load[c] < load[b]) b = c;
+            load[b] += L.cost;
+            st = ws->rstream[b];
         }
         StreamArgs a;
-        a.pairs = d_pairs + q;
-        a.n_pairs = (uint32_t)(e2 - q);
-        a.queue = d_status + 2 + qi;
+        a.pairs = d_pairs + L.q;
+        a.n_pairs = (uint32_t)(L.e2 - L.q);
+        a.queue = d_status + 2 + order[oi];
         a.models = d_models;
         a.idx = idx_dev;
         a.misses = misses_dev;
         a.bits = hitbits_dev;
-        a.slab = ws->slab.as<uint8_t>();
-        a.slab_bytes = slab_bytes;
-        a.epoch_base = ws->epoch + (uint32_t)q;
+        a.slab = ws->slab.as<uint8_t>() + L.region;
+        a.slab_bytes = L.slab_bytes;
+        a.epoch_base = ws->epoch + (uint32_t)L.q;
         a.elem_shift = 2;
         a.abort_flag = abort_flag_dev();
         a.status = d_status;
-        PC_HIP(launch_stream(pol, W, a, (uint32_t)blocks, stream));
-        ++qi;
-        q = e2;
-        if (qi >= 60) {
-            // more buckets than status words: drain before reusing queues
-            PC_HIP(hipStreamSynchronize(stream));
-            PC_HIP(launch_fill_u32(d_status + 2, 62, 0, stream));
-            qi = 0;
-        }
+        PC_HIP(launch_stream(L.pol, L.W, a, (uint32_t)L.blocks, st));
     }
-    ws->epoch += (uint32_t)n_pairs + 1;
+    for (int b = 0; b < ns; ++b) {
+        PC_HIP(hipEventRecord(ws->rjoin[b], ws->rstream[b]));
+        PC_HIP(hipStreamWaitEvent(stream, ws->rjoin[b], 0));
+    }
+    ws->epoch += (uint32_t)n_items + 1;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;
     PC_HIP(hipMemcpy(&status, d_status, sizeof status, hipMemcpyDeviceToHost));

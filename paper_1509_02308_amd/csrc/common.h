@@ -48,7 +48,7 @@ struct UDiv32 {
     }
 };
 
-inline UDiv32 make_udiv32(uint32_t d) {
+__host__ __device__ inline UDiv32 make_udiv32(uint32_t d) {
     uint32_t l = 0;
     while (l < 32 && (1ull << l) < d) ++l;
     UDiv32 u;

@@ -31,6 +31,8 @@ struct InferPlan;
 
 // Parallel graph branches of a batched replay.
 constexpr int kBranches = 4;
+// Streams of the materialised-trace replay's concurrent buckets.
+constexpr int kReplayStreams = 8;
 
 struct Workspace {
     int device = -1;
@@ -48,6 +50,8 @@ struct Workspace {
     bool lds_ready = false;
     hipStream_t branch[kBranches] = {};   // capture-side streams (default priority)
     hipEvent_t fork = nullptr, join[kBranches] = {};
+    hipStream_t rstream[kReplayStreams] = {};   // default priority
+    hipEvent_t rfork = nullptr, rjoin[kReplayStreams] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
     ~Workspace();
 };

@@ -133,6 +133,11 @@ Workspace::~Workspace() {
         if (branch[b]) (void)hipStreamDestroy(branch[b]);
         if (join[b]) (void)hipEventDestroy(join[b]);
     }
+    for (int b = 0; b < kReplayStreams; ++b) {
+        if (rstream[b]) (void)hipStreamDestroy(rstream[b]);
+        if (rjoin[b]) (void)hipEventDestroy(rjoin[b]);
+    }
+    if (rfork) (void)hipEventDestroy(rfork);
     if (fork) (void)hipEventDestroy(fork);
     stage.release();
     aux.release();
@@ -185,6 +190,14 @@ int workspace(Workspace** out, std::unique_lock<std::mutex>* lock) {
             if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
         }
         e = hipEventCreateWithFlags(&ws->fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+        for (int b = 0; b < kReplayStreams; ++b) {
+            e = hipStreamCreateWithFlags(&ws->rstream[b], hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+            e = hipEventCreateWithFlags(&ws->rjoin[b], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+        }
+        e = hipEventCreateWithFlags(&ws->rfork, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
         ws->lds_ready = true;
     }

@@ -50,35 +50,100 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
     const uint32_t T = m.sets;
     const uint32_t epoch = args.epoch_base + pair_index + 1;
     SetHeader* hdr = reinterpret_cast<SetHeader*>(slab);
-    uint2* ent = reinterpret_cast<uint2*>(slab + (size_t)T * sizeof(SetHeader));
     const uint64_t gmask = (W == 64) ? ~0ull : (((1ull << (W & 63)) - 1ull) << gbase);
     const bool two = (W == 64) && (a > 64);
     const bool own0 = (uint32_t)gl < a;
     const bool own1 = two && (uint32_t)(gl + 64) < a;
 
     uint64_t mt = 0, ms = 0;
-    uint32_t word = 0;
     uint32_t* bits = args.bits ? args.bits + pr.bitoff : nullptr;
     bool bad = false;
+    // a long pair, or one with a large state, may be split into parts by set
+    // (set mod nparts == part, nparts a power of two), each part holding only
+    // its own sets (slot set >> log2 nparts):
+    // sets are independent, so each part replays its own sets exactly and
+    // merges its hit bits and counts into zeroed outputs
+    const uint32_t nparts = pr.pad >> 16, part = pr.pad & 0xFFFFu;
+    const bool split = nparts > 1;
+    const uint32_t pshift = split ? (uint32_t)(__ffs((int)nparts) - 1) : 0u;   // part p keeps its sets at set >> pshift
+    const uint32_t Tl = split ? (T + nparts - 1) >> pshift : T;   // set slots of this pair or part
+    uint2* ent = reinterpret_cast<uint2*>(slab + (size_t)Tl * sizeof(SetHeader));
+    uint64_t cur_w = ~0ull;
+    uint32_t word = 0;
+    auto flush = [&]() {
+        if (bits != nullptr && gl == 0 && cur_w != ~0ull) {
+            if (split) {
+                if (word) atomicOr(bits + cur_w, word);
+            } else {
+                bits[cur_w] = word;
+            }
+        }
+    };
+    auto put_bit = [&](uint64_t k, bool hit) {
+        if ((k >> 5) != cur_w) {
+            flush();
+            cur_w = k >> 5;
+            word = 0;
+        }
+        word |= (hit ? 1u : 0u) << (k & 31);
+    };
+    // line of the previous access of this part: a repeat is a hit that
+    // leaves every policy's state as it is (the way is already the most
+    // recent one, FIFO and random replacement change nothing on a hit, and
+    // the PLRU path bits already point away from it), so it needs no state
+    // access
+    uint32_t last_line = kInvalidTag;
 
-    for (uint64_t k0 = 0; k0 < pr.len; k0 += W) {
-        int32_t mine = 0;
-        if (k0 + gl < pr.len) mine = args.idx[pr.start + k0 + gl];
-        const uint32_t nstep = (pr.len - k0 < (uint64_t)W) ? (uint32_t)(pr.len - k0) : (uint32_t)W;
+    // the trace is read V indices per lane per round (W * V per group), the
+    // next round prefetched while this one is replayed, so that a narrow
+    // group does not wait on one load per access
+    constexpr int V = (W >= 64) ? 1 : 8;
+    const uint64_t CH = (uint64_t)W * V;
+    int32_t cur[V], nxt[V];
+    auto load = [&](uint64_t c0, int32_t (&dst)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint64_t kk = c0 + (uint64_t)gl * V + v;
+            dst[v] = kk < pr.len ? args.idx[pr.start + kk] : 0;
+        }
+    };
+    load(0, cur);
+    const UDiv32 tdiv = make_udiv32(T);
+
+    for (uint64_t k0 = 0; k0 < pr.len; k0 += CH) {
+        if (k0 + CH < pr.len) load(k0 + CH, nxt);
+        const uint32_t nstep = (pr.len - k0 < CH) ? (uint32_t)(pr.len - k0) : (uint32_t)CH;
         for (uint32_t i = 0; i < nstep; ++i) {
             const uint64_t k = k0 + i;
-            const int32_t j = __shfl(mine, gbase + (int)i, kWave);
+            const uint32_t comp = i % V;
+            int32_t mv = cur[0];
+#pragma unroll
+            for (int v = 1; v < V; ++v) mv = comp == (uint32_t)v ? cur[v] : mv;
+            const int32_t j = __shfl(mv, gbase + (int)(i / V), kWave);
             bad |= j < 0;
             const uint64_t xa = pr.base + ((uint64_t)(uint32_t)(j < 0 ? 0 : j) << args.elem_shift);
             const uint32_t line = (uint32_t)(xa >> m.line_shift);
-            const uint32_t set = (uint32_t)umod64(xa >> m.unit_shift, T);
+            if (line == last_line) {
+                put_bit(k, true);
+                continue;
+            }
+            const uint32_t ux = (uint32_t)(xa >> m.unit_shift);
+            const uint32_t set = ux - tdiv.div(ux) * T;
+            if (split && (set & (nparts - 1)) != part) continue;
+            last_line = line;
 
-            // header: first lane of the group only
+            // the set's entries and (first lane) header, loaded together
+            const uint32_t lset = set >> pshift;
+            const uint64_t eb = (uint64_t)lset * a;
+            uint2 e0 = make_uint2(kInvalidTag, 0xFFu), e1 = make_uint2(kInvalidTag, 0xFFu);
+            uint2 r0 = e0, r1 = e1;
+            if (own0) r0 = ent[eb + gl];
+            if (own1) r1 = ent[eb + gl + 64];
             uint32_t h_ep = 0, h_ptr = 0;
             uint64_t h_lo = 0, h_hi = 0;
             if (gl == 0) {
-                const SetHeader h = hdr[set];
-                h_ep = (h.epoch == (kEpochTag | epoch)) ? epoch : 0u;
+                const SetHeader h = hdr[lset];
+                h_ep = (h.epoch == (kEpochTag | epoch) && (uint32_t)(h.ptr >> 32) == ~epoch) ? epoch : 0u;
                 h_ptr = (uint32_t)h.ptr;
                 h_lo = h.lo;
                 h_hi = h.hi;
@@ -93,13 +158,8 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
                 h_ptr = __shfl(h_ptr, gbase, kWave);
                 h_lo = __shfl(h_lo, gbase, kWave);
                 h_hi = __shfl(h_hi, gbase, kWave);
-            }
-
-            uint2 e0 = make_uint2(kInvalidTag, 0xFFu), e1 = make_uint2(kInvalidTag, 0xFFu);
-            const uint64_t eb = (uint64_t)set * a;
-            if (!fresh) {
-                if (own0) e0 = ent[eb + gl];
-                if (own1) e1 = ent[eb + gl + 64];
+                e0 = r0;
+                e1 = r1;
             }
             const uint64_t hm0 = __ballot(own0 && e0.x == line) & gmask;
             const uint64_t hm1 = __ballot(own1 && e1.x == line) & gmask;
@@ -181,24 +241,28 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
                 h.epoch = kEpochTag | epoch;
                 h.lo = h_lo;
                 h.hi = h_hi;
-                h.ptr = h_ptr;
-                hdr[set] = h;
+                h.ptr = (uint64_t)h_ptr | ((uint64_t)(~epoch) << 32);
+                hdr[lset] = h;
             }
 
             if (!hit) {
                 ++mt;
                 ms += (k >= pr.count_from) ? 1u : 0u;
             }
-            word |= (hit ? 1u : 0u) << (k & 31);
-            if (((k & 31) == 31) || k + 1 == pr.len) {
-                if (bits != nullptr && gl == 0) bits[k >> 5] = word;
-                word = 0;
-            }
+            put_bit(k, hit);
         }
+#pragma unroll
+        for (int v = 0; v < V; ++v) cur[v] = nxt[v];
     }
+    flush();
     if (gl == 0) {
-        args.misses[2 * (uint64_t)pr.out] = mt;
-        args.misses[2 * (uint64_t)pr.out + 1] = ms;
+        if (split) {
+            if (mt) atomicAdd((unsigned long long*)&args.misses[2 * (uint64_t)pr.out], (unsigned long long)mt);
+            if (ms) atomicAdd((unsigned long long*)&args.misses[2 * (uint64_t)pr.out + 1], (unsigned long long)ms);
+        } else {
+            args.misses[2 * (uint64_t)pr.out] = mt;
+            args.misses[2 * (uint64_t)pr.out + 1] = ms;
+        }
         if (bad) atomicOr(args.status, 2u);
     }
 }
