@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=2)
     ap.add_argument("--learned-targets", type=int, default=200)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--large-pairs", type=int, default=1_000_000)
+    ap.add_argument("--large-verify", choices=["sample", "all"], default="sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -143,6 +145,10 @@ def main():
     if not args.no_learned:
         learned = learned_leg(torch, capi, W, crows, args)
 
+    large = None
+    if args.large_pairs > 0:
+        large = large_batch_leg(torch, capi, W, args)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(crows, prows, lens, bits, bitoff, args.cpu_seconds)
@@ -172,6 +178,7 @@ def main():
         "zero_class": int(res.n_zero),
         "plain": plain,
         "learned": learned,
+        "large_batch": large,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -246,6 +253,62 @@ def learned_leg(torch, capi, W, crows, args):
             "exhaustive_time_to_params_ms": float(np.median(t_e) * 1e3),
             "replayed_accesses_per_target": acc_l / len(targets),
             "exhaustive_replayed_accesses_per_target": acc_e / len(targets)}
+
+
+def large_batch_leg(torch, capi, W, args):
+    """Large batch of materialised traces: seeded (model, trace) pairs of
+    uneven length (log-uniform 1e3..1e5 accesses, uniform-stride P-chases),
+    caches 8 KB..4 MB, a up to 128, LRU/FIFO/PLRU/RANDOM; traces generated on
+    the device (untimed), then one cache_replay_batch call is timed.  The CPU
+    oracle checks the per-access bits and both miss counts of a seeded 1%
+    sample of the pairs (all pairs' counts with --large-verify all)."""
+    import oracle as orc
+    n = args.large_pairs
+    mrows, prows = W.large_batch(n)
+    marr, parr = capi.models(mrows), capi.probes(prows)
+    lc = np.array([capi.pchase_trace_len(parr[i]) for i in range(n)], dtype=np.uint64)
+    lens, cyc = lc[:, 0], lc[:, 1]
+    total = int(lens.sum())
+    idx = torch.empty(total + 1, dtype=torch.int32, device="cuda")
+    off = capi.pchase_trace(parr, idx)
+    words = (lens + 31) // 32
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.zeros(int(words.sum()) + 1, dtype=torch.int32, device="cuda")
+    misses = torch.zeros(2 * n, dtype=torch.int64, device="cuda")
+    bases = np.array([int(p["base"]) for p in prows], np.uint64)
+    pm = np.arange(n, dtype=np.uint32)
+    capi.cache_replay_batch(marr, idx, off, bases, pm, pm, cyc, misses, bits, bitoff)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.cache_replay_batch(marr, idx, off, bases, pm, pm, cyc, misses, bits, bitoff)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    rng = np.random.default_rng(4711)
+    sample = rng.choice(n, max(1, n // 100), replace=False)
+    check = np.arange(n) if args.large_verify == "all" else sample
+    b = bits.cpu().numpy().view(np.uint32) if len(sample) else None
+    in_sample = set(sample.tolist())
+    bad = 0
+    t1 = time.perf_counter()
+    for i in check:
+        i = int(i)
+        r, p = mrows[i], prows[i]
+        om = orc.make_model(int(r["C"]), int(r["b"]), int(r["a"]), int(r["policy"]), set_shift=int(r["set_shift"]),
+                            seed=int(r["seed"]))
+        tr = orc.trace(orc.make_probe(int(p["N"]), int(p["s"]), int(p["passes"]), int(p["j0"]), int(p["base"])))
+        hits, mt, ms = orc.replay(om, tr, base=int(p["base"]), trace_id=i, count_from=int(cyc[i]))
+        ok = (int(mis[i, 0]), int(mis[i, 1])) == (mt, ms)
+        if i in in_sample:
+            w = b[int(bitoff[i]):int(bitoff[i]) + int(words[i])].astype(np.uint64)
+            got = ((w[:, None] >> np.arange(32, dtype=np.uint64)) & 1).astype(np.uint8).reshape(-1)[:int(lens[i])]
+            ok = ok and np.array_equal(got, hits)
+        bad += not ok
+    del idx, bits
+    return {"pairs": n, "accesses": total, "trace_bytes": 4 * total, "replay_s": dt,
+            "value": total / dt, "unit": "accesses/s", "verified_pairs": int(len(check)),
+            "verified_bitmaps": int(len(sample)), "mismatches": int(bad),
+            "verify_s": time.perf_counter() - t1}
 
 
 def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):

@@ -457,6 +457,36 @@ static int build_infer_plan(const pchase_observation* obs, const pchase_model* c
     return PCHASE_OK;
 }
 
+// The exact inputs that shape an inference plan, as bytes: a cached plan is
+// used only when its stored inputs equal these (the digest only finds it).
+static std::string infer_key(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
+                             int probe_select, const uint64_t* bitoff, const std::vector<uint8_t>* allow) {
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    put(&n_cands, sizeof n_cands);
+    put(&obs->n_probes, sizeof obs->n_probes);
+    put(&probe_select, sizeof probe_select);
+    const uint8_t has_cf = obs->count_from != nullptr, has_allow = allow != nullptr;
+    put(&has_cf, 1);
+    put(&has_allow, 1);
+    put(cands, n_cands * sizeof(pchase_model));
+    put(obs->probes, obs->n_probes * sizeof(pchase_probe));
+    if (has_cf) put(obs->count_from, obs->n_probes * sizeof(uint64_t));
+    put(bitoff, obs->n_probes * sizeof(uint64_t));
+    if (has_allow) put(allow->data(), allow->size());
+    return k;
+}
+
+static std::string digest_of(const std::string& blob) {
+    Digest dg;
+    dg.add(blob.data(), blob.size());
+    return dg.str();
+}
+
+// Runs a built plan and reads its result back (synchronises).
+static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pchase_result* out, uint64_t* mn_dev,
+                          uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched);
+
 // cache = false builds a one-off plan (the learned path's top-k subsets)
 static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const pchase_model* cands,
                             uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
@@ -472,21 +502,15 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
         if (rc) return rc;
         ip = once.get();
     } else {
-        // plan cache key: everything that shapes the schedule
-        Digest dg;
-        dg.add(&n_cands, sizeof n_cands);
-        dg.add(cands, n_cands * sizeof(pchase_model));
-        dg.add(obs->probes, obs->n_probes * sizeof(pchase_probe));
-        dg.add(cf.data(), cf.size() * sizeof(uint64_t));
-        dg.add(bitoff.data(), bitoff.size() * sizeof(uint64_t));
-        dg.add(&probe_select, sizeof probe_select);
-        if (allow) dg.add(allow->data(), allow->size());
-        const std::string key = dg.str();
+        std::string blob = infer_key(obs, cands, n_cands, probe_select, bitoff.data(), allow);
+        const std::string key = digest_of(blob);
         auto it = ws->plans.find(key);
-        if (it == ws->plans.end()) {
+        if (it == ws->plans.end() || it->second->key != blob) {
             std::unique_ptr<InferPlan> np;
             int rc = build_infer_plan(obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &np);
             if (rc) return rc;
+            np->key = std::move(blob);
+            np->cached = true;
             if (ws->plans.size() > 16) ws->plans.clear();
             ip = np.get();
             ws->plans[key] = std::move(np);
@@ -494,6 +518,12 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
             ip = it->second.get();
         }
     }
+    return run_infer_plan(ws, ip, bits, out, mn_dev, zero_host, stream, replayed, sched);
+}
+
+static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pchase_result* out, uint64_t* mn_dev,
+                          uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched) {
+    const uint32_t n_cands = ip->n_cands;
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
@@ -502,7 +532,7 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,
-                            sched, stream, tail, "argmin");
+                            sched, stream, tail, "argmin", ip->cached);
     if (rc) return rc;
     ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
     PC_HIP(hipMemcpyAsync(hr, ip->d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));
@@ -539,6 +569,24 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     if (mode == PCHASE_LEARNED && (!net || topk == 0)) return set_error(PCHASE_EINVAL, "LEARNED needs a network and topk >= 1");
     if (n_cands == 0) return set_error(PCHASE_EINVAL, "no candidates");
     if (zero_host && (n_cands + 31) / 32 * 4 > 4096 - 256) return set_error(PCHASE_ERANGE, "zero-class bitmap too large");
+    if (mode == PCHASE_EXHAUSTIVE && obs->bits_dev && !obs->lat_dev && obs->bitoff && obs->probes && obs->n_probes) {
+        // repeated inference on the same inputs: the cached plan (built, and
+        // so validated, for exactly these inputs) runs without re-validation
+        Workspace* ws;
+        std::unique_lock<std::mutex> lk;
+        int rc = workspace(&ws, &lk);
+        if (rc) return rc;
+        const std::string blob = infer_key(obs, cands, n_cands, probe_select, obs->bitoff, nullptr);
+        auto it = ws->plans.find(digest_of(blob));
+        if (it != ws->plans.end() && it->second->key == blob) {
+            out->threshold_used = 0xFFFFFFFFu;
+            out->fallback = 0;
+            uint64_t replayed = 0;
+            rc = run_infer_plan(ws, it->second.get(), obs->bits_dev, out, mn_dev, zero_host, stream, &replayed, sched);
+            out->replayed_accesses = replayed;
+            return rc;
+        }
+    }
     std::vector<DevModel> dm;
     std::vector<DevProbe> dp;
     std::vector<uint64_t> len;

@@ -39,6 +39,7 @@ struct SweepPlan {
     // captured batched run
     hipGraphExec_t gexec = nullptr;
     std::string gkey;
+    int strategy = 0;                // branch strategy of gexec
     ~SweepPlan();
 };
 
@@ -50,12 +51,17 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models,
 // Runs the plan: zeroes `counters` (n_counters words) and the bitmap ranges
 // (when clear_bits), then replays every job.  `tail` (may be empty) is
 // enqueued after the replay, inside the same graph.
+// With autotune (plans that are cached and run again), the first batched
+// run captures every branch strategy, times each and keeps the fastest.
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
-                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key);
+                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key,
+                   bool autotune = false);
 
 // Cached schedule + score buffers of one inference problem.
 struct InferPlan {
+    std::string key;                // the exact inputs the plan was built for
+    bool cached = false;            // kept for later calls (worth autotuning)
     SweepPlan sweep;
     std::vector<uint64_t> n_host;   // compared accesses per candidate
     DevBuf dev;                     // m | n | zero bits | argmin out

@@ -21,13 +21,22 @@
 namespace pc {
 
 void Digest::add(const void* p, size_t n) {
+    // eight bytes per step, two independent multiply-xorshift lanes
     const uint8_t* c = static_cast<const uint8_t*>(p);
-    for (size_t i = 0; i < n; ++i) {
-        a = (a ^ c[i]) * 1099511628211ull;
-        b = (b + c[i] + 1) * 0xFF51AFD7ED558CCDull;
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, c + i, 8);
+        a = (a ^ w) * 0x9E3779B97F4A7C15ull;
+        a ^= a >> 32;
+        b = (b + w) * 0xFF51AFD7ED558CCDull;
         b ^= b >> 29;
     }
-    a ^= n;
+    uint64_t t = 0;
+    for (size_t k = 0; i < n; ++i, ++k) t |= (uint64_t)c[i] << (8 * k);
+    a = (a ^ t ^ n) * 0x9E3779B97F4A7C15ull;
+    b = (b + t + n) * 0xC4CEB9FE1A85EC53ull;
+    b ^= b >> 33;
 }
 
 std::string Digest::str() const {
@@ -222,29 +231,48 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
 // persistent kernel each, are spread over parallel branches (least-loaded
 // branch first, largest bucket first) so that one bucket's tail overlaps the
 // next bucket's work; the branches join before the tail.
+// Branch assignment strategies the autotuner tries (strategy 0 is the
+// untuned default): 0 greedy over 4 branches by estimated cost; 1 the same
+// with LDS-class buckets weighted 3x (their occupancy is LDS-bound); 2 greedy
+// over 2 branches; 3 one branch; 4 LDS-class buckets each on a branch of
+// their own first, then the rest greedily.
+constexpr int kStrategies = 5;
+
 static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters,
                            uint64_t n_counters, uint32_t* bits, bool clear_bits, hipStream_t s,
-                           const std::function<hipError_t(hipStream_t)>& tail) {
+                           const std::function<hipError_t(hipStream_t)>& tail, int strategy = 0) {
     const uint32_t nq = (uint32_t)plan->batched.size() + 2;
     PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, s));
     PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
     if (clear_bits && bits)
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
-    const int nb = (int)std::min<size_t>(kBranches, plan->batched.size());
+    const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
+    const int nb = (int)std::min<size_t>(want, plan->batched.size());
     if (nb > 1) {
         PC_HIP(hipEventRecord(ws->fork, s));
         for (int b = 0; b < nb; ++b) PC_HIP(hipStreamWaitEvent(ws->branch[b], ws->fork, 0));
     }
+    auto lds_class = [](const Bucket& bk) { return bk.cls == kAMap || bk.cls == kALds; };
+    auto weight = [&](const Bucket& bk) { return (strategy == 1 && lds_class(bk)) ? 3.0 * bk.cost : bk.cost; };
     std::vector<size_t> idx(plan->batched.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return plan->batched[x].cost > plan->batched[y].cost; });
+    std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+        const Bucket &bx = plan->batched[x], &by = plan->batched[y];
+        if (strategy == 4 && lds_class(bx) != lds_class(by)) return lds_class(bx);
+        return weight(bx) > weight(by);
+    });
     std::vector<double> load(nb > 1 ? nb : 1, 0.0);
+    int next_own = 0;
     for (size_t qi : idx) {
         const Bucket& bk = plan->batched[qi];
         int br = 0;
-        for (int b = 1; b < (int)load.size(); ++b)
-            if (load[b] < load[br]) br = b;
-        load[br] += bk.cost;
+        if (strategy == 4 && lds_class(bk) && next_own < (int)load.size()) {
+            br = next_own++;
+        } else {
+            for (int b = 1; b < (int)load.size(); ++b)
+                if (load[b] < load[br]) br = b;
+        }
+        load[br] += weight(bk);
         hipStream_t bs = nb > 1 ? ws->branch[br] : s;
         SweepArgs a;
         a.tasks = plan->d_lpt + bk.first;
@@ -284,7 +312,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
 
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
-                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key) {
+                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key, bool autotune) {
     if (mode == PCHASE_PLAIN) {
         const uint32_t nq = (uint32_t)plan->batched.size() + 2;
         PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, stream));
@@ -318,7 +346,9 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
         return PCHASE_OK;
     }
 
-    // batched: capture once per (outputs, tail) and replay the graph
+    // batched: capture once per (outputs, tail) and replay the graph; with
+    // autotune, every branch strategy is captured and timed and the fastest
+    // graph is kept
     char kb[160];
     snprintf(kb, sizeof kb, "%d|%p|%llu|%p|%d|", (int)score, (void*)counters, (unsigned long long)n_counters,
              (void*)bits, (int)clear_bits);
@@ -328,25 +358,75 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             (void)hipGraphExecDestroy(plan->gexec);
             plan->gexec = nullptr;
         }
-        hipStream_t cs;
-        PC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        int rc = PCHASE_OK;
-        if (e == hipSuccess) rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, cs, tail);
-        hipError_t e2 = hipStreamEndCapture(cs, &g);
-        (void)hipStreamDestroy(cs);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
-        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            plan->gexec = nullptr;
-            return hip_fail(e, "hipGraphInstantiate");
+        auto capture = [&](int strategy, hipGraphExec_t* out) -> int {
+            hipStream_t cs;
+            PC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            int rc = PCHASE_OK;
+            if (e == hipSuccess)
+                rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, cs, tail, strategy);
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            (void)hipStreamDestroy(cs);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+            e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                *out = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            return PCHASE_OK;
+        };
+        if (!autotune || plan->batched.size() < 2) {
+            int rc = capture(0, &plan->gexec);
+            if (rc) return rc;
+            plan->strategy = 0;
+        } else {
+            hipEvent_t t0, t1;
+            PC_HIP(hipEventCreate(&t0));
+            PC_HIP(hipEventCreate(&t1));
+            float best_ms = 0;
+            for (int st = 0; st < kStrategies; ++st) {
+                hipGraphExec_t ge = nullptr;
+                int rc = capture(st, &ge);
+                if (rc) {
+                    (void)hipEventDestroy(t0);
+                    (void)hipEventDestroy(t1);
+                    return rc;
+                }
+                float ms = 0;
+                hipError_t e = hipGraphLaunch(ge, stream);   // warm
+                for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+                    e = hipEventRecord(t0, stream);
+                    if (e == hipSuccess) e = hipGraphLaunch(ge, stream);
+                    if (e == hipSuccess) e = hipEventRecord(t1, stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(t1);
+                    float m = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&m, t0, t1);
+                    if (e == hipSuccess && (r == 0 || m < ms)) ms = m;
+                }
+                if (e != hipSuccess) {
+                    (void)hipGraphExecDestroy(ge);
+                    (void)hipEventDestroy(t0);
+                    (void)hipEventDestroy(t1);
+                    return hip_fail(e, "autotune run");
+                }
+                if (!plan->gexec || ms < best_ms) {
+                    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+                    plan->gexec = ge;
+                    plan->strategy = st;
+                    best_ms = ms;
+                } else {
+                    (void)hipGraphExecDestroy(ge);
+                }
+            }
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
         }
         plan->gkey = key;
     }
