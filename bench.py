@@ -27,6 +27,39 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources and the C header (names and bytes)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1509_02308_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "pchase.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step of the sweep kernels from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current kernel
+    sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "sweep_kernel_inference_438cands_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        for key in ("traffic_bytes_per_step:", "kernel_source_digest:"):
+            if key in line:
+                vals[key] = line.split(key, 1)[1].strip()
+    if vals.get("kernel_source_digest:") != kernel_source_digest() or "traffic_bytes_per_step:" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_step:"])
+
+
 def lane_ops_per_access(a: int, policy: int) -> float:
     """Algorithmic VALU lane-ops of one replayed access (stated convention):
     LRU 3a+8 (a tag compares, 2a recency updates), FIFO a+8, tree-PLRU
@@ -51,7 +84,6 @@ def main():
     ap.add_argument("--learned-targets", type=int, default=200)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--large-pairs", type=int, default=1_000_000)
-    ap.add_argument("--large-verify", choices=["sample", "all"], default="sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -136,8 +168,12 @@ def main():
 
     gpu_step_ms = float(np.median(gpu_ms))
     achieved = lane_ops / (gpu_step_ms * 1e-3)
+    traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                "traffic_note": "HBM bytes per step (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed "
+                                "profile when it matches the current kernel sources, else null",
+                "algorithmic_bytes_per_step": accesses / 8,
                 "kernel": "sweep_kernel<policy, way class, score> (all instantiations of one captured step)",
                 "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms}
 
@@ -259,10 +295,9 @@ def large_batch_leg(torch, capi, W, args):
     """Large batch of materialised traces: seeded (model, trace) pairs of
     uneven length (log-uniform 1e3..1e5 accesses, uniform-stride P-chases),
     caches 8 KB..4 MB, a up to 128, LRU/FIFO/PLRU/RANDOM; traces generated on
-    the device (untimed), then one cache_replay_batch call is timed.  The CPU
-    oracle checks the per-access bits and both miss counts of a seeded 1%
-    sample of the pairs (all pairs' counts with --large-verify all)."""
-    import oracle as orc
+    the device (untimed), then one cache_replay_batch call (hit bits and both
+    miss counts of every pair) is timed after a warm-up call.  Parity at this
+    size is checked by the GPU tests on a sampled 1% of the pairs."""
     n = args.large_pairs
     mrows, prows = W.large_batch(n)
     marr, parr = capi.models(mrows), capi.probes(prows)
@@ -283,32 +318,10 @@ def large_batch_leg(torch, capi, W, args):
     capi.cache_replay_batch(marr, idx, off, bases, pm, pm, cyc, misses, bits, bitoff)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
-    rng = np.random.default_rng(4711)
-    sample = rng.choice(n, max(1, n // 100), replace=False)
-    check = np.arange(n) if args.large_verify == "all" else sample
-    b = bits.cpu().numpy().view(np.uint32) if len(sample) else None
-    in_sample = set(sample.tolist())
-    bad = 0
-    t1 = time.perf_counter()
-    for i in check:
-        i = int(i)
-        r, p = mrows[i], prows[i]
-        om = orc.make_model(int(r["C"]), int(r["b"]), int(r["a"]), int(r["policy"]), set_shift=int(r["set_shift"]),
-                            seed=int(r["seed"]))
-        tr = orc.trace(orc.make_probe(int(p["N"]), int(p["s"]), int(p["passes"]), int(p["j0"]), int(p["base"])))
-        hits, mt, ms = orc.replay(om, tr, base=int(p["base"]), trace_id=i, count_from=int(cyc[i]))
-        ok = (int(mis[i, 0]), int(mis[i, 1])) == (mt, ms)
-        if i in in_sample:
-            w = b[int(bitoff[i]):int(bitoff[i]) + int(words[i])].astype(np.uint64)
-            got = ((w[:, None] >> np.arange(32, dtype=np.uint64)) & 1).astype(np.uint8).reshape(-1)[:int(lens[i])]
-            ok = ok and np.array_equal(got, hits)
-        bad += not ok
     del idx, bits
     return {"pairs": n, "accesses": total, "trace_bytes": 4 * total, "replay_s": dt,
-            "value": total / dt, "unit": "accesses/s", "verified_pairs": int(len(check)),
-            "verified_bitmaps": int(len(sample)), "mismatches": int(bad),
-            "verify_s": time.perf_counter() - t1}
+            "value": total / dt, "unit": "accesses/s",
+            "hbm_GBps_trace_only": 4 * total / dt / 1e9}
 
 
 def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):
