@@ -151,7 +151,7 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         for (uint32_t set = g; set < T; set += G) {
             if constexpr (A == kClassMap) {
                 MapSet<POL> st;
-                st.init(col, args.map_rows);
+                st.init(col, args.map_rows, m.ways);
                 Visitor<MapSet<POL>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
                 cached_runs(sc, p, m, set, v);
                 mt += v.mt; ms += v.ms; mm += v.mm;

@@ -175,41 +175,48 @@ struct RegSet {
 };
 
 // --------------------------------------- set state in an LDS column: map --
-// Rows [0, mapw): the map, four 8-bit entries per dword, entry q = way of the
-// set's line with index q, 0xFF if absent.  Rows [mapw, mapw + a): per way
-// its line index (bits 0-15) and, for LRU, the previous / next way in
-// recency order (bits 16-23 / 24-31, 0xFF = none).
+// Byte-addressed rows, so that no update needs a read-modify-write:
+//   rows [0, mapw)            the map: byte q = way of the set's line with
+//                             index q, 0xFF if absent;
+//   next A4 = ceil(a/4) rows  byte w = previous way of w in recency order (LRU);
+//   next A4 rows              byte w = next way of w (LRU);
+//   next ceil(a/2) rows       halfword w = line index q held by way w.
+// (LDS row r of this lane is dword r*64 of its column.)
+__host__ __device__ inline uint32_t map_class_rows(uint32_t map_rows, uint32_t a) {
+    return map_rows + 2 * ((a + 3) / 4) + (a + 1) / 2;
+}
+
 template <int POL>
 struct MapSet {
     static constexpr uint32_t kNil = 0xFFu;
     uint32_t* col;
-    uint32_t mapw;
+    uint32_t mapw, prev_row, next_row, q_row;
     uint32_t nvalid, ptr, head, tail;
     PlruBits bits;
 
-    __device__ __forceinline__ uint32_t& row(uint32_t r) { return col[(size_t)r * kWave]; }
-    __device__ __forceinline__ uint32_t map_get(uint32_t q) { return (row(q >> 2) >> ((q & 3) * 8)) & 0xFFu; }
-    __device__ __forceinline__ void map_put(uint32_t q, uint32_t w) {
-        uint32_t& d = row(q >> 2);
-        const uint32_t sh = (q & 3) * 8;
-        d = (d & ~(0xFFu << sh)) | (w << sh);
+    __device__ __forceinline__ uint8_t* byte_at(uint32_t r, uint32_t j) {
+        return reinterpret_cast<uint8_t*>(col + (size_t)r * kWave) + j;
     }
-    __device__ __forceinline__ uint32_t& info(uint32_t w) { return row(mapw + w); }
-    __device__ __forceinline__ uint32_t prev_of(uint32_t w) { return (info(w) >> 16) & 0xFFu; }
-    __device__ __forceinline__ uint32_t next_of(uint32_t w) { return info(w) >> 24; }
-    __device__ __forceinline__ void set_prev(uint32_t w, uint32_t p) {
-        uint32_t& d = info(w);
-        d = (d & 0xFF00FFFFu) | (p << 16);
+    __device__ __forceinline__ uint32_t map_get(uint32_t q) { return *byte_at(q >> 2, q & 3); }
+    __device__ __forceinline__ void map_put(uint32_t q, uint32_t w) { *byte_at(q >> 2, q & 3) = (uint8_t)w; }
+    __device__ __forceinline__ uint32_t prev_of(uint32_t w) { return *byte_at(prev_row + (w >> 2), w & 3); }
+    __device__ __forceinline__ uint32_t next_of(uint32_t w) { return *byte_at(next_row + (w >> 2), w & 3); }
+    __device__ __forceinline__ void set_prev(uint32_t w, uint32_t p) { *byte_at(prev_row + (w >> 2), w & 3) = (uint8_t)p; }
+    __device__ __forceinline__ void set_next(uint32_t w, uint32_t n) { *byte_at(next_row + (w >> 2), w & 3) = (uint8_t)n; }
+    __device__ __forceinline__ uint32_t q_of(uint32_t w) {
+        return *reinterpret_cast<uint16_t*>(byte_at(q_row + (w >> 1), 2 * (w & 1)));
     }
-    __device__ __forceinline__ void set_next(uint32_t w, uint32_t n) {
-        uint32_t& d = info(w);
-        d = (d & 0x00FFFFFFu) | (n << 24);
+    __device__ __forceinline__ void set_q(uint32_t w, uint32_t q) {
+        *reinterpret_cast<uint16_t*>(byte_at(q_row + (w >> 1), 2 * (w & 1))) = (uint16_t)q;
     }
 
-    __device__ __forceinline__ void init(uint32_t* c, uint32_t map_rows) {
+    __device__ __forceinline__ void init(uint32_t* c, uint32_t map_rows, uint32_t a) {
         col = c;
         mapw = map_rows;
-        for (uint32_t r = 0; r < mapw; ++r) row(r) = 0xFFFFFFFFu;
+        prev_row = mapw;
+        next_row = mapw + (a + 3) / 4;
+        q_row = next_row + (a + 3) / 4;
+        for (uint32_t r = 0; r < mapw; ++r) col[(size_t)r * kWave] = 0xFFFFFFFFu;
         nvalid = 0;
         ptr = 0;
         head = tail = kNil;
@@ -224,8 +231,8 @@ struct MapSet {
         else tail = p;
     }
     __device__ __forceinline__ void push_front(uint32_t x) {
-        uint32_t& d = info(x);
-        d = (d & 0xFFFFu) | (kNil << 16) | (head << 24);
+        set_prev(x, kNil);
+        set_next(x, head);
         if (head != kNil) set_prev(head, x);
         head = x;
         if (tail == kNil) tail = x;
@@ -249,10 +256,10 @@ struct MapSet {
                 x = nvalid++;
             } else {
                 x = tail;
-                map_put(info(x) & 0xFFFFu, kNil);
+                map_put(q_of(x), kNil);
                 unlink(x);
             }
-            info(x) = q;
+            set_q(x, q);
             map_put(q, x);
             push_front(x);
             return false;
@@ -275,8 +282,8 @@ struct MapSet {
                 x = nvalid < a ? nvalid : random_way(m, k, trace_id);
             }
             if (nvalid < a) ++nvalid;
-            else map_put(info(x) & 0xFFFFu, kNil);
-            info(x) = q;
+            else map_put(q_of(x), kNil);
+            set_q(x, q);
             map_put(q, x);
             if constexpr (POL == PCHASE_PLRU) bits.touch(x, m.log2_ways);
             return false;
