@@ -115,7 +115,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         const DevModel& m = models[tasks[i].model];
         if (tcls[i] == kAMap) {
             *map_rows = tmap[i];
-            *lds_rows = map_class_rows(tmap[i], m.ways);
+            *lds_rows = map_class_rows(tmap[i], m.ways, (int)m.policy);
         } else if (tcls[i] == kALds) {
             *map_rows = 0;
             *lds_rows = m.ways + (m.ways + 3) / 4;
@@ -140,7 +140,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         if (b.cls == kAMap || b.cls == kALds) {
             uint32_t amax = 0;
             for (uint32_t i = b.first; i < b.first + b.count; ++i) amax = std::max(amax, models[tasks[i].model].ways);
-            b.lds_rows = b.cls == kAMap ? map_class_rows(b.map_rows, amax) : amax + (amax + 3) / 4;
+            b.lds_rows = b.cls == kAMap ? map_class_rows(b.map_rows, amax, b.pol) : amax + (amax + 3) / 4;
         }
 
     // --- batched order: group by (policy, class), longest first within a group
@@ -183,7 +183,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     }
     for (size_t k = 0; k < plan->batched.size(); ++k) {
         Bucket& b = plan->batched[k];
-        if (b.cls == kAMap) b.lds_rows = map_class_rows(b.map_rows, bucket_amax[k]);
+        if (b.cls == kAMap) b.lds_rows = map_class_rows(b.map_rows, bucket_amax[k], b.pol);
         else if (b.cls == kALds) b.lds_rows = bucket_amax[k] + (bucket_amax[k] + 3) / 4;
     }
 

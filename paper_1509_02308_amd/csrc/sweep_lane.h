@@ -178,12 +178,15 @@ struct RegSet {
 // Byte-addressed rows, so that no update needs a read-modify-write:
 //   rows [0, mapw)            the map: byte q = way of the set's line with
 //                             index q, 0xFF if absent;
-//   next A4 = ceil(a/4) rows  byte w = previous way of w in recency order (LRU);
-//   next A4 rows              byte w = next way of w (LRU);
-//   next ceil(a/2) rows       halfword w = line index q held by way w.
+//   LRU only, A4 = ceil(a/4) rows each: byte w = previous, then next, way of
+//                             w in recency order;
+//   then the line index q held by way w: one byte per way when the map has
+//                             at most 256 entries, else a halfword.
 // (LDS row r of this lane is dword r*64 of its column.)
-__host__ __device__ inline uint32_t map_class_rows(uint32_t map_rows, uint32_t a) {
-    return map_rows + 2 * ((a + 3) / 4) + (a + 1) / 2;
+__host__ __device__ inline bool map_q8(uint32_t map_rows) { return 4 * map_rows <= 256; }
+__host__ __device__ inline uint32_t map_class_rows(uint32_t map_rows, uint32_t a, int policy) {
+    const uint32_t links = policy == PCHASE_LRU ? 2 * ((a + 3) / 4) : 0;
+    return map_rows + links + (map_q8(map_rows) ? (a + 3) / 4 : (a + 1) / 2);
 }
 
 template <int POL>
@@ -191,6 +194,7 @@ struct MapSet {
     static constexpr uint32_t kNil = 0xFFu;
     uint32_t* col;
     uint32_t mapw, prev_row, next_row, q_row;
+    bool q8;
     uint32_t nvalid, ptr, head, tail;
     PlruBits bits;
 
@@ -204,18 +208,21 @@ struct MapSet {
     __device__ __forceinline__ void set_prev(uint32_t w, uint32_t p) { *byte_at(prev_row + (w >> 2), w & 3) = (uint8_t)p; }
     __device__ __forceinline__ void set_next(uint32_t w, uint32_t n) { *byte_at(next_row + (w >> 2), w & 3) = (uint8_t)n; }
     __device__ __forceinline__ uint32_t q_of(uint32_t w) {
+        if (q8) return *byte_at(q_row + (w >> 2), w & 3);
         return *reinterpret_cast<uint16_t*>(byte_at(q_row + (w >> 1), 2 * (w & 1)));
     }
     __device__ __forceinline__ void set_q(uint32_t w, uint32_t q) {
-        *reinterpret_cast<uint16_t*>(byte_at(q_row + (w >> 1), 2 * (w & 1))) = (uint16_t)q;
+        if (q8) *byte_at(q_row + (w >> 2), w & 3) = (uint8_t)q;
+        else *reinterpret_cast<uint16_t*>(byte_at(q_row + (w >> 1), 2 * (w & 1))) = (uint16_t)q;
     }
 
     __device__ __forceinline__ void init(uint32_t* c, uint32_t map_rows, uint32_t a) {
         col = c;
         mapw = map_rows;
+        q8 = map_q8(map_rows);
         prev_row = mapw;
         next_row = mapw + (a + 3) / 4;
-        q_row = next_row + (a + 3) / 4;
+        q_row = POL == PCHASE_LRU ? next_row + (a + 3) / 4 : mapw;
         for (uint32_t r = 0; r < mapw; ++r) col[(size_t)r * kWave] = 0xFFFFFFFFu;
         nvalid = 0;
         ptr = 0;
