@@ -39,20 +39,36 @@ struct PlruBits {
         if (n < 64) lo = (lo & ~(1ull << n)) | ((uint64_t)v << n);
         else hi = (hi & ~(1ull << (n - 64))) | ((uint64_t)v << (n - 64));
     }
-    // a use of way x makes every node on its path point to the other child
-    __device__ __forceinline__ void touch(uint32_t x, uint32_t depth) {
-        if (depth <= 6) {
-            // all a-1 <= 63 nodes sit in `lo`: build the path's mask and
-            // values, then merge them in one step
-            uint64_t mask = 0, val = 0;
-            uint32_t node = 0;
-            for (uint32_t d = 0; d < depth; ++d) {
+    // a use of way x makes every node on its path point to the other child.
+    // The node of level d on the path is 2^d - 1 + (x >> (depth - d)) (heap
+    // order is level order) and the direction taken there is bit
+    // depth-1-d of x, so all path bits follow from x without a chain; up to
+    // depth MAXD <= 6 every node sits in `lo`.
+    template <int MAXD>
+    __device__ __forceinline__ void touch_upto(uint32_t x, uint32_t depth) {
+        uint64_t mask = 0, val = 0;
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d) {
+            if (d < (int)depth) {
+                const uint32_t node = (1u << d) - 1u + (x >> (depth - d));
                 const uint32_t dir = (x >> (depth - 1 - d)) & 1u;
                 mask |= 1ull << node;
                 val |= (uint64_t)(dir ^ 1u) << node;
-                node = 2 * node + 1 + dir;
             }
-            lo = (lo & ~mask) | val;
+        }
+        lo = (lo & ~mask) | val;
+    }
+    template <int MAXD>
+    __device__ __forceinline__ uint32_t victim_upto(uint32_t depth, uint32_t a) const {
+        uint32_t node = 0;
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < (int)depth) node = 2 * node + 1 + ((uint32_t)(lo >> node) & 1u);
+        return node - (a - 1);
+    }
+    __device__ __forceinline__ void touch(uint32_t x, uint32_t depth) {
+        if (depth <= 6) {
+            touch_upto<6>(x, depth);
             return;
         }
         uint32_t node = 0;
@@ -63,36 +79,40 @@ struct PlruBits {
         }
     }
     __device__ __forceinline__ uint32_t victim(uint32_t depth, uint32_t a) const {
+        if (depth <= 6) return victim_upto<6>(depth, a);
         uint32_t node = 0;
-        if (depth <= 6) {
-            for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + ((uint32_t)(lo >> node) & 1u);
-        } else {
-            for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + get(node);
-        }
+        for (uint32_t d = 0; d < depth; ++d) node = 2 * node + 1 + get(node);
         return node - (a - 1);
     }
 };
 
-// k < 2^32 (traces are shorter than 2^32 accesses): the counter is
-// (k, 0, trace_id, 0)
 __device__ __forceinline__ uint32_t random_way(const DevModel& m, uint32_t k, uint32_t trace_id) {
     return philox_x(k, 0u, trace_id, 0u, m.seed_lo, m.seed_hi) % m.ways;
 }
 
 // ----------------------------------------------- set state in registers --
+template <int A>
+struct Log2Of {
+    static constexpr int v = A <= 1 ? 0 : 1 + Log2Of<(A > 1 ? A / 2 : 1)>::v;
+};
+template <>
+struct Log2Of<1> {
+    static constexpr int v = 0;
+};
+
 template <int POL, int A>
 struct RegSet {
     uint32_t tag[A];
-    uint32_t age[A];  // LRU recency rank (0 = most recent); 0xFF = empty way
-    uint32_t nvalid;  // ways fill in index order, so ways < nvalid are valid
-    uint32_t ptr;     // FIFO: next way to replace
+    uint32_t stamp[A];  // LRU: trace index of the way's last use (distinct, so the minimum is the LRU way)
+    uint32_t nvalid;    // ways fill in index order, so ways < nvalid are valid
+    uint32_t ptr;       // FIFO: next way to replace
     PlruBits bits;
 
     __device__ __forceinline__ void init() {
 #pragma unroll
         for (int w = 0; w < A; ++w) {
             tag[w] = kInvalidTag;
-            age[w] = 0xFFu;
+            stamp[w] = 0;
         }
         nvalid = 0;
         ptr = 0;
@@ -103,44 +123,33 @@ struct RegSet {
                                            uint32_t trace_id) {
         const uint32_t a = m.ways;
         int hw = -1;
-        uint32_t vic = 0;
 #pragma unroll
-        for (int w = 0; w < A; ++w) {
-            if (w < (int)a) {
-                if (tag[w] == line) hw = w;
-                if constexpr (POL == PCHASE_LRU) {
-                    if (age[w] == a - 1) vic = (uint32_t)w;
-                }
-            }
-        }
+        for (int w = 0; w < A; ++w)
+            if (w < (int)a && tag[w] == line) hw = w;
         const bool hit = hw >= 0;
         if constexpr (POL == PCHASE_LRU) {
-            uint32_t x, ax = 0;
-#pragma unroll
-            for (int w = 0; w < A; ++w)
-                if (w == hw) ax = age[w];
+            uint32_t x;
             if (hit) {
                 x = (uint32_t)hw;
             } else if (nvalid < a) {
-                x = nvalid;
-                ax = nvalid;
-                ++nvalid;
+                x = nvalid++;
             } else {
-                x = vic;
-                ax = a - 1;
+                // all ways valid: the least recently used is the oldest stamp
+                x = 0;
+                uint32_t old = stamp[0];
+#pragma unroll
+                for (int w = 1; w < A; ++w)
+                    if (w < (int)a && stamp[w] < old) {
+                        old = stamp[w];
+                        x = (uint32_t)w;
+                    }
             }
 #pragma unroll
-            for (int w = 0; w < A; ++w) {
-                if (w < (int)a) {
-                    uint32_t g = age[w];
-                    g += (g < ax) ? 1u : 0u;
-                    if ((uint32_t)w == x) {
-                        g = 0;
-                        tag[w] = line;
-                    }
-                    age[w] = g;
+            for (int w = 0; w < A; ++w)
+                if ((uint32_t)w == x) {
+                    stamp[w] = k;
+                    tag[w] = line;
                 }
-            }
         } else if constexpr (POL == PCHASE_FIFO) {
             if (!hit) {
                 uint32_t x = ptr;
@@ -150,11 +159,12 @@ struct RegSet {
                     if ((uint32_t)w == x) tag[w] = line;
             }
         } else if constexpr (POL == PCHASE_PLRU) {
+            constexpr int D = Log2Of<A>::v;
             uint32_t x;
             if (hit) x = (uint32_t)hw;
             else if (nvalid < a) x = nvalid++;
-            else x = bits.victim(m.log2_ways, a);
-            bits.touch(x, m.log2_ways);
+            else x = bits.victim_upto<D>(m.log2_ways, a);
+            bits.touch_upto<D>(x, m.log2_ways);
             if (!hit) {
 #pragma unroll
                 for (int w = 0; w < A; ++w)
