@@ -19,6 +19,8 @@
 // or-ed into a caller bitmap.  In scoring mode the lane compares its
 // decisions with an observed bitmap instead and accumulates mismatches per
 // candidate model.
+#include <type_traits>
+
 #include "sweep_lane.h"
 
 namespace pc {
@@ -65,21 +67,21 @@ __device__ __forceinline__ void or_run(uint32_t* w, uint32_t k0, uint32_t r, boo
         if (!hit) mask &= ~1ull;
         mask <<= (k0 & 31);
         const uint32_t word = k0 >> 5;
-        if ((uint32_t)mask) atomicOr(w + word, (uint32_t)mask);
+        atomicOr(w + word, (uint32_t)mask);   // or-ing 0 changes nothing: no branch
         if (mask >> 32) atomicOr(w + word + 1, (uint32_t)(mask >> 32));
     } else {
         or_bits(w, hit ? k0 : k0 + 1, k0 + r);
     }
 }
 
-template <class S, bool SCORE>
+template <class S, bool SCORE, bool BM>
 struct Visitor {
     S* st;
     const DevModel* m;
     uint32_t trace_id;
     uint32_t cf;
     uint32_t* bits;   // memory bitmap of the job (observed or output), or null
-    uint32_t* bm;     // LDS bitmap of the job, or null
+    uint32_t* bm;     // LDS bitmap of the job (BM)
     uint32_t mt = 0, ms = 0, mm = 0;
     __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint32_t k0, uint32_t r) {
         const bool hit = st->access(line, q, *m, k0, trace_id);
@@ -87,7 +89,7 @@ struct Visitor {
             ++mt;
             ms += (k0 >= cf) ? 1u : 0u;
         }
-        if (bm != nullptr) {
+        if constexpr (BM) {
             or_run(bm, k0, r, hit);
         } else if constexpr (SCORE) {
             if (k0 >= cf) {
@@ -148,27 +150,33 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         const uint32_t cf = job.count_from < len ? (uint32_t)job.count_from : len;
         SweepCache sc;
         sweep_cache(sc, p, m);
-        for (uint32_t set = g; set < T; set += G) {
-            if constexpr (A == kClassMap) {
-                MapSet<POL> st;
-                st.init(col, args.map_rows, m.ways);
-                Visitor<MapSet<POL>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
-                cached_runs(sc, p, m, set, v);
-                mt += v.mt; ms += v.ms; mm += v.mm;
-            } else if constexpr (A == kClassScan) {
-                ScanSet<POL> st;
-                st.init(col, m.ways);
-                Visitor<ScanSet<POL>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
-                cached_runs(sc, p, m, set, v);
-                mt += v.mt; ms += v.ms; mm += v.mm;
-            } else {
-                RegSet<POL, A> st;
-                st.init();
-                Visitor<RegSet<POL, A>, SCORE> v{&st, &m, job.trace_id, cf, bits, jbm};
-                cached_runs(sc, p, m, set, v);
-                mt += v.mt; ms += v.ms; mm += v.mm;
+        // the bitmap choice is uniform over the task: branch once, not per run
+        auto sets = [&](auto bm_tag) {
+            constexpr bool BM = decltype(bm_tag)::value;
+            for (uint32_t set = g; set < T; set += G) {
+                if constexpr (A == kClassMap) {
+                    MapSet<POL> st;
+                    st.init(col, args.map_rows, m.ways);
+                    Visitor<MapSet<POL>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
+                    cached_runs(sc, p, m, set, v);
+                    mt += v.mt; ms += v.ms; mm += v.mm;
+                } else if constexpr (A == kClassScan) {
+                    ScanSet<POL> st;
+                    st.init(col, m.ways);
+                    Visitor<ScanSet<POL>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
+                    cached_runs(sc, p, m, set, v);
+                    mt += v.mt; ms += v.ms; mm += v.mm;
+                } else {
+                    RegSet<POL, A> st;
+                    st.init();
+                    Visitor<RegSet<POL, A>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
+                    cached_runs(sc, p, m, set, v);
+                    mt += v.mt; ms += v.ms; mm += v.mm;
+                }
             }
-        }
+        };
+        if (use_bm) sets(std::true_type{});
+        else sets(std::false_type{});
     }
     if (use_bm) {
         // every lane's runs are in the LDS bitmap: compare it with the
