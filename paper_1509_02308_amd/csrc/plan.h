@@ -40,6 +40,9 @@ struct SweepPlan {
     hipGraphExec_t gexec = nullptr;
     std::string gkey;
     int strategy = 0;                // branch strategy of gexec
+    SweepPlan() = default;
+    SweepPlan(const SweepPlan&) = delete;
+    SweepPlan& operator=(const SweepPlan&) = delete;
     ~SweepPlan();
 };
 
@@ -70,6 +73,10 @@ struct InferPlan {
     uint32_t* d_zero = nullptr;
     ArgminOut* d_out = nullptr;
     uint32_t n_cands = 0;
+    InferPlan() = default;
+    InferPlan(const InferPlan&) = delete;
+    InferPlan& operator=(const InferPlan&) = delete;
+    ~InferPlan() { dev.release(); }
 };
 
 // Learned proposer: marks in *allow the top-k candidates of the network for
