@@ -93,7 +93,7 @@ struct SweepTask {
     uint32_t n;
     uint32_t model;
     uint32_t bm_words;    // LDS bitmap words of the task's jobs (0: bits go straight to memory)
-    uint32_t pad;
+    uint32_t lanes;       // G: lanes per job (lane g of a job owns sets g, g+G, ...)
 };
 
 // Materialised-trace pair.

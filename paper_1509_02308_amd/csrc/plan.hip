@@ -60,8 +60,8 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     plan->n_jobs = jobs_in.size();
     std::vector<SweepJob> jobs(jobs_in);
 
-    // --- natural task order: per model run of jobs; a task holds whole jobs
-    // (floor(64 / T) of them when T < 64, else one job over 64 lanes)
+    // --- natural task order: per model run of jobs; a task holds whole jobs,
+    // G lanes each (G chosen per model below)
     std::vector<SweepTask> tasks;
     std::vector<float> cost;
     std::vector<uint8_t> tcls;
@@ -74,8 +74,25 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         size_t e = j;
         while (e < jobs.size() && jobs[e].model == mi) ++e;
         const DevModel& m = models[mi];
-        const uint64_t G = m.sets < (uint32_t)kWave ? m.sets : (uint64_t)kWave;
-        const uint64_t jpt = std::max<uint64_t>(1, kWave / G);  // jobs per task
+        // G lanes per job: the choice that keeps most lanes busy, counting
+        // lanes left idle (64 mod G) and sets shared unevenly (T mod G), with
+        // at most as many jobs per task as the LDS bitmap holds
+        uint64_t maxw = 1;
+        for (size_t q = j; q < e; ++q) maxw = std::max<uint64_t>(maxw, (probe_len[jobs[q].probe] + 31) / 32);
+        const uint64_t jpt_bm = std::max<uint64_t>(1, kBmMaxWords / maxw);
+        const uint64_t T = m.sets;
+        uint64_t G = std::min<uint64_t>(T, kWave);
+        double best = -1;
+        for (uint64_t d = std::min<uint64_t>(T, kWave); d >= 1; --d) {
+            const uint64_t jp = std::min<uint64_t>(std::max<uint64_t>(1, kWave / d), jpt_bm);
+            const double sets_per_lane = std::ceil((double)T / (double)d);
+            const double eff = (double)(jp * d) / kWave * ((double)T / (double)d) / sets_per_lane;
+            if (eff > best + 0.03) {
+                best = eff;
+                G = d;
+            }
+        }
+        const uint64_t jpt = std::min<uint64_t>(std::max<uint64_t>(1, kWave / G), jpt_bm);  // jobs per task
         const double per_set = std::ceil((double)m.sets / (double)G) / (double)m.sets;
         const int base_cls = way_class(m.ways);
         for (uint64_t q0 = j; q0 < e; q0 += jpt) {
@@ -85,7 +102,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
             t.item0 = (uint32_t)((q0 - j) * G);
             t.n = (uint32_t)((q1 - q0) * G);
             t.model = mi;
-            t.pad = 0;
+            t.lanes = (uint32_t)G;
             uint64_t ml = 0, me = 0, words = 0;
             for (uint64_t q = q0; q < q1; ++q) {
                 const uint64_t len = probe_len[jobs[q].probe];

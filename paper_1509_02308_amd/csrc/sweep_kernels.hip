@@ -126,7 +126,7 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
     const bool active = (uint32_t)lane < task.n;
     const bool use_bm = task.bm_words != 0 && (SCORE || args.bits != nullptr);
     const uint32_t T = m.sets;
-    const uint32_t G = T < (uint32_t)kWave ? T : (uint32_t)kWave;
+    const uint32_t G = task.lanes;
     if (use_bm) {
         for (uint32_t w = (uint32_t)lane; w < task.bm_words; w += kWave) bm[w] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -136,8 +136,8 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
     uint32_t key = kInvalidTag;
     uint32_t mt = 0, ms = 0, mm = 0;   // per lane: below the trace length < 2^32
     if (active) {
-        // G = min(T, 64) lanes per replay; lane g of a replay owns the sets
-        // g, g+G, g+2G, ... and replays them one after the other
+        // G lanes per replay (chosen by the plan); lane g of a replay owns
+        // the sets g, g+G, g+2G, ... and replays them one after the other
         const uint32_t item = task.item0 + (uint32_t)lane;
         const uint32_t jrel = item / G;
         const uint32_t g = item - jrel * G;
