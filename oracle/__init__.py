@@ -8,6 +8,7 @@ Functions follow the paper (Mei & Chu, "Dissecting GPU Memory Hierarchy
 through Microbenchmarking"):
 
 * :func:`trace` -- Listing 1 + Listing 2: j <- A[j] with A[i] = (i+s) mod N.
+* :func:`trace_nu` -- Section 5.2 / Fig. 13(b): the non-uniform-stride chase.
 * :func:`replay` -- Section 4.1 set-associative model (Assumptions 1-3),
   plus the non-LRU policies of Sections 4.5/4.6.
 * :func:`classify`, :func:`auto_threshold` -- Section 4.1, t = t0 + tm*r.
@@ -32,6 +33,10 @@ LRU, FIFO, PLRU, RANDOM = 0, 1, 2, 3
 class OrcModel(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("capacity", "line", "ways", "sets", "policy", "set_shift", "seed")]
+
+
+class OrcNuProbe(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("n_bytes", "base", "j0", "elem", "passes", "n_segments")]
 
 
 class OrcProbe(ctypes.Structure):
@@ -66,6 +71,10 @@ def lib():
         L.orc_cycle_len.restype = u64
         L.orc_trace.argtypes = [ctypes.POINTER(OrcProbe), p, u64]
         L.orc_trace.restype = u64
+        L.orc_trace_nu_len.argtypes = [ctypes.POINTER(OrcNuProbe), p]
+        L.orc_trace_nu_len.restype = u64
+        L.orc_trace_nu.argtypes = [ctypes.POINTER(OrcNuProbe), p, p, p, u64]
+        L.orc_trace_nu.restype = u64
         L.orc_model_check.argtypes = [ctypes.POINTER(OrcModel)]
         L.orc_model_check.restype = ctypes.c_int
         L.orc_replay.argtypes = [ctypes.POINTER(OrcModel), p, u64, u64, u64, u64, u64, p, p, p]
@@ -119,6 +128,21 @@ def trace(probe: OrcProbe) -> np.ndarray:
     out = np.empty(n, dtype=np.int32)
     got = lib().orc_trace(ctypes.byref(probe), _ptr(out), n)
     assert got == n
+    return out
+
+
+def trace_nu(N, segments, passes=1, j0=0, base=0, elem=4) -> np.ndarray:
+    """Section 5.2 non-uniform-stride chase; segments = [(s_bytes, count), ...]."""
+    s = np.ascontiguousarray([int(x[0]) for x in segments], dtype=np.uint64)
+    c = np.ascontiguousarray([int(x[1]) for x in segments], dtype=np.uint64)
+    pr = OrcNuProbe(N, base, j0, elem, passes, len(segments))
+    n = int(lib().orc_trace_nu_len(ctypes.byref(pr), _ptr(c))) if len(segments) else 0
+    if n == 0:
+        raise ValueError("invalid non-uniform probe")
+    out = np.empty(n, dtype=np.int32)
+    got = lib().orc_trace_nu(ctypes.byref(pr), _ptr(s), _ptr(c), _ptr(out), n)
+    if got != n:
+        raise ValueError("invalid non-uniform probe")
     return out
 
 

@@ -11,7 +11,8 @@ TEST INFRASTRUCTURE ONLY.  Pure Python, deliberately different in form from
 * Tree-PLRU is an explicit tree of node objects with lines at the leaves.
 * RANDOM lists the ways of a set and draws the victim from an independent
   pure-Python Philox4x32-10 (Salmon et al., SC'11).
-* The trace is Listing 1 + Listing 2 run literally on an array.
+* The trace is Listing 1 + Listing 2 run literally on an array; the
+  non-uniform chase is Fig. 13(b)'s array set up and chased the same way.
 """
 from __future__ import annotations
 
@@ -39,6 +40,27 @@ def listing_trace(n_elems: int, stride: int, steps: int, j0: int = 0):
     A = [(i + stride) % n_elems for i in range(n_elems)]
     j = j0
     out = []
+    for _ in range(steps):
+        out.append(j)
+        j = A[j]
+    return out
+
+
+def pointer_array_chase(n_elems: int, segments, steps: int, j0: int = 0):
+    """Fig. 13(b) literally: initialise an array so that the element reached
+    at position k of a pass points to the element of position k+1 (position
+    of access k = j0 + sum of the strides taken before it, modulo the size),
+    the last one back to j0, then chase j = A[j].  Only for segment lists
+    that visit each element at most once per pass (else no such array
+    exists: returns None)."""
+    strides = [st for st, cnt in segments for _ in range(cnt)]
+    pos = [(j0 + sum(strides[:k])) % n_elems for k in range(len(strides))]
+    if len(set(pos)) != len(pos):
+        return None
+    A = [None] * n_elems
+    for k, x in enumerate(pos):
+        A[x] = pos[k + 1] if k + 1 < len(pos) else j0
+    j, out = j0, []
     for _ in range(steps):
         out.append(j)
         j = A[j]

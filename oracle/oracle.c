@@ -103,6 +103,48 @@ uint64_t orc_trace(const orc_probe *p, int32_t *out, uint64_t cap)
 }
 
 /* ---------------------------------------------------------------------- */
+/* Non-uniform-stride trace (Section 5.2, Fig. 13(b)): the array is set up
+ * so that the chase leaves each visited element by the stride of the
+ * segment that element belongs to.  Walked literally: visit, then step by
+ * the current segment's stride modulo the array size; every pass starts
+ * again at j0 (the last element of a pass points back to the first).      */
+/* ---------------------------------------------------------------------- */
+uint64_t orc_trace_nu_len(const orc_nu_probe *p, const uint64_t *counts)
+{
+    if (p->elem == 0 || p->n_bytes == 0 || p->n_bytes % p->elem != 0) return 0;
+    uint64_t ne = p->n_bytes / p->elem;
+    if (ne >= (1ull << 31) || p->j0 >= ne || p->passes == 0 || p->n_segments == 0) return 0;
+    uint64_t per_pass = 0;
+    for (uint64_t i = 0; i < p->n_segments; ++i) {
+        if (counts[i] == 0) return 0;
+        per_pass += counts[i];
+    }
+    return per_pass * p->passes;
+}
+
+uint64_t orc_trace_nu(const orc_nu_probe *p, const uint64_t *s_bytes, const uint64_t *counts,
+                      int32_t *out, uint64_t cap)
+{
+    uint64_t len = orc_trace_nu_len(p, counts);
+    if (len == 0 || len > cap) return 0;
+    for (uint64_t i = 0; i < p->n_segments; ++i)
+        if (s_bytes[i] % p->elem != 0) return 0;
+    uint64_t ne = p->n_bytes / p->elem;
+    uint64_t k = 0;
+    for (uint64_t pass = 0; pass < p->passes; ++pass) {
+        uint64_t j = p->j0;
+        for (uint64_t i = 0; i < p->n_segments; ++i) {
+            uint64_t step = (s_bytes[i] / p->elem) % ne;
+            for (uint64_t t = 0; t < counts[i]; ++t) {
+                out[k++] = (int32_t)j;
+                j = (j + step) % ne;
+            }
+        }
+    }
+    return len;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Model checks: Assumption 1 (T*a*b == C), a power-of-two line, a
  * power-of-two associativity for the binary PLRU tree, and a set unit no
  * smaller than a line.                                                     */

@@ -9,7 +9,8 @@
  * declared here on their own on purpose.
  *
  * Every function follows one passage of the paper:
- *   - trace generation:   Listing 1 (array initialisation) + Listing 2 (chase)
+ *   - trace generation:   Listing 1 (array initialisation) + Listing 2 (chase);
+ *                         the non-uniform-stride chase of Section 5.2
  *   - replay:             Section 4.1, Assumptions 1-3 (set-associative model,
  *                         set bits directly above the offset bits, LRU) and
  *                         the non-LRU policies the paper observes
@@ -61,6 +62,24 @@ uint64_t orc_trace_len(const orc_probe *p);
 uint64_t orc_cycle_len(const orc_probe *p);
 /* Writes the accessed element indices j_0 .. j_{len-1}; returns len or 0. */
 uint64_t orc_trace(const orc_probe *p, int32_t *out, uint64_t cap);
+
+/* Non-uniform-stride probe (Section 5.2, Fig. 13(b)): segment i has
+ * counts[i] >= 1 accesses, each left by a step of s_bytes[i]; a pass walks
+ * the segments in order from j0 and every pass starts again at j0. */
+typedef struct orc_nu_probe {
+    uint64_t n_bytes;
+    uint64_t base;
+    uint64_t j0;
+    uint64_t elem;
+    uint64_t passes;
+    uint64_t n_segments;
+} orc_nu_probe;
+
+/* passes * (sum of counts), 0 on error. */
+uint64_t orc_trace_nu_len(const orc_nu_probe *p, const uint64_t *counts);
+/* Writes the visited element indices; returns the length or 0. */
+uint64_t orc_trace_nu(const orc_nu_probe *p, const uint64_t *s_bytes, const uint64_t *counts,
+                      int32_t *out, uint64_t cap);
 
 /* 0 if the model is valid, negative otherwise. */
 int orc_model_check(const orc_model *m);

@@ -39,6 +39,103 @@ def test_trace_rejects_bad_probes(orc):
     assert orc.trace_len(orc.make_probe(16, 4, passes=0)) == 0
 
 
+# ------------------------------------------ non-uniform stride (5.2) ----
+def _fig13b():
+    segs, visited, n = [], None, None
+    with open(os.path.join(HERE, "golden", "fig13b_nonuniform_chase.txt")) as f:
+        for line in f:
+            w = line.split()
+            if not w or w[0].startswith("#"):
+                continue
+            if w[0] == "n_elems":
+                n = int(w[1])
+            elif w[0] == "segment":
+                segs.append((int(w[1]), int(w[2])))
+            elif w[0] == "visited":
+                visited = [int(x) for x in w[1:]]
+    return n, segs, visited
+
+
+def test_nonuniform_fig13b_example(orc):
+    """Section 5.2, Fig. 13(b): the drawn array gives the drawn chase."""
+    n, segs, visited = _fig13b()
+    got = orc.trace_nu(4 * n, [(4 * st, c) for st, c in segs], passes=2)
+    assert got.tolist() == visited * 2
+
+
+@pytest.mark.parametrize("n,s,j0,passes", [(13, 1, 0, 3), (16, 4, 0, 2), (12, 8, 3, 2), (24, 9, 5, 3),
+                                           (5, 0, 1, 2), (64, 96, 0, 2), (1000, 36, 17, 2)])
+def test_nonuniform_one_segment_is_uniform(orc, n, s, j0, passes):
+    """One segment of one full cycle is the Listing 1 + 2 chase."""
+    L = n // gcd(n, s % n)
+    got = orc.trace_nu(4 * n, [(4 * s, L)], passes=passes, j0=j0)
+    assert got.tolist() == brute.listing_trace(n, s, passes * L, j0)
+
+
+def test_nonuniform_matches_pointer_array(orc):
+    """Random segment lists that an array can realise (each element at most
+    once per pass): the chase over the explicitly initialised array."""
+    rng = np.random.default_rng(5)
+    done = 0
+    for _ in range(400):
+        n = int(rng.integers(8, 400))
+        segs = [(int(rng.integers(0, 3 * n)), int(rng.integers(1, 6))) for _ in range(int(rng.integers(1, 6)))]
+        j0 = int(rng.integers(0, n))
+        K = sum(c for _, c in segs)
+        want = brute.pointer_array_chase(n, segs, 3 * K, j0)
+        if want is None:
+            continue
+        got = orc.trace_nu(4 * n, [(4 * st, c) for st, c in segs], passes=3, j0=j0)
+        assert got.tolist() == want
+        done += 1
+    assert done > 100
+
+
+def test_nonuniform_rejects_bad_segments(orc):
+    with pytest.raises(ValueError):
+        orc.trace_nu(64, [])                     # no segment
+    with pytest.raises(ValueError):
+        orc.trace_nu(64, [(4, 0)])               # empty segment
+    with pytest.raises(ValueError):
+        orc.trace_nu(64, [(6, 2)])               # stride not a multiple of elem
+    with pytest.raises(ValueError):
+        orc.trace_nu(64, [(4, 2)], j0=16)        # start outside the array
+
+
+def test_nonuniform_revisit_breaks_lru_fifo_tie(orc):
+    """Lines A, B, A, C, A in one fully associative 2-way set: LRU keeps A
+    (the C miss evicts B) and hits the last access, FIFO evicts A (first in)
+    and misses it.  Uniform chases cannot show this difference (Section 4.2
+    step 4); a non-uniform chase that returns into a line can.  Elements
+    0, 8, 1, 16, 2 with 32-byte lines are lines 0, 1, 0, 2, 0."""
+    n = 64
+    segs = [(4 * 8, 1), (4 * (n - 7), 1), (4 * 15, 1), (4 * (n - 14), 1), (4, 1)]
+    idx = orc.trace_nu(4 * n, segs)
+    assert idx.tolist() == [0, 8, 1, 16, 2]
+    lru = orc.replay(orc.make_model(64, 32, 2, orc.LRU), idx)[0]
+    fifo = orc.replay(orc.make_model(64, 32, 2, orc.FIFO), idx)[0]
+    assert lru.tolist() == [0, 0, 1, 0, 1]
+    assert fifo.tolist() == [0, 0, 1, 0, 0]
+
+
+def test_nonuniform_section52_pattern(orc):
+    """The Section 5.2 construction with s1 = 32 MB (65 accesses, then the
+    same lines again three times) and s3 = one element (64 accesses from
+    the start).  A fully associative LRU cache of 128 lines of 128 B keeps
+    the 65 lines: 65 cold misses, 195 hits, then elements 0..31 hit (line
+    0 is resident) and 32..63 are a new line: one miss, 31 hits.  With 64
+    lines the 65-line loop thrashes: 260 misses; line 0 was evicted, so
+    each of the two element lines misses once."""
+    s1 = 32 << 20
+    N = 65 * s1
+    idx = orc.trace_nu(N, [(s1, 65 * 4), (4, 64)])
+    assert idx[65] == 0 and idx[260] == 0 and idx[-1] == 63
+    h128 = orc.replay(orc.make_model(128 * 128, 128, 128, orc.LRU), idx)[0]
+    assert h128.tolist() == [0] * 65 + [1] * 195 + [1] * 32 + [0] + [1] * 31
+    h64 = orc.replay(orc.make_model(64 * 128, 128, 64, orc.LRU), idx)[0]
+    assert h64.tolist() == [0] * 260 + [0] + [1] * 31 + [0] + [1] * 31
+
+
 # ---------------------------------------------------- I1: Fig. 3 --------
 def test_fig3_worked_example(orc):
     """Section 4.1, Fig. 3: 12-word 2-way cache, 2-word lines, 3 sets, array
