@@ -28,12 +28,13 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9      # int32 VALU lane-ops/s: 256 CUs x 64 lane
 
 
 def kernel_source_digest() -> str:
-    """Digest of the HIP sources and the C header (names and bytes)."""
-    import glob
+    """Digest (names and bytes) of the sources that decide what the sweep
+    kernels of one inference step execute: the kernels, the per-lane replay,
+    the shared device structures and the plan that builds their tasks."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1509_02308_amd", "csrc", "*"))) + \
-        [os.path.join(ROOT, "include", "pchase.h")]
+    files = [os.path.join(ROOT, "paper_1509_02308_amd", "csrc", f)
+             for f in ("common.h", "plan.h", "plan.hip", "sweep_kernels.hip", "sweep_lane.h")]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -84,6 +85,7 @@ def main():
     ap.add_argument("--learned-targets", type=int, default=200)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--large-pairs", type=int, default=1_000_000)
+    ap.add_argument("--nu-probes", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -185,6 +187,10 @@ def main():
     if args.large_pairs > 0:
         large = large_batch_leg(torch, capi, W, args)
 
+    nonuniform = None
+    if args.nu_probes > 0:
+        nonuniform = nonuniform_leg(torch, capi, W, args, stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(crows, prows, lens, bits, bitoff, args.cpu_seconds)
@@ -215,6 +221,7 @@ def main():
         "plain": plain,
         "learned": learned,
         "large_batch": large,
+        "nonuniform": nonuniform,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -322,6 +329,48 @@ def large_batch_leg(torch, capi, W, args):
     return {"pairs": n, "accesses": total, "trace_bytes": 4 * total, "replay_s": dt,
             "value": total / dt, "unit": "accesses/s",
             "hbm_GBps_trace_only": 4 * total / dt / 1e9}
+
+
+def nonuniform_leg(torch, capi, W, args, stream):
+    """Non-uniform-stride chases (Section 5.2): seeded segment lists over
+    arrays of 64 B..64 MB; the traces are generated on the device (HIP events
+    around the call after a warm-up call: bound by the 4-byte index writes),
+    then each trace is replayed through one of 16 caches (8-64 KB, 64 B lines,
+    4-32 ways, all four policies) with hit bits and both miss counts, timed
+    after a warm-up.  Parity on such traces is checked by the GPU tests."""
+    rows = W.nonuniform_rows(n=args.nu_probes, seed=5209, n_hi=64 << 20, max_count=60_000)
+    parr, sarr = capi.nu_probes(rows)
+    lens = np.array([capi.pchase_trace_nu_len(parr, sarr, i)[0] for i in range(len(rows))], dtype=np.uint64)
+    total = int(lens.sum())
+    idx = torch.empty(total + 1, dtype=torch.int32, device="cuda")
+    capi.pchase_trace_nu(parr, sarr, idx)       # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    off = capi.pchase_trace_nu(parr, sarr, idx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gen_ms = e0.elapsed_time(e1)
+    mrows = [(8192 << (i // 4), 64, 4 << (i % 4), i % 4, 0, 1000 + i) for i in range(16)]
+    marr = capi.models(mrows)
+    n = len(rows)
+    pm = (np.arange(n) % len(mrows)).astype(np.uint32)
+    pt = np.arange(n, dtype=np.uint32)
+    bases = np.array([r[4] for r in rows], np.uint64)
+    words = (lens + 31) // 32
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.zeros(int(words.sum()) + 1, dtype=torch.int32, device="cuda")
+    misses = torch.zeros(2 * n, dtype=torch.int64, device="cuda")
+    capi.cache_replay_batch(marr, idx, off, bases, pm, pt, None, misses, bits, bitoff)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.cache_replay_batch(marr, idx, off, bases, pm, pt, None, misses, bits, bitoff)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del idx, bits
+    gbps = 4 * total / (gen_ms * 1e-3) / 1e9
+    return {"probes": n, "segments": int(sarr.n), "accesses": total,
+            "trace_gen_ms": gen_ms, "trace_gen_GBps": gbps, "trace_gen_hbm_frac": gbps / 8000.0,
+            "replay_s": dt, "value": total / dt, "unit": "accesses/s"}
 
 
 def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):

@@ -119,6 +119,48 @@ int pchase_trace_len(const pchase_probe *probe, uint64_t *len, uint64_t *cycle);
 int pchase_trace(const pchase_probe *probes, uint32_t n_probes, int32_t *idx_dev,
                  uint64_t *off, uint64_t cap, hipStream_t stream);
 
+/* Non-uniform-stride chase (Section 5.2, Fig. 13(b)): the array is set up
+ * so that the chase leaves each element by the stride of the segment it
+ * belongs to, which lets one run mix access patterns (far strides that
+ * miss every cache and TLB level, revisits of resident lines, steps inside
+ * a line).  Segment i of a pass has `count` >= 1 accesses and each of them
+ * is followed by a step of s_bytes (a multiple of elem_bytes; any size,
+ * taken modulo n_bytes).  A pass visits segments first_segment ..
+ * first_segment + n_segments - 1 of the segment array in order, starting
+ * at element j0; each of the `passes` passes starts again at j0.  Element
+ * i sits at byte base_offset + elem_bytes*i, as for pchase_probe.  Probes
+ * may share segments.  Valid iff elem_bytes is 4, n_bytes is a multiple of
+ * it with 1 <= Ne < 2^31, j0 < Ne, passes >= 1, n_segments >= 1, the
+ * segment range lies inside the array, base_offset is a multiple of 4
+ * below 2^33 and passes * (accesses per pass) < 2^32. */
+typedef struct pchase_segment {
+    uint64_t s_bytes;     /* step after each access of the segment */
+    uint64_t count;       /* accesses in the segment, >= 1 */
+} pchase_segment;
+
+typedef struct pchase_nu_probe {
+    uint64_t n_bytes;       /* N */
+    uint64_t base_offset;   /* byte address of element 0 */
+    uint64_t j0;            /* first element visited in every pass */
+    uint32_t elem_bytes;    /* 4 */
+    uint32_t passes;
+    uint32_t first_segment; /* index into the segment array */
+    uint32_t n_segments;
+} pchase_nu_probe;
+
+/* *len = passes * (accesses per pass), *pass_len = accesses per pass
+ * (either may be NULL).  segs has n_segs entries.  Host only. */
+int pchase_trace_nu_len(const pchase_nu_probe *probe, const pchase_segment *segs, uint32_t n_segs,
+                        uint64_t *len, uint64_t *pass_len);
+
+/* Writes the visited element indices of n_probes non-uniform probes back
+ * to back into idx_dev (int32, device, capacity `cap` elements), laid out
+ * and reported through `off` (host, n_probes+1 entries, may be NULL) as
+ * for pchase_trace.  probes and segs are host arrays.  EINVAL for an
+ * invalid probe, ERANGE if the total exceeds cap.  Synchronises. */
+int pchase_trace_nu(const pchase_nu_probe *probes, uint32_t n_probes, const pchase_segment *segs,
+                    uint32_t n_segs, int32_t *idx_dev, uint64_t *off, uint64_t cap, hipStream_t stream);
+
 /* ------------------------------------------------------------ replay --- */
 /* Replay scheduling: BATCHED runs every pair in one captured graph of
  * persistent kernels fed by a cost-ordered work queue; PLAIN launches one
@@ -264,6 +306,18 @@ int microbench_hbm_stream(const void *src_dev, void *dst_dev, uint64_t bytes, ui
  * (x100, rounded) to cycles_dev[stride - stride_lo].  stride_hi <= 64. */
 int microbench_lds_bank(uint32_t stride_lo, uint32_t stride_hi, uint32_t reps,
                         uint32_t *cycles_dev, hipStream_t stream);
+
+/* LDS throughput (Section 6.1): blocks_per_cu x (number of CUs) blocks of
+ * `block` threads (a multiple of 64, at most 1024) each stream accesses of
+ * width_bytes (4 or 16) over a 16 KB LDS buffer, ilp (1, 2, 4 or 8)
+ * independent reads in flight per thread, reps rounds, consecutive lanes on
+ * consecutive words (no bank conflicts).  copy = 1 stores every value read
+ * into a second 16 KB buffer (the paper's shared-to-shared copy: read and
+ * written bytes both count); copy = 0 only reads.  *gbps = LDS bytes moved
+ * / elapsed time of one launch after a warm-up launch (HIP events).
+ * Returns PCHASE_EINVAL for arguments outside those sets.  Synchronises. */
+int microbench_lds_stream(uint32_t blocks_per_cu, uint32_t block, uint32_t ilp, uint32_t width_bytes,
+                          uint32_t copy, uint32_t reps, double *gbps, hipStream_t stream);
 
 /* ------------------------------------------------------ learned model --- */
 /* The learned proposer ranks candidates from a fixed set of fine-grained

@@ -39,6 +39,15 @@ class PchaseProbe(ctypes.Structure):
                 ("elem_bytes", u32), ("passes", u32)]
 
 
+class PchaseSegment(ctypes.Structure):
+    _fields_ = [("s_bytes", u64), ("count", u64)]
+
+
+class PchaseNuProbe(ctypes.Structure):
+    _fields_ = [("n_bytes", u64), ("base_offset", u64), ("j0", u64), ("elem_bytes", u32), ("passes", u32),
+                ("first_segment", u32), ("n_segments", u32)]
+
+
 class PchaseObservation(ctypes.Structure):
     _fields_ = [("probes", vp), ("n_probes", u32), ("threshold", u32), ("bits_dev", vp),
                 ("bitoff", vp), ("lat_dev", vp), ("lat_off", vp), ("count_from", vp)]
@@ -67,6 +76,8 @@ def lib():
         L.pchase_last_error.restype = ctypes.c_char_p
         L.pchase_trace_len.argtypes = [ctypes.POINTER(PchaseProbe), vp, vp]
         L.pchase_trace.argtypes = [vp, u32, vp, vp, u64, vp]
+        L.pchase_trace_nu_len.argtypes = [ctypes.POINTER(PchaseNuProbe), vp, u32, vp, vp]
+        L.pchase_trace_nu.argtypes = [vp, u32, vp, u32, vp, vp, u64, vp]
         L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
         L.cache_replay_probes.argtypes = [vp, u32, vp, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
         L.infer_cache_params.argtypes = [ctypes.POINTER(PchaseObservation), vp, u32, ctypes.c_int,
@@ -75,6 +86,7 @@ def lib():
         L.pchase_microbench_max_k.restype = u64
         L.microbench_hbm_stream.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp, vp]
         L.microbench_lds_bank.argtypes = [u32, u32, u32, vp, vp]
+        L.microbench_lds_stream.argtypes = [u32, u32, u32, u32, u32, u32, vp, vp]
         L.pchase_abort.argtypes = [ctypes.c_int]
         L.pchase_release.argtypes = []
         L.pchase_mlp_grid.argtypes = [vp, u64]
@@ -180,6 +192,46 @@ def pchase_trace(probe_arr, idx, stream=None) -> np.ndarray:
     return off
 
 
+def nu_probes(rows):
+    """Non-uniform probe and segment arrays from rows
+    (N, [(s_bytes, count), ...][, passes[, j0[, base]]]); each row gets its
+    own run of segments.  Returns (probe array, segment array)."""
+    rows = list(rows)
+    segs = [sg for r in rows for sg in r[1]]
+    parr = (PchaseNuProbe * max(len(rows), 1))()
+    sarr = (PchaseSegment * max(len(segs), 1))()
+    first = 0
+    for i, r in enumerate(rows):
+        N, sl = int(r[0]), r[1]
+        passes = int(r[2]) if len(r) > 2 else 1
+        j0 = int(r[3]) if len(r) > 3 else 0
+        base = int(r[4]) if len(r) > 4 else 0
+        parr[i] = PchaseNuProbe(N, base, j0, 4, passes, first, len(sl))
+        for t, (s, c) in enumerate(sl):
+            sarr[first + t] = PchaseSegment(int(s), int(c))
+        first += len(sl)
+    parr.n = len(rows)
+    sarr.n = len(segs)
+    return parr, sarr
+
+
+def pchase_trace_nu_len(probe_arr, seg_arr, i=0):
+    n, K = u64(), u64()
+    check(lib().pchase_trace_nu_len(ctypes.byref(probe_arr[i]), ctypes.cast(seg_arr, vp), seg_arr.n,
+                                    ctypes.byref(n), ctypes.byref(K)))
+    return int(n.value), int(K.value)
+
+
+def pchase_trace_nu(probe_arr, seg_arr, idx, stream=None) -> np.ndarray:
+    """Fills idx (int32 CUDA tensor) with the non-uniform probes' traces;
+    returns the offsets."""
+    off = np.zeros(probe_arr.n + 1, dtype=np.uint64)
+    check(lib().pchase_trace_nu(ctypes.cast(probe_arr, vp), probe_arr.n, ctypes.cast(seg_arr, vp), seg_arr.n,
+                                _dptr(idx), off.ctypes.data_as(vp), idx.numel() if idx is not None else 0,
+                                _stream(stream)))
+    return off
+
+
 def cache_replay_batch(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
                        misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None):
     toff, p_toff = _hptr(trace_off, np.uint64)
@@ -243,6 +295,13 @@ def microbench_hbm_stream(src, dst, nbytes, dtype, grid, block, ilp, reps, strea
 
 def microbench_lds_bank(stride_lo, stride_hi, reps, cycles, stream=None):
     check(lib().microbench_lds_bank(stride_lo, stride_hi, reps, _dptr(cycles), _stream(stream)))
+
+
+def microbench_lds_stream(blocks_per_cu, block, ilp, width_bytes, reps, copy=False, stream=None) -> float:
+    g = ctypes.c_double()
+    check(lib().microbench_lds_stream(blocks_per_cu, block, ilp, width_bytes, int(bool(copy)), reps,
+                                      ctypes.byref(g), _stream(stream)))
+    return float(g.value)
 
 
 def pchase_abort(on: bool):

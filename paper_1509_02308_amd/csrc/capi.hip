@@ -69,6 +69,16 @@ int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vecto
 using namespace pc;
 
 // ------------------------------------------------------------- traces ---
+// First chunk of every trace in the flat trace-generation grid (one block
+// per chunk of kTraceChunkAccesses accesses), n + 1 entries.
+static int chunk_offsets(const std::vector<uint64_t>& off, std::vector<uint64_t>* co) {
+    co->assign(off.size(), 0);
+    for (size_t i = 0; i + 1 < off.size(); ++i)
+        (*co)[i + 1] = (*co)[i] + (off[i + 1] - off[i] + kTraceChunkAccesses - 1) / kTraceChunkAccesses;
+    if (co->back() >= (1ull << 31)) return set_error(PCHASE_ERANGE, "trace too long for one launch");
+    return PCHASE_OK;
+}
+
 extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32_t* idx_dev, uint64_t* off,
                             uint64_t cap, hipStream_t stream) {
     std::vector<DevProbe> dp;
@@ -76,11 +86,7 @@ extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32
     int rc = validate_probes(probes, n_probes, &dp, &len);
     if (rc) return rc;
     std::vector<uint64_t> o(n_probes + 1, 0);
-    uint64_t maxlen = 0;
-    for (uint32_t i = 0; i < n_probes; ++i) {
-        o[i + 1] = o[i] + len[i];
-        maxlen = std::max(maxlen, len[i]);
-    }
+    for (uint32_t i = 0; i < n_probes; ++i) o[i + 1] = o[i] + len[i];
     if (o[n_probes] > cap)
         return set_error(PCHASE_ERANGE, "trace needs %llu elements, capacity is %llu",
                          (unsigned long long)o[n_probes], (unsigned long long)cap);
@@ -91,14 +97,118 @@ extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32
     std::unique_lock<std::mutex> lk;
     rc = workspace(&ws, &lk);
     if (rc) return rc;
-    const size_t bytes = dp.size() * sizeof(DevProbe) + o.size() * sizeof(uint64_t);
-    hipError_t e = ws->stage.ensure(bytes);
+    std::vector<uint64_t> co;
+    rc = chunk_offsets(o, &co);
+    if (rc) return rc;
+    const size_t b_p = dp.size() * sizeof(DevProbe), b_o = o.size() * sizeof(uint64_t);
+    const size_t b_c = co.back() * sizeof(ChunkRef);
+    hipError_t e = ws->stage.ensure(b_p + 2 * b_o + b_c);
     if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
-    DevProbe* d_p = ws->stage.as<DevProbe>();
-    uint64_t* d_o = reinterpret_cast<uint64_t*>(ws->stage.as<uint8_t>() + dp.size() * sizeof(DevProbe));
-    PC_HIP(hipMemcpyAsync(d_p, dp.data(), dp.size() * sizeof(DevProbe), hipMemcpyHostToDevice, stream));
-    PC_HIP(hipMemcpyAsync(d_o, o.data(), o.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream));
-    PC_HIP(launch_trace(d_p, d_o, n_probes, maxlen, idx_dev, stream));
+    uint8_t* st = ws->stage.as<uint8_t>();
+    DevProbe* d_p = reinterpret_cast<DevProbe*>(st);
+    uint64_t* d_o = reinterpret_cast<uint64_t*>(st + b_p);
+    uint64_t* d_co = reinterpret_cast<uint64_t*>(st + b_p + b_o);
+    ChunkRef* d_c = reinterpret_cast<ChunkRef*>(st + b_p + 2 * b_o);
+    PC_HIP(hipMemcpyAsync(d_p, dp.data(), b_p, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_o, o.data(), b_o, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_co, co.data(), b_o, hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_chunk_table(d_co, n_probes, d_c, stream));
+    PC_HIP(launch_trace(d_p, d_o, d_c, co.back(), idx_dev, stream));
+    // the staging buffer is reused by the next call: finish before releasing it
+    PC_HIP(hipStreamSynchronize(stream));
+    return PCHASE_OK;
+}
+
+// ------------------------------------------------- non-uniform traces ---
+static int check_nu_probe(const pchase_nu_probe& p, const pchase_segment* segs, uint32_t n_segs, uint64_t i,
+                          uint64_t* pass_len, uint64_t* len) {
+    if (p.elem_bytes != 4) return set_error(PCHASE_EINVAL, "probe %llu: elem_bytes must be 4", (unsigned long long)i);
+    if (p.n_bytes == 0 || p.n_bytes % 4)
+        return set_error(PCHASE_EINVAL, "probe %llu: N must be a positive multiple of elem_bytes", (unsigned long long)i);
+    const uint64_t ne = p.n_bytes / 4;
+    if (ne >= (1ull << 31)) return set_error(PCHASE_EINVAL, "probe %llu: N/elem must be below 2^31", (unsigned long long)i);
+    if (p.j0 >= ne) return set_error(PCHASE_EINVAL, "probe %llu: j0 outside the array", (unsigned long long)i);
+    if (p.passes == 0) return set_error(PCHASE_EINVAL, "probe %llu: passes must be >= 1", (unsigned long long)i);
+    if (p.base_offset >= (1ull << 33) || p.base_offset % 4)
+        return set_error(PCHASE_EINVAL, "probe %llu: base_offset must be a multiple of 4 below 2^33", (unsigned long long)i);
+    if (p.n_segments == 0) return set_error(PCHASE_EINVAL, "probe %llu: no segments", (unsigned long long)i);
+    if ((uint64_t)p.first_segment + p.n_segments > n_segs || !segs)
+        return set_error(PCHASE_EINVAL, "probe %llu: segment range outside the segment array", (unsigned long long)i);
+    uint64_t k = 0;
+    for (uint32_t t = 0; t < p.n_segments; ++t) {
+        const pchase_segment& sg = segs[p.first_segment + t];
+        if (sg.count == 0 || sg.s_bytes % 4)
+            return set_error(PCHASE_EINVAL, "probe %llu: segment %u needs count >= 1 and a stride multiple of elem_bytes",
+                             (unsigned long long)i, p.first_segment + t);
+        if (sg.count >= (1ull << 32) || (k += sg.count) >= (1ull << 32))
+            return set_error(PCHASE_ERANGE, "probe %llu: passes * accesses per pass must stay below 2^32", (unsigned long long)i);
+    }
+    if (k * (uint64_t)p.passes >= (1ull << 32))
+        return set_error(PCHASE_ERANGE, "probe %llu: passes * accesses per pass must stay below 2^32", (unsigned long long)i);
+    if (pass_len) *pass_len = k;
+    if (len) *len = k * p.passes;
+    return PCHASE_OK;
+}
+
+extern "C" int pchase_trace_nu_len(const pchase_nu_probe* probe, const pchase_segment* segs, uint32_t n_segs,
+                                   uint64_t* len, uint64_t* pass_len) {
+    if (!probe) return set_error(PCHASE_EINVAL, "probe is NULL");
+    return check_nu_probe(*probe, segs, n_segs, 0, pass_len, len);
+}
+
+extern "C" int pchase_trace_nu(const pchase_nu_probe* probes, uint32_t n_probes, const pchase_segment* segs,
+                               uint32_t n_segs, int32_t* idx_dev, uint64_t* off, uint64_t cap, hipStream_t stream) {
+    if (n_probes && !probes) return set_error(PCHASE_EINVAL, "probes is NULL");
+    std::vector<uint64_t> o(n_probes + 1, 0);
+    std::vector<DevNuProbe> dp(n_probes);
+    std::vector<DevNuSeg> ds;
+    for (uint32_t i = 0; i < n_probes; ++i) {
+        const pchase_nu_probe& p = probes[i];
+        uint64_t K = 0, len = 0;
+        int rc = check_nu_probe(p, segs, n_segs, i, &K, &len);
+        if (rc) return rc;
+        const uint64_t ne = p.n_bytes / 4;
+        dp[i] = DevNuProbe{K, (uint32_t)ds.size(), p.n_segments, (uint32_t)ne, 0};
+        // element of each segment's first access: j0 plus every step taken before it, modulo ne
+        uint64_t pos = p.j0, start = 0;
+        for (uint32_t t = 0; t < p.n_segments; ++t) {
+            const pchase_segment& sg = segs[p.first_segment + t];
+            const uint64_t se = (sg.s_bytes / 4) % ne;
+            ds.push_back(DevNuSeg{start, (uint32_t)pos, (uint32_t)se});
+            pos = (uint64_t)((pos + (unsigned __int128)se * (sg.count % ne)) % ne);
+            start += sg.count;
+        }
+        o[i + 1] = o[i] + len;
+    }
+    if (o[n_probes] > cap)
+        return set_error(PCHASE_ERANGE, "trace needs %llu elements, capacity is %llu",
+                         (unsigned long long)o[n_probes], (unsigned long long)cap);
+    if (o[n_probes] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
+    if (off) std::memcpy(off, o.data(), o.size() * sizeof(uint64_t));
+    if (n_probes == 0 || o[n_probes] == 0) return PCHASE_OK;
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    int rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    std::vector<uint64_t> co;
+    rc = chunk_offsets(o, &co);
+    if (rc) return rc;
+    const size_t b_p = dp.size() * sizeof(DevNuProbe), b_s = ds.size() * sizeof(DevNuSeg);
+    const size_t b_o = o.size() * sizeof(uint64_t), b_c = co.back() * sizeof(ChunkRef);
+    hipError_t e = ws->stage.ensure(b_p + b_s + 2 * b_o + b_c);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    uint8_t* st = ws->stage.as<uint8_t>();
+    DevNuProbe* d_p = reinterpret_cast<DevNuProbe*>(st);
+    DevNuSeg* d_s = reinterpret_cast<DevNuSeg*>(st + b_p);
+    uint64_t* d_o = reinterpret_cast<uint64_t*>(st + b_p + b_s);
+    uint64_t* d_co = reinterpret_cast<uint64_t*>(st + b_p + b_s + b_o);
+    ChunkRef* d_c = reinterpret_cast<ChunkRef*>(st + b_p + b_s + 2 * b_o);
+    PC_HIP(hipMemcpyAsync(d_p, dp.data(), b_p, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_s, ds.data(), b_s, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_o, o.data(), b_o, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_co, co.data(), b_o, hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_chunk_table(d_co, n_probes, d_c, stream));
+    PC_HIP(launch_trace_nu(d_p, d_s, d_o, d_c, co.back(), idx_dev, stream));
     // the staging buffer is reused by the next call: finish before releasing it
     PC_HIP(hipStreamSynchronize(stream));
     return PCHASE_OK;

@@ -162,8 +162,33 @@ void sweep_geometry(int cls, uint32_t lds_rows, uint32_t bm_words, uint32_t* thr
 hipError_t sweep_prepare_lds();
 hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream);
 hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu);
-hipError_t launch_trace(const DevProbe* probes, const uint64_t* off, uint32_t n_probes, uint64_t maxlen,
+// Trace generation: one block per chunk of kTraceChunkAccesses accesses;
+// chunk table entry = (probe, chunk number within the probe).
+constexpr uint64_t kTraceChunkAccesses = 4096;
+struct ChunkRef {
+    uint32_t probe;
+    uint32_t chunk;
+};
+hipError_t launch_chunk_table(const uint64_t* chunk_off, uint32_t n_traces, ChunkRef* chunks, hipStream_t stream);
+hipError_t launch_trace(const DevProbe* probes, const uint64_t* off, const ChunkRef* chunks, uint64_t n_chunks,
                         int32_t* idx, hipStream_t stream);
+// Non-uniform-stride chase: a probe's pass is a list of segments; segment
+// i of a probe starts at access `start` of the pass on element `pos` and
+// steps by `se` (elements, reduced modulo ne) after each of its accesses.
+struct DevNuSeg {
+    uint64_t start;
+    uint32_t pos;
+    uint32_t se;
+};
+struct DevNuProbe {
+    uint64_t pass_len;   // accesses per pass
+    uint32_t first;      // its first segment in the DevNuSeg array
+    uint32_t nseg;
+    uint32_t ne;         // array size in elements
+    uint32_t pad;
+};
+hipError_t launch_trace_nu(const DevNuProbe* probes, const DevNuSeg* segs, const uint64_t* off,
+                           const ChunkRef* chunks, uint64_t n_chunks, int32_t* idx, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_argmin(const uint64_t* m, const uint64_t* n, uint32_t nc, uint32_t* zero_bits,
                          ArgminOut* out, hipStream_t stream);
@@ -223,4 +248,6 @@ int hip_fail(hipError_t e, const char *what);
 
 static_assert(sizeof(pchase_model) == 40, "pchase_model layout");
 static_assert(sizeof(pchase_probe) == 40, "pchase_probe layout");
+static_assert(sizeof(pchase_segment) == 16, "pchase_segment layout");
+static_assert(sizeof(pchase_nu_probe) == 40, "pchase_nu_probe layout");
 static_assert(sizeof(pchase_result) == 48, "pchase_result layout");

@@ -227,9 +227,112 @@ __global__ void __launch_bounds__(64) lds_bank_kernel(uint32_t stride, uint32_t 
     if (threadIdx.x == 0) *out = (uint32_t)((best * 100 + 32) / 64);
 }
 
+// LDS throughput (Section 6.1): every thread streams words of a 16 KB LDS
+// source buffer, ILP independent reads in flight, consecutive lanes on
+// consecutive words (no bank conflicts).  With COPY each value read is
+// stored to the same place of a second 16 KB buffer (the paper's
+// shared-to-shared copy); without it the xor of the values read is kept.
+// Either way something observable depends on every access.
+constexpr uint32_t kLdsStreamWords = 4096;
+
+template <class V, int ILP, bool COPY>
+__global__ void __launch_bounds__(1024) lds_stream_kernel(uint32_t reps, uint32_t* sink) {
+    __shared__ __align__(16) uint32_t src[kLdsStreamWords];
+    __shared__ __align__(16) uint32_t dst[COPY ? kLdsStreamWords : 4];
+    for (uint32_t i = threadIdx.x; i < kLdsStreamWords; i += blockDim.x) src[i] = i * 2654435761u;
+    __syncthreads();
+    constexpr uint32_t per = sizeof(V) / 4;                 // words per access
+    constexpr uint32_t n = kLdsStreamWords / per;           // accesses that fit a buffer
+    const V* vs = reinterpret_cast<const V*>(src);
+    V* vd = reinterpret_cast<V*>(dst);
+    uint32_t acc[ILP];
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) acc[j] = 0;
+#pragma unroll 1   // reads in flight = ILP: each round waits for its own reads
+    for (uint32_t r = 0; r < reps; ++r) {
+        V v[ILP];
+#pragma unroll
+        for (int j = 0; j < ILP; ++j) v[j] = vs[(threadIdx.x + (r * ILP + j) * blockDim.x) & (n - 1)];
+#pragma unroll
+        for (int j = 0; j < ILP; ++j) {
+            if constexpr (COPY) {
+                vd[(threadIdx.x + (r * ILP + j) * blockDim.x) & (n - 1)] = v[j];
+            } else if constexpr (sizeof(V) == 4) {
+                acc[j] ^= (uint32_t)v[j];
+            } else {
+                acc[j] ^= v[j].x ^ v[j].y ^ v[j].z ^ v[j].w;
+            }
+        }
+    }
+    uint32_t x = 0;
+    if constexpr (COPY) {
+        __syncthreads();
+        x = dst[threadIdx.x & (kLdsStreamWords - 1)];
+    } else {
+#pragma unroll
+        for (int j = 0; j < ILP; ++j) x ^= acc[j];
+    }
+    if (x == 0x9E3779B9u) sink[blockIdx.x] = x;   // practically never: keeps the accesses alive
+}
+
+template <class V, bool COPY>
+static hipError_t launch_lds_stream(uint32_t grid, uint32_t block, uint32_t ilp, uint32_t reps, uint32_t* sink,
+                                    hipStream_t s) {
+    switch (ilp) {
+        case 1: hipLaunchKernelGGL((lds_stream_kernel<V, 1, COPY>), dim3(grid), dim3(block), 0, s, reps, sink); break;
+        case 2: hipLaunchKernelGGL((lds_stream_kernel<V, 2, COPY>), dim3(grid), dim3(block), 0, s, reps, sink); break;
+        case 4: hipLaunchKernelGGL((lds_stream_kernel<V, 4, COPY>), dim3(grid), dim3(block), 0, s, reps, sink); break;
+        default: hipLaunchKernelGGL((lds_stream_kernel<V, 8, COPY>), dim3(grid), dim3(block), 0, s, reps, sink); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace pc
 
 using namespace pc;
+
+extern "C" int microbench_lds_stream(uint32_t blocks_per_cu, uint32_t block, uint32_t ilp, uint32_t width_bytes,
+                                     uint32_t copy, uint32_t reps, double* gbps, hipStream_t stream) {
+    if (!gbps) return set_error(PCHASE_EINVAL, "gbps is NULL");
+    if (blocks_per_cu == 0 || blocks_per_cu > 32) return set_error(PCHASE_EINVAL, "blocks_per_cu must be 1..32");
+    if (block == 0 || block > 1024 || block % 64) return set_error(PCHASE_EINVAL, "block must be a multiple of 64 up to 1024");
+    if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8) return set_error(PCHASE_EINVAL, "ilp must be 1, 2, 4 or 8");
+    if (width_bytes != 4 && width_bytes != 16) return set_error(PCHASE_EINVAL, "width_bytes must be 4 or 16");
+    if (copy > 1) return set_error(PCHASE_EINVAL, "copy must be 0 or 1");
+    if (reps == 0) return set_error(PCHASE_EINVAL, "reps must be >= 1");
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    int rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    const uint32_t grid = blocks_per_cu * (uint32_t)ws->cus;
+    hipError_t e = ws->aux.ensure((size_t)grid * 4);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "aux: %s", hipGetErrorString(e));
+    uint32_t* sink = ws->aux.as<uint32_t>();
+    auto run = [&]() -> hipError_t {
+        if (copy)
+            return width_bytes == 4 ? launch_lds_stream<uint32_t, true>(grid, block, ilp, reps, sink, stream)
+                                    : launch_lds_stream<uint4, true>(grid, block, ilp, reps, sink, stream);
+        return width_bytes == 4 ? launch_lds_stream<uint32_t, false>(grid, block, ilp, reps, sink, stream)
+                                : launch_lds_stream<uint4, false>(grid, block, ilp, reps, sink, stream);
+    };
+    e = run();   // warm-up
+    if (e != hipSuccess) return hip_fail(e, "lds stream kernel");
+    hipEvent_t a, b;
+    PC_HIP(hipEventCreate(&a));
+    PC_HIP(hipEventCreate(&b));
+    PC_HIP(hipEventRecord(a, stream));
+    e = run();
+    PC_HIP(hipEventRecord(b, stream));
+    PC_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    PC_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "lds stream kernel");
+    const double bytes = (double)grid * block * reps * ilp * width_bytes * (copy ? 2 : 1);
+    *gbps = bytes / (ms * 1e-3) / 1e9;
+    return PCHASE_OK;
+}
 
 extern "C" uint64_t pchase_microbench_max_k(void) { return lds_record_bytes() / 8; }
 

@@ -6,26 +6,52 @@
 namespace pc {
 
 // ------------------------------------------------------ trace generation --
-// Probe p's k-th access visits (j0 + k*se) mod ne; each thread writes a run
-// of consecutive accesses, computing the first with one modulo and the rest
-// by adding se with a conditional wrap.
+// One block writes one chunk of 4096 consecutive accesses of one probe (the
+// chunks of all probes form a flat 1-D grid; a table built on the device
+// from the per-probe chunk offsets gives each block its probe and its chunk
+// within the probe in one load).  Each thread computes a
+// run of 16 consecutive accesses, the first from the closed form and the
+// rest incrementally; the block then transposes the chunk through LDS so
+// that consecutive threads store consecutive indices (coalesced writes
+// whatever the alignment of the probe's offset).
 constexpr int kTraceRun = 16;
+constexpr uint32_t kTraceThreads = 256;
+constexpr uint32_t kTraceChunk = kTraceThreads * kTraceRun;
+static_assert(kTraceChunk == kTraceChunkAccesses, "chunk size shared with the host");
+constexpr uint32_t kTraceLds = kTraceChunk + kTraceChunk / kTraceRun;   // one pad word per run
 
-__global__ void __launch_bounds__(256) trace_kernel(const DevProbe* probes, const uint64_t* off,
-                                                    uint32_t n_probes, int32_t* idx) {
-    const uint32_t p = blockIdx.x;
-    if (p >= n_probes) return;
+// v[r] is access 16 * threadIdx.x + r of the chunk starting at access k0.
+__device__ inline void store_chunk(const int32_t (&v)[kTraceRun], int32_t* out, uint64_t k0, uint64_t len,
+                                   int32_t* buf) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kTraceRun; ++r) buf[(kTraceRun + 1) * t + r] = v[r];   // word x at x + x/16
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTraceRun; ++i) {
+        const uint32_t x = i * kTraceThreads + t;
+        if (k0 + x < len) out[k0 + x] = buf[x + x / kTraceRun];
+    }
+}
+
+// Uniform chase (Listing 1 + Listing 2): access k visits (j0 + (k mod L)*se)
+// mod ne.
+__global__ void __launch_bounds__(kTraceThreads) trace_kernel(const DevProbe* probes, const uint64_t* off,
+                                                              const ChunkRef* chunks, int32_t* idx) {
+    __shared__ int32_t buf[kTraceLds];
+    const ChunkRef c = chunks[blockIdx.x];
+    const uint32_t p = c.probe;
     const DevProbe pr = probes[p];
     const uint64_t len = off[p + 1] - off[p];
-    int32_t* out = idx + off[p];
-    const uint64_t step = (uint64_t)gridDim.y * blockDim.x * kTraceRun;
-    for (uint64_t k = ((uint64_t)blockIdx.y * blockDim.x + threadIdx.x) * kTraceRun; k < len; k += step) {
-        const uint64_t kc = k % pr.L;
-        uint64_t j = (pr.j0 + kc * (uint64_t)pr.se) % pr.ne;
-        uint64_t kk = kc;
+    const uint64_t k0 = (uint64_t)c.chunk * kTraceChunk;
+    const uint64_t k = k0 + (uint64_t)threadIdx.x * kTraceRun;
+    int32_t v[kTraceRun] = {};
+    if (k < len) {                        // len < 2^32: 32-bit remainder
+        uint64_t kk = (uint32_t)k % (uint32_t)pr.L;
+        uint64_t j = (pr.j0 + kk * (uint64_t)pr.se) % pr.ne;
 #pragma unroll
-        for (int i = 0; i < kTraceRun; ++i) {
-            if (k + i < len) out[k + i] = (int32_t)j;
+        for (int r = 0; r < kTraceRun; ++r) {
+            v[r] = (int32_t)j;
             ++kk;
             if (kk == pr.L) {
                 kk = 0;
@@ -36,16 +62,88 @@ __global__ void __launch_bounds__(256) trace_kernel(const DevProbe* probes, cons
             }
         }
     }
+    store_chunk(v, idx + off[p], k0, len, buf);
 }
 
-hipError_t launch_trace(const DevProbe* probes, const uint64_t* off, uint32_t n_probes, uint64_t maxlen,
+// Non-uniform-stride chase (Section 5.2 / Fig. 13(b)): access k of a pass
+// lies in the segment with the last start <= k and visits
+// (pos + se * (k - start)) mod ne; the run moves to the next segment at its
+// start and back to the first segment at the end of a pass.
+__global__ void __launch_bounds__(kTraceThreads) trace_nu_kernel(const DevNuProbe* probes, const DevNuSeg* segs,
+                                                                 const uint64_t* off, const ChunkRef* chunks,
+                                                                 int32_t* idx) {
+    __shared__ int32_t buf[kTraceLds];
+    const ChunkRef c = chunks[blockIdx.x];
+    const uint32_t p = c.probe;
+    const DevNuProbe pr = probes[p];
+    const DevNuSeg* sg = segs + pr.first;
+    const uint64_t len = off[p + 1] - off[p];
+    const uint64_t k0 = (uint64_t)c.chunk * kTraceChunk;
+    const uint64_t k = k0 + (uint64_t)threadIdx.x * kTraceRun;
+    int32_t v[kTraceRun] = {};
+    if (k < len) {                        // len < 2^32: 32-bit remainder
+        const uint64_t kc = (uint32_t)k % (uint32_t)pr.pass_len;
+        uint32_t lo = 0, hi = pr.nseg - 1;            // last segment with start <= kc
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (sg[mid].start <= kc) lo = mid; else hi = mid - 1;
+        }
+        uint32_t i = lo;
+        DevNuSeg cur = sg[i];
+        uint64_t next = (i + 1 < pr.nseg) ? sg[i + 1].start : pr.pass_len;
+        uint64_t j = (cur.pos + (uint64_t)cur.se * ((kc - cur.start) % pr.ne)) % pr.ne;
+        uint64_t kk = kc;
+#pragma unroll
+        for (int r = 0; r < kTraceRun; ++r) {
+            v[r] = (int32_t)j;
+            ++kk;
+            if (kk == pr.pass_len) {          // pass ends: back to the start
+                kk = 0;
+                i = 0;
+                cur = sg[0];
+                next = (pr.nseg > 1) ? sg[1].start : pr.pass_len;
+                j = cur.pos;
+            } else if (kk == next) {          // next segment
+                ++i;
+                cur = sg[i];
+                next = (i + 1 < pr.nseg) ? sg[i + 1].start : pr.pass_len;
+                j = cur.pos;
+            } else {
+                j += cur.se;
+                if (j >= pr.ne) j -= pr.ne;
+            }
+        }
+    }
+    store_chunk(v, idx + off[p], k0, len, buf);
+}
+
+// Chunk table from the per-trace first chunks: block p writes the entries
+// of trace p.
+__global__ void __launch_bounds__(256) chunk_table_kernel(const uint64_t* chunk_off, ChunkRef* chunks) {
+    const uint32_t p = blockIdx.x;
+    const uint64_t c0 = chunk_off[p], n = chunk_off[p + 1] - c0;
+    for (uint64_t k = threadIdx.x; k < n; k += blockDim.x) chunks[c0 + k] = ChunkRef{p, (uint32_t)k};
+}
+
+hipError_t launch_chunk_table(const uint64_t* chunk_off, uint32_t n_traces, ChunkRef* chunks, hipStream_t stream) {
+    if (n_traces == 0) return hipSuccess;
+    hipLaunchKernelGGL(chunk_table_kernel, dim3(n_traces), dim3(256), 0, stream, chunk_off, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const DevProbe* probes, const uint64_t* off, const ChunkRef* chunks, uint64_t n_chunks,
                         int32_t* idx, hipStream_t stream) {
-    uint64_t per_block = 256ull * kTraceRun;
-    uint64_t y = (maxlen + per_block - 1) / per_block;
-    if (y < 1) y = 1;
-    if (y > 65535) y = 65535;
-    hipLaunchKernelGGL(trace_kernel, dim3(n_probes, (uint32_t)y), dim3(256), 0, stream, probes, off,
-                       n_probes, idx);
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(trace_kernel, dim3((uint32_t)n_chunks), dim3(kTraceThreads), 0, stream, probes, off, chunks,
+                       idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_nu(const DevNuProbe* probes, const DevNuSeg* segs, const uint64_t* off,
+                           const ChunkRef* chunks, uint64_t n_chunks, int32_t* idx, hipStream_t stream) {
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(trace_nu_kernel, dim3((uint32_t)n_chunks), dim3(kTraceThreads), 0, stream, probes, segs, off,
+                       chunks, idx);
     return hipGetLastError();
 }
 

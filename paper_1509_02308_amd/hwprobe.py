@@ -3,6 +3,7 @@ and the cache inference fed with real fine-grained P-chase latencies.
 
     python -m paper_1509_02308_amd.hwprobe stream [--bytes B] [--sweep]
     python -m paper_1509_02308_amd.hwprobe lds
+    python -m paper_1509_02308_amd.hwprobe ldsbw
     python -m paper_1509_02308_amd.hwprobe l1 [--flavor 0]
     python -m paper_1509_02308_amd.hwprobe curve --s 128 --n-lo 4096 --n-hi 131072
 
@@ -10,6 +11,8 @@ and the cache inference fed with real fine-grained P-chase latencies.
   shapes (blocks per CU x block size x words in flight per thread).
 * lds: average cycles per LDS load against the word stride of the 64 lanes
   (Section 6.2, the bank-conflict sweep).
+* ldsbw: LDS throughput over blocks per CU x block size x reads in flight,
+  4-byte and 16-byte accesses, read-only and LDS-to-LDS copy (Section 6.1).
 * curve: the classic average-latency curve (Section 4.1): for each array
   size N, the mean and median cycles per access of a P-chase.
 * l1: the Section 4.2 procedure on the per-CU vector L1: fine-grained
@@ -68,6 +71,27 @@ def cmd_lds(a):
     c = cyc.cpu().numpy() / 100.0
     print(json.dumps({"probe": "lds_bank", "stride_words": list(range(1, 65)),
                       "cycles_per_load": [round(float(v), 2) for v in c]}), flush=True)
+
+
+def cmd_ldsbw(a):
+    torch, capi = _torch_capi()
+    best = {}
+    for copy in (False, True):
+        for width in (4, 16):
+            for bpc in (1, 2, 4, 8):
+                for block in (64, 256, 1024):
+                    for ilp in (1, 2, 4, 8):
+                        if bpc * block > 2048:
+                            continue
+                        g = capi.microbench_lds_stream(bpc, block, ilp, width, a.reps, copy=copy)
+                        row = {"probe": "lds_stream", "copy": copy, "width_bytes": width, "blocks_per_cu": bpc,
+                               "block": block, "ilp": ilp, "GBps": g,
+                               "bytes_per_clk_per_cu": g * 1e9 / (256 * 2.4e9)}
+                        print(json.dumps(row), flush=True)
+                        if copy not in best or g > best[copy]["GBps"]:
+                            best[copy] = row
+    for row in best.values():
+        print(json.dumps({**row, "probe": "lds_stream_best"}), flush=True)
 
 
 def _chase(torch, capi, N, s, passes, flavor, arr):
@@ -148,6 +172,8 @@ def main(argv=None):
     p.add_argument("--sweep", action="store_true")
     p = sub.add_parser("lds")
     p.add_argument("--reps", type=int, default=16)
+    p = sub.add_parser("ldsbw")
+    p.add_argument("--reps", type=int, default=2048)
     p = sub.add_parser("curve")
     p.add_argument("--s", type=int, default=128)
     p.add_argument("--n-lo", type=int, default=4096)
@@ -157,7 +183,7 @@ def main(argv=None):
     p = sub.add_parser("l1")
     p.add_argument("--flavor", type=int, default=0)
     a = ap.parse_args(argv)
-    {"stream": cmd_stream, "lds": cmd_lds, "curve": cmd_curve, "l1": cmd_l1}[a.cmd](a)
+    {"stream": cmd_stream, "lds": cmd_lds, "ldsbw": cmd_ldsbw, "curve": cmd_curve, "l1": cmd_l1}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -131,3 +131,44 @@ def large_batch(n_pairs: int, seed: int = 4711, len_lo: int = 1000, len_hi: int 
         per_pass = max(1, int(round(L / p)))
         prow.append((int(per_pass * s), int(s), int(p)))
     return models(mrows), probes(prow)
+
+
+# --------------------------------------------------------------------------
+# Non-uniform-stride chases (Section 5.2, Fig. 13(b)): rows
+# (N, [(s_bytes, count), ...], passes, j0, base).
+# --------------------------------------------------------------------------
+def section52_rows(s1: int = 32 << 20, s2: int = 1 << 20, lines: int = 65, revisits: int = 3,
+                   in_line: int = 64, passes: int = 2):
+    """The Section 5.2 construction, scaled by its parameters: `lines` far
+    steps of s1 over an array of lines * s1 bytes (every access a new line
+    and page), the same lines `revisits` more times, `lines` steps of s2
+    (s2 < s1: nearby pages), then `in_line` one-element steps."""
+    N = lines * s1
+    return [(N, [(s1, lines), (s1, lines * revisits), (s2, lines), (4, in_line)], passes, 0, 0)]
+
+
+def nonuniform_rows(n: int = 48, seed: int = 52, n_lo: int = 64, n_hi: int = 4 << 20, max_count: int = 3000):
+    """Random non-uniform chases: N log-uniform on [n_lo, n_hi] bytes, 1-8
+    segments whose strides mix one element, a few lines, a large fraction of
+    N, zero and more than N, counts 1..max_count, 1-3 passes, random start
+    and base offset."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for _ in range(n):
+        N = 4 * max(1, int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))) // 4)
+        segs = []
+        for _ in range(int(rng.integers(1, 9))):
+            kind = int(rng.integers(5))
+            if kind == 0:
+                s = 4
+            elif kind == 1:
+                s = 4 * int(rng.integers(1, 129))
+            elif kind == 2:
+                s = 4 * int(rng.integers(0, N // 4))
+            elif kind == 3:
+                s = 0
+            else:
+                s = 4 * int(rng.integers(N // 4, 4 * (N // 4) + 1))
+            segs.append((s, int(rng.integers(1, max_count + 1))))
+        rows.append((N, segs, int(rng.integers(1, 4)), int(rng.integers(0, N // 4)), 4 * int(rng.integers(0, 1024))))
+    return rows

@@ -40,6 +40,8 @@ def test_struct_layouts_match_header(capi):
     assert ctypes.sizeof(capi.PchaseModel) == 40
     assert ctypes.sizeof(capi.PchaseProbe) == 40
     assert ctypes.sizeof(capi.PchaseResult) == 48
+    assert ctypes.sizeof(capi.PchaseSegment) == 16
+    assert ctypes.sizeof(capi.PchaseNuProbe) == 40
 
 
 def _rc(capi, rc):
@@ -143,6 +145,39 @@ def test_microbench_argument_checks(capi):
                                ctypes.c_void_p(16), ctypes.byref(ovh), None) == -2   # array too small
     assert L.microbench_pchase(ctypes.byref(p), 9, ctypes.c_void_p(16), 8192, 10, ctypes.c_void_p(16),
                                ctypes.c_void_p(16), ctypes.byref(ovh), None) == -1   # flavour
+    for args in ((0, 64, 1, 4, 0), (1, 100, 1, 4, 0), (1, 64, 3, 4, 0), (1, 64, 1, 8, 0), (1, 64, 1, 4, 2)):
+        assert L.microbench_lds_stream(*args, 1, ctypes.byref(g), None) == -1
+
+
+def test_nonuniform_trace_len_and_validation(capi, orc):
+    """Host-only checks of the non-uniform chase (Section 5.2): the length
+    agrees with the oracle; invalid probes are rejected before any launch."""
+    rows = [(96, [(32, 1), (16, 1), (8, 1), (16, 1), (8, 2), (80, 1), (8, 3)], 3),
+            (65 * (32 << 20), [(32 << 20, 260), (4, 64)], 2, 7)]
+    parr, sarr = capi.nu_probes(rows)
+    for i, r in enumerate(rows):
+        n, K = capi.pchase_trace_nu_len(parr, sarr, i)
+        assert n == len(orc.trace_nu(r[0], r[1], passes=r[2], j0=r[3] if len(r) > 3 else 0))
+        assert K * r[2] == n
+    L = capi.lib()
+    n, K = ctypes.c_uint64(), ctypes.c_uint64()
+    bad = [capi.nu_probes([(64, [(4, 0)])]),                 # empty segment
+           capi.nu_probes([(64, [(6, 2)])]),                 # stride not a multiple of elem
+           capi.nu_probes([(64, [(4, 2)], 1, 16)]),          # start outside the array
+           capi.nu_probes([(64, [], 1)]),                    # no segment
+           capi.nu_probes([(64, [(4, 1 << 31)], 2)])]        # 2^32 accesses
+    for parr, sarr in bad:
+        assert L.pchase_trace_nu_len(ctypes.byref(parr[0]), ctypes.cast(sarr, ctypes.c_void_p), sarr.n,
+                                     ctypes.byref(n), ctypes.byref(K)) in (-1, -2)
+    parr, sarr = capi.nu_probes([(64, [(4, 2)])])
+    parr[0].first_segment = 1                                 # segment range outside the array
+    assert L.pchase_trace_nu_len(ctypes.byref(parr[0]), ctypes.cast(sarr, ctypes.c_void_p), sarr.n,
+                                 ctypes.byref(n), ctypes.byref(K)) == -1
+    parr, sarr = capi.nu_probes([(4096, [(4, 1000)], 2)])
+    off = (ctypes.c_uint64 * 2)()
+    rc = L.pchase_trace_nu(ctypes.cast(parr, ctypes.c_void_p), 1, ctypes.cast(sarr, ctypes.c_void_p), 1,
+                           ctypes.c_void_p(16), off, 100, None)
+    assert rc == -2 and "capacity" in capi.last_error()
 
 
 def test_mlp_grid_matches_reference(capi):

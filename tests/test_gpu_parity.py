@@ -365,6 +365,20 @@ def test_microbench_hbm_stream_positive():
     assert torch.equal(src, dst)
 
 
+def test_microbench_lds_stream_occupancy_and_bound():
+    torch, capi = need_gpu()
+    say("microbench_lds_stream")
+    lo = capi.microbench_lds_stream(1, 64, 1, 4, 512)     # one wave per CU, one read in flight
+    hi = capi.microbench_lds_stream(4, 256, 4, 16, 512)   # 16 waves per CU, 4 wide reads in flight
+    # latency-bound vs throughput-bound; and no more than 256 B/clk/CU at 2.4 GHz on 256 CUs
+    # (a figure above that would mean the loads were not all executed)
+    assert 0 < lo and 2 * lo < hi < 256 * 2.4 * 256
+    cp = capi.microbench_lds_stream(4, 256, 4, 16, 512, copy=True)
+    assert 2 * lo < cp < 256 * 2.4 * 256
+    with pytest.raises(capi.PchaseError):
+        capi.microbench_lds_stream(4, 100, 4, 4, 1)
+
+
 def test_trace_array_replay_mixed_set_counts_reusing_slabs():
     """Regression: one lane group replays pair after pair of models with the
     same way-group width but different set counts, so its state slab is
