@@ -11,6 +11,9 @@ through Microbenchmarking"):
 * :func:`trace_nu` -- Section 5.2 / Fig. 13(b): the non-uniform-stride chase.
 * :func:`replay` -- Section 4.1 set-associative model (Assumptions 1-3),
   plus the non-LRU policies of Sections 4.5/4.6.
+* :func:`replay_general` -- the organisations of Sections 4.3-4.5 that break
+  those assumptions: per-set associativity (L2 TLB), a set table (texture
+  L1), weighted random replacement (Fermi L1).
 * :func:`classify`, :func:`auto_threshold` -- Section 4.1, t = t0 + tm*r.
 * :func:`infer` -- Section 4.2 / Fig. 6, as an exhaustive exact search.
 * :func:`philox` -- Philox4x32-10 (Salmon et al., SC'11).
@@ -27,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-LRU, FIFO, PLRU, RANDOM = 0, 1, 2, 3
+LRU, FIFO, PLRU, RANDOM, WRANDOM = 0, 1, 2, 3, 4
 
 
 class OrcModel(ctypes.Structure):
@@ -37,6 +40,12 @@ class OrcModel(ctypes.Structure):
 
 class OrcNuProbe(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("n_bytes", "base", "j0", "elem", "passes", "n_segments")]
+
+
+class OrcGeneral(ctypes.Structure):
+    _fields_ = [("line", ctypes.c_uint64), ("sets", ctypes.c_uint64), ("ways", ctypes.c_void_p),
+                ("policy", ctypes.c_uint64), ("set_shift", ctypes.c_uint64), ("table_len", ctypes.c_uint64),
+                ("table", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("seed", ctypes.c_uint64)]
 
 
 class OrcProbe(ctypes.Structure):
@@ -75,6 +84,10 @@ def lib():
         L.orc_trace_nu_len.restype = u64
         L.orc_trace_nu.argtypes = [ctypes.POINTER(OrcNuProbe), p, p, p, u64]
         L.orc_trace_nu.restype = u64
+        L.orc_general_check.argtypes = [ctypes.POINTER(OrcGeneral)]
+        L.orc_general_check.restype = ctypes.c_int
+        L.orc_replay_general.argtypes = [ctypes.POINTER(OrcGeneral), p, u64, u64, u64, u64, u64, p, p, p]
+        L.orc_replay_general.restype = ctypes.c_int
         L.orc_model_check.argtypes = [ctypes.POINTER(OrcModel)]
         L.orc_model_check.restype = ctypes.c_int
         L.orc_replay.argtypes = [ctypes.POINTER(OrcModel), p, u64, u64, u64, u64, u64, p, p, p]
@@ -144,6 +157,38 @@ def trace_nu(N, segments, passes=1, j0=0, base=0, elem=4) -> np.ndarray:
     if got != n:
         raise ValueError("invalid non-uniform probe")
     return out
+
+
+class General:
+    """A generalised cache (see oracle.h): line bytes, per-set ways, policy,
+    optional set_shift, set table and WRANDOM weights.  Keeps its arrays
+    alive for the C struct."""
+
+    def __init__(self, line, ways, policy=LRU, set_shift=0, table=None, weights=None, seed=0):
+        self.ways = np.ascontiguousarray(ways, dtype=np.uint64)
+        self.table = None if table is None else np.ascontiguousarray(table, dtype=np.uint64)
+        self.weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint64)
+        self.line, self.policy, self.set_shift, self.seed = int(line), int(policy), int(set_shift), int(seed)
+        self.c = OrcGeneral(self.line, len(self.ways), _ptr(self.ways), self.policy, self.set_shift,
+                            0 if self.table is None else len(self.table),
+                            None if self.table is None else _ptr(self.table),
+                            None if self.weights is None else _ptr(self.weights), self.seed)
+
+    def ok(self) -> bool:
+        return lib().orc_general_check(ctypes.byref(self.c)) == 0
+
+
+def replay_general(g: General, idx, base=0, elem=4, trace_id=0, count_from=0):
+    """Returns (hits uint8[len], misses_total, misses_steady)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    hits = np.empty(max(len(idx), 1), dtype=np.uint8)
+    mt = ctypes.c_uint64()
+    ms = ctypes.c_uint64()
+    rc = lib().orc_replay_general(ctypes.byref(g.c), _ptr(idx), len(idx), base, elem, trace_id,
+                                  count_from, _ptr(hits), ctypes.byref(mt), ctypes.byref(ms))
+    if rc != 0:
+        raise ValueError(f"orc_replay_general failed ({rc})")
+    return hits[: len(idx)], int(mt.value), int(ms.value)
 
 
 def model_ok(model: OrcModel) -> bool:

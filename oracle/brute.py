@@ -204,3 +204,82 @@ def hits_for(policy: int, idx, b, a, T, seed=0, trace_id=0, base=0, elem=4, set_
     if policy == 2:
         return plru_hits(idx, b, a, T, base, elem, set_shift)
     return random_hits(idx, b, a, T, seed, trace_id, base, elem, set_shift)
+
+
+def general_hits(policy: int, idx, b, ways, table=None, weights=None, seed=0, trace_id=0, base=0, elem=4,
+                 set_shift=0):
+    """Generalised cache restated per set: set t has ways[t] ways; the set of
+    an access is table[unit mod len(table)] (or unit mod len(ways)); LRU by
+    reuse distance, FIFO by queue, tree-PLRU by node objects, RANDOM and
+    weighted random by a list of ways and the pure-Python Philox (the weighted
+    victim is found by walking the weights: u mod S falls in the w-th
+    interval of widths weights[0], weights[1], ...)."""
+    T = len(ways)
+    seq = []
+    for j in idx:
+        addr = base + elem * j
+        line = addr // b
+        unit = (addr >> set_shift) if set_shift else line
+        seq.append((line, table[unit % len(table)] if table is not None else unit % T))
+    hits = []
+    state = {}
+    key = (seed & MASK32, seed >> 32)
+    for k, (line, s) in enumerate(seq):
+        a = ways[s]
+        if policy == 0:
+            last = None
+            for q in range(k - 1, -1, -1):
+                if seq[q][0] == line:
+                    last = q
+                    break
+            if last is None:
+                hits.append(0)
+            else:
+                between = {seq[q][0] for q in range(last + 1, k) if seq[q][1] == s}
+                hits.append(1 if len(between) < a else 0)
+            continue
+        if policy == 1:
+            q = state.setdefault(s, deque())
+            if line in q:
+                hits.append(1)
+                continue
+            hits.append(0)
+            if len(q) == a:
+                q.popleft()
+            q.append(line)
+            continue
+        if policy == 2:
+            root = state.get(s)
+            if root is None:
+                root = state[s] = _build_tree(0, a)
+            leaves = _leaves(root)
+            found = [lf for lf in leaves if lf.line == line]
+            if found:
+                hits.append(1)
+                _touch(root, found[0].way, a)
+                continue
+            hits.append(0)
+            empty = [lf for lf in leaves if lf.line is None]
+            leaf = empty[0] if empty else _victim(root)
+            leaf.line = line
+            _touch(root, leaf.way, a)
+            continue
+        w = state.setdefault(s, [None] * a)
+        if line in w:
+            hits.append(1)
+            continue
+        hits.append(0)
+        if None in w:
+            w[w.index(None)] = line
+            continue
+        u = philox4x32_10((k & MASK32, k >> 32, trace_id & MASK32, trace_id >> 32), key)[0]
+        if policy == 3:
+            w[u % a] = line
+        else:
+            r = u % sum(weights[:a])
+            v = 0
+            while r >= weights[v]:
+                r -= weights[v]
+                v += 1
+            w[v] = line
+    return hits

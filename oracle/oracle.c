@@ -297,6 +297,127 @@ int orc_replay(const orc_model *m, const int32_t *idx, uint64_t len,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Generalised cache: sets of their own associativity, a table mapping and
+ * weighted random replacement.  Same fill rule (lowest empty way first) and
+ * the same per-set LRU/FIFO stamps, PLRU trees and Philox draws as above,
+ * each set sized by its own way count.                                      */
+/* ---------------------------------------------------------------------- */
+int orc_general_check(const orc_general *g)
+{
+    if (g->line == 0 || !is_pow2(g->line) || g->sets == 0 || g->ways == NULL) return -1;
+    if (g->policy > ORC_WRANDOM) return -1;
+    if (g->set_shift != 0 && (g->set_shift >= 63 || (1ull << g->set_shift) < g->line)) return -1;
+    if (g->table_len != 0) {
+        if (g->table == NULL) return -1;
+        for (uint64_t i = 0; i < g->table_len; ++i)
+            if (g->table[i] >= g->sets) return -1;
+    }
+    for (uint64_t t = 0; t < g->sets; ++t) {
+        if (g->ways[t] == 0) return -1;
+        if (g->policy == ORC_PLRU && !is_pow2(g->ways[t])) return -1;
+        if (g->policy == ORC_WRANDOM) {
+            if (g->weights == NULL) return -1;
+            uint64_t sum = 0;
+            for (uint64_t w = 0; w < g->ways[t]; ++w) sum += g->weights[w];
+            if (sum == 0 || sum > 65536) return -1;
+        }
+    }
+    return 0;
+}
+
+static uint64_t weighted_victim(const orc_general *g, uint64_t a, uint64_t k, uint64_t trace_id)
+{
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32),
+                       (uint32_t)trace_id, (uint32_t)(trace_id >> 32)};
+    uint32_t key[2] = {(uint32_t)g->seed, (uint32_t)(g->seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    uint64_t sum = 0;
+    for (uint64_t w = 0; w < a; ++w) sum += g->weights[w];
+    uint64_t r = (uint64_t)out[0] % sum;
+    uint64_t cum = 0;
+    for (uint64_t w = 0; w < a; ++w) {
+        cum += g->weights[w];
+        if (r < cum) return w;
+    }
+    return a - 1;  /* not reached: r < sum */
+}
+
+int orc_replay_general(const orc_general *g, const int32_t *idx, uint64_t len,
+                       uint64_t base, uint64_t elem, uint64_t trace_id,
+                       uint64_t count_from, uint8_t *hits,
+                       uint64_t *misses_total, uint64_t *misses_steady)
+{
+    if (orc_general_check(g) != 0 || elem == 0) return -1;
+    /* each set's ways live at first[t] .. first[t] + ways[t] - 1 */
+    uint64_t *first = (uint64_t *)calloc(g->sets + 1, sizeof(uint64_t));
+    if (!first) return -3;
+    for (uint64_t t = 0; t < g->sets; ++t) first[t + 1] = first[t] + g->ways[t];
+    const uint64_t total = first[g->sets];
+    uint8_t *valid = (uint8_t *)calloc(total, 1);
+    uint64_t *tag = (uint64_t *)calloc(total, sizeof(uint64_t));
+    uint64_t *stamp = (uint64_t *)calloc(total, sizeof(uint64_t));
+    uint8_t *tree = (uint8_t *)calloc(total, 1);   /* a-1 node bits of a set at first[t] */
+    if (!valid || !tag || !stamp || !tree) {
+        free(first); free(valid); free(tag); free(stamp); free(tree);
+        return -3;
+    }
+    uint64_t mt = 0, ms = 0;
+    int rc = 0;
+    for (uint64_t k = 0; k < len; ++k) {
+        if (idx[k] < 0) { rc = -1; break; }
+        uint64_t addr = base + elem * (uint64_t)idx[k];
+        uint64_t line = addr / g->line;
+        uint64_t unit = g->set_shift ? (addr >> g->set_shift) : line;
+        uint64_t set = g->table_len ? g->table[unit % g->table_len] : unit % g->sets;
+        uint64_t a = g->ways[set], o = first[set];
+        int64_t way = -1;
+        for (uint64_t w = 0; w < a; ++w)
+            if (valid[o + w] && tag[o + w] == line) way = (int64_t)w;
+        int hit = (way >= 0);
+        if (hit) {
+            if (g->policy == ORC_LRU) stamp[o + way] = k;
+            if (g->policy == ORC_PLRU && a > 1) plru_touch(tree + o, a, (uint64_t)way);
+        } else {
+            int64_t empty = -1;
+            for (uint64_t w = 0; w < a && empty < 0; ++w)
+                if (!valid[o + w]) empty = (int64_t)w;
+            uint64_t v;
+            if (empty >= 0) {
+                v = (uint64_t)empty;
+            } else if (g->policy == ORC_LRU || g->policy == ORC_FIFO) {
+                v = 0;
+                for (uint64_t w = 1; w < a; ++w)
+                    if (stamp[o + w] < stamp[o + v]) v = w;
+            } else if (g->policy == ORC_PLRU) {
+                v = a > 1 ? plru_victim(tree + o, a) : 0;
+            } else if (g->policy == ORC_RANDOM) {
+                uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32),
+                                   (uint32_t)trace_id, (uint32_t)(trace_id >> 32)};
+                uint32_t key[2] = {(uint32_t)g->seed, (uint32_t)(g->seed >> 32)};
+                uint32_t out[4];
+                orc_philox4x32_10(ctr, key, out);
+                v = (uint64_t)out[0] % a;
+            } else {
+                v = weighted_victim(g, a, k, trace_id);
+            }
+            valid[o + v] = 1;
+            tag[o + v] = line;
+            stamp[o + v] = k;
+            if (g->policy == ORC_PLRU && a > 1) plru_touch(tree + o, a, v);
+            mt += 1;
+            if (k >= count_from) ms += 1;
+        }
+        if (hits) hits[k] = (uint8_t)hit;
+    }
+    free(first); free(valid); free(tag); free(stamp); free(tree);
+    if (rc) return rc;
+    if (misses_total) *misses_total = mt;
+    if (misses_steady) *misses_steady = ms;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Latency -> hit/miss.  The paper's average-latency model t = t0 + tm*r
  * separates accesses into a fast (hit) and a slow (miss) population; the
  * threshold is the lower end of the widest gap between distinct values.   */

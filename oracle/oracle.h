@@ -94,6 +94,42 @@ int orc_replay(const orc_model *m, const int32_t *idx, uint64_t len,
                uint64_t count_from, uint8_t *hits,
                uint64_t *misses_total, uint64_t *misses_steady);
 
+/*
+ * Generalised cache (the organisations the paper finds that break
+ * Assumptions 1-2 or 3): per-set associativity (the L2 TLB of Sec. 4.4 and
+ * Fig. 9: one set of 17 entries and six of 8), a table from the set unit to
+ * the set (the texture-L1 and read-only-cache mappings of Sec. 4.3), and
+ * weighted random replacement (the Fermi L1 of Sec. 4.5: way 2 replaced
+ * with probability 1/2, the others 1/6).
+ *   unit = set_shift ? addr >> set_shift : addr / line
+ *   set  = table_len ? table[unit mod table_len] : unit mod sets
+ * Set t has ways[t] ways.  ORC_WRANDOM draws u = Philox4x32-10(key = seed,
+ * counter = (k_lo, k_hi, trace_lo, trace_hi)).x for access k and evicts the
+ * lowest way w with (u mod S) < weights[0] + ... + weights[w], S being the
+ * sum of the set's first ways[t] weights.
+ */
+enum { ORC_WRANDOM = 4 };
+
+typedef struct orc_general {
+    uint64_t line;            /* b, bytes, power of two */
+    uint64_t sets;            /* T */
+    const uint64_t *ways;     /* [T], each >= 1 */
+    uint64_t policy;          /* ORC_LRU .. ORC_WRANDOM */
+    uint64_t set_shift;
+    uint64_t table_len;
+    const uint64_t *table;    /* [table_len], entries < T */
+    const uint64_t *weights;  /* ORC_WRANDOM: one per way of the widest set */
+    uint64_t seed;
+} orc_general;
+
+/* 0 if valid, negative otherwise. */
+int orc_general_check(const orc_general *g);
+/* As orc_replay, for a generalised cache. */
+int orc_replay_general(const orc_general *g, const int32_t *idx, uint64_t len,
+                       uint64_t base, uint64_t elem, uint64_t trace_id,
+                       uint64_t count_from, uint8_t *hits,
+                       uint64_t *misses_total, uint64_t *misses_steady);
+
 /* Latency -> hit bit: hit iff lat <= theta. */
 void orc_classify(const uint32_t *lat, uint64_t n, uint32_t theta, uint8_t *hits);
 /* Largest-gap threshold over the distinct latency values. */
