@@ -337,7 +337,8 @@ def nonuniform_leg(torch, capi, W, args, stream):
     around the call after a warm-up call: bound by the 4-byte index writes),
     then each trace is replayed through one of 16 caches (8-64 KB, 64 B lines,
     4-32 ways, all four policies) with hit bits and both miss counts, timed
-    after a warm-up.  Parity on such traces is checked by the GPU tests."""
+    after a warm-up, and once more through the paper-shaped generalised
+    caches.  Parity on such traces is checked by the GPU tests."""
     rows = W.nonuniform_rows(n=args.nu_probes, seed=5209, n_hi=64 << 20, max_count=60_000)
     parr, sarr = capi.nu_probes(rows)
     lens = np.array([capi.pchase_trace_nu_len(parr, sarr, i)[0] for i in range(len(rows))], dtype=np.uint64)
@@ -366,11 +367,25 @@ def nonuniform_leg(torch, capi, W, args, stream):
     capi.cache_replay_batch(marr, idx, off, bases, pm, pt, None, misses, bits, bitoff)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same traces through the paper-shaped generalised caches (texture L1,
+    # table-mapped read-only cache, unequal-set L2 TLB, weighted-random Fermi
+    # L1), one per trace in turn
+    targets = [{k: v for k, v in d.items() if k != "name"} for d in W.paper_general_targets()]
+    garr = capi.general_models(targets)
+    gm = (np.arange(n) % len(targets)).astype(np.uint32)
+    capi.cache_replay_general(garr, idx, off, bases, gm, pt, None, misses, bits, bitoff)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.cache_replay_general(garr, idx, off, bases, gm, pt, None, misses, bits, bitoff)
+    torch.cuda.synchronize()
+    gdt = time.perf_counter() - t0
     del idx, bits
     gbps = 4 * total / (gen_ms * 1e-3) / 1e9
     return {"probes": n, "segments": int(sarr.n), "accesses": total,
             "trace_gen_ms": gen_ms, "trace_gen_GBps": gbps, "trace_gen_hbm_frac": gbps / 8000.0,
-            "replay_s": dt, "value": total / dt, "unit": "accesses/s"}
+            "replay_s": dt, "value": total / dt, "unit": "accesses/s",
+            "general_replay_s": gdt, "general_value": total / gdt,
+            "general_targets": [d["name"] for d in W.paper_general_targets()]}
 
 
 def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):

@@ -67,7 +67,8 @@ enum {
     PCHASE_LRU = 0,
     PCHASE_FIFO = 1,
     PCHASE_PLRU = 2,
-    PCHASE_RANDOM = 3
+    PCHASE_RANDOM = 3,
+    PCHASE_WRANDOM = 4   /* weighted random: generalised models only */
 };
 
 /* A cache model (Table 4 notation).  Valid iff sets*ways*line_bytes ==
@@ -161,6 +162,37 @@ int pchase_trace_nu_len(const pchase_nu_probe *probe, const pchase_segment *segs
 int pchase_trace_nu(const pchase_nu_probe *probes, uint32_t n_probes, const pchase_segment *segs,
                     uint32_t n_segs, int32_t *idx_dev, uint64_t *off, uint64_t cap, hipStream_t stream);
 
+/* Generalised cache model: the organisations the paper finds that break
+ * Assumptions 1-3.
+ *   - set_ways: each set has its own associativity (the L2 TLB of
+ *     Section 4.4 / Fig. 9: one set of 17 entries and six of 8);
+ *   - set_table: the set of an address is set_table[unit mod table_len]
+ *     (unit = address >> set_shift, or address / line_bytes when set_shift
+ *     is 0), for mappings that are not a bit field (the read-only and
+ *     texture caches of Section 4.3); table_len = 0 keeps unit mod n_sets;
+ *   - PCHASE_WRANDOM: a miss in a full set of a ways draws
+ *     u = Philox4x32-10(key = seed, counter = (k_lo, k_hi, trace_lo,
+ *     trace_hi)).x and evicts the lowest way w with
+ *     (u mod S) < way_weights[0] + ... + way_weights[w], S being the sum of
+ *     the set's first a weights (the Fermi L1 of Section 4.5: weights
+ *     1, 3, 1, 1 replace way 2 half of the time).
+ * Valid iff line_bytes is a power of two >= 4, 1 <= n_sets, every set has
+ * 1..128 ways (a power of two for PLRU), every table entry is below n_sets,
+ * set_shift is 0 or >= log2(line_bytes), and for WRANDOM each set's weight
+ * sum is in [1, 65536].  All arrays are host memory, read during the call. */
+typedef struct pchase_general_model {
+    uint32_t line_bytes;
+    uint32_t n_sets;
+    uint32_t policy;                /* PCHASE_LRU .. PCHASE_WRANDOM */
+    uint32_t set_shift;
+    const uint32_t *set_ways;       /* n_sets entries */
+    const uint32_t *set_table;      /* table_len entries, or NULL */
+    uint32_t table_len;
+    uint32_t weights_len;           /* entries of way_weights (>= the widest set for WRANDOM) */
+    const uint32_t *way_weights;    /* WRANDOM only, else NULL */
+    uint64_t seed;                  /* RANDOM / WRANDOM key */
+} pchase_general_model;
+
 /* ------------------------------------------------------------ replay --- */
 /* Replay scheduling: BATCHED runs every pair in one captured graph of
  * persistent kernels fed by a cost-ordered work queue; PLAIN launches one
@@ -193,6 +225,17 @@ int cache_replay_batch(const pchase_model *models, uint32_t n_models,
                        const uint64_t *count_from, uint64_t n_pairs,
                        uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
                        uint32_t mode, hipStream_t stream);
+
+/* cache_replay_batch for generalised models (the declarations above):
+ * same traces, pairs, outputs, ownership and errors.  A pair's state slab
+ * holds n_sets 32-byte headers and 8 bytes per way; a long pair whose state
+ * is at most 256 KB replays as up to 64 parts by set, each with its own copy
+ * of that layout. */
+int cache_replay_general(const pchase_general_model *models, uint32_t n_models, const int32_t *idx_dev,
+                         const uint64_t *trace_off, const uint64_t *trace_base, uint32_t elem_bytes,
+                         uint32_t n_traces, const uint32_t *pair_model, const uint32_t *pair_trace,
+                         const uint64_t *count_from, uint64_t n_pairs, uint64_t *misses_dev,
+                         uint32_t *hitbits_dev, const uint64_t *bitoff, uint32_t mode, hipStream_t stream);
 
 /* Same replay with traces given as probes instead of index arrays: pair i
  * replays probe pair_probe[i] through model pair_model[i]; the trace id of

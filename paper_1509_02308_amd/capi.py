@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpchase.so")
 
 PCHASE_OK = 0
-LRU, FIFO, PLRU, RANDOM = 0, 1, 2, 3
+LRU, FIFO, PLRU, RANDOM, WRANDOM = 0, 1, 2, 3, 4
 BATCHED, PLAIN = 0, 1
 PROBES_ALL, PROBES_OWN_SWEEP = 0, 1
 EXHAUSTIVE, LEARNED = 0, 1
@@ -37,6 +37,12 @@ class PchaseModel(ctypes.Structure):
 class PchaseProbe(ctypes.Structure):
     _fields_ = [("n_bytes", u64), ("s_bytes", u64), ("base_offset", u64), ("j0", u64),
                 ("elem_bytes", u32), ("passes", u32)]
+
+
+class PchaseGeneralModel(ctypes.Structure):
+    _fields_ = [("line_bytes", u32), ("n_sets", u32), ("policy", u32), ("set_shift", u32),
+                ("set_ways", vp), ("set_table", vp), ("table_len", u32), ("weights_len", u32),
+                ("way_weights", vp), ("seed", u64)]
 
 
 class PchaseSegment(ctypes.Structure):
@@ -76,6 +82,7 @@ def lib():
         L.pchase_last_error.restype = ctypes.c_char_p
         L.pchase_trace_len.argtypes = [ctypes.POINTER(PchaseProbe), vp, vp]
         L.pchase_trace.argtypes = [vp, u32, vp, vp, u64, vp]
+        L.cache_replay_general.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
         L.pchase_trace_nu_len.argtypes = [ctypes.POINTER(PchaseNuProbe), vp, u32, vp, vp]
         L.pchase_trace_nu.argtypes = [vp, u32, vp, u32, vp, vp, u64, vp]
         L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
@@ -243,6 +250,40 @@ def cache_replay_batch(model_arr, idx, trace_off, trace_base, pair_model, pair_t
     check(lib().cache_replay_batch(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
                                    len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
                                    p_bo, mode, _stream(stream)))
+
+
+def general_models(rows) -> ctypes.Array:
+    """Generalised model descriptors from dicts with keys line, ways (list,
+    one per set), policy, and optionally set_shift, table (list), weights
+    (list) and seed.  The returned array keeps its host arrays alive."""
+    rows = list(rows)
+    out = (PchaseGeneralModel * max(len(rows), 1))()
+    keep = []
+    for i, r in enumerate(rows):
+        ways = np.ascontiguousarray(r["ways"], dtype=np.uint32)
+        table = None if r.get("table") is None else np.ascontiguousarray(r["table"], dtype=np.uint32)
+        weights = None if r.get("weights") is None else np.ascontiguousarray(r["weights"], dtype=np.uint32)
+        keep += [ways, table, weights]
+        out[i] = PchaseGeneralModel(int(r["line"]), len(ways), int(r.get("policy", LRU)), int(r.get("set_shift", 0)),
+                                    ways.ctypes.data, None if table is None else table.ctypes.data,
+                                    0 if table is None else len(table), 0 if weights is None else len(weights),
+                                    None if weights is None else weights.ctypes.data, int(r.get("seed", 0)))
+    out.n = len(rows)
+    out.keep = keep
+    return out
+
+
+def cache_replay_general(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
+                         misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None):
+    toff, p_toff = _hptr(trace_off, np.uint64)
+    tb, p_tb = _hptr(trace_base, np.uint64)
+    pm, p_pm = _hptr(pair_model, np.uint32)
+    pt, p_pt = _hptr(pair_trace, np.uint32)
+    cf, p_cf = _hptr(count_from, np.uint64)
+    bo, p_bo = _hptr(bitoff, np.uint64)
+    check(lib().cache_replay_general(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
+                                     len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
+                                     p_bo, mode, _stream(stream)))
 
 
 def cache_replay_probes(model_arr, probe_arr, pair_model, pair_probe, count_from, misses, hitbits=None,

@@ -270,6 +270,91 @@ extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models
 }
 
 // -------------------------------------------------- trace-array replay ---
+// Host-side descriptors of generalised models: per model its DevGeneral and
+// the state bytes of one pair; flat per-set (ways, entry base), set tables
+// and cumulative way weights.
+struct GeneralDesc {
+    std::vector<DevGeneral> gen;
+    std::vector<uint64_t> state;
+    std::vector<uint2> set_info;
+    std::vector<uint32_t> table;
+    std::vector<uint32_t> cum;
+};
+
+static int build_general(const pchase_general_model* models, uint32_t n, std::vector<DevModel>* dm,
+                         GeneralDesc* gd) {
+    if (n && !models) return set_error(PCHASE_EINVAL, "models is NULL");
+    dm->assign(n, DevModel{});
+    gd->gen.assign(n, DevGeneral{});
+    gd->state.assign(n, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const pchase_general_model& g = models[i];
+        const uint32_t b = g.line_bytes;
+        if (b < 4 || (b & (b - 1))) return set_error(PCHASE_EINVAL, "model %u: line_bytes must be a power of two >= 4", i);
+        if (g.n_sets == 0 || !g.set_ways) return set_error(PCHASE_EINVAL, "model %u: needs n_sets >= 1 and set_ways", i);
+        if (g.policy > PCHASE_WRANDOM) return set_error(PCHASE_EINVAL, "model %u: unknown policy %u", i, g.policy);
+        const uint32_t lb = (uint32_t)__builtin_ctz(b);
+        if (g.set_shift != 0 && (g.set_shift < lb || g.set_shift > 40))
+            return set_error(PCHASE_EINVAL, "model %u: set_shift must be 0 or in [log2(line_bytes), 40]", i);
+        if (g.table_len && !g.set_table) return set_error(PCHASE_EINVAL, "model %u: set_table is NULL", i);
+        for (uint32_t t = 0; t < g.table_len; ++t)
+            if (g.set_table[t] >= g.n_sets) return set_error(PCHASE_EINVAL, "model %u: set_table[%u] >= n_sets", i, t);
+        if (gd->set_info.size() + g.n_sets >= (1ull << 31) || gd->table.size() + g.table_len >= (1ull << 31))
+            return set_error(PCHASE_ERANGE, "generalised models: too many sets or table entries");
+        uint32_t amax = 0;
+        uint64_t entries = 0;
+        DevGeneral& d = gd->gen[i];
+        d.set_off = (uint32_t)gd->set_info.size();
+        d.table_off = (uint32_t)gd->table.size();
+        d.table_len = g.table_len;
+        for (uint32_t t = 0; t < g.n_sets; ++t) {
+            const uint32_t a = g.set_ways[t];
+            if (a == 0 || a > 128) return set_error(PCHASE_EINVAL, "model %u: set %u needs 1..128 ways", i, t);
+            if (g.policy == PCHASE_PLRU && (a & (a - 1)))
+                return set_error(PCHASE_EINVAL, "model %u: PLRU needs a power-of-two number of ways", i);
+            if (entries >= (1ull << 32)) return set_error(PCHASE_ERANGE, "model %u: too many ways", i);
+            gd->set_info.push_back(make_uint2(a, (uint32_t)entries));
+            entries += a;
+            amax = std::max(amax, a);
+        }
+        for (uint32_t t = 0; t < g.table_len; ++t) gd->table.push_back(g.set_table[t]);
+        d.cum_off = (uint32_t)gd->cum.size();
+        if (g.policy == PCHASE_WRANDOM) {
+            if (!g.way_weights || g.weights_len < amax)
+                return set_error(PCHASE_EINVAL, "model %u: WRANDOM needs a weight for every way of its widest set", i);
+            uint64_t c = 0;
+            for (uint32_t w = 0; w < amax; ++w) {
+                c += g.way_weights[w];
+                if (c > 65536) c = 65537;   // flagged below for any set that reaches it
+                gd->cum.push_back((uint32_t)c);
+            }
+            for (uint32_t t = 0; t < g.n_sets; ++t) {
+                const uint32_t sum = gd->cum[d.cum_off + g.set_ways[t] - 1];
+                if (sum == 0 || sum > 65536)
+                    return set_error(PCHASE_EINVAL, "model %u: set %u's weights must sum to 1..65536", i, t);
+            }
+        }
+        DevModel& m = (*dm)[i];
+        m = DevModel{};
+        m.line_shift = lb;
+        m.unit_shift = g.set_shift ? g.set_shift : lb;
+        m.sets = g.n_sets;
+        m.ways = amax;
+        m.policy = g.policy;
+        m.log2_ways = 31u - (uint32_t)__builtin_clz(amax);
+        m.seed_lo = (uint32_t)g.seed;
+        m.seed_hi = (uint32_t)(g.seed >> 32);
+        gd->state[i] = (uint64_t)g.n_sets * 32 + entries * 8;
+    }
+    return PCHASE_OK;
+}
+
+static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDesc* gd, uint32_t n_models,
+                               const int32_t* idx_dev, const uint64_t* trace_off, const uint64_t* trace_base,
+                               uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
+                               const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
+                               uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, hipStream_t stream);
+
 extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models, const int32_t* idx_dev,
                                   const uint64_t* trace_off, const uint64_t* trace_base, uint32_t elem_bytes,
                                   uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
@@ -281,6 +366,32 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     std::vector<DevModel> dm;
     int rc = validate_models(models, n_models, &dm);
     if (rc) return rc;
+    return replay_materialised(dm, nullptr, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model,
+                               pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
+}
+
+extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t n_models, const int32_t* idx_dev,
+                                    const uint64_t* trace_off, const uint64_t* trace_base, uint32_t elem_bytes,
+                                    uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
+                                    const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
+                                    uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode,
+                                    hipStream_t stream) {
+    if (mode > PCHASE_PLAIN) return set_error(PCHASE_EINVAL, "unknown mode %u", mode);
+    if (elem_bytes != 4) return set_error(PCHASE_EINVAL, "elem_bytes must be 4");
+    std::vector<DevModel> dm;
+    GeneralDesc gd;
+    int rc = build_general(models, n_models, &dm, &gd);
+    if (rc) return rc;
+    return replay_materialised(dm, &gd, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model,
+                               pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
+}
+
+static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDesc* gd, uint32_t n_models,
+                               const int32_t* idx_dev, const uint64_t* trace_off, const uint64_t* trace_base,
+                               uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
+                               const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
+                               uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, hipStream_t stream) {
+    int rc = PCHASE_OK;
     if (n_pairs == 0) return PCHASE_OK;
     if (!trace_off || !pair_model || !pair_trace) return set_error(PCHASE_EINVAL, "trace or pair arrays are NULL");
     if (!misses_dev) return set_error(PCHASE_EINVAL, "misses_dev is NULL");
@@ -317,16 +428,23 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
         int wl = 0;
         while ((1u << wl) < w) ++wl;
         const uint64_t len = trace_off[pair_trace[i] + 1] - trace_off[pair_trace[i]];
-        const int key = (int)m.policy * 8 + wl;
+        const int key = (gd ? 64 : 0) + (int)m.policy * 8 + wl;
         // parts: a power of two (at most 64 and at most T) until each part's
-        // chain is at most kSplitLen accesses and its state at most kPartState
+        // chain is at most kSplitLen accesses and its state at most
+        // kPartState.  A generalised model's sets differ in size, so each of
+        // its parts keeps the whole state layout: it splits only for length
+        // and only while that state is small.
         const uint64_t per_set = 32 + (uint64_t)m.ways * 8;
         uint32_t parts = 1;
-        while (parts < 64 && 2 * parts <= m.sets &&
-               ((uint64_t)parts * kSplitLen < len || ((m.sets + parts - 1) / parts) * per_set > kPartState))
-            parts *= 2;
+        if (!gd) {
+            while (parts < 64 && 2 * parts <= m.sets &&
+                   ((uint64_t)parts * kSplitLen < len || ((m.sets + parts - 1) / parts) * per_set > kPartState))
+                parts *= 2;
+        } else if (gd->state[pair_model[i]] <= kPartState) {
+            while (parts < 64 && 2 * parts <= m.sets && (uint64_t)parts * kSplitLen < len) parts *= 2;
+        }
         uint64_t& bs = bucket_state[key];
-        bs = std::max<uint64_t>(bs, (uint64_t)((m.sets + parts - 1) / parts) * per_set);
+        bs = std::max<uint64_t>(bs, gd ? gd->state[pair_model[i]] : (uint64_t)((m.sets + parts - 1) / parts) * per_set);
         for (uint32_t p = 0; p < parts; ++p) items.push_back(Item{key, len, (uint32_t)i, parts, p});
         if (parts > 1) {
             zero_cnt.push_back(4 * i);   // the pair's two 64-bit counters, as 32-bit words
@@ -369,7 +487,14 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     const size_t o_pairs = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
     const size_t o_status = o_pairs + (pairs.size() * sizeof(StreamPair) + 255) / 256 * 256;
     const size_t o_zero = o_status + 512;
-    const size_t total = o_zero + (zero_cnt.size() + zero_bits.size()) * sizeof(uint64_t) + 256;
+    const size_t o_gen = (o_zero + (zero_cnt.size() + zero_bits.size()) * sizeof(uint64_t) + 255) / 256 * 256;
+    size_t o_info = o_gen, o_table = o_gen, o_cum = o_gen, total = o_gen + 256;
+    if (gd) {
+        o_info = o_gen + (gd->gen.size() * sizeof(DevGeneral) + 255) / 256 * 256;
+        o_table = o_info + (gd->set_info.size() * sizeof(uint2) + 255) / 256 * 256;
+        o_cum = o_table + (gd->table.size() * sizeof(uint32_t) + 255) / 256 * 256;
+        total = o_cum + (gd->cum.size() * sizeof(uint32_t) + 255) / 256 * 256 + 256;
+    }
     hipError_t e = ws->stage.ensure(total);
     if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
     uint8_t* sb = ws->stage.as<uint8_t>();
@@ -379,6 +504,25 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(StreamPair), hipMemcpyHostToDevice, stream));
     PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
+    const DevGeneral* d_gen = nullptr;
+    const uint2* d_info = nullptr;
+    const uint32_t *d_table = nullptr, *d_cum = nullptr;
+    if (gd) {
+        d_gen = reinterpret_cast<const DevGeneral*>(sb + o_gen);
+        d_info = reinterpret_cast<const uint2*>(sb + o_info);
+        d_table = reinterpret_cast<const uint32_t*>(sb + o_table);
+        d_cum = reinterpret_cast<const uint32_t*>(sb + o_cum);
+        PC_HIP(hipMemcpyAsync(sb + o_gen, gd->gen.data(), gd->gen.size() * sizeof(DevGeneral), hipMemcpyHostToDevice,
+                              stream));
+        PC_HIP(hipMemcpyAsync(sb + o_info, gd->set_info.data(), gd->set_info.size() * sizeof(uint2),
+                              hipMemcpyHostToDevice, stream));
+        if (!gd->table.empty())
+            PC_HIP(hipMemcpyAsync(sb + o_table, gd->table.data(), gd->table.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, stream));
+        if (!gd->cum.empty())
+            PC_HIP(hipMemcpyAsync(sb + o_cum, gd->cum.data(), gd->cum.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                  stream));
+    }
     if (!zero_cnt.empty()) {
         // split pairs merge into their outputs: zero those first
         uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + o_zero);
@@ -411,6 +555,7 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
     // the workspace's replay streams, each on its own region of the slab
     // pool, so that one bucket's longest pair does not wait for another's
     struct Launch {
+        bool gen;
         int pol, W;
         uint64_t q, e2, blocks, gpb, slab_bytes, region;
         double cost;
@@ -424,15 +569,17 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
             work += (double)items[e2].len / items[e2].parts;
             ++e2;
         }
-        const int pol = key / 8, wl = key % 8, W = 1 << wl;
-        int occ = ws->occ_stream[pol][wl];
+        const bool gen = key >= 64;
+        const int pol = (key % 64) / 8, wl = key % 8, W = 1 << wl;
+        int occ = ws->occ_stream[gen][pol][wl];
         if (occ == 0) {
-            hipError_t eo = stream_occupancy(pol, W, &occ);
+            hipError_t eo = stream_occupancy(pol, W, gen, &occ);
             if (eo != hipSuccess) return hip_fail(eo, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
             if (occ < 1) occ = 1;
-            ws->occ_stream[pol][wl] = occ;
+            ws->occ_stream[gen][pol][wl] = occ;
         }
         Launch L;
+        L.gen = gen;
         L.pol = pol;
         L.W = W;
         L.q = q;
@@ -511,7 +658,11 @@ extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models,
         a.elem_shift = 2;
         a.abort_flag = abort_flag_dev();
         a.status = d_status;
-        PC_HIP(launch_stream(L.pol, L.W, a, (uint32_t)L.blocks, st));
+        a.gen = d_gen;
+        a.set_info = d_info;
+        a.set_table = d_table;
+        a.cum_w = d_cum;
+        PC_HIP(launch_stream(L.pol, L.W, L.gen, a, (uint32_t)L.blocks, st));
     }
     for (int b = 0; b < ns; ++b) {
         PC_HIP(hipEventRecord(ws->rjoin[b], ws->rstream[b]));

@@ -132,6 +132,15 @@ struct SweepArgs {
 // bits to memory directly.
 constexpr uint32_t kBmMaxWords = 1024;
 
+// Generalised model (per-set ways, set table, weighted random): offsets of
+// its entries in the flat arrays of StreamArgs.
+struct DevGeneral {
+    uint32_t set_off;     // first (ways, entry base) pair of its sets in set_info
+    uint32_t table_off;   // first entry of its set table
+    uint32_t table_len;   // 0: set = unit mod sets
+    uint32_t cum_off;     // first of its cumulative way weights
+};
+
 struct StreamArgs {
     const StreamPair* pairs;
     uint32_t n_pairs;
@@ -146,6 +155,11 @@ struct StreamArgs {
     uint32_t elem_shift;
     const volatile uint32_t* abort_flag;
     uint32_t* status;        // bit 0: aborted, bit 1: negative index seen
+    // generalised models only
+    const DevGeneral* gen;
+    const uint2* set_info;   // per set: (ways, first entry of the set in the slab)
+    const uint32_t* set_table;
+    const uint32_t* cum_w;   // cumulative way weights
 };
 
 struct ArgminOut {
@@ -160,8 +174,8 @@ hipError_t launch_sweep(bool score, int pol, int cls, const SweepArgs& args, uin
 hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, uint32_t bm_words, int* blocks_per_cu);
 void sweep_geometry(int cls, uint32_t lds_rows, uint32_t bm_words, uint32_t* threads, size_t* lds);
 hipError_t sweep_prepare_lds();
-hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream);
-hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu);
+hipError_t launch_stream(int pol, int w, bool gen, const StreamArgs& args, uint32_t blocks, hipStream_t stream);
+hipError_t stream_occupancy(int pol, int w, bool gen, int* blocks_per_cu);
 // Trace generation: one block per chunk of kTraceChunkAccesses accesses;
 // chunk table entry = (probe, chunk number within the probe).
 constexpr uint64_t kTraceChunkAccesses = 4096;
@@ -250,4 +264,5 @@ static_assert(sizeof(pchase_model) == 40, "pchase_model layout");
 static_assert(sizeof(pchase_probe) == 40, "pchase_probe layout");
 static_assert(sizeof(pchase_segment) == 16, "pchase_segment layout");
 static_assert(sizeof(pchase_nu_probe) == 40, "pchase_nu_probe layout");
+static_assert(sizeof(pchase_general_model) == 56, "pchase_general_model layout");
 static_assert(sizeof(pchase_result) == 48, "pchase_result layout");

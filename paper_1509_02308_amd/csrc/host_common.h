@@ -46,7 +46,7 @@ struct Workspace {
     size_t slab_clean = 0;  // bytes of `slab` known to hold epoch 0 or older epochs
     uint32_t epoch = 0;
     void* host_res = nullptr;  // pinned result staging
-    int occ_stream[4][7] = {};
+    int occ_stream[2][5][7] = {};   // [generalised][policy][log2 width]
     bool lds_ready = false;
     hipStream_t branch[kBranches] = {};   // capture-side streams (default priority)
     hipEvent_t fork = nullptr, join[kBranches] = {};

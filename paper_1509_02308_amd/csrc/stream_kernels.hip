@@ -42,18 +42,23 @@ __device__ __forceinline__ void plru_put(uint64_t& lo, uint64_t& hi, uint32_t n,
     else hi = (hi & ~(1ull << (n - 64))) | ((uint64_t)v << (n - 64));
 }
 
-template <int POL, int W>
+// GEN: a generalised model (per-set ways, optional set table, weighted
+// random replacement): the set's way count and entry base come from
+// set_info, and m.ways is the widest set.
+template <int POL, int W, bool GEN>
 __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32_t pair_index,
                             int gl, int gbase, uint8_t* slab) {
     const DevModel m = args.models[pr.model];
-    const uint32_t a = m.ways;
+    const uint32_t amax = m.ways;
     const uint32_t T = m.sets;
+    DevGeneral g{};
+    if constexpr (GEN) g = args.gen[pr.model];
     const uint32_t epoch = args.epoch_base + pair_index + 1;
     SetHeader* hdr = reinterpret_cast<SetHeader*>(slab);
     const uint64_t gmask = (W == 64) ? ~0ull : (((1ull << (W & 63)) - 1ull) << gbase);
-    const bool two = (W == 64) && (a > 64);
-    const bool own0 = (uint32_t)gl < a;
-    const bool own1 = two && (uint32_t)(gl + 64) < a;
+    const bool two = (W == 64) && (amax > 64);
+    const bool own0_all = (uint32_t)gl < amax;
+    const bool own1_all = two && (uint32_t)(gl + 64) < amax;
 
     uint64_t mt = 0, ms = 0;
     uint32_t* bits = args.bits ? args.bits + pr.bitoff : nullptr;
@@ -65,8 +70,10 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
     // merges its hit bits and counts into zeroed outputs
     const uint32_t nparts = pr.pad >> 16, part = pr.pad & 0xFFFFu;
     const bool split = nparts > 1;
-    const uint32_t pshift = split ? (uint32_t)(__ffs((int)nparts) - 1) : 0u;   // part p keeps its sets at set >> pshift
-    const uint32_t Tl = split ? (T + nparts - 1) >> pshift : T;   // set slots of this pair or part
+    // part p keeps its sets at set >> pshift; a generalised model's part
+    // keeps the whole layout (its sets differ in size), skipping the others
+    const uint32_t pshift = (split && !GEN) ? (uint32_t)(__ffs((int)nparts) - 1) : 0u;
+    const uint32_t Tl = (split && !GEN) ? (T + nparts - 1) >> pshift : T;   // set slots of this pair or part
     uint2* ent = reinterpret_cast<uint2*>(slab + (size_t)Tl * sizeof(SetHeader));
     uint64_t cur_w = ~0ull;
     uint32_t word = 0;
@@ -128,13 +135,30 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
                 continue;
             }
             const uint32_t ux = (uint32_t)(xa >> m.unit_shift);
-            const uint32_t set = ux - tdiv.div(ux) * T;
+            uint32_t set;
+            if constexpr (GEN) {
+                set = g.table_len ? args.set_table[g.table_off + ux % g.table_len] : ux - tdiv.div(ux) * T;
+            } else {
+                set = ux - tdiv.div(ux) * T;
+            }
             if (split && (set & (nparts - 1)) != part) continue;
             last_line = line;
 
             // the set's entries and (first lane) header, loaded together
             const uint32_t lset = set >> pshift;
-            const uint64_t eb = (uint64_t)lset * a;
+            uint32_t a = amax, log2a = m.log2_ways;
+            uint64_t eb;
+            bool own0 = own0_all, own1 = own1_all;
+            if constexpr (GEN) {
+                const uint2 si = args.set_info[g.set_off + set];
+                a = si.x;
+                eb = si.y;
+                own0 = (uint32_t)gl < a;
+                own1 = two && (uint32_t)(gl + 64) < a;
+                log2a = 31u - (uint32_t)__clz((int)a);
+            } else {
+                eb = (uint64_t)lset * a;
+            }
             uint2 e0 = make_uint2(kInvalidTag, 0xFFu), e1 = make_uint2(kInvalidTag, 0xFFu);
             uint2 r0 = e0, r1 = e1;
             if (own0) r0 = ent[eb + gl];
@@ -204,16 +228,33 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
                 else if (nvalid < a) x = nvalid;
                 else {
                     uint32_t node = 0;
-                    for (uint32_t d = 0; d < m.log2_ways; ++d) node = 2 * node + 1 + plru_get(h_lo, h_hi, node);
+                    for (uint32_t d = 0; d < log2a; ++d) node = 2 * node + 1 + plru_get(h_lo, h_hi, node);
                     x = node - (a - 1);
                 }
                 uint32_t node = 0;
-                for (uint32_t d = 0; d < m.log2_ways; ++d) {
-                    const uint32_t dir = (x >> (m.log2_ways - 1 - d)) & 1u;
+                for (uint32_t d = 0; d < log2a; ++d) {
+                    const uint32_t dir = (x >> (log2a - 1 - d)) & 1u;
                     plru_put(h_lo, h_hi, node, dir ^ 1u);
                     node = 2 * node + 1 + dir;
                 }
                 hdr_dirty = true;
+            } else if (POL == PCHASE_WRANDOM) {
+                if (hit) x = hw;
+                else if (nvalid < a) x = nvalid;
+                else {
+                    // lowest way whose cumulative weight exceeds u mod S: the
+                    // weights are positive-sum and cumulative, so one lane of
+                    // the set's a ways qualifies; the lowest is the victim
+                    const uint32_t u = philox_x((uint32_t)k, (uint32_t)(k >> 32), pr.trace_id, 0u, m.seed_lo,
+                                                m.seed_hi);
+                    const uint32_t r = u % args.cum_w[g.cum_off + a - 1];
+                    const uint32_t c0 = own0 ? args.cum_w[g.cum_off + gl] : 0u;
+                    const uint32_t c1 = own1 ? args.cum_w[g.cum_off + gl + 64] : 0u;
+                    const uint64_t q0 = __ballot(own0 && r < c0) & gmask;
+                    const uint64_t q1 = __ballot(own1 && r < c1) & gmask;
+                    x = q0 ? (uint32_t)(__ffsll((long long)q0) - 1 - gbase)
+                           : (uint32_t)(__ffsll((long long)q1) - 1 - gbase) + 64;
+                }
             } else {
                 if (hit) x = hw;
                 else if (nvalid < a) x = nvalid;
@@ -267,7 +308,7 @@ __device__ void stream_pair(const StreamArgs& args, const StreamPair& pr, uint32
     }
 }
 
-template <int POL, int W>
+template <int POL, int W, bool GEN>
 __global__ void __launch_bounds__(256) stream_kernel(StreamArgs args) {
     constexpr int G = kWave / W;
     const int lane = threadIdx.x & (kWave - 1);
@@ -287,40 +328,54 @@ __global__ void __launch_bounds__(256) stream_kernel(StreamArgs args) {
         }
         t = __shfl(t, gbase, kWave);
         if (t >= args.n_pairs) break;
-        stream_pair<POL, W>(args, args.pairs[t], t, gl, gbase, slab);
+        stream_pair<POL, W, GEN>(args, args.pairs[t], t, gl, gbase, slab);
     }
 }
 
 using StreamFn = void (*)(StreamArgs);
 
+template <bool GEN>
 static StreamFn pick_stream(int pol, int w) {
-#define PC_W(P)                                   \
-    switch (w) {                                  \
-        case 1: return stream_kernel<P, 1>;       \
-        case 2: return stream_kernel<P, 2>;       \
-        case 4: return stream_kernel<P, 4>;       \
-        case 8: return stream_kernel<P, 8>;       \
-        case 16: return stream_kernel<P, 16>;     \
-        case 32: return stream_kernel<P, 32>;     \
-        default: return stream_kernel<P, 64>;     \
+#define PC_W(P)                                        \
+    switch (w) {                                       \
+        case 1: return stream_kernel<P, 1, GEN>;       \
+        case 2: return stream_kernel<P, 2, GEN>;       \
+        case 4: return stream_kernel<P, 4, GEN>;       \
+        case 8: return stream_kernel<P, 8, GEN>;       \
+        case 16: return stream_kernel<P, 16, GEN>;     \
+        case 32: return stream_kernel<P, 32, GEN>;     \
+        default: return stream_kernel<P, 64, GEN>;     \
     }
     switch (pol) {
         case PCHASE_LRU: PC_W(PCHASE_LRU)
         case PCHASE_FIFO: PC_W(PCHASE_FIFO)
         case PCHASE_PLRU: PC_W(PCHASE_PLRU)
-        default: PC_W(PCHASE_RANDOM)
+        case PCHASE_RANDOM: PC_W(PCHASE_RANDOM)
+        default:
+            if constexpr (GEN) {
+                PC_W(PCHASE_WRANDOM)
+            } else {
+                return nullptr;   // weighted random exists for generalised models only
+            }
     }
 #undef PC_W
 }
 
-hipError_t launch_stream(int pol, int w, const StreamArgs& args, uint32_t blocks, hipStream_t stream) {
-    hipLaunchKernelGGL(pick_stream(pol, w), dim3(blocks), dim3(256), 0, stream, args);
+static StreamFn pick_stream_any(int pol, int w, bool gen) {
+    return gen ? pick_stream<true>(pol, w) : pick_stream<false>(pol, w);
+}
+
+hipError_t launch_stream(int pol, int w, bool gen, const StreamArgs& args, uint32_t blocks, hipStream_t stream) {
+    const StreamFn f = pick_stream_any(pol, w, gen);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(256), 0, stream, args);
     return hipGetLastError();
 }
 
-hipError_t stream_occupancy(int pol, int w, int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)pick_stream(pol, w),
-                                                        256, 0);
+hipError_t stream_occupancy(int pol, int w, bool gen, int* blocks_per_cu) {
+    const StreamFn f = pick_stream_any(pol, w, gen);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)f, 256, 0);
 }
 
 }  // namespace pc

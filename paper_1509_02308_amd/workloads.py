@@ -12,8 +12,8 @@ from __future__ import annotations
 
 import numpy as np
 
-LRU, FIFO, PLRU, RANDOM = 0, 1, 2, 3
-POLICY_NAMES = {LRU: "LRU", FIFO: "FIFO", PLRU: "PLRU", RANDOM: "RANDOM"}
+LRU, FIFO, PLRU, RANDOM, WRANDOM = 0, 1, 2, 3, 4
+POLICY_NAMES = {LRU: "LRU", FIFO: "FIFO", PLRU: "PLRU", RANDOM: "RANDOM", WRANDOM: "WRANDOM"}
 
 MODEL_DT = np.dtype([("C", "<u8"), ("b", "<u8"), ("a", "<u8"), ("policy", "<u8"),
                      ("set_shift", "<u8"), ("seed", "<u8")])
@@ -172,3 +172,57 @@ def nonuniform_rows(n: int = 48, seed: int = 52, n_lo: int = 64, n_hi: int = 4 <
             segs.append((s, int(rng.integers(1, max_count + 1))))
         rows.append((N, segs, int(rng.integers(1, 4)), int(rng.integers(0, N // 4)), 4 * int(rng.integers(0, 1024))))
     return rows
+
+
+# --------------------------------------------------------------------------
+# Generalised caches (descriptors): the organisations of Sections 4.3-4.5
+# as synthetic targets, and seeded random ones for parity tests.
+# --------------------------------------------------------------------------
+def paper_general_targets():
+    """Dicts (line, ways per set, policy, set_shift, table, weights, name):
+    * texture L1 (Sec. 4.3): 12 KB, 4 sets x 96 ways of 32 B, set from
+      address bits 7-8;
+    * read-only cache with a non-bit-field mapping (Sec. 4.3): the same
+      geometry, set = a seeded table over 128 B blocks;
+    * L2 TLB (Sec. 4.4, Fig. 9): 2 MB entries, one set of 17 and six of 8,
+      a 65-entry table giving the large set 17 residues and each small set
+      8 (residues 0..6 on sets 0..6);
+    * Fermi L1 (Sec. 4.5): 16 KB, 32 sets x 4 ways of 128 B, way 2 replaced
+      with probability 1/2 (weights 1, 3, 1, 1)."""
+    rng = np.random.default_rng(980)
+    return [
+        {"name": "texture_l1", "line": 32, "ways": [96] * 4, "policy": LRU, "set_shift": 7},
+        {"name": "readonly_table", "line": 32, "ways": [96] * 4, "policy": LRU, "set_shift": 7,
+         "table": [int(x) for x in rng.permutation(np.arange(64) % 4)]},
+        {"name": "l2_tlb", "line": 2 << 20, "ways": [17] + [8] * 6, "policy": LRU,
+         "table": [r % 7 for r in range(56)] + [0] * 9},
+        {"name": "fermi_l1", "line": 128, "ways": [4] * 32, "policy": WRANDOM, "weights": [1, 3, 1, 1],
+         "seed": 1509},
+    ]
+
+
+def random_general(n: int, seed: int = 7):
+    """Seeded random generalised caches: 1-12 sets of 1..128 ways (powers of
+    two for PLRU), lines 4..128 B, all five policies, half with a set
+    table, some with a set_shift, weights 0..7 per way (first > 0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        pol = i % 5
+        T = int(rng.integers(1, 13))
+        if pol == PLRU:
+            ways = [int(2 ** rng.integers(0, 8)) for _ in range(T)]
+        else:
+            ways = [int(rng.integers(1, 129)) if rng.random() < 0.3 else int(rng.integers(1, 17)) for _ in range(T)]
+        line = int(4 << rng.integers(0, 6))
+        d = {"line": line, "ways": ways, "policy": pol, "seed": int(rng.integers(0, 2 ** 40))}
+        if rng.random() < 0.5:
+            d["table"] = [int(x) for x in rng.integers(0, T, size=int(rng.integers(1, 40)))]
+        if rng.random() < 0.3:
+            d["set_shift"] = int(np.log2(line)) + int(rng.integers(0, 3))
+        if pol == WRANDOM:
+            w = [int(x) for x in rng.integers(0, 8, size=max(ways))]
+            w[0] += 1
+            d["weights"] = w
+        out.append(d)
+    return out

@@ -42,6 +42,7 @@ def test_struct_layouts_match_header(capi):
     assert ctypes.sizeof(capi.PchaseResult) == 48
     assert ctypes.sizeof(capi.PchaseSegment) == 16
     assert ctypes.sizeof(capi.PchaseNuProbe) == 40
+    assert ctypes.sizeof(capi.PchaseGeneralModel) == 56
 
 
 def _rc(capi, rc):
@@ -178,6 +179,27 @@ def test_nonuniform_trace_len_and_validation(capi, orc):
     rc = L.pchase_trace_nu(ctypes.cast(parr, ctypes.c_void_p), 1, ctypes.cast(sarr, ctypes.c_void_p), 1,
                            ctypes.c_void_p(16), off, 100, None)
     assert rc == -2 and "capacity" in capi.last_error()
+
+
+def test_general_model_validation_before_launch(capi):
+    """Invalid generalised models are rejected on the host (no GPU needed)."""
+    bad = [{"line": 48, "ways": [4]},                                  # line not a power of two
+           {"line": 32, "ways": [4, 0]},                               # empty set
+           {"line": 32, "ways": [200]},                                # more than 128 ways
+           {"line": 32, "ways": [4, 3], "policy": 2},                  # PLRU needs 2^k ways
+           {"line": 32, "ways": [4], "table": [0, 1]},                 # table entry outside the sets
+           {"line": 32, "ways": [4], "policy": 4},                     # WRANDOM without weights
+           {"line": 32, "ways": [2], "policy": 4, "weights": [0, 0]},  # zero total weight
+           {"line": 32, "ways": [4], "policy": 5},                     # unknown policy
+           {"line": 64, "ways": [4], "set_shift": 5}]                  # set unit below a line
+    pm = (ctypes.c_uint32 * 1)(0)
+    pt = (ctypes.c_uint32 * 1)(0)
+    off = (ctypes.c_uint64 * 2)(0, 4)
+    for d in bad:
+        m = capi.general_models([d])
+        rc = capi.lib().cache_replay_general(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.c_void_p(16), off, None, 4,
+                                             1, pm, pt, None, 1, ctypes.c_void_p(16), None, None, 0, None)
+        assert rc == -1, d
 
 
 def test_mlp_grid_matches_reference(capi):

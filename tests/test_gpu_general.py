@@ -1,0 +1,108 @@
+"""GPU parity of the generalised caches (per-set ways, set tables, weighted
+random replacement) through cache_replay_general, bit-exact against the
+CPU oracle: seeded random models on random, uniform and non-uniform traces,
+and the paper-shaped targets of Sections 4.3-4.5."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1509_02308_amd import workloads as W
+from tests.gpu_common import need_gpu, say, unpack_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def _orc_general(d):
+    return orc.General(d["line"], d["ways"], d["policy"], d.get("set_shift", 0), d.get("table"),
+                       d.get("weights"), d.get("seed", 0))
+
+
+def _traces(rng):
+    tr = [rng.integers(0, int(rng.integers(50, 6000)), size=int(rng.integers(1, 2500))).astype(np.int32)
+          for _ in range(10)]
+    for N, s, passes in [(4096, 32, 3), (12288 + 512, 32, 2), (65536 + 128, 128, 2), (2048, 4, 2)]:
+        tr.append(orc.trace(orc.make_probe(N, s, passes=passes)))
+    for r in W.nonuniform_rows(n=4, seed=61, n_hi=1 << 20, max_count=600):
+        tr.append(orc.trace_nu(r[0], r[1], passes=r[2], j0=r[3]))
+    # long enough to be replayed as parts by set (state permitting)
+    tr.append(rng.integers(0, 20000, size=60001).astype(np.int32))
+    tr.append(orc.trace(orc.make_probe(24576 + 128, 32, passes=20)))
+    return tr
+
+
+def _run(torch, capi, models, traces, bases, mode):
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    pairs = [(m, t) for m in range(len(models)) for t in range(len(traces))]
+    pm = np.array([m for m, _ in pairs], dtype=np.uint32)
+    pt = np.array([t for _, t in pairs], dtype=np.uint32)
+    cf = np.array([len(traces[t]) // 3 for _, t in pairs], dtype=np.uint64)
+    words = [(len(traces[t]) + 31) // 32 for _, t in pairs]
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.full((int(sum(words)) + 1,), 0x77, dtype=torch.int32, device="cuda")
+    misses = torch.full((2 * len(pairs),), -1, dtype=torch.int64, device="cuda")
+    say(f"cache_replay_general mode={mode}: {len(models)} models, {len(pairs)} pairs")
+    capi.cache_replay_general(capi.general_models(models), idx, off, bases, pm, pt, cf, misses, bits, bitoff, mode)
+    torch.cuda.synchronize()
+    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    b = bits.cpu().numpy().view(np.uint32)
+    for i, (m, t) in enumerate(pairs):
+        hits, mt, ms = orc.replay_general(_orc_general(models[m]), traces[t], base=bases[t], trace_id=t,
+                                          count_from=int(cf[i]))
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms), (models[m], t)
+        assert np.array_equal(unpack_bits(b[bitoff[i]:], len(traces[t])), hits), (models[m], t)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_general_random_models_match_oracle(mode):
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(100 + mode)
+    models = W.random_general(30, seed=8 + mode)
+    for d in models:
+        assert _orc_general(d).ok(), d
+    traces = _traces(rng)
+    bases = [4 * int(rng.integers(0, 2048)) for _ in traces]
+    _run(torch, capi, models, traces, bases, mode)
+
+
+def test_paper_shaped_targets_match_oracle():
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(44)
+    models = [{k: v for k, v in d.items() if k != "name"} for d in W.paper_general_targets()]
+    traces = _traces(rng)
+    page = 2 << 20
+    for n in (64, 65, 66, 70):                     # the L2 TLB staircase: chases at s = 2 MB
+        traces.append(orc.trace(orc.make_probe(n * page, page, passes=3)))
+    traces.append(orc.trace(orc.make_probe(5 * 128 * 32, 128 * 32, passes=400)))   # Fermi L1 one-line overflow
+    bases = [0] * len(traces)
+    _run(torch, capi, models, traces, bases, 0)
+
+
+def test_general_equal_sets_match_standard_replay():
+    """A generalised model with equal sets and no table is the standard
+    model: both entry points give the same bits and counts."""
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(12)
+    rows = [(4096, 32, 4, p, 0, 77) for p in range(4)] + [(12288, 32, 96, 0, 7, 0), (65536, 64, 128, 2, 0, 0)]
+    gen = [{"line": b, "ways": [a] * (C // (a * b)), "policy": p, "set_shift": sh, "seed": sd}
+           for C, b, a, p, sh, sd in rows]
+    traces = _traces(rng)
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    pairs = [(m, t) for m in range(len(rows)) for t in range(len(traces))]
+    pm = np.array([m for m, _ in pairs], dtype=np.uint32)
+    pt = np.array([t for _, t in pairs], dtype=np.uint32)
+    words = [(len(traces[t]) + 31) // 32 for _, t in pairs]
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    out = []
+    for name in ("standard", "general"):
+        bits = torch.zeros(int(sum(words)) + 1, dtype=torch.int32, device="cuda")
+        misses = torch.zeros(2 * len(pairs), dtype=torch.int64, device="cuda")
+        say(f"equal sets through the {name} entry point")
+        if name == "standard":
+            capi.cache_replay_batch(capi.models(rows), idx, off, None, pm, pt, None, misses, bits, bitoff)
+        else:
+            capi.cache_replay_general(capi.general_models(gen), idx, off, None, pm, pt, None, misses, bits, bitoff)
+        torch.cuda.synchronize()
+        out.append((bits.cpu().numpy(), misses.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
