@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--large-pairs", type=int, default=1_000_000)
     ap.add_argument("--nu-probes", type=int, default=4096)
+    ap.add_argument("--adaptive-targets", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -187,6 +188,10 @@ def main():
     if args.large_pairs > 0:
         large = large_batch_leg(torch, capi, W, args)
 
+    adaptive = None
+    if args.adaptive_targets > 0:
+        adaptive = adaptive_leg(torch, capi, W, crows, args)
+
     nonuniform = None
     if args.nu_probes > 0:
         nonuniform = nonuniform_leg(torch, capi, W, args, stream)
@@ -222,6 +227,7 @@ def main():
         "learned": learned,
         "large_batch": large,
         "nonuniform": nonuniform,
+        "adaptive": adaptive,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -329,6 +335,64 @@ def large_batch_leg(torch, capi, W, args):
     return {"pairs": n, "accesses": total, "trace_bytes": 4 * total, "replay_s": dt,
             "value": total / dt, "unit": "accesses/s",
             "hbm_GBps_trace_only": 4 * total / dt / 1e9}
+
+
+def adaptive_leg(torch, capi, W, crows, args):
+    """Adaptive probing (Fig. 6 as a greedy split) over the 768-probe feature
+    grid for the 438 candidates: per seeded target, choose a probe, observe
+    the target on it (a replay standing in for a hardware run), keep the zero
+    class of a one-probe inference, until no probe splits the survivors.
+    Reports probes and accesses observed against observing the whole grid,
+    and the planner's time per step (the class matrix is built by the first
+    call, timed separately)."""
+    carr = capi.models(crows)
+    grid = capi.pchase_mlp_grid()
+    rows = [(grid[i].n_bytes, grid[i].s_bytes, grid[i].passes) for i in range(grid.n)]
+    lens = [capi.pchase_trace_len(grid[i])[0] for i in range(grid.n)]
+    nc = len(crows)
+    full = np.full((nc + 31) // 32, 0xFFFFFFFF, dtype=np.uint32)
+    if nc % 32:
+        full[-1] = (1 << (nc % 32)) - 1
+    t0 = time.perf_counter()
+    capi.pchase_plan_next_probe(carr, grid, full)
+    cold_ms = (time.perf_counter() - t0) * 1e3
+    rng = np.random.default_rng(1509)
+    targets = rng.choice(nc, size=min(args.adaptive_targets, nc), replace=False)
+    steps, observed, plan_s, exact = [], [], 0.0, 0
+    for tgt in targets:
+        alive = np.ones(nc, dtype=bool)
+        used = 0
+        acc = 0
+        while True:
+            words = np.zeros((nc + 31) // 32, dtype=np.uint32)
+            for c in np.nonzero(alive)[0]:
+                words[c // 32] |= np.uint32(1 << (c % 32))
+            tp = time.perf_counter()
+            ch = capi.pchase_plan_next_probe(carr, grid, words)
+            plan_s += time.perf_counter() - tp
+            if ch.probe < 0:
+                break
+            p = int(ch.probe)
+            one = capi.probes([rows[p]])
+            bits = torch.zeros((lens[p] + 31) // 32 + 1, dtype=torch.int32, device="cuda")
+            misses = torch.zeros(2, dtype=torch.int64, device="cuda")
+            capi.cache_replay_probes(capi.models([crows[tgt]]), one, np.zeros(1, np.uint32),
+                                     np.zeros(1, np.uint32), None, misses, bits, np.zeros(1, np.uint64))
+            _, zero = capi.infer_cache_params(one, carr, bits=bits, bitoff=np.zeros(1, np.uint64),
+                                              probe_select=capi.PROBES_ALL, want_zero=True)
+            keep = ((zero[np.arange(nc) // 32] >> (np.arange(nc) % 32)) & 1).astype(bool)
+            alive &= keep
+            used += 1
+            acc += lens[p]
+        steps.append(used)
+        observed.append(acc)
+        exact += int(alive[tgt])
+    n_plan = sum(steps) + len(steps)
+    return {"candidates": nc, "pool": grid.n, "targets": len(targets),
+            "probes_observed_mean": float(np.mean(steps)), "probes_observed_max": int(np.max(steps)),
+            "accesses_observed_mean": float(np.mean(observed)), "accesses_whole_pool": int(sum(lens)),
+            "target_in_survivors_rate": exact / len(targets),
+            "plan_cold_ms": cold_ms, "plan_step_ms": plan_s * 1e3 / n_plan}
 
 
 def nonuniform_leg(torch, capi, W, args, stream):

@@ -193,6 +193,35 @@ typedef struct pchase_general_model {
     uint64_t seed;                  /* RANDOM / WRANDOM key */
 } pchase_general_model;
 
+/* ------------------------------------------------------ probe planner --- */
+/* Adaptive probing (Sec. 4.2, Fig. 6): the paper chooses each next (N, s)
+ * from what the earlier runs showed.  Here the choice is made over a pool:
+ * on each pool probe the candidates fall into classes of identical
+ * steady-pass hit bits (accesses L .. len-1), a class named by its lowest
+ * candidate index; among the surviving candidates (bitmap alive_host, bit c
+ * of word c/32) the chosen probe has the smallest largest class, then the
+ * most classes, then the lowest pool index.  probe = -1 when no pool probe
+ * splits the survivors (they are indistinguishable on the pool) or none is
+ * alive.  The caller observes the target on the chosen probe (e.g.
+ * microbench_pchase + classification, or a replay) and keeps the survivors
+ * whose prediction matches, e.g. through infer_cache_params's zero class.
+ * classes_dev (nullable, device, n_pool x n_cands uint32, row = probe)
+ * receives the class matrix.  The first call for a (cands, pool) pair
+ * replays every candidate on every probe (at most 2^13 candidates, 2^20
+ * probes and 8 GB of hit bits); later calls with the same pair only score.
+ * Synchronises. */
+typedef struct pchase_plan_choice {
+    int64_t probe;        /* pool index, or -1 */
+    uint32_t worst;       /* largest class among the survivors on that probe */
+    uint32_t n_classes;   /* classes among the survivors on that probe */
+    uint32_t n_alive;     /* survivors */
+    uint32_t reserved;
+} pchase_plan_choice;
+
+int pchase_plan_next_probe(const pchase_model *cands, uint32_t n_cands, const pchase_probe *pool,
+                           uint32_t n_pool, const uint32_t *alive_host, uint32_t *classes_dev,
+                           pchase_plan_choice *out, hipStream_t stream);
+
 /* ------------------------------------------------------------ replay --- */
 /* Replay scheduling: BATCHED runs every pair in one captured graph of
  * persistent kernels fed by a cost-ordered work queue; PLAIN launches one

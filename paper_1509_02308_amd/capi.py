@@ -45,6 +45,10 @@ class PchaseGeneralModel(ctypes.Structure):
                 ("way_weights", vp), ("seed", u64)]
 
 
+class PchasePlanChoice(ctypes.Structure):
+    _fields_ = [("probe", i64), ("worst", u32), ("n_classes", u32), ("n_alive", u32), ("reserved", u32)]
+
+
 class PchaseSegment(ctypes.Structure):
     _fields_ = [("s_bytes", u64), ("count", u64)]
 
@@ -83,6 +87,7 @@ def lib():
         L.pchase_trace_len.argtypes = [ctypes.POINTER(PchaseProbe), vp, vp]
         L.pchase_trace.argtypes = [vp, u32, vp, vp, u64, vp]
         L.cache_replay_general.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.pchase_plan_next_probe.argtypes = [vp, u32, vp, u32, vp, vp, ctypes.POINTER(PchasePlanChoice), vp]
         L.pchase_trace_nu_len.argtypes = [ctypes.POINTER(PchaseNuProbe), vp, u32, vp, vp]
         L.pchase_trace_nu.argtypes = [vp, u32, vp, u32, vp, vp, u64, vp]
         L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
@@ -313,6 +318,17 @@ def infer_cache_params(probe_arr, cand_arr, bits=None, bitoff=None, lat=None, la
                                    zero.ctypes.data_as(vp) if zero is not None else None,
                                    _stream(stream)))
     return res, zero
+
+
+def pchase_plan_next_probe(cand_arr, pool_arr, alive, classes=None, stream=None) -> PchasePlanChoice:
+    """Next probe of the adaptive procedure for the surviving candidates
+    (alive: uint32 bitmap words); classes (int32 CUDA tensor of
+    n_pool * n_cands, optional) receives the class matrix."""
+    a = np.ascontiguousarray(alive, dtype=np.uint32)
+    out = PchasePlanChoice()
+    check(lib().pchase_plan_next_probe(ctypes.cast(cand_arr, vp), cand_arr.n, ctypes.cast(pool_arr, vp), pool_arr.n,
+                                       a.ctypes.data_as(vp), _dptr(classes), ctypes.byref(out), _stream(stream)))
+    return out
 
 
 def pchase_microbench_max_k() -> int:

@@ -53,6 +53,9 @@ struct Workspace {
     hipStream_t rstream[kReplayStreams] = {};   // default priority
     hipEvent_t rfork = nullptr, rjoin[kReplayStreams] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
+    // probe planner: class matrix of the last (candidates, pool) pair
+    DevBuf planner;
+    std::string planner_key;
     ~Workspace();
 };
 

@@ -144,6 +144,7 @@ Workspace::~Workspace() {
     obs.release();
     slab.release();
     mlp.release();
+    planner.release();
     if (host_res) (void)hipHostFree(host_res);
 }
 

@@ -43,6 +43,7 @@ def test_struct_layouts_match_header(capi):
     assert ctypes.sizeof(capi.PchaseSegment) == 16
     assert ctypes.sizeof(capi.PchaseNuProbe) == 40
     assert ctypes.sizeof(capi.PchaseGeneralModel) == 56
+    assert ctypes.sizeof(capi.PchasePlanChoice) == 24
 
 
 def _rc(capi, rc):
@@ -200,6 +201,27 @@ def test_general_model_validation_before_launch(capi):
         rc = capi.lib().cache_replay_general(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.c_void_p(16), off, None, 4,
                                              1, pm, pt, None, 1, ctypes.c_void_p(16), None, None, 0, None)
         assert rc == -1, d
+
+
+def test_planner_argument_checks(capi):
+    """Planner arguments are checked on the host before any launch."""
+    L = capi.lib()
+    cands = capi.models([(4096, 32, 4, 0)])
+    pool = capi.probes([(4096, 32, 2)])
+    alive = (ctypes.c_uint32 * 1)(1)
+    out = capi.PchasePlanChoice()
+    vp = ctypes.c_void_p
+    assert L.pchase_plan_next_probe(ctypes.cast(cands, vp), 0, ctypes.cast(pool, vp), 1, alive, None,
+                                    ctypes.byref(out), None) == -1                       # no candidate
+    assert L.pchase_plan_next_probe(ctypes.cast(cands, vp), 1, ctypes.cast(pool, vp), 0, alive, None,
+                                    ctypes.byref(out), None) == -1                       # no probe
+    assert L.pchase_plan_next_probe(ctypes.cast(cands, vp), 1, ctypes.cast(pool, vp), 1, None, None,
+                                    ctypes.byref(out), None) == -1                       # no alive bitmap
+    assert L.pchase_plan_next_probe(ctypes.cast(cands, vp), 9000, ctypes.cast(pool, vp), 1, alive, None,
+                                    ctypes.byref(out), None) == -2                       # too many candidates
+    bad = capi.models([(4096, 32, 3, 0)])                                                # T*a*b != C
+    assert L.pchase_plan_next_probe(ctypes.cast(bad, vp), 1, ctypes.cast(pool, vp), 1, alive, None,
+                                    ctypes.byref(out), None) == -1
 
 
 def test_mlp_grid_matches_reference(capi):
