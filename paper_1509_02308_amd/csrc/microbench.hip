@@ -317,17 +317,17 @@ extern "C" int microbench_lds_stream(uint32_t blocks_per_cu, uint32_t block, uin
     };
     e = run();   // warm-up
     if (e != hipSuccess) return hip_fail(e, "lds stream kernel");
-    hipEvent_t a, b;
-    PC_HIP(hipEventCreate(&a));
-    PC_HIP(hipEventCreate(&b));
-    PC_HIP(hipEventRecord(a, stream));
-    e = run();
-    PC_HIP(hipEventRecord(b, stream));
-    PC_HIP(hipEventSynchronize(b));
+    hipEvent_t a = nullptr, b = nullptr;
     float ms = 0;
-    PC_HIP(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, stream);
+    if (e == hipSuccess) e = run();
+    if (e == hipSuccess) e = hipEventRecord(b, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "lds stream kernel");
     const double bytes = (double)grid * block * reps * ilp * width_bytes * (copy ? 2 : 1);
     *gbps = bytes / (ms * 1e-3) / 1e9;
@@ -391,21 +391,19 @@ extern "C" int microbench_hbm_stream(const void* src_dev, void* dst_dev, uint64_
     hipError_t e = dtype ? launch_copy<f32x4>(src_dev, dst_dev, n, grid, block, ilp, stream)
                          : launch_copy<float>(src_dev, dst_dev, n, grid, block, ilp, stream);
     if (e != hipSuccess) return hip_fail(e, "copy kernel");
-    hipEvent_t a, b;
-    PC_HIP(hipEventCreate(&a));
-    PC_HIP(hipEventCreate(&b));
-    PC_HIP(hipEventRecord(a, stream));
-    for (uint32_t r = 0; r < reps; ++r) {
+    hipEvent_t a = nullptr, b = nullptr;
+    float ms = 0;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, stream);
+    for (uint32_t r = 0; r < reps && e == hipSuccess; ++r)
         e = dtype ? launch_copy<f32x4>(src_dev, dst_dev, n, grid, block, ilp, stream)
                   : launch_copy<float>(src_dev, dst_dev, n, grid, block, ilp, stream);
-        if (e != hipSuccess) break;
-    }
-    PC_HIP(hipEventRecord(b, stream));
-    PC_HIP(hipEventSynchronize(b));
-    float ms = 0;
-    PC_HIP(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    if (e == hipSuccess) e = hipEventRecord(b, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "copy kernel");
     *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return PCHASE_OK;

@@ -164,23 +164,27 @@ extern "C" int pchase_plan_next_probe(const pchase_model* cands, uint32_t n_cand
         // every candidate on every probe, hit bits in one bank: probe p's
         // bitmaps start at bitbase[p], one per candidate
         std::vector<PlanProbe> pp(n_pool);
-        std::vector<SweepJob> jobs;
-        jobs.reserve((size_t)n_pool * n_cands);
         uint64_t words = 0;
         for (uint32_t p = 0; p < n_pool; ++p) {
             const uint32_t w = (uint32_t)((len[p] + 31) / 32);
             pp[p] = PlanProbe{words, w, dp[p].L, (uint32_t)len[p], 0};
-            for (uint32_t c = 0; c < n_cands; ++c) {
+            words += (uint64_t)w * n_cands;
+        }
+        // jobs grouped by candidate (the sweep plan packs each model's jobs
+        // into shared tasks)
+        std::vector<SweepJob> jobs;
+        jobs.reserve((size_t)n_pool * n_cands);
+        for (uint32_t c = 0; c < n_cands; ++c) {
+            for (uint32_t p = 0; p < n_pool; ++p) {
                 SweepJob j{};
                 j.model = c;
                 j.probe = p;
                 j.out = (uint32_t)jobs.size();
                 j.trace_id = p;
                 j.count_from = dp[p].L;
-                j.bitoff = words + (uint64_t)c * w;
+                j.bitoff = pp[p].bitbase + (uint64_t)c * pp[p].words;
                 jobs.push_back(j);
             }
-            words += (uint64_t)w * n_cands;
         }
         if (words * 4 > kPlanMaxBitBytes) return set_error(PCHASE_ERANGE, "pool x candidates needs %llu bytes of hit bits",
                                                            (unsigned long long)(words * 4));
