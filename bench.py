@@ -24,7 +24,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_LANE_OPS = 256 * 64 * 2.4e9      # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# VALU lane-ops/s: 256 CUs x 128 vector lanes per clock x 2.4 GHz (the
+# published 157.3 TFLOP/s fp32 vector rate counts an FMA as two operations).
+# 32-bit integer add/shift/xor measure 58.9 T on one MI355X (microbench_valu,
+# 16 blocks of 256 per CU), above the 39.3 T of 64 lanes per clock, so the
+# 128-lane rate is the ceiling used here.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def kernel_source_digest() -> str:
@@ -171,6 +176,7 @@ def main():
 
     gpu_step_ms = float(np.median(gpu_ms))
     achieved = lane_ops / (gpu_step_ms * 1e-3)
+    measured_peak = capi.microbench_valu(8, 20000)
     traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                 "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
@@ -178,7 +184,9 @@ def main():
                                 "profile when it matches the current kernel sources, else null",
                 "algorithmic_bytes_per_step": accesses / 8,
                 "kernel": "sweep_kernel<policy, way class, score> (all instantiations of one captured step)",
-                "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms}
+                "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms,
+                "measured_valu_peak": measured_peak / 1e12, "frac_of_measured_peak": achieved / measured_peak,
+                "hbm_frac_algorithmic": accesses / 8 / (gpu_step_ms * 1e-3) / 8e12}
 
     learned = None
     if not args.no_learned:

@@ -391,6 +391,15 @@ int microbench_lds_bank(uint32_t stride_lo, uint32_t stride_hi, uint32_t reps,
 int microbench_lds_stream(uint32_t blocks_per_cu, uint32_t block, uint32_t ilp, uint32_t width_bytes,
                           uint32_t copy, uint32_t reps, double *gbps, hipStream_t stream);
 
+/* VALU issue rate: not an experiment of the paper but the denominator of
+ * the replay's roofline (the replay is integer VALU work).  blocks_per_cu x
+ * (number of CUs) blocks of 256 threads each run reps rounds of 8
+ * independent chains of three full-rate 32-bit VALU instructions (add,
+ * shift, xor); *lane_ops_per_s = 32-bit lane operations / elapsed time of
+ * one launch after a warm-up launch.  EINVAL for blocks_per_cu outside
+ * 1..32 or reps = 0.  Synchronises. */
+int microbench_valu(uint32_t blocks_per_cu, uint32_t reps, double *lane_ops_per_s, hipStream_t stream);
+
 /* ------------------------------------------------------ learned model --- */
 /* The learned proposer ranks candidates from a fixed set of fine-grained
  * runs (the Section 4.2 procedure of Fig. 6 frozen into one grid: array

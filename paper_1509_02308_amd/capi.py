@@ -99,6 +99,7 @@ def lib():
         L.microbench_hbm_stream.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp, vp]
         L.microbench_lds_bank.argtypes = [u32, u32, u32, vp, vp]
         L.microbench_lds_stream.argtypes = [u32, u32, u32, u32, u32, u32, vp, vp]
+        L.microbench_valu.argtypes = [u32, u32, vp, vp]
         L.pchase_abort.argtypes = [ctypes.c_int]
         L.pchase_release.argtypes = []
         L.pchase_mlp_grid.argtypes = [vp, u64]
@@ -358,6 +359,13 @@ def microbench_lds_stream(blocks_per_cu, block, ilp, width_bytes, reps, copy=Fal
     g = ctypes.c_double()
     check(lib().microbench_lds_stream(blocks_per_cu, block, ilp, width_bytes, int(bool(copy)), reps,
                                       ctypes.byref(g), _stream(stream)))
+    return float(g.value)
+
+
+def microbench_valu(blocks_per_cu=8, reps=20000, stream=None) -> float:
+    """Measured 32-bit VALU lane operations per second."""
+    g = ctypes.c_double()
+    check(lib().microbench_valu(blocks_per_cu, reps, ctypes.byref(g), _stream(stream)))
     return float(g.value)
 
 

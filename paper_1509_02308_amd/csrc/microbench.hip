@@ -287,9 +287,66 @@ static hipError_t launch_lds_stream(uint32_t grid, uint32_t block, uint32_t ilp,
     return hipGetLastError();
 }
 
+// VALU issue rate: every thread runs 8 independent chains of
+// x = (x + c) ^ (x >> 1) (add, shift, xor: three full-rate 32-bit VALU
+// instructions per chain and round, a nonlinear map the compiler cannot
+// fold across rounds); the xor of the chains decides a store that keeps
+// them alive.
+constexpr int kValuChains = 8;
+constexpr uint32_t kValuOpsPerChainRound = 3;
+
+__global__ void __launch_bounds__(256) valu_kernel(uint32_t reps, uint32_t* sink) {
+    uint32_t x[kValuChains];
+#pragma unroll
+    for (int j = 0; j < kValuChains; ++j) x[j] = threadIdx.x * 2654435761u + (uint32_t)j * 40503u + blockIdx.x;
+    for (uint32_t r = 0; r < reps; ++r) {
+#pragma unroll
+        for (int j = 0; j < kValuChains; ++j) x[j] = (x[j] + 0x9E3779B9u + (uint32_t)j) ^ (x[j] >> 1);
+    }
+    uint32_t y = 0;
+#pragma unroll
+    for (int j = 0; j < kValuChains; ++j) y ^= x[j];
+    if (y == 0x12345678u) sink[blockIdx.x] = y;   // practically never
+}
+
 }  // namespace pc
 
 using namespace pc;
+
+extern "C" int microbench_valu(uint32_t blocks_per_cu, uint32_t reps, double* lane_ops_per_s, hipStream_t stream) {
+    if (!lane_ops_per_s) return set_error(PCHASE_EINVAL, "lane_ops_per_s is NULL");
+    if (blocks_per_cu == 0 || blocks_per_cu > 32) return set_error(PCHASE_EINVAL, "blocks_per_cu must be 1..32");
+    if (reps == 0) return set_error(PCHASE_EINVAL, "reps must be >= 1");
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    int rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    const uint32_t grid = blocks_per_cu * (uint32_t)ws->cus;
+    hipError_t e = ws->aux.ensure((size_t)grid * 4);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "aux: %s", hipGetErrorString(e));
+    uint32_t* sink = ws->aux.as<uint32_t>();
+    hipLaunchKernelGGL(valu_kernel, dim3(grid), dim3(256), 0, stream, reps, sink);   // warm-up
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "valu kernel");
+    hipEvent_t a = nullptr, b = nullptr;
+    float ms = 0;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(valu_kernel, dim3(grid), dim3(256), 0, stream, reps, sink);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(b, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "valu kernel");
+    const double ops = (double)grid * 256.0 * reps * kValuChains * kValuOpsPerChainRound;
+    *lane_ops_per_s = ops / (ms * 1e-3);
+    return PCHASE_OK;
+}
 
 extern "C" int microbench_lds_stream(uint32_t blocks_per_cu, uint32_t block, uint32_t ilp, uint32_t width_bytes,
                                      uint32_t copy, uint32_t reps, double* gbps, hipStream_t stream) {

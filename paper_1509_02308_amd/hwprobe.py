@@ -4,6 +4,7 @@ and the cache inference fed with real fine-grained P-chase latencies.
     python -m paper_1509_02308_amd.hwprobe stream [--bytes B] [--sweep]
     python -m paper_1509_02308_amd.hwprobe lds
     python -m paper_1509_02308_amd.hwprobe ldsbw
+    python -m paper_1509_02308_amd.hwprobe valu
     python -m paper_1509_02308_amd.hwprobe l1 [--flavor 0]
     python -m paper_1509_02308_amd.hwprobe curve --s 128 --n-lo 4096 --n-hi 131072
 
@@ -13,6 +14,8 @@ and the cache inference fed with real fine-grained P-chase latencies.
   (Section 6.2, the bank-conflict sweep).
 * ldsbw: LDS throughput over blocks per CU x block size x reads in flight,
   4-byte and 16-byte accesses, read-only and LDS-to-LDS copy (Section 6.1).
+* valu: 32-bit VALU lane operations per second over blocks per CU (the
+  replay's roofline denominator, measured).
 * curve: the classic average-latency curve (Section 4.1): for each array
   size N, the mean and median cycles per access of a P-chase.
 * l1: the Section 4.2 procedure on the per-CU vector L1: fine-grained
@@ -92,6 +95,18 @@ def cmd_ldsbw(a):
                             best[copy] = row
     for row in best.values():
         print(json.dumps({**row, "probe": "lds_stream_best"}), flush=True)
+
+
+def cmd_valu(a):
+    torch, capi = _torch_capi()
+    best = 0.0
+    for bpc in (1, 2, 4, 8, 16):
+        v = capi.microbench_valu(bpc, a.reps)
+        best = max(best, v)
+        print(json.dumps({"probe": "valu", "blocks_per_cu": bpc, "lane_ops_per_s": v,
+                          "frac_of_nominal": v / (256 * 64 * 2.4e9)}), flush=True)
+    print(json.dumps({"probe": "valu_best", "lane_ops_per_s": best, "frac_of_nominal": best / (256 * 64 * 2.4e9)}),
+          flush=True)
 
 
 def _chase(torch, capi, N, s, passes, flavor, arr):
@@ -174,6 +189,8 @@ def main(argv=None):
     p.add_argument("--reps", type=int, default=16)
     p = sub.add_parser("ldsbw")
     p.add_argument("--reps", type=int, default=2048)
+    p = sub.add_parser("valu")
+    p.add_argument("--reps", type=int, default=20000)
     p = sub.add_parser("curve")
     p.add_argument("--s", type=int, default=128)
     p.add_argument("--n-lo", type=int, default=4096)
@@ -183,7 +200,8 @@ def main(argv=None):
     p = sub.add_parser("l1")
     p.add_argument("--flavor", type=int, default=0)
     a = ap.parse_args(argv)
-    {"stream": cmd_stream, "lds": cmd_lds, "ldsbw": cmd_ldsbw, "curve": cmd_curve, "l1": cmd_l1}[a.cmd](a)
+    {"stream": cmd_stream, "lds": cmd_lds, "ldsbw": cmd_ldsbw, "valu": cmd_valu, "curve": cmd_curve,
+     "l1": cmd_l1}[a.cmd](a)
 
 
 if __name__ == "__main__":

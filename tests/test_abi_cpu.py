@@ -149,6 +149,8 @@ def test_microbench_argument_checks(capi):
                                ctypes.c_void_p(16), ctypes.byref(ovh), None) == -1   # flavour
     for args in ((0, 64, 1, 4, 0), (1, 100, 1, 4, 0), (1, 64, 3, 4, 0), (1, 64, 1, 8, 0), (1, 64, 1, 4, 2)):
         assert L.microbench_lds_stream(*args, 1, ctypes.byref(g), None) == -1
+    assert L.microbench_valu(0, 1, ctypes.byref(g), None) == -1
+    assert L.microbench_valu(1, 0, ctypes.byref(g), None) == -1
 
 
 def test_nonuniform_trace_len_and_validation(capi, orc):

@@ -379,6 +379,18 @@ def test_microbench_lds_stream_occupancy_and_bound():
         capi.microbench_lds_stream(4, 100, 4, 4, 1)
 
 
+def test_microbench_valu_near_nominal_peak():
+    torch, capi = need_gpu()
+    say("microbench_valu")
+    v = capi.microbench_valu(8, 4000)
+    # 64 lanes per CU per clock at 2.4 GHz; gfx950 issues some 32-bit ops
+    # faster (measured about 1.3x), so the bound is the 128-lane vector rate
+    nominal = 256 * 64 * 2.4e9
+    assert 0.3 * nominal < v < 2.05 * nominal
+    with pytest.raises(capi.PchaseError):
+        capi.microbench_valu(0, 1)
+
+
 def test_trace_array_replay_mixed_set_counts_reusing_slabs():
     """Regression: one lane group replays pair after pair of models with the
     same way-group width but different set counts, so its state slab is
