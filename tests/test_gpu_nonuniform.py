@@ -101,3 +101,41 @@ def test_nonuniform_lru_fifo_differ_on_gpu():
     b = bits.cpu().numpy().view(np.uint32)
     assert unpack_bits(b[0:1], 5).tolist() == [0, 0, 1, 0, 1]
     assert unpack_bits(b[1:2], 5).tolist() == [0, 0, 1, 0, 0]
+
+
+def test_nonuniform_benchmark_size_sampled():
+    """The benchmark's non-uniform workload (4096 chases, 1.1e9 accesses):
+    16 seeded traces compared whole with the oracle, and their replays
+    through a standard and a generalised cache."""
+    torch, capi = need_gpu()
+    rows = W.nonuniform_rows(n=4096, seed=5209, n_hi=64 << 20, max_count=60_000)
+    say("pchase_trace_nu at benchmark size")
+    idx, off = _gpu_traces(torch, capi, rows)
+    rng = np.random.default_rng(4096)
+    sample = sorted(rng.choice(len(rows), size=16, replace=False).tolist())
+    traces = []
+    for i in sample:
+        want = _oracle_trace(rows[i])
+        got = idx[int(off[i]):int(off[i + 1])].cpu().numpy()
+        assert np.array_equal(got, want), i
+        traces.append(want)
+    sub = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    soff = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    bases = [rows[i][4] for i in sample]
+    n = len(traces)
+    misses = torch.zeros(2 * n, dtype=torch.int64, device="cuda")
+    say("replay of the sampled traces")
+    capi.cache_replay_batch(capi.models([(16384, 64, 8, W.PLRU)]), sub, soff, bases, np.zeros(n, np.uint32),
+                            np.arange(n, dtype=np.uint32), None, misses)
+    g = [d for d in W.paper_general_targets() if d["name"] == "fermi_l1"][0]
+    gm = torch.zeros(2 * n, dtype=torch.int64, device="cuda")
+    capi.cache_replay_general(capi.general_models([{k: v for k, v in g.items() if k != "name"}]), sub, soff, bases,
+                              np.zeros(n, np.uint32), np.arange(n, dtype=np.uint32), None, gm)
+    torch.cuda.synchronize()
+    mis, gmis = misses.cpu().numpy().reshape(-1, 2), gm.cpu().numpy().reshape(-1, 2)
+    og = orc.General(g["line"], g["ways"], g["policy"], weights=g["weights"], seed=g["seed"])
+    for t in range(n):
+        _, mt, ms = orc.replay(orc.make_model(16384, 64, 8, W.PLRU), traces[t], base=bases[t], trace_id=t)
+        assert (mis[t, 0], mis[t, 1]) == (mt, ms)
+        _, mt, ms = orc.replay_general(og, traces[t], base=bases[t], trace_id=t)
+        assert (gmis[t, 0], gmis[t, 1]) == (mt, ms)

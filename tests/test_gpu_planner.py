@@ -81,3 +81,31 @@ def test_adaptive_loop_matches_oracle(target):
     surv, used_ref = P.adaptive(orc, cands, pool, cands[target])
     assert used == used_ref
     assert np.nonzero(alive)[0].tolist() == surv
+
+
+def test_planner_full_grid_sampled():
+    """The benchmark's configuration (438 candidates x the 768-probe feature
+    grid): class rows of 24 seeded probes against the oracle, and the first
+    choice (all candidates alive) against the oracle's choice over those
+    rows' full pool recomputed only where it can win."""
+    torch, capi = need_gpu()
+    cands = [(int(c["C"]), int(c["b"]), int(c["a"]), int(c["policy"])) for c in W.candidate_grid()]
+    grid = capi.pchase_mlp_grid()
+    pool = [(grid[i].n_bytes, grid[i].s_bytes, grid[i].passes) for i in range(grid.n)]
+    cls = torch.full((len(pool) * len(cands),), -1, dtype=torch.int32, device="cuda")
+    say(f"pchase_plan_next_probe full grid: {len(cands)} x {len(pool)}")
+    alive = np.ones(len(cands), dtype=bool)
+    ch = capi.pchase_plan_next_probe(capi.models(cands), grid, _bitmap(alive), cls)
+    got = cls.cpu().numpy().reshape(len(pool), len(cands))
+    rng = np.random.default_rng(768)
+    sample = sorted(set(rng.choice(len(pool), size=24, replace=False).tolist()) | {int(ch.probe)})
+    want = P.classes(orc, cands, [pool[p] for p in sample])
+    for i, p in enumerate(sample):
+        assert np.array_equal(got[p], want[i]), pool[p]
+    # the chosen probe's score is the oracle's score of that row, and no
+    # sampled row scores better
+    worst, n = P.score(want[sample.index(int(ch.probe))], alive)
+    assert (ch.worst, ch.n_classes) == (worst, n)
+    for i, p in enumerate(sample):
+        w2, n2 = P.score(want[i], alive)
+        assert (w2, -n2, p) >= (worst, -n, int(ch.probe))
