@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned-samples", type=int, default=1_000_000)
     ap.add_argument("--learned-epochs", type=int, default=2)
-    ap.add_argument("--learned-targets", type=int, default=200)
+    ap.add_argument("--learned-targets", type=int, default=1000)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--large-pairs", type=int, default=1_000_000)
     ap.add_argument("--nu-probes", type=int, default=4096)
