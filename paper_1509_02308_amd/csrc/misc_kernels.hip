@@ -12,8 +12,10 @@ namespace pc {
 // within the probe in one load).  Each thread computes a
 // run of 16 consecutive accesses, the first from the closed form and the
 // rest incrementally; the block then transposes the chunk through LDS so
-// that consecutive threads store consecutive indices (coalesced writes
-// whatever the alignment of the probe's offset).
+// that consecutive threads store consecutive 16-byte groups of indices
+// (coalesced writes; the up to 3 words before and after the chunk's
+// 16-byte-aligned middle are stored one by one, whatever the alignment of
+// the probe's offset).
 constexpr int kTraceRun = 16;
 constexpr uint32_t kTraceThreads = 256;
 constexpr uint32_t kTraceChunk = kTraceThreads * kTraceRun;
@@ -27,11 +29,29 @@ __device__ inline void store_chunk(const int32_t (&v)[kTraceRun], int32_t* out, 
 #pragma unroll
     for (int r = 0; r < kTraceRun; ++r) buf[(kTraceRun + 1) * t + r] = v[r];   // word x at x + x/16
     __syncthreads();
+    // 16-byte stores for the part of the chunk that is 16-byte aligned in
+    // memory, single words for the up to 3 words before and after it
+    int32_t* dst = out + k0;
+    const uint32_t n = (uint32_t)((len - k0) < kTraceChunk ? (len - k0) : kTraceChunk);
+    const uint32_t h = (uint32_t)((4u - (uint32_t)((reinterpret_cast<uintptr_t>(dst) >> 2) & 3u)) & 3u);
+    auto word = [&](uint32_t x) { return buf[x + x / kTraceRun]; };
+    if (t < h && t < n) dst[t] = word(t);
+    const uint32_t nv = n > h ? (n - h) / 4u : 0u;
 #pragma unroll
-    for (int i = 0; i < kTraceRun; ++i) {
-        const uint32_t x = i * kTraceThreads + t;
-        if (k0 + x < len) out[k0 + x] = buf[x + x / kTraceRun];
+    for (int i = 0; i < kTraceRun / 4; ++i) {
+        const uint32_t q = i * kTraceThreads + t;
+        if (q < nv) {
+            const uint32_t x = h + 4u * q;
+            int4 w;
+            w.x = word(x);
+            w.y = word(x + 1);
+            w.z = word(x + 2);
+            w.w = word(x + 3);
+            *reinterpret_cast<int4*>(dst + x) = w;
+        }
     }
+    const uint32_t t0 = h + 4u * nv;
+    if (t < 4u && t0 + t < n) dst[t0 + t] = word(t0 + t);
 }
 
 // Uniform chase (Listing 1 + Listing 2): access k visits (j0 + (k mod L)*se)
