@@ -25,7 +25,7 @@ def _traces(rng):
     for r in W.nonuniform_rows(n=4, seed=61, n_hi=1 << 20, max_count=600):
         tr.append(orc.trace_nu(r[0], r[1], passes=r[2], j0=r[3]))
     # long enough to be replayed as parts by set (state permitting)
-    tr.append(rng.integers(0, 20000, size=60001).astype(np.int32))
+    tr.append(rng.integers(0, 20000, size=300001).astype(np.int32))
     tr.append(orc.trace(orc.make_probe(24576 + 128, 32, passes=20)))
     return tr
 

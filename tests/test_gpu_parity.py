@@ -172,6 +172,34 @@ def test_trace_array_replay_matches_oracle(mode):
         assert np.array_equal(unpack_bits(b[bitoff[i]:], len(traces[t])), hits), (MODELS[m], t)
 
 
+def test_trace_array_replay_long_traces_split_by_set():
+    """Traces longer than the split length replay as parts by set that merge
+    their bits and counts; every policy and way class against the oracle."""
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(131)
+    traces = [rng.integers(0, 40000, size=300007).astype(np.int32),
+              orc.trace(orc.make_probe(65536 + 256, 32, passes=40))]
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    mrows = [MODELS[i] for i in (0, 1, 2, 3, 9, 12, 13, 17, 25, 26, 27)]
+    pairs = [(m, t) for m in range(len(mrows)) for t in range(len(traces))]
+    cf = np.array([len(traces[t]) // 5 for _, t in pairs], dtype=np.uint64)
+    words = [(len(traces[t]) + 31) // 32 for _, t in pairs]
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.full((int(sum(words)) + 1,), 0x0F0F0F0F, dtype=torch.int32, device="cuda")
+    misses = torch.full((2 * len(pairs),), -1, dtype=torch.int64, device="cuda")
+    say(f"cache_replay_batch long traces: {len(pairs)} pairs")
+    capi.cache_replay_batch(capi.models(mrows), idx, off, None, np.array([m for m, _ in pairs], np.uint32),
+                            np.array([t for _, t in pairs], np.uint32), cf, misses, bits, bitoff)
+    torch.cuda.synchronize()
+    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    b = bits.cpu().numpy().view(np.uint32)
+    for i, (m, t) in enumerate(pairs):
+        hits, mt, ms = orc.replay(orc_model(mrows[m]), traces[t], trace_id=t, count_from=int(cf[i]))
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms), (mrows[m], t)
+        assert np.array_equal(unpack_bits(b[bitoff[i]:], len(traces[t])), hits), (mrows[m], t)
+
+
 def test_trace_array_replay_repeated_calls_reuse_state():
     """Second call with other pairs on the same (reused) state slabs."""
     torch, capi = need_gpu()
