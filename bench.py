@@ -66,6 +66,14 @@ def measured_traffic():
     return int(vals["traffic_bytes_per_step:"])
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg: str):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
 def lane_ops_per_access(a: int, policy: int) -> float:
     """Algorithmic VALU lane-ops of one replayed access (stated convention):
     LRU 3a+8 (a tag compares, 2a recency updates), FIFO a+8, tree-PLRU
@@ -92,6 +100,9 @@ def main():
     ap.add_argument("--large-pairs", type=int, default=1_000_000)
     ap.add_argument("--nu-probes", type=int, default=4096)
     ap.add_argument("--adaptive-targets", type=int, default=50)
+    ap.add_argument("--plain-sweep-calls", type=int, default=50)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="capture the batched step with its default branch assignment (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -107,6 +118,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    log("inference sweep: building inputs")
 
     cands, probes, target = W.inference_sweep()
     crows = [tuple(int(x) for x in c) for c in cands]
@@ -132,14 +144,18 @@ def main():
         accesses += acc
         lane_ops += acc * lane_ops_per_access(a, pol)
 
-    def step(sched=0):
-        return capi.infer_cache_params(parr, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_OWN_SWEEP,
-                                       mode=capi.EXHAUSTIVE | sched)[0]
+    tune_flag = capi.SCHED_UNTUNED if args.no_autotune else 0
 
+    def step(sched=0, mn=None):
+        return capi.infer_cache_params(parr, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_OWN_SWEEP,
+                                       mode=capi.EXHAUSTIVE | sched | tune_flag, mn=mn)[0]
+
+    log("inference sweep: cold step (plan, capture" + ("" if args.no_autotune else ", autotune") + ")")
     t_cold0 = time.perf_counter()
     res = step()
     cold_ms = (time.perf_counter() - t_cold0) * 1e3
     assert res.replayed_accesses == accesses, (res.replayed_accesses, accesses)
+    log(f"inference sweep: cold step {cold_ms:.1f} ms; {args.warmup} warm-up, {args.steps} timed steps")
     for _ in range(max(0, args.warmup - 1)):
         res = step()
 
@@ -159,10 +175,16 @@ def main():
     gpu_ms = [a.elapsed_time(b) for a, b in ev]
     value = accesses * args.steps / wall
     exact = bool(res.best >= 0 and res.best_m == 0)
+    log(f"inference sweep: {wall * 1e3 / args.steps:.2f} ms per step")
+    # every candidate's (m, n), for the oracle comparison of the CPU leg
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+    step(mn=mn)
+    gpu_mn = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
 
     # plain schedule: one launch per candidate, no persistent queue, no graph
     plain = None
     if args.plain_steps > 0:
+        log("inference sweep: plain schedule")
         step(capi.SCHED_PLAIN)
         torch.cuda.synchronize()
         tp = time.perf_counter()
@@ -188,25 +210,33 @@ def main():
                 "measured_valu_peak": measured_peak / 1e12, "frac_of_measured_peak": achieved / measured_peak,
                 "hbm_frac_algorithmic": accesses / 8 / (gpu_step_ms * 1e-3) / 8e12}
 
+    plain_sweep = None
+    if args.plain_sweep_calls > 0:
+        log("plain sweep: per-call latency")
+        plain_sweep = plain_sweep_leg(torch, capi, W, args)
+
     learned = None
     if not args.no_learned:
         learned = learned_leg(torch, capi, W, crows, args)
 
     large = None
     if args.large_pairs > 0:
-        large = large_batch_leg(torch, capi, W, args)
+        large = large_batch_leg(torch, capi, W, args, stream)
 
     adaptive = None
     if args.adaptive_targets > 0:
+        log("adaptive probing")
         adaptive = adaptive_leg(torch, capi, W, crows, args)
 
     nonuniform = None
     if args.nu_probes > 0:
+        log("non-uniform chases")
         nonuniform = nonuniform_leg(torch, capi, W, args, stream)
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(crows, prows, lens, bits, bitoff, args.cpu_seconds)
+        log("CPU oracle")
+        cpu = cpu_baseline(crows, prows, lens, bits, bitoff, args.cpu_seconds, gpu_mn)
 
     out = {
         "metric": "cache-model replayed accesses/sec and time-to-inferred-params, batched vs plain",
@@ -232,6 +262,7 @@ def main():
         "best": int(res.best),
         "zero_class": int(res.n_zero),
         "plain": plain,
+        "plain_sweep": plain_sweep,
         "learned": learned,
         "large_batch": large,
         "nonuniform": nonuniform,
@@ -242,6 +273,42 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def plain_sweep_leg(torch, capi, W, args):
+    """The small plain sweep (one LRU cache of 4 KB, 32 B lines, 4 ways;
+    N = 2..8 KB in 32 B steps x s in {32, 64, 128} B, 2 passes: 579 traces,
+    150,320 accesses) with per-access hit bits and both miss counts, as one
+    cache_replay_probes call.  It is launch-bound: the figure is the latency
+    of one call (median over calls, host clock around the call and a
+    stream synchronisation), batched (one captured persistent launch) vs
+    plain (one ordinary launch per model)."""
+    model, prow = W.plain_sweep()
+    mrow = tuple(int(v) for v in model)
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in prow]
+    marr, parr = capi.models([mrow]), capi.probes(prows)
+    lens = np.array([capi.pchase_trace_len(parr[i])[0] for i in range(len(prows))], dtype=np.uint64)
+    words = (lens + 31) // 32
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.zeros(int(words.sum()) + 1, dtype=torch.int32, device="cuda")
+    misses = torch.zeros(2 * len(prows), dtype=torch.int64, device="cuda")
+    pm = np.zeros(len(prows), np.uint32)
+    pp = np.arange(len(prows), dtype=np.uint32)
+    out = {"traces": len(prows), "accesses": int(lens.sum())}
+    for name, mode in (("batched", capi.BATCHED), ("plain", capi.PLAIN)):
+        for _ in range(3):
+            capi.cache_replay_probes(marr, parr, pm, pp, None, misses, bits, bitoff, mode)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(args.plain_sweep_calls):
+            t = time.perf_counter()
+            capi.cache_replay_probes(marr, parr, pm, pp, None, misses, bits, bitoff, mode)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t) * 1e3)
+        out[f"{name}_ms_per_call"] = float(np.median(lat))
+        out[f"{name}_accesses_per_s"] = int(lens.sum()) / (np.median(lat) * 1e-3)
+    out["calls"] = args.plain_sweep_calls
+    return out
+
+
 def learned_leg(torch, capi, W, crows, args):
     """Learned proposer on the fixed 768-probe grid: canonical labels,
     Philox-noised training samples, bf16-MFMA training, then learned
@@ -249,10 +316,12 @@ def learned_leg(torch, capi, W, crows, args):
     seeded targets, both comparing every grid probe."""
     carr = capi.models(crows)
     n = len(crows)
+    log("learned: labels")
     t0 = time.perf_counter()
     labels = capi.pchase_mlp_labels(carr)
     t_labels = time.perf_counter() - t0
     ns = args.learned_samples
+    log(f"learned: {ns} samples")
     x = torch.zeros(ns, 768, dtype=torch.float32, device="cuda")
     y = torch.zeros(ns, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
@@ -261,6 +330,7 @@ def learned_leg(torch, capi, W, crows, args):
     t_samples = time.perf_counter() - t0
     net = capi.Mlp(n, 2308)
     torch.cuda.synchronize()
+    log(f"learned: training {args.learned_epochs} epochs")
     t0 = time.perf_counter()
     loss = net.train(x, y, 1024, args.learned_epochs, 1e-3)
     t_train = time.perf_counter() - t0
@@ -282,7 +352,10 @@ def learned_leg(torch, capi, W, crows, args):
     capi.cache_replay_probes(carr, g, pm, pp, None, misses, all_bits, bo)
     obs = torch.zeros(tw, dtype=torch.int32, device="cuda")
     t_l, t_e, acc_l, acc_e, fb, exact, agree = [], [], 0, 0, 0, 0, 0
+    log(f"learned: {len(targets)} held-out targets")
     for k, t in enumerate(targets):
+        if k and k % 250 == 0:
+            log(f"learned: target {k}")
         obs.copy_(all_bits[k * tw:(k + 1) * tw])
         torch.cuda.synchronize()
         a = time.perf_counter()
@@ -312,14 +385,16 @@ def learned_leg(torch, capi, W, crows, args):
             "exhaustive_replayed_accesses_per_target": acc_e / len(targets)}
 
 
-def large_batch_leg(torch, capi, W, args):
+def large_batch_leg(torch, capi, W, args, stream):
     """Large batch of materialised traces: seeded (model, trace) pairs of
     uneven length (log-uniform 1e3..1e5 accesses, uniform-stride P-chases),
     caches 8 KB..4 MB, a up to 128, LRU/FIFO/PLRU/RANDOM; traces generated on
     the device (untimed), then one cache_replay_batch call (hit bits and both
-    miss counts of every pair) is timed after a warm-up call.  Parity at this
-    size is checked by the GPU tests on a sampled 1% of the pairs."""
+    miss counts of every pair) is timed after a warm-up call, on the host
+    clock and with HIP events on the launch stream.  Parity at this size
+    (every pair's counts, 1% of the bitmaps) is a GPU test."""
     n = args.large_pairs
+    log(f"large batch: {n} pairs, traces")
     mrows, prows = W.large_batch(n)
     marr, parr = capi.models(mrows), capi.probes(prows)
     lc = np.array([capi.pchase_trace_len(parr[i]) for i in range(n)], dtype=np.uint64)
@@ -333,16 +408,42 @@ def large_batch_leg(torch, capi, W, args):
     misses = torch.zeros(2 * n, dtype=torch.int64, device="cuda")
     bases = np.array([int(p["base"]) for p in prows], np.uint64)
     pm = np.arange(n, dtype=np.uint32)
+    log("large batch: warm-up call")
     capi.cache_replay_batch(marr, idx, off, bases, pm, pm, cyc, misses, bits, bitoff)   # warm-up
     torch.cuda.synchronize()
+    log("large batch: timed call")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record(stream)
     capi.cache_replay_batch(marr, idx, off, bases, pm, pm, cyc, misses, bits, bitoff)
+    e1.record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ev_s = e0.elapsed_time(e1) * 1e-3
+    mis = misses.cpu().numpy().astype(np.float64).reshape(-1, 2)
     del idx, bits
+    # algorithmic work: lane-ops of the policy convention per access (RANDOM:
+    # + 60 per miss, every miss counted as evicting: an upper bound), bytes =
+    # 4 per trace index + 1/8 of hit bit + 16 of counters per pair
+    a = mrows["a"].astype(np.float64)
+    pol = mrows["policy"].astype(np.int64)
+    per = np.where(pol == 0, 3 * a + 8, np.where(pol == 2, a + 2 * np.log2(a) + 8, a + 8))
+    lane_ops = float((lens.astype(np.float64) * per).sum() + 60.0 * mis[pol == 3, 0].sum())
+    alg_bytes = 4.0 * total + total / 8.0 + 16.0 * n
+    hbm_frac = alg_bytes / ev_s / 8e12
+    alu_frac = lane_ops / ev_s / PEAK_LANE_OPS
+    bound = "hbm" if hbm_frac >= alu_frac else "alu"
+    roof = {"bound": bound,
+            "achieved": (alg_bytes / ev_s / 1e9) if bound == "hbm" else (lane_ops / ev_s / 1e12),
+            "peak": 8000.0 if bound == "hbm" else PEAK_LANE_OPS / 1e12,
+            "unit": "GB/s" if bound == "hbm" else "Tlane-op/s",
+            "frac": max(hbm_frac, alu_frac), "traffic": None,
+            "hbm_frac": hbm_frac, "alu_frac": alu_frac,
+            "algorithmic_bytes": alg_bytes, "algorithmic_lane_ops": lane_ops, "kernel_s": ev_s}
+    log(f"large batch: {dt:.3f} s ({total / dt:.3e} accesses/s)")
     return {"pairs": n, "accesses": total, "trace_bytes": 4 * total, "replay_s": dt,
             "value": total / dt, "unit": "accesses/s",
-            "hbm_GBps_trace_only": 4 * total / dt / 1e9}
+            "hbm_GBps_trace_only": 4 * total / dt / 1e9, "roofline": roof}
 
 
 def adaptive_leg(torch, capi, W, crows, args):
@@ -460,9 +561,11 @@ def nonuniform_leg(torch, capi, W, args, stream):
             "general_targets": [d["name"] for d in W.paper_general_targets()]}
 
 
-def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):
+def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s, gpu_mn):
     """The CPU oracle (single-threaded) on a bounded sample of the same
-    inference: a few candidates, each on its full own sweep."""
+    inference: a few candidates, each on its full own sweep; then the same
+    oracle across the host's cores.  Every candidate the oracle scores is
+    compared with the GPU's (m, n)."""
     import oracle as orc
 
     b = bits.cpu().numpy().view(np.uint32)
@@ -479,23 +582,26 @@ def cpu_baseline(crows, prows, lens, bits, bitoff, budget_s):
     oprobes = [orc.make_probe(*r) for r in prows]
     # a seeded random order over the whole grid, until the time budget is used
     order = np.random.default_rng(2308).permutation(len(crows)).tolist()
-    done, acc, t_used = [], 0, 0.0
+    done, acc, t_used, mismatch = [], 0, 0.0, []
     for i in order:
         if t_used > budget_s:
             break
         m = orc.make_model(*crows[i][:4])
         t = time.perf_counter()
-        _, _, n = orc.infer([m], oprobes, flat, off, cf, probe_select=1)
+        _, mm, nn = orc.infer([m], oprobes, flat, off, cf, probe_select=1)
         t_used += time.perf_counter() - t
+        if (int(mm[0]), int(nn[0])) != (int(gpu_mn[i, 0]), int(gpu_mn[i, 1])):
+            mismatch.append(i)
         own = [p for p in range(len(prows)) if orc.in_own_sweep(m, oprobes[p])]
         acc += int(sum(int(lens[p]) for p in own))
         done.append(crows[i])
     out = {"value": acc / t_used, "unit": "accesses/s", "cores": 1, "kind": "oracle",
            "sample": f"{len(done)} of the {len(crows)} candidates (seeded random order) on their full own "
                      f"sweeps against the same observation, {acc} replayed accesses, {t_used:.1f} s "
-                     f"single-threaded"}
+                     f"single-threaded",
+           "parity_checked": len(done), "parity_mismatches": mismatch}
     try:
-        out["all_cores"] = cpu_pool(crows, prows, lens, flat, off, cf, order, budget_s)
+        out["all_cores"] = cpu_pool(crows, prows, lens, flat, off, cf, order, budget_s, gpu_mn)
     except Exception as e:   # the single-core figure stands on its own
         out["all_cores"] = {"error": f"{type(e).__name__}: {e}"}
     return out
@@ -510,20 +616,20 @@ def _cpu_pool_worker(task):
     d = np.load(path)
     prows = [tuple(int(x) for x in r) for r in d["prows"]]
     oprobes = [orc.make_probe(*r) for r in prows]
-    acc, t_used, count = 0, 0.0, 0
-    for row in rows:
+    acc, t_used, scores = 0, 0.0, []
+    for ci, row in rows:
         if t_used > budget_s:
             break
         m = orc.make_model(*[int(x) for x in row[:4]])
         t = time.perf_counter()
-        orc.infer([m], oprobes, d["flat"], d["off"], d["cf"], probe_select=1)
+        _, mm, nn = orc.infer([m], oprobes, d["flat"], d["off"], d["cf"], probe_select=1)
         t_used += time.perf_counter() - t
         acc += int(sum(int(d["lens"][p]) for p in range(len(prows)) if orc.in_own_sweep(m, oprobes[p])))
-        count += 1
-    return acc, t_used, count
+        scores.append((ci, int(mm[0]), int(nn[0])))
+    return acc, t_used, scores
 
 
-def cpu_pool(crows, prows, lens, flat, off, cf, order, budget_s):
+def cpu_pool(crows, prows, lens, flat, off, cf, order, budget_s, gpu_mn):
     """The same oracle, one independent candidate per process at a time,
     across the host's cores (at most 16 processes), each process on its own
     share of the seeded order for the same time budget; aggregate rate =
@@ -537,16 +643,19 @@ def cpu_pool(crows, prows, lens, flat, off, cf, order, budget_s):
         path = os.path.join(tmp, "obs.npz")
         np.savez(path, flat=flat, off=off, cf=cf, lens=np.asarray(lens, np.uint64),
                  prows=np.asarray(prows, np.int64))
-        shares = [[crows[i] for i in order[k::procs]] for k in range(procs)]
+        shares = [[(i, crows[i]) for i in order[k::procs]] for k in range(procs)]
         # fresh interpreters (nothing inherited from this GPU process); a
         # worker that dies fails the map instead of being replaced
         with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn")) as ex:
             res = list(ex.map(_cpu_pool_worker, [(path, sh, budget_s) for sh in shares], timeout=budget_s * 4 + 120))
     acc = sum(r[0] for r in res)
     t = max(r[1] for r in res)
+    scores = [sc for r in res for sc in r[2]]
+    mismatch = [ci for ci, mm, nn in scores if (mm, nn) != (int(gpu_mn[ci, 0]), int(gpu_mn[ci, 1]))]
     return {"value": acc / t, "unit": "accesses/s", "cores": procs, "kind": "oracle",
-            "sample": f"{sum(r[2] for r in res)} candidates over {procs} processes, {acc} replayed accesses, "
-                      f"{t:.1f} s per process"}
+            "sample": f"{len(scores)} candidates over {procs} processes, {acc} replayed accesses, "
+                      f"{t:.1f} s per process",
+            "parity_checked": len(scores), "parity_mismatches": mismatch}
 
 
 if __name__ == "__main__":

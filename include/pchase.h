@@ -284,6 +284,11 @@ enum { PCHASE_EXHAUSTIVE = 0, PCHASE_LEARNED = 1 };
 /* OR into infer_cache_params' mode to replay with the PLAIN schedule (one
  * launch per candidate) instead of the captured persistent batch. */
 #define PCHASE_SCHED_PLAIN 0x100
+/* OR into infer_cache_params' mode to capture the batched schedule with its
+ * default branch assignment instead of timing every assignment on the first
+ * call of a problem (for profiling runs, where the timing loop would be
+ * serialised by the profiler). */
+#define PCHASE_SCHED_UNTUNED 0x200
 
 /* Observed fine-grained P-chase runs (Listing 3 outputs): probe p's trace
  * is known from the probe; its hit bits are either given (bits_dev, layout
@@ -413,9 +418,12 @@ int microbench_valu(uint32_t blocks_per_cu, uint32_t reps, double *lane_ops_per_
  * accesses [L, 2L) divided by L, rounded once to float.
  * Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3 with
  * W1 [256][768], W2 [256][256], W3 [n_out][256] row-major; products run on
- * bf16 operands (weights rounded to nearest-even from fp32 masters,
- * activations likewise) with fp32 accumulation; loss = mean softmax
- * cross-entropy; Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected). */
+ * the bf16 matrix cores with fp32 accumulation: weights are bf16 copies
+ * (nearest-even) of fp32 masters, the input features are rounded to bf16,
+ * and the fp32 hidden activations and back-propagated errors enter each
+ * product as a pair hi + lo of bf16 values (hi = bf16(v), lo = bf16(v - hi),
+ * about 2^-17 relative); loss = mean softmax cross-entropy; Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected). */
 #define PCHASE_MLP_IN 768
 #define PCHASE_MLP_HIDDEN 256
 
@@ -461,7 +469,10 @@ int pchase_mlp_train_step(pchase_mlp *net, const float *x_dev, const int32_t *la
                           uint32_t batch, float lr, float *loss, hipStream_t stream);
 /* `epochs` passes of consecutive batches over n_samples rows (a trailing
  * partial batch is skipped); *last_loss (nullable) = loss of the last
- * batch.  Synchronises. */
+ * batch.  The step is captured into a graph on the first call for given
+ * (x_dev, labels_dev, batch, lr) and replayed once per batch; the result
+ * equals that of pchase_mlp_train_step on each batch in turn.
+ * Synchronises. */
 int pchase_mlp_train(pchase_mlp *net, const float *x_dev, const int32_t *labels_dev, uint64_t n_samples,
                      uint32_t batch, uint32_t epochs, float lr, float *last_loss, hipStream_t stream);
 /* Logits fp32 [batch][n_out] of x_dev (device). */
@@ -482,9 +493,10 @@ int pchase_mlp_param(const pchase_mlp *net, uint32_t which, uint32_t slot, void 
 int pchase_mlp_step_count(const pchase_mlp *net, uint64_t *steps, int set);
 
 /* --------------------------------------------------------- lifecycle --- */
-/* Sets a host flag that running persistent replays poll; they drain and
- * the call that launched them returns PCHASE_EABORTED.  pchase_abort(0)
- * clears it. */
+/* Sets a host flag that the persistent replays of the BATCHED schedule
+ * poll (each wave on its first queue pull and every 8th after it); they
+ * drain and the call that launched them returns PCHASE_EABORTED, outputs
+ * unspecified.  pchase_abort(0) clears it; later calls are unaffected. */
 void pchase_abort(int on);
 /* Frees the calling thread's current device workspace. */
 int pchase_release(void);

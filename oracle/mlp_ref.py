@@ -28,10 +28,7 @@ What it computes
 * Network.  h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3,
   loss = mean softmax cross-entropy, in float64 on given (bf16-representable)
   weights and inputs, with the analytic backward pass; Adam with
-  beta = (0.9, 0.999), eps = 1e-8 and bias correction.  Optionally the
-  operands of every product are rounded to bf16 where a bf16-operand
-  network rounds them (hidden activations, back-propagated errors); the
-  products themselves stay exact.
+  beta = (0.9, 0.999), eps = 1e-8 and bias correction.
 """
 from __future__ import annotations
 
@@ -152,18 +149,15 @@ def sample(orc, i, seed, model_rows, labels, rho_q16):
 
 
 # ------------------------------------------------------------ MLP ---
-def forward(params, X, rnd=None):
+def forward(params, X):
     """params = (W1, b1, W2, b2, W3, b3) with W_l of shape (out, in); X of
-    shape (batch, 768).  Returns (logits, cache) in float64.  rnd (e.g.
-    bf16_round) is applied to the hidden activations that feed the next
-    product, as a network with bf16 operands stores them."""
-    r = rnd if rnd is not None else (lambda v: v)
+    shape (batch, 768).  Returns (logits, cache) in float64."""
     W1, b1, W2, b2, W3, b3 = [np.asarray(p, dtype=np.float64) for p in params]
     X = np.asarray(X, dtype=np.float64)
     a1 = X @ W1.T + b1
-    h1 = np.asarray(r(np.maximum(a1, 0.0)), dtype=np.float64)
+    h1 = np.maximum(a1, 0.0)
     a2 = h1 @ W2.T + b2
-    h2 = np.asarray(r(np.maximum(a2, 0.0)), dtype=np.float64)
+    h2 = np.maximum(a2, 0.0)
     z = h2 @ W3.T + b3
     return z, (X, a1, h1, a2, h2)
 
@@ -175,15 +169,11 @@ def loss_fn(z, y) -> float:
     return float(np.mean(lse - z[np.arange(len(y)), y]))
 
 
-def loss_and_grads(params, X, y, rnd=None):
-    """Loss and its gradient with respect to (W1, b1, W2, b2, W3, b3).
-    With rnd, the activations and the back-propagated errors that enter a
-    matrix product are rounded by it (bias gradients sum the unrounded
-    errors), which is how a network with bf16 operands evaluates them."""
-    r = rnd if rnd is not None else (lambda v: v)
-    f = lambda v: np.asarray(r(v), dtype=np.float64)
+def loss_and_grads(params, X, y):
+    """Loss and its gradient with respect to (W1, b1, W2, b2, W3, b3), by
+    the chain rule through the softmax cross-entropy and both ReLUs."""
     W1, b1, W2, b2, W3, b3 = [np.asarray(p, dtype=np.float64) for p in params]
-    z, (X, a1, h1, a2, h2) = forward(params, X, rnd)
+    z, (X, a1, h1, a2, h2) = forward(params, X)
     B = z.shape[0]
     loss = loss_fn(z, y)
     zmax = z.max(axis=1, keepdims=True)
@@ -191,13 +181,13 @@ def loss_and_grads(params, X, y, rnd=None):
     dz = e / e.sum(axis=1, keepdims=True)
     dz[np.arange(B), y] -= 1.0
     dz /= B
-    gW3 = f(dz).T @ h2
+    gW3 = dz.T @ h2
     gb3 = dz.sum(axis=0)
-    dh2 = (f(dz) @ W3) * (h2 > 0 if rnd is not None else a2 > 0)
-    gW2 = f(dh2).T @ h1
+    dh2 = (dz @ W3) * (a2 > 0)
+    gW2 = dh2.T @ h1
     gb2 = dh2.sum(axis=0)
-    dh1 = (f(dh2) @ W2) * (h1 > 0 if rnd is not None else a1 > 0)
-    gW1 = f(dh1).T @ X
+    dh1 = (dh2 @ W2) * (a1 > 0)
+    gW1 = dh1.T @ X
     gb1 = dh1.sum(axis=0)
     return loss, (gW1, gb1, gW2, gb2, gW3, gb3)
 

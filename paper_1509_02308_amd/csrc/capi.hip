@@ -5,6 +5,7 @@
 #include <map>
 
 #include "plan.h"
+#include "tile.h"
 
 namespace pc {
 
@@ -386,6 +387,196 @@ extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t
                                pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
 }
 
+// Standard models: the set-partitioned tile replay.  Every pair becomes
+// one or more (pair, part) items: the fewest parts P (a power of two, at
+// most T) for which one part's sets fit a wave's LDS state of at most
+// row_cap dwords per lane.  Items are grouped by (policy, row class: the
+// state rows rounded up to a power of two, at least 16), each group one
+// launch whose LDS fits its class, longest items first; BATCHED runs each
+// group as a persistent grid pulling items from an atomic queue, the
+// groups concurrently on the workspace's replay streams; PLAIN launches one
+// block per item, group after group.
+static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, const int32_t* idx_dev,
+                        const uint64_t* trace_off, const uint64_t* trace_base, uint32_t n_traces,
+                        const uint32_t* pair_model, const uint32_t* pair_trace, const uint64_t* count_from,
+                        uint64_t n_pairs, uint64_t* misses_dev, uint32_t* hitbits_dev, const uint64_t* bitoff,
+                        uint32_t mode, hipStream_t stream) {
+    const uint32_t row_cap = 256;
+    struct Key {
+        uint32_t key;   // policy * 8 + log2(row class) - 4
+        float cost;
+        uint32_t item;
+    };
+    std::vector<TileItem> items;
+    items.reserve(n_pairs);
+    std::vector<Key> keys;
+    keys.reserve(n_pairs);
+    std::vector<uint64_t> zero_cnt, zero_bits;
+    for (uint64_t i = 0; i < n_pairs; ++i) {
+        if (pair_model[i] >= n_models) return set_error(PCHASE_EINVAL, "pair %llu: model index out of range", (unsigned long long)i);
+        if (pair_trace[i] >= n_traces) return set_error(PCHASE_EINVAL, "pair %llu: trace index out of range", (unsigned long long)i);
+        const DevModel& m = dm[pair_model[i]];
+        const uint32_t RS = m.ways + tile_meta_rows((int)m.policy, m.ways);
+        uint32_t lp = 0;
+        auto rows_of = [&](uint32_t l) {
+            const uint64_t sets = ((uint64_t)m.sets + (1ull << l) - 1) >> l;   // part 0 holds the most
+            return (uint64_t)((sets + kWave - 1) / kWave) * RS;
+        };
+        while (rows_of(lp) > row_cap && (2ull << lp) <= m.sets) ++lp;
+        const uint64_t rows = rows_of(lp);
+        if (rows > kTileMaxRows)
+            return set_error(PCHASE_ERANGE, "pair %llu: a set of %u ways does not fit the replay state",
+                             (unsigned long long)i, m.ways);
+        uint32_t rc = 16, cls = 0;
+        while (rc < rows) {
+            rc *= 2;
+            ++cls;
+        }
+        const uint64_t len = trace_off[pair_trace[i] + 1] - trace_off[pair_trace[i]];
+        const uint32_t P = 1u << lp;
+        for (uint32_t p = 0; p < P; ++p) {
+            TileItem t;
+            t.start = trace_off[pair_trace[i]];
+            t.len = len;
+            t.base = trace_base ? trace_base[pair_trace[i]] : 0;
+            t.count_from = count_from ? count_from[i] : 0;
+            t.bitoff = bitoff ? bitoff[i] : 0;
+            t.model = pair_model[i];
+            t.trace_id = pair_trace[i];
+            t.out = (uint32_t)i;
+            t.part = p | (lp << 16);
+            keys.push_back(Key{m.policy * 8u + cls, (float)((double)len * (8.0 + (double)m.ways / P)),
+                               (uint32_t)items.size()});
+            items.push_back(t);
+        }
+        if (P > 1) {
+            zero_cnt.push_back(4 * i);   // the pair's two 64-bit counters, as 32-bit words
+            zero_cnt.push_back(4);
+            if (hitbits_dev) {
+                zero_bits.push_back(bitoff[i]);
+                zero_bits.push_back((len + 31) / 32);
+            }
+        }
+    }
+    if (items.size() >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many pairs");
+    std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+        if (x.key != y.key) return x.key < y.key;
+        if (x.cost != y.cost) return x.cost > y.cost;
+        return x.item < y.item;
+    });
+    std::vector<TileItem> sorted(items.size());
+    for (size_t q = 0; q < keys.size(); ++q) sorted[q] = items[keys[q].item];
+
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    int rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    const size_t o_models = 0;
+    const size_t o_items = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
+    const size_t o_status = o_items + (sorted.size() * sizeof(TileItem) + 255) / 256 * 256;
+    const size_t o_zero = o_status + 512;
+    const size_t total = o_zero + (zero_cnt.size() + zero_bits.size()) * sizeof(uint64_t) + 256;
+    hipError_t e = ws->stage.ensure(total);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    uint8_t* sb = ws->stage.as<uint8_t>();
+    DevModel* d_models = reinterpret_cast<DevModel*>(sb + o_models);
+    TileItem* d_items = reinterpret_cast<TileItem*>(sb + o_items);
+    uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + o_status);
+    PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_items, sorted.data(), sorted.size() * sizeof(TileItem), hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
+    if (!zero_cnt.empty()) {
+        // split pairs merge into their outputs: zero those first
+        uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + o_zero);
+        uint64_t* d_zb = d_zc + zero_cnt.size();
+        PC_HIP(hipMemcpyAsync(d_zc, zero_cnt.data(), zero_cnt.size() * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(launch_clear_ranges(reinterpret_cast<uint32_t*>(misses_dev), d_zc, (uint32_t)(zero_cnt.size() / 2),
+                                   stream));
+        if (!zero_bits.empty()) {
+            PC_HIP(hipMemcpyAsync(d_zb, zero_bits.data(), zero_bits.size() * 8, hipMemcpyHostToDevice, stream));
+            PC_HIP(launch_clear_ranges(hitbits_dev, d_zb, (uint32_t)(zero_bits.size() / 2), stream));
+        }
+    }
+    if (!ws->tile_ready) {
+        PC_HIP(tile_prepare_lds());
+        ws->tile_ready = true;
+    }
+    // one launch per (policy, row class) group
+    struct Launch {
+        int pol;
+        uint32_t rows;
+        uint64_t q, e2, blocks;
+        double cost;
+    };
+    std::vector<Launch> launches;
+    for (uint64_t q = 0; q < keys.size();) {
+        const uint32_t key = keys[q].key;
+        uint64_t e2 = q;
+        double work = 0;
+        while (e2 < keys.size() && keys[e2].key == key) work += keys[e2++].cost;
+        Launch L;
+        L.pol = (int)(key / 8);
+        L.rows = 16u << (key % 8);
+        L.q = q;
+        L.e2 = e2;
+        int occ = ws->occ_tile[L.pol][key % 8];
+        if (occ == 0) {
+            PC_HIP(tile_occupancy(L.pol, L.rows, &occ));
+            if (occ < 1) occ = 1;
+            ws->occ_tile[L.pol][key % 8] = occ;
+        }
+        L.blocks = mode == PCHASE_PLAIN ? e2 - q : std::min<uint64_t>((uint64_t)occ * ws->cus, e2 - q);
+        L.cost = std::max((double)keys[q].cost, work / (double)L.blocks);
+        launches.push_back(L);
+        q = e2;
+    }
+    std::vector<size_t> order(launches.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return launches[x].cost > launches[y].cost; });
+    const int ns = mode == PCHASE_PLAIN ? 0 : (int)std::min<size_t>(kReplayStreams, launches.size());
+    double load[kReplayStreams] = {};
+    if (ns > 1) {
+        PC_HIP(hipEventRecord(ws->rfork, stream));
+        for (int b = 0; b < ns; ++b) PC_HIP(hipStreamWaitEvent(ws->rstream[b], ws->rfork, 0));
+    }
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const Launch& L = launches[order[oi]];
+        hipStream_t st = stream;
+        if (ns > 1) {
+            int b = 0;
+            for (int c = 1; c < ns; ++c)
+                if (load[c] < load[b]) b = c;
+            load[b] += L.cost;
+            st = ws->rstream[b];
+        }
+        TileArgs a;
+        a.items = d_items + L.q;
+        a.n_items = (uint32_t)(L.e2 - L.q);
+        a.persistent = mode == PCHASE_PLAIN ? 0u : 1u;
+        a.queue = d_status + 2 + order[oi];
+        a.models = d_models;
+        a.idx = idx_dev;
+        a.misses = misses_dev;
+        a.bits = hitbits_dev;
+        a.rows = L.rows;
+        a.abort_flag = mode == PCHASE_PLAIN ? nullptr : abort_flag_dev();
+        a.status = d_status;
+        PC_HIP(launch_tile(L.pol, a, (uint32_t)L.blocks, st));
+    }
+    if (ns > 1) {
+        for (int b = 0; b < ns; ++b) {
+            PC_HIP(hipEventRecord(ws->rjoin[b], ws->rstream[b]));
+            PC_HIP(hipStreamWaitEvent(stream, ws->rjoin[b], 0));
+        }
+    }
+    PC_HIP(hipStreamSynchronize(stream));
+    uint32_t status = 0;
+    PC_HIP(hipMemcpy(&status, d_status, sizeof status, hipMemcpyDeviceToHost));
+    if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
+    if (status & 2u) return set_error(PCHASE_EINVAL, "a trace holds a negative element index");
+    return PCHASE_OK;
+}
+
 static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDesc* gd, uint32_t n_models,
                                const int32_t* idx_dev, const uint64_t* trace_off, const uint64_t* trace_base,
                                uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
@@ -404,7 +595,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
     }
     if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
 
-    // bucket pairs by (policy, group width), longest first inside a bucket;
+    // generalised models: bucket pairs by (policy, group width), longest first inside a bucket;
     // a pair that is long, or whose state is large, is split by set into
     // parts that run side by side: each part's serial chain of state updates
     // and its state slab shrink by the number of parts
@@ -753,7 +944,8 @@ static std::string digest_of(const std::string& blob) {
 
 // Runs a built plan and reads its result back (synchronises).
 static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pchase_result* out, uint64_t* mn_dev,
-                          uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched);
+                          uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched,
+                          bool tune = true);
 
 // cache = false builds a one-off plan (the learned path's top-k subsets)
 static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const pchase_model* cands,
@@ -762,7 +954,7 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
                             const std::vector<uint64_t>& bitoff, const uint32_t* bits, int probe_select,
                             const std::vector<uint8_t>* allow, pchase_result* out, uint64_t* mn_dev,
                             uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched,
-                            bool cache = true) {
+                            bool cache = true, bool tune = true) {
     InferPlan* ip;
     std::unique_ptr<InferPlan> once;
     if (!cache) {
@@ -786,11 +978,11 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
             ip = it->second.get();
         }
     }
-    return run_infer_plan(ws, ip, bits, out, mn_dev, zero_host, stream, replayed, sched);
+    return run_infer_plan(ws, ip, bits, out, mn_dev, zero_host, stream, replayed, sched, tune);
 }
 
 static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pchase_result* out, uint64_t* mn_dev,
-                          uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched) {
+                          uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched, bool tune) {
     const uint32_t n_cands = ip->n_cands;
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
@@ -800,7 +992,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,
-                            sched, stream, tail, "argmin", ip->cached);
+                            sched, stream, tail, "argmin", ip->cached && tune);
     if (rc) return rc;
     ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
     PC_HIP(hipMemcpyAsync(hr, ip->d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));
@@ -832,7 +1024,8 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     if (probe_select != PCHASE_PROBES_ALL && probe_select != PCHASE_PROBES_OWN_SWEEP)
         return set_error(PCHASE_EINVAL, "unknown probe_select %d", probe_select);
     const uint32_t sched = (mode & PCHASE_SCHED_PLAIN) ? PCHASE_PLAIN : PCHASE_BATCHED;
-    mode &= ~PCHASE_SCHED_PLAIN;
+    const bool tune = !(mode & PCHASE_SCHED_UNTUNED);
+    mode &= ~(PCHASE_SCHED_PLAIN | PCHASE_SCHED_UNTUNED);
     if (mode != PCHASE_EXHAUSTIVE && mode != PCHASE_LEARNED) return set_error(PCHASE_EINVAL, "unknown mode %d", mode);
     if (mode == PCHASE_LEARNED && (!net || topk == 0)) return set_error(PCHASE_EINVAL, "LEARNED needs a network and topk >= 1");
     if (n_cands == 0) return set_error(PCHASE_EINVAL, "no candidates");
@@ -850,7 +1043,8 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
             out->threshold_used = 0xFFFFFFFFu;
             out->fallback = 0;
             uint64_t replayed = 0;
-            rc = run_infer_plan(ws, it->second.get(), obs->bits_dev, out, mn_dev, zero_host, stream, &replayed, sched);
+            rc = run_infer_plan(ws, it->second.get(), obs->bits_dev, out, mn_dev, zero_host, stream, &replayed, sched,
+                                tune);
             out->replayed_accesses = replayed;
             return rc;
         }
@@ -949,7 +1143,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         }
     }
     rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, nullptr, out, mn_dev,
-                          zero_host, stream, &replayed, sched);
+                          zero_host, stream, &replayed, sched, true, tune);
     if (rc) return rc;
     out->replayed_accesses += replayed;
     if (mode == PCHASE_EXHAUSTIVE) out->replayed_accesses = replayed;

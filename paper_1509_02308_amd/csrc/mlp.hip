@@ -176,38 +176,47 @@ __global__ void __launch_bounds__(256) pair_differ_kernel(const uint32_t* bits, 
 }
 
 // ------------------------------------------------------------- GEMM ---
-// C(m, n) = alpha * sum_k A(m, k) B(k, n) over bf16 operands with fp32
-// accumulation on v_mfma_f32_32x32x8_bf16: a 256-thread block computes a
-// 64 x 64 tile as 2 x 2 waves of 32 x 32, K staged through LDS 32 at a time.
-// Operands are addressed through element strides, so transposed products
-// need no copies.  Epilogue: + bias[n], ReLU, keep only where mask(m, n) > 0
-// (ReLU backward), fp32 and/or bf16 row-major stores.
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+// C(m, n) = alpha * sum_k A(m, k) B(k, n) with fp32 accumulation on gfx950's
+// v_mfma_f32_32x32x16_bf16: a 256-thread block computes a 64 x 64 tile as
+// 2 x 2 waves of 32 x 32, K staged through LDS 32 at a time.
+// An operand is either bf16 (the weights and the input features, whose
+// values are exactly bf16) or fp32 (hidden activations and back-propagated
+// errors).  An fp32 operand is split while it is staged into v = hi + lo,
+// hi = bf16(v), lo = bf16(v - hi), which holds v to about 2^-17 relative;
+// the product then takes hi*hi + lo*hi + hi*lo (lo*lo is below fp32
+// rounding of the sum).  Operands are addressed through element strides, so
+// transposed products need no copies.  Epilogue: + bias[n], ReLU, keep only
+// where mask(m, n) > 0 (ReLU backward on the fp32 activation), fp32 store.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 struct GemmArgs {
-    const uint16_t* A;
+    const uint16_t* A;    // bf16 operand, or NULL when Af is given
+    const float* Af;      // fp32 operand, split into hi + lo
     const uint16_t* B;
+    const float* Bf;
     int64_t a_m, a_k, b_k, b_n;
     uint32_t M, N, K;
     float alpha;
     const float* bias;
-    const uint16_t* mask;
+    const float* mask;
     int64_t ld;
     float* out_f;
-    uint16_t* out_b;
     int relu;
 };
 
 constexpr int kTM = 64, kTN = 64, kTK = 32, kPitch = 40;
 
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-    __shared__ __align__(16) uint16_t As[kTM * kPitch];
-    __shared__ __align__(16) uint16_t Bs[kTN * kPitch];   // [n][k]
+    __shared__ __align__(16) uint16_t As[2][kTM * kPitch];   // [hi|lo][m][k]
+    __shared__ __align__(16) uint16_t Bs[2][kTN * kPitch];   // [hi|lo][n][k]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const uint32_t m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const bool a_kfast = g.a_k == 1, b_kfast = g.b_k == 1;
+    const bool a_split = g.Af != nullptr, b_split = g.Bf != nullptr;
     f32x16 acc = {};
     for (uint32_t k0 = 0; k0 < g.K; k0 += kTK) {
 #pragma unroll
@@ -216,20 +225,49 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
             int mm, kk;
             if (a_kfast) { kk = e & 31; mm = e >> 5; } else { mm = e & 63; kk = e >> 6; }
             uint32_t gm = m0 + mm, gk = k0 + kk;
-            As[mm * kPitch + kk] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.a_m + (int64_t)gk * g.a_k] : 0;
+            const bool a_in = gm < g.M && gk < g.K;
+            const int64_t ai = (int64_t)gm * g.a_m + (int64_t)gk * g.a_k;
+            if (a_split) {
+                const float v = a_in ? g.Af[ai] : 0.f;
+                const uint16_t hi = f2bf(v);
+                As[0][mm * kPitch + kk] = hi;
+                As[1][mm * kPitch + kk] = f2bf(v - bf2f(hi));
+            } else {
+                As[0][mm * kPitch + kk] = a_in ? g.A[ai] : 0;
+            }
             int nn;
             if (b_kfast) { kk = e & 31; nn = e >> 5; } else { nn = e & 63; kk = e >> 6; }
             const uint32_t gn = n0 + nn;
             gk = k0 + kk;
-            Bs[nn * kPitch + kk] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.b_k + (int64_t)gn * g.b_n] : 0;
+            const bool b_in = gn < g.N && gk < g.K;
+            const int64_t bi = (int64_t)gk * g.b_k + (int64_t)gn * g.b_n;
+            if (b_split) {
+                const float v = b_in ? g.Bf[bi] : 0.f;
+                const uint16_t hi = f2bf(v);
+                Bs[0][nn * kPitch + kk] = hi;
+                Bs[1][nn * kPitch + kk] = f2bf(v - bf2f(hi));
+            } else {
+                Bs[0][nn * kPitch + kk] = b_in ? g.B[bi] : 0;
+            }
         }
         __syncthreads();
+        // lane l feeds row (l mod 32) with 8 consecutive k at 8 (l div 32);
+        // A and B use the same k positions, so the sum is over all 16
 #pragma unroll
-        for (int ks = 0; ks < kTK; ks += 8) {
-            const int row = lane & 31, kq = ks + (lane >> 5) * 4;
-            const bf16x4 av = *reinterpret_cast<const bf16x4*>(&As[(wm * 32 + row) * kPitch + kq]);
-            const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Bs[(wn * 32 + row) * kPitch + kq]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+        for (int ks = 0; ks < kTK; ks += 16) {
+            const int row = lane & 31, kq = ks + (lane >> 5) * 8;
+            const int ao = (wm * 32 + row) * kPitch + kq, bo = (wn * 32 + row) * kPitch + kq;
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&As[0][ao]);
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Bs[0][bo]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+            if (a_split) {
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(&As[1][ao]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+            }
+            if (b_split) {
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Bs[1][bo]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -243,12 +281,8 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         if (g.bias) v += g.bias[col];
         if (g.relu) v = v > 0.f ? v : 0.f;
         const int64_t at = (int64_t)row * g.ld + col;
-        if (g.mask) {
-            const uint16_t h = g.mask[at];
-            if ((h & 0x8000u) || !(h & 0x7FFFu)) v = 0.f;
-        }
-        if (g.out_f) g.out_f[at] = v;
-        if (g.out_b) g.out_b[at] = f2bf(v);
+        if (g.mask && !(g.mask[at] > 0.f)) v = 0.f;
+        g.out_f[at] = v;
     }
 }
 
@@ -260,16 +294,39 @@ static hipError_t gemm(const GemmArgs& g, hipStream_t s) {
 }
 
 // ------------------------------------------------ small MLP kernels ---
-__global__ void cvt_bf16_kernel(const float* x, uint16_t* y, uint64_t n) {
+// Training state on the device, so that one captured step serves every
+// batch of a pass: the step reads batch `batch` of the sample arrays, and
+// the loss kernel advances the batch and the Adam step count t (with the
+// bias corrections c1 = 1 / (1 - 0.9^t), c2 = 1 / (1 - 0.999^t)).
+struct TrainState {
+    uint64_t step;
+    uint32_t batch, n_batches;
+    float c1, c2;
+    uint32_t pad[2];
+};
+
+__global__ void set_state_kernel(TrainState* st, uint64_t step, uint32_t n_batches) {
+    st->step = step;
+    st->batch = 0;
+    st->n_batches = n_batches;
+    st->c1 = st->c2 = 0.f;
+}
+
+// y = bf16(x) for the n elements of batch st->batch (stride n), or of x
+// itself when st is NULL
+__global__ void cvt_bf16_kernel(const float* x, uint16_t* y, uint64_t n, const TrainState* st) {
+    if (st) x += (uint64_t)st->batch * n;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         y[i] = f2bf(x[i]);
 }
 
-// softmax cross-entropy, one wave per row; dz = (softmax - onehot) / B
+// softmax cross-entropy, one wave per row; dz = (softmax - onehot) / B;
+// labels of batch st->batch
 __global__ void __launch_bounds__(256) xent_kernel(const float* z, const int32_t* y, uint32_t rows, uint32_t C,
-                                                   float inv_b, float* dz_f, uint16_t* dz_b, float* loss_row) {
+                                                   float inv_b, float* dz_f, float* loss_row, const TrainState* st) {
     const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (r >= rows) return;
+    y += (uint64_t)st->batch * rows;
     const float* zr = z + (uint64_t)r * C;
     float mx = -INFINITY;
     for (uint32_t c = lane; c < C; c += 64) mx = fmaxf(mx, zr[c]);
@@ -284,7 +341,6 @@ __global__ void __launch_bounds__(256) xent_kernel(const float* z, const int32_t
         float d = expf(zr[c] - mx) * inv - ((int32_t)c == lab ? 1.f : 0.f);
         d *= inv_b;
         dz_f[(uint64_t)r * C + c] = d;
-        dz_b[(uint64_t)r * C + c] = f2bf(d);
     }
     if (lane == 0) loss_row[r] = ok ? logf(sum) + mx - zr[lab] : NAN;
 }
@@ -301,7 +357,9 @@ __global__ void __launch_bounds__(256) colsum_kernel(const float* G, uint32_t ro
     if (ph == 0 && c < cols) out[c] = (part[threadIdx.x] + part[threadIdx.x + 64]) + (part[threadIdx.x + 128] + part[threadIdx.x + 192]);
 }
 
-__global__ void __launch_bounds__(256) mean_kernel(const float* v, uint32_t n, float* out) {
+// mean loss of the batch; then (every read of the batch's samples is done)
+// the next batch and the next Adam step
+__global__ void __launch_bounds__(256) mean_kernel(const float* v, uint32_t n, float* out, TrainState* st) {
     __shared__ float part[256];
     float s = 0.f;
     for (uint32_t i = threadIdx.x; i < n; i += 256) s += v[i];
@@ -311,7 +369,15 @@ __global__ void __launch_bounds__(256) mean_kernel(const float* v, uint32_t n, f
         if (threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = part[0] / (float)n;
+    if (threadIdx.x == 0) {
+        out[0] = part[0] / (float)n;
+        const uint32_t nb = st->batch + 1;
+        st->batch = nb >= st->n_batches ? 0u : nb;
+        const uint64_t t = st->step + 1;
+        st->step = t;
+        st->c1 = (float)(1.0 / (1.0 - pow(0.9, (double)t)));
+        st->c2 = (float)(1.0 / (1.0 - pow(0.999, (double)t)));
+    }
 }
 
 struct AdamSeg {
@@ -324,18 +390,20 @@ struct AdamSeg {
 };
 struct AdamArgs {
     AdamSeg seg[6];
-    float lr, b1, b2, eps, c1, c2;   // c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+    float lr, b1, b2, eps;
+    const TrainState* st;   // bias corrections of the step
 };
 
 __global__ void __launch_bounds__(256) adam_kernel(AdamArgs a) {
     const AdamSeg s = a.seg[blockIdx.y];
+    const float c1 = a.st->c1, c2 = a.st->c2;
     for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < s.n; i += (uint64_t)gridDim.x * 256) {
         const float g = s.g[i];
         const float m = a.b1 * s.m[i] + (1.f - a.b1) * g;
         const float v = a.b2 * s.v[i] + (1.f - a.b2) * g * g;
         s.m[i] = m;
         s.v[i] = v;
-        const float p = s.p[i] - a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+        const float p = s.p[i] - a.lr * (m * c1) / (sqrtf(v * c2) + a.eps);
         s.p[i] = p;
         if (s.wb) s.wb[i] = f2bf(p);
     }
@@ -510,12 +578,18 @@ struct pchase_mlp {
     float* v[6] = {};
     float* g[6] = {};
     uint16_t* wb[3] = {};
+    pc::TrainState* st = nullptr;
     DevBuf act;
     uint32_t act_batch = 0;
-    uint16_t *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *dz_b = nullptr, *dh2_b = nullptr, *dh1_b = nullptr;
-    float *z = nullptr, *dz_f = nullptr, *dh2_f = nullptr, *dh1_f = nullptr, *loss_row = nullptr, *loss = nullptr;
+    uint16_t* xb = nullptr;
+    float *h1 = nullptr, *h2 = nullptr, *z = nullptr, *dz_f = nullptr, *dh2_f = nullptr, *dh1_f = nullptr;
+    float *loss_row = nullptr, *loss = nullptr;
     int32_t* idx = nullptr;
+    // captured training step (replayed once per batch by pchase_mlp_train)
+    hipGraphExec_t gexec = nullptr;
+    std::string gkey;
     ~pchase_mlp() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         params.release();
         act.release();
     }
@@ -532,24 +606,20 @@ static int ensure_act(pchase_mlp* net, uint32_t batch) {
         off += (bytes + 255) / 256 * 256;
         return o;
     };
-    const size_t o_xb = take(B * kIn * 2), o_h1 = take(B * kHid * 2), o_h2 = take(B * kHid * 2);
-    const size_t o_z = take(B * C * 4), o_dzf = take(B * C * 4), o_dzb = take(B * C * 2);
-    const size_t o_dh2f = take(B * kHid * 4), o_dh2b = take(B * kHid * 2);
-    const size_t o_dh1f = take(B * kHid * 4), o_dh1b = take(B * kHid * 2);
+    const size_t o_xb = take(B * kIn * 2), o_h1 = take(B * kHid * 4), o_h2 = take(B * kHid * 4);
+    const size_t o_z = take(B * C * 4), o_dzf = take(B * C * 4);
+    const size_t o_dh2f = take(B * kHid * 4), o_dh1f = take(B * kHid * 4);
     const size_t o_lr = take(B * 4), o_l = take(256), o_idx = take(B * kMaxTopK * 4);
     hipError_t e = net->act.ensure(off);
     if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "activations for batch %u: %s", batch, hipGetErrorString(e));
     uint8_t* b = net->act.as<uint8_t>();
     net->xb = reinterpret_cast<uint16_t*>(b + o_xb);
-    net->h1 = reinterpret_cast<uint16_t*>(b + o_h1);
-    net->h2 = reinterpret_cast<uint16_t*>(b + o_h2);
+    net->h1 = reinterpret_cast<float*>(b + o_h1);
+    net->h2 = reinterpret_cast<float*>(b + o_h2);
     net->z = reinterpret_cast<float*>(b + o_z);
     net->dz_f = reinterpret_cast<float*>(b + o_dzf);
-    net->dz_b = reinterpret_cast<uint16_t*>(b + o_dzb);
     net->dh2_f = reinterpret_cast<float*>(b + o_dh2f);
-    net->dh2_b = reinterpret_cast<uint16_t*>(b + o_dh2b);
     net->dh1_f = reinterpret_cast<float*>(b + o_dh1f);
-    net->dh1_b = reinterpret_cast<uint16_t*>(b + o_dh1b);
     net->loss_row = reinterpret_cast<float*>(b + o_lr);
     net->loss = reinterpret_cast<float*>(b + o_l);
     net->idx = reinterpret_cast<int32_t*>(b + o_idx);
@@ -557,11 +627,16 @@ static int ensure_act(pchase_mlp* net, uint32_t batch) {
     return PCHASE_OK;
 }
 
-static GemmArgs gargs(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_t* B, int64_t b_k, int64_t b_n,
-                      uint32_t M, uint32_t N, uint32_t K, int64_t ld) {
+// A(m, k) at element a_m * m + a_k * k, B(k, n) at b_k * k + b_n * n; the
+// operand given as fp32 (Af / Bf) is split, the bf16 one is taken as is
+static GemmArgs gargs(const uint16_t* A, const float* Af, int64_t a_m, int64_t a_k, const uint16_t* B,
+                      const float* Bf, int64_t b_k, int64_t b_n, uint32_t M, uint32_t N, uint32_t K, int64_t ld,
+                      float* out) {
     GemmArgs g{};
     g.A = A;
+    g.Af = Af;
     g.B = B;
+    g.Bf = Bf;
     g.a_m = a_m;
     g.a_k = a_k;
     g.b_k = b_k;
@@ -571,73 +646,66 @@ static GemmArgs gargs(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
     g.K = K;
     g.alpha = 1.f;
     g.ld = ld;
+    g.out_f = out;
     return g;
 }
 
-// forward of xb (already bf16 in net->xb) into net->z
-static hipError_t forward_bf16(const pchase_mlp* net, uint32_t B, hipStream_t s) {
+// forward of xb (already bf16 in net->xb) into net->z; the hidden
+// activations stay fp32 and enter the next product split
+static hipError_t forward_net(const pchase_mlp* net, uint32_t B, hipStream_t s) {
     const uint32_t C = net->n_out;
-    GemmArgs g = gargs(net->xb, kIn, 1, net->wb[0], 1, kIn, B, kHid, kIn, kHid);
+    GemmArgs g = gargs(net->xb, nullptr, kIn, 1, net->wb[0], nullptr, 1, kIn, B, kHid, kIn, kHid, net->h1);
     g.bias = net->p[1];
     g.relu = 1;
-    g.out_b = net->h1;
     hipError_t e = gemm(g, s);
     if (e != hipSuccess) return e;
-    g = gargs(net->h1, kHid, 1, net->wb[1], 1, kHid, B, kHid, kHid, kHid);
+    g = gargs(nullptr, net->h1, kHid, 1, net->wb[1], nullptr, 1, kHid, B, kHid, kHid, kHid, net->h2);
     g.bias = net->p[3];
     g.relu = 1;
-    g.out_b = net->h2;
     if ((e = gemm(g, s)) != hipSuccess) return e;
-    g = gargs(net->h2, kHid, 1, net->wb[2], 1, kHid, B, C, kHid, C);
+    g = gargs(nullptr, net->h2, kHid, 1, net->wb[2], nullptr, 1, kHid, B, C, kHid, C, net->z);
     g.bias = net->p[5];
-    g.out_f = net->z;
     return gemm(g, s);
 }
 
-static hipError_t to_bf16(const float* x, uint16_t* y, uint64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(cvt_bf16_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, y, n);
+static hipError_t to_bf16(const float* x, uint16_t* y, uint64_t n, const TrainState* st, hipStream_t s) {
+    hipLaunchKernelGGL(cvt_bf16_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, y, n, st);
     return hipGetLastError();
 }
 
-static int train_step_impl(pchase_mlp* net, const float* x, const int32_t* y, uint32_t B, float lr, hipStream_t s) {
+// One training step on batch net->st->batch of (x, y), B rows per batch;
+// launches only (capturable): nothing on the host depends on the step.
+static int enqueue_step(pchase_mlp* net, const float* x, const int32_t* y, uint32_t B, float lr, hipStream_t s) {
     const uint32_t C = net->n_out;
-    PC_HIP(to_bf16(x, net->xb, (uint64_t)B * kIn, s));
-    PC_HIP(forward_bf16(net, B, s));
+    PC_HIP(to_bf16(x, net->xb, (uint64_t)B * kIn, net->st, s));
+    PC_HIP(forward_net(net, B, s));
     hipLaunchKernelGGL(xent_kernel, dim3((B + 3) / 4), dim3(256), 0, s, net->z, y, B, C, 1.f / (float)B, net->dz_f,
-                       net->dz_b, net->loss_row);
+                       net->loss_row, net->st);
     PC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, net->loss_row, B, net->loss);
+    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, net->loss_row, B, net->loss, net->st);
     PC_HIP(hipGetLastError());
-    // layer 3
-    GemmArgs g = gargs(net->dz_b, 1, C, net->h2, kHid, 1, C, kHid, B, kHid);
-    g.out_f = net->g[4];
+    // layer 3: dW3 = dz^T h2, db3 = colsum dz, dh2 = (dz W3) * [h2 > 0]
+    GemmArgs g = gargs(nullptr, net->dz_f, 1, C, nullptr, net->h2, kHid, 1, C, kHid, B, kHid, net->g[4]);
     PC_HIP(gemm(g, s));
     hipLaunchKernelGGL(colsum_kernel, dim3((C + 63) / 64), dim3(256), 0, s, net->dz_f, B, C, net->g[5]);
     PC_HIP(hipGetLastError());
-    g = gargs(net->dz_b, C, 1, net->wb[2], kHid, 1, B, kHid, C, kHid);
+    g = gargs(nullptr, net->dz_f, C, 1, net->wb[2], nullptr, kHid, 1, B, kHid, C, kHid, net->dh2_f);
     g.mask = net->h2;
-    g.out_f = net->dh2_f;
-    g.out_b = net->dh2_b;
     PC_HIP(gemm(g, s));
     // layer 2
-    g = gargs(net->dh2_b, 1, kHid, net->h1, kHid, 1, kHid, kHid, B, kHid);
-    g.out_f = net->g[2];
+    g = gargs(nullptr, net->dh2_f, 1, kHid, nullptr, net->h1, kHid, 1, kHid, kHid, B, kHid, net->g[2]);
     PC_HIP(gemm(g, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(kHid / 64), dim3(256), 0, s, net->dh2_f, B, kHid, net->g[3]);
     PC_HIP(hipGetLastError());
-    g = gargs(net->dh2_b, kHid, 1, net->wb[1], kHid, 1, B, kHid, kHid, kHid);
+    g = gargs(nullptr, net->dh2_f, kHid, 1, net->wb[1], nullptr, kHid, 1, B, kHid, kHid, kHid, net->dh1_f);
     g.mask = net->h1;
-    g.out_f = net->dh1_f;
-    g.out_b = net->dh1_b;
     PC_HIP(gemm(g, s));
-    // layer 1
-    g = gargs(net->dh1_b, 1, kHid, net->xb, kIn, 1, kHid, kIn, B, kIn);
-    g.out_f = net->g[0];
+    // layer 1 (the input is exactly bf16)
+    g = gargs(nullptr, net->dh1_f, 1, kHid, net->xb, nullptr, kIn, 1, kHid, kIn, B, kIn, net->g[0]);
     PC_HIP(gemm(g, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(kHid / 64), dim3(256), 0, s, net->dh1_f, B, kHid, net->g[1]);
     PC_HIP(hipGetLastError());
     // Adam
-    net->steps += 1;
     AdamArgs a{};
     for (int i = 0; i < 6; ++i) {
         a.seg[i].p = net->p[i];
@@ -651,11 +719,17 @@ static int train_step_impl(pchase_mlp* net, const float* x, const int32_t* y, ui
     a.b1 = 0.9f;
     a.b2 = 0.999f;
     a.eps = 1e-8f;
-    a.c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)net->steps)));
-    a.c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)net->steps)));
+    a.st = net->st;
     hipLaunchKernelGGL(adam_kernel, dim3(64, 6), dim3(256), 0, s, a);
     PC_HIP(hipGetLastError());
     return PCHASE_OK;
+}
+
+// Training state for a run of steps over n_batches batches, from the
+// host's step count.
+static hipError_t begin_steps(pchase_mlp* net, uint32_t n_batches, hipStream_t s) {
+    hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, net->st, net->steps, n_batches);
+    return hipGetLastError();
 }
 
 static int check_net(const pchase_mlp* net) {
@@ -716,8 +790,8 @@ int infer_learned(Workspace* ws, const pchase_observation* obs, const pchase_mod
     fa.n_probes = kIn;
     fa.x = d_x;
     PC_HIP(launch_features(fa, stream));
-    PC_HIP(to_bf16(d_x, net->xb, kIn, stream));
-    PC_HIP(forward_bf16(net, 1, stream));
+    PC_HIP(to_bf16(d_x, net->xb, kIn, nullptr, stream));
+    PC_HIP(forward_net(net, 1, stream));
     hipLaunchKernelGGL(topk_kernel, dim3(1), dim3(64), 0, stream, net->z, n_cands, topk, net->idx);
     PC_HIP(hipGetLastError());
     int32_t* hr = static_cast<int32_t*>(ws->host_res);
@@ -764,6 +838,8 @@ extern "C" int pchase_mlp_create(uint32_t n_out, uint64_t seed, pchase_mlp** out
         ow[i] = off;
         off += (cnt[2 * i] * 2 + 255) / 256 * 256;
     }
+    const size_t o_st = off;
+    off += 256;
     hipError_t e = net->params.ensure(off);
     if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "parameters: %s", hipGetErrorString(e));
     uint8_t* b = net->params.as<uint8_t>();
@@ -774,6 +850,7 @@ extern "C" int pchase_mlp_create(uint32_t n_out, uint64_t seed, pchase_mlp** out
         net->g[i] = reinterpret_cast<float*>(b + o[i][3]);
     }
     for (int i = 0; i < 3; ++i) net->wb[i] = reinterpret_cast<uint16_t*>(b + ow[i]);
+    net->st = reinterpret_cast<TrainState*>(b + o_st);
     PC_HIP(hipMemset(b, 0, off));
     const uint32_t fan_in[3] = {kIn, kHid, kHid};
     for (int i = 0; i < 6; ++i) {
@@ -1010,8 +1087,10 @@ extern "C" int pchase_mlp_train_step(pchase_mlp* net, const float* x_dev, const 
     if (batch > 65536) return set_error(PCHASE_ERANGE, "batch above 65536");
     rc = ensure_act(net, batch);
     if (rc) return rc;
-    rc = train_step_impl(net, x_dev, labels_dev, batch, lr, stream);
+    PC_HIP(begin_steps(net, 1, stream));
+    rc = enqueue_step(net, x_dev, labels_dev, batch, lr, stream);
     if (rc) return rc;
+    net->steps += 1;
     if (loss) {
         PC_HIP(hipMemcpyAsync(loss, net->loss, 4, hipMemcpyDeviceToHost, stream));
         PC_HIP(hipStreamSynchronize(stream));
@@ -1019,20 +1098,54 @@ extern "C" int pchase_mlp_train_step(pchase_mlp* net, const float* x_dev, const 
     return PCHASE_OK;
 }
 
+// The step is captured once per (samples, labels, batch, lr, buffers) and
+// its graph replayed once per batch: the batch index and the Adam step
+// count live on the device and advance inside the step.
 extern "C" int pchase_mlp_train(pchase_mlp* net, const float* x_dev, const int32_t* labels_dev, uint64_t n_samples,
                                 uint32_t batch, uint32_t epochs, float lr, float* last_loss, hipStream_t stream) {
     int rc = check_net(net);
     if (rc) return rc;
     if (batch == 0 || batch > 65536) return set_error(PCHASE_EINVAL, "batch must be in 1..65536");
     if (n_samples < batch) return set_error(PCHASE_EINVAL, "fewer samples than one batch");
+    if (!x_dev || !labels_dev) return set_error(PCHASE_EINVAL, "x_dev and labels_dev must not be NULL");
+    const uint64_t steps = n_samples / batch;
+    if (steps >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many batches");
     rc = ensure_act(net, batch);
     if (rc) return rc;
-    const uint64_t steps = n_samples / batch;
-    for (uint32_t ep = 0; ep < epochs; ++ep)
-        for (uint64_t s = 0; s < steps; ++s) {
-            rc = train_step_impl(net, x_dev + s * batch * kIn, labels_dev + s * batch, batch, lr, stream);
-            if (rc) return rc;
+    char kb[192];
+    snprintf(kb, sizeof kb, "%p|%p|%u|%a|%p|%p", (const void*)x_dev, (const void*)labels_dev, batch, (double)lr,
+             net->act.p, net->params.p);
+    if (!net->gexec || net->gkey != kb) {
+        if (net->gexec) {
+            (void)hipGraphExecDestroy(net->gexec);
+            net->gexec = nullptr;
         }
+        hipStream_t cs;
+        PC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc2 = PCHASE_OK;
+        if (e == hipSuccess) rc2 = enqueue_step(net, x_dev, labels_dev, batch, lr, cs);
+        hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cs, &g) : hipSuccess;
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        if (rc2) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc2;
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&net->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            net->gexec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        net->gkey = kb;
+    }
+    PC_HIP(begin_steps(net, (uint32_t)steps, stream));
+    for (uint32_t ep = 0; ep < epochs; ++ep)
+        for (uint64_t s = 0; s < steps; ++s) PC_HIP(hipGraphLaunch(net->gexec, stream));
+    net->steps += steps * epochs;
     if (last_loss) {
         PC_HIP(hipMemcpyAsync(last_loss, net->loss, 4, hipMemcpyDeviceToHost, stream));
     }
@@ -1050,8 +1163,8 @@ extern "C" int pchase_mlp_forward(const pchase_mlp* cnet, const float* x_dev, ui
     if (batch > 65536) return set_error(PCHASE_ERANGE, "batch above 65536");
     rc = ensure_act(net, batch);
     if (rc) return rc;
-    PC_HIP(to_bf16(x_dev, net->xb, (uint64_t)batch * kIn, stream));
-    PC_HIP(forward_bf16(net, batch, stream));
+    PC_HIP(to_bf16(x_dev, net->xb, (uint64_t)batch * kIn, nullptr, stream));
+    PC_HIP(forward_net(net, batch, stream));
     PC_HIP(hipMemcpyAsync(logits_dev, net->z, (size_t)batch * net->n_out * 4, hipMemcpyDeviceToDevice, stream));
     return PCHASE_OK;
 }

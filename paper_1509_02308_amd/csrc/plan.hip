@@ -399,7 +399,11 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             }
             return PCHASE_OK;
         };
-        if (!autotune || plan->batched.size() < 2) {
+        // timings of replays that pchase_abort cut short say nothing: with
+        // the flag set the default strategy runs untuned, and the key is
+        // marked so that the next call captures and tunes again
+        const bool aborting = abort_flag_host() != 0;
+        if (!autotune || plan->batched.size() < 2 || aborting) {
             int rc = capture(0, &plan->gexec);
             if (rc) return rc;
             plan->strategy = 0;
@@ -445,7 +449,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             (void)hipEventDestroy(t0);
             (void)hipEventDestroy(t1);
         }
-        plan->gkey = key;
+        plan->gkey = (autotune && aborting) ? key + "|untuned" : key;
     }
     PC_HIP(hipGraphLaunch(plan->gexec, stream));
     return PCHASE_OK;

@@ -321,7 +321,8 @@ __global__ void __launch_bounds__(256) stream_kernel(StreamArgs args) {
         uint32_t t = 0;
         if (gl == 0) {
             t = atomicAdd(args.queue, 1u);
-            if ((iter & 15) == 15 && args.abort_flag != nullptr && *args.abort_flag != 0) {
+            // the host flag is polled on the first pull and every 8th after it
+            if ((iter & 7) == 0 && args.abort_flag != nullptr && *args.abort_flag != 0) {
                 atomicOr(args.status, 1u);
                 t = args.n_pairs;
             }

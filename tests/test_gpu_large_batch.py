@@ -2,8 +2,8 @@
 uneven length (1e3..1e5 accesses, log-uniform), caches from 8 KB to 4 MB
 with up to 128 ways and all four policies (RANDOM keyed per model, counter
 = (access index, trace id)).  Every pair's miss totals and a 1% sample of
-the per-access bitmaps must equal the CPU oracle's, in both schedules (pairs above 8192 accesses are split
-by set into parts that merge their outputs)."""
+the per-access bitmaps must equal the CPU oracle's, in both schedules, at a
+small batch and at the benchmark's full size."""
 import numpy as np
 import pytest
 
@@ -49,10 +49,14 @@ def test_large_batch_shape_matches_oracle(mode):
             assert np.array_equal(unpack_bits(b[int(bitoff[i]):], int(lens[i])), hits), (i, tuple(r))
 
 
-def test_large_batch_full_size_sampled():
+@pytest.mark.timeout(900)
+def test_large_batch_full_size():
     """The benchmark's large batch at full size (1e6 pairs, 2.15e10 accesses,
-    one call in the batched schedule): a seeded 1% of the pairs is checked
-    against the oracle, bitmaps and both counts."""
+    one call in the batched schedule): every pair's (misses_total,
+    misses_steady) against the oracle (replayed in host processes), and a
+    seeded 1% of the pairs' bitmaps."""
+    from oracle import pool
+
     torch, capi = need_gpu()
     n = 1_000_000
     mrows, prows = W.large_batch(n)
@@ -73,14 +77,24 @@ def test_large_batch_full_size_sampled():
     torch.cuda.synchronize()
     del idx
     mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
-    sample = np.random.default_rng(4711).choice(n, n // 100, replace=False)
     bw = bits.cpu().numpy().view(np.uint32)
-    say("large batch full size: replayed; checking the sample")
+    del bits
+    sample = sorted(int(i) for i in np.random.default_rng(4711).choice(n, n // 100, replace=False))
+    say(f"large batch full size: replayed; oracle on all pairs ({pool.default_procs()} processes)")
+    om = [(int(r["C"]), int(r["b"]), int(r["a"]), int(r["policy"]), int(r["set_shift"]), int(r["seed"]))
+          for r in mrows]
+    op = [(int(p["N"]), int(p["s"]), int(p["passes"]), int(p["j0"]), int(p["base"])) for p in prows]
+    last = [0]
+
+    def progress(done, total):
+        if done - last[0] >= total // 10 or done == total:
+            last[0] = done
+            say(f"large batch full size: oracle {done}/{total} pairs")
+
+    want, hits = pool.replay_probe_pairs(om, op, cyc, bits_of=sample, progress=progress)
+    bad = np.nonzero((mis != want).any(axis=1))[0]
+    assert len(bad) == 0, (len(bad), [(int(i), om[int(i)], tuple(mis[i]), tuple(want[i])) for i in bad[:5]])
+    say(f"large batch full size: all {n} totals equal; checking {len(sample)} bitmaps")
     for i in sample:
-        i = int(i)
-        r, p = mrows[i], prows[i]
-        om = orc_model((int(r["C"]), int(r["b"]), int(r["a"]), int(r["policy"]), int(r["set_shift"]), int(r["seed"])))
-        tr = orc.trace(orc.make_probe(int(p["N"]), int(p["s"]), int(p["passes"]), int(p["j0"]), int(p["base"])))
-        hits, mt, ms = orc.replay(om, tr, base=int(p["base"]), trace_id=i, count_from=int(cyc[i]))
-        assert (mis[i, 0], mis[i, 1]) == (mt, ms), (i, tuple(r))
-        assert np.array_equal(unpack_bits(bw[int(bitoff[i]):int(bitoff[i]) + int(words[i])], int(lens[i])), hits), i
+        got = unpack_bits(bw[int(bitoff[i]):int(bitoff[i]) + int(words[i])], int(lens[i]))
+        assert np.array_equal(got, hits[i]), (i, om[i])

@@ -1,6 +1,8 @@
 """GPU parity of the learned proposer against oracle/mlp_ref.py: features,
 canonical labels and noised samples bit-exact; forward logits, gradients
-and the Adam update of the bf16-MFMA network within the stated tolerances;
+and the Adam update of the MFMA network against the plain fp64 reference
+within the derived tolerance; the captured multi-step training equal to
+step-by-step training;
 checkpoint/resume; and the learned inference, which must return exact
 (m = 0) answers while replaying far less than the exhaustive search."""
 import time
@@ -15,11 +17,19 @@ from tests.gpu_common import need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
-# relative L2 error allowed between the bf16-operand network (fp32
-# accumulate, activations rounded to bf16 between layers) and the fp64
-# reference on the same bf16 weights and inputs: a handful of bf16 roundings
-# (2^-9 relative each) per element, averaged over the tensor.
-TOL_REL_L2 = 1e-2
+# Relative L2 error allowed between the network and the plain fp64
+# reference on the same bf16 weights and bf16 inputs.  Weights and inputs
+# are exact bf16 operands.  Every fp32 operand (hidden activation,
+# back-propagated error) enters its product as hi + lo with hi = bf16(v),
+# lo = bf16(v - hi): |v - hi - lo| <= 2^-18 |v|, and the dropped lo*lo term
+# is below 2^-18 of the product; fp32 accumulation over K <= 1024 terms adds
+# about sqrt(K) 2^-24.  Per term that is ~1e-5 relative; the batch sums of
+# the weight gradients cancel, which magnifies it by the ratio of the sum of
+# magnitudes to the magnitude of the sum (about 15 on these shapes, measured
+# as the ratio of the old bf16-operand network's 3% W1 error to its 2^-9
+# operand rounding), to ~1.5e-4.  The bound leaves a 10x margin and stays
+# inside the 1e-2 that the plan allows for bf16-operand products.
+TOL_REL_L2 = 2e-3
 
 ROWS = [(8192, 32, 1, 0), (8192, 32, 1, 1), (8192, 32, 2, 2), (8192, 32, 4, 0), (8192, 32, 4, 1),
         (12288, 64, 4, 2), (12288, 32, 3, 0), (16384, 128, 8, 3), (24576, 64, 64, 0), (65536, 64, 16, 2)]
@@ -94,7 +104,9 @@ def test_forward_matches_reference():
     net.forward(x, z)
     torch.cuda.synchronize()
     want, _ = R.forward(_ref_params(net, n_out), R.bf16_round(xh))
-    assert _rel(z.cpu().numpy(), want) <= TOL_REL_L2
+    err = _rel(z.cpu().numpy(), want)
+    say(f"forward rel L2 vs the fp64 reference: {err:.2e}")
+    assert err <= TOL_REL_L2
     net.close()
 
 
@@ -112,13 +124,9 @@ def test_train_step_gradients_and_adam():
     want_loss, want_g = R.loss_and_grads(ref, R.bf16_round(xh), yh)
     assert abs(loss - want_loss) <= TOL_REL_L2 * abs(want_loss)
     grads = [net.param(i, 3) for i in range(6)]
-    # gradients: against the reference that rounds product operands to bf16
-    # where the network does (the batch sums cancel, which magnifies the
-    # 2^-9 operand roundings against a fully fp64 evaluation)
-    _, want_r = R.loss_and_grads(ref, R.bf16_round(xh), yh, rnd=R.bf16_round)
-    errs = [_rel(grads[i], want_r[i]) for i in range(6)]
-    say(f"gradient rel L2 vs bf16-operand reference: {errs}; vs fp64: "
-        f"{[_rel(grads[i], want_g[i]) for i in range(6)]}")
+    # gradients: against the plain fp64 reference
+    errs = [_rel(grads[i], want_g[i]) for i in range(6)]
+    say(f"gradient rel L2 vs the fp64 reference: {errs}")
     for i in range(6):
         assert errs[i] <= TOL_REL_L2, (i, errs[i])
     # the update itself: Adam step 1 on the network's own gradients
@@ -151,6 +159,32 @@ def test_checkpoint_resume_is_exact():
     for w in range(6):
         for s in range(3):
             assert np.array_equal(a.param(w, s), b.param(w, s)), (w, s)
+    a.close()
+    b.close()
+
+
+def test_captured_training_equals_eager_steps():
+    """pchase_mlp_train replays one captured step per batch; its parameters,
+    moments and step count must equal those of eager single steps on the
+    same batches, after the first call and after a second call that
+    replays the same graph again."""
+    torch, capi = need_gpu()
+    n_out, B, nb = 60, 64, 4
+    say("captured training vs eager steps")
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.random((B * nb + 7, 768), dtype=np.float32)).cuda()   # trailing partial batch
+    y = torch.from_numpy(rng.integers(0, n_out, B * nb + 7).astype(np.int32)).cuda()
+    a = capi.Mlp(n_out, 21)
+    b = capi.Mlp(n_out, 21)
+    for rnd in range(2):
+        a.train(x, y, B, 1, 1e-3)
+        for k in range(nb):
+            b.train_step(x[k * B:(k + 1) * B], y[k * B:(k + 1) * B], 1e-3, want_loss=False)
+        torch.cuda.synchronize()
+        assert a.steps() == b.steps() == nb * (rnd + 1)
+        for w in range(6):
+            for sl in range(3):
+                assert np.array_equal(a.param(w, sl), b.param(w, sl)), (rnd, w, sl)
     a.close()
     b.close()
 

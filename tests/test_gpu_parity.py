@@ -320,11 +320,15 @@ def test_inference_all_probes_mode():
     assert res.best == best
 
 
-def test_inference_full_candidate_grid_sampled():
+@pytest.mark.timeout(600)
+def test_inference_full_candidate_grid():
     """The full search: 438 candidates (C 8..64 KB, b 32..128 B, a 1..64,
     LRU/FIFO/PLRU), each on its own N sweep at s in {b/2, b, 2b}, against one
-    seeded target; 1,079,586 replays.  The oracle recomputes the scores of
-    a sample of candidates (plus the target and the reported best)."""
+    seeded target; 1,079,586 replays.  The oracle scores every candidate
+    (host processes), and the best and the zero class come from its
+    scores."""
+    from oracle import pool
+
     torch, capi = need_gpu()
     cands, probes, target = W.inference_sweep()
     crows = [tuple(int(x) for x in c) for c in cands]
@@ -339,16 +343,15 @@ def test_inference_full_candidate_grid_sampled():
                                         probe_select=1, mn=mn, want_zero=True)
     got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
     assert res.replayed_accesses == 3361069440
-    assert got[target, 0] == 0
-    zc = [i for i in range(len(crows)) if got[i, 0] == 0 and got[i, 1] > 0]
-    assert res.best == min(zc) and res.n_zero == len(zc)
-    rng = np.random.default_rng(5)
-    sample = sorted(set(rng.choice(len(crows), size=5, replace=False).tolist()) | {target, int(res.best)})
-    flat = np.concatenate(hits_all)
-    for c in sample:
-        say(f"oracle scores candidate {c}")
-        _, m, n = orc.infer([orc_model(crows[c])], [orc_probe(r) for r in prows], flat, off, cfs, 1)
-        assert (got[c, 0], got[c, 1]) == (m[0], n[0]), crows[c]
+    say(f"oracle scores all {len(crows)} candidates ({pool.default_procs()} processes)")
+    m, n, best, zc = pool.infer_scores(crows, prows, np.concatenate(hits_all), off, cfs, probe_select=1)
+    bad = np.nonzero((got[:, 0] != m) | (got[:, 1] != n))[0]
+    assert len(bad) == 0, [(int(c), crows[int(c)], tuple(got[c]), (int(m[c]), int(n[c]))) for c in bad[:5]]
+    assert m[target] == 0
+    assert res.best == best and (res.best_m, res.best_n) == (m[best], n[best])
+    assert res.n_zero == len(zc)
+    got_zero = [c for c in range(len(crows)) if (zero[c // 32] >> (c % 32)) & 1]
+    assert got_zero == zc.tolist()
 
 
 # -------------------------------------------------------- microbenches ---

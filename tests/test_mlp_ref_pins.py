@@ -158,16 +158,3 @@ def test_noiseless_sample_is_clean_features(orc):
         x, y, (mi, base, thr) = R.sample(orc, i, 99, rows, labels, 0)
         assert thr == 0 and y == mi and base % 4 == 0 and base < rows[mi][1]
         assert np.array_equal(x, R.features(orc, rows[mi], base))
-
-
-def test_rounding_hook_identity_is_plain_reference():
-    rng = np.random.default_rng(12)
-    params = _net(rng, 7, 6, 5)
-    X = rng.normal(0, 1, (4, 7))
-    y = np.array([1, 2, 0, 4])
-    l0, g0 = R.loss_and_grads(params, X, y)
-    l1, g1 = R.loss_and_grads(params, X, y, rnd=lambda v: v)
-    assert l0 == l1 and all(np.array_equal(a, b) for a, b in zip(g0, g1))
-    # rounding only perturbs by about the bf16 step
-    l2, g2 = R.loss_and_grads(params, X, y, rnd=R.bf16_round)
-    assert abs(l2 - l0) < 1e-2 * abs(l0)
