@@ -403,7 +403,7 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
                         uint32_t mode, hipStream_t stream) {
     const uint32_t row_cap = 256;
     struct Key {
-        uint32_t key;   // policy * 8 + log2(row class) - 4
+        uint32_t key;   // (policy * kTileWayClasses + way class) * 8 + log2(row class) - 4
         float cost;
         uint32_t item;
     };
@@ -416,25 +416,28 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
         if (pair_model[i] >= n_models) return set_error(PCHASE_EINVAL, "pair %llu: model index out of range", (unsigned long long)i);
         if (pair_trace[i] >= n_traces) return set_error(PCHASE_EINVAL, "pair %llu: trace index out of range", (unsigned long long)i);
         const DevModel& m = dm[pair_model[i]];
-        const uint32_t RS = m.ways + tile_meta_rows((int)m.policy, m.ways);
-        uint32_t lp = 0;
+        // rows of the largest part's layout when split into 2^l parts (the
+        // parts hold ceil(T / 2^l) or floor(T / 2^l) sets: parts 0 and last)
         auto rows_of = [&](uint32_t l) {
-            const uint64_t sets = ((uint64_t)m.sets + (1ull << l) - 1) >> l;   // part 0 holds the most
-            return (uint64_t)((sets + kWave - 1) / kWave) * RS;
+            const TileLayout l0 = tile_layout((int)m.policy, m.ways, m.sets, l, 0);
+            const TileLayout l1 = tile_layout((int)m.policy, m.ways, m.sets, l, (1u << l) - 1);
+            return std::max<uint64_t>((uint64_t)l0.slots * l0.rs, (uint64_t)l1.slots * l1.rs);
         };
+        uint32_t lp = 0;
         while (rows_of(lp) > row_cap && (2ull << lp) <= m.sets) ++lp;
-        const uint64_t rows = rows_of(lp);
-        if (rows > kTileMaxRows)
+        if (rows_of(lp) > kTileMaxRows)
             return set_error(PCHASE_ERANGE, "pair %llu: a set of %u ways does not fit the replay state",
                              (unsigned long long)i, m.ways);
-        uint32_t rc = 16, cls = 0;
-        while (rc < rows) {
-            rc *= 2;
-            ++cls;
-        }
         const uint64_t len = trace_off[pair_trace[i] + 1] - trace_off[pair_trace[i]];
         const uint32_t P = 1u << lp;
         for (uint32_t p = 0; p < P; ++p) {
+            const TileLayout ly = tile_layout((int)m.policy, m.ways, m.sets, lp, p);
+            const uint64_t rows = (uint64_t)ly.slots * ly.rs;
+            uint32_t rc = 16, cls = 0;
+            while (rc < rows) {
+                rc *= 2;
+                ++cls;
+            }
             TileItem t;
             t.start = trace_off[pair_trace[i]];
             t.len = len;
@@ -445,7 +448,8 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
             t.trace_id = pair_trace[i];
             t.out = (uint32_t)i;
             t.part = p | (lp << 16);
-            keys.push_back(Key{m.policy * 8u + cls, (float)((double)len * (8.0 + (double)m.ways / P)),
+            const uint32_t grp = m.policy * kTileWayClasses + (uint32_t)tile_way_class(ly.kw);
+            keys.push_back(Key{grp * 8u + cls, (float)((double)len * (8.0 + (double)ly.kw * (1u << ly.lw) / P)),
                                (uint32_t)items.size()});
             items.push_back(t);
         }
@@ -503,7 +507,7 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
     }
     // one launch per (policy, row class) group
     struct Launch {
-        int pol;
+        int pol, wcls;
         uint32_t rows;
         uint64_t q, e2, blocks;
         double cost;
@@ -515,15 +519,15 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
         double work = 0;
         while (e2 < keys.size() && keys[e2].key == key) work += keys[e2++].cost;
         Launch L;
-        L.pol = (int)(key / 8);
+        L.pol = (int)(key / 8 / kTileWayClasses);
+        L.wcls = (int)(key / 8 % kTileWayClasses);
         L.rows = 16u << (key % 8);
         L.q = q;
         L.e2 = e2;
-        int occ = ws->occ_tile[L.pol][key % 8];
+        int& occ = ws->occ_tile[key / 8][key % 8];
         if (occ == 0) {
-            PC_HIP(tile_occupancy(L.pol, L.rows, &occ));
+            PC_HIP(tile_occupancy(L.pol, L.wcls, L.rows, &occ));
             if (occ < 1) occ = 1;
-            ws->occ_tile[L.pol][key % 8] = occ;
         }
         L.blocks = mode == PCHASE_PLAIN ? e2 - q : std::min<uint64_t>((uint64_t)occ * ws->cus, e2 - q);
         L.cost = std::max((double)keys[q].cost, work / (double)L.blocks);
@@ -561,7 +565,7 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
         a.rows = L.rows;
         a.abort_flag = mode == PCHASE_PLAIN ? nullptr : abort_flag_dev();
         a.status = d_status;
-        PC_HIP(launch_tile(L.pol, a, (uint32_t)L.blocks, st));
+        PC_HIP(launch_tile(L.pol, L.wcls, a, (uint32_t)L.blocks, st));
     }
     if (ns > 1) {
         for (int b = 0; b < ns; ++b) {
@@ -594,6 +598,9 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
             return set_error(PCHASE_EINVAL, "trace %u: base must be a multiple of 4 below 2^33", t);
     }
     if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
+    if (!gd)
+        return replay_tiles(dm, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model, pair_trace, count_from,
+                            n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
 
     // generalised models: bucket pairs by (policy, group width), longest first inside a bucket;
     // a pair that is long, or whose state is large, is split by set into

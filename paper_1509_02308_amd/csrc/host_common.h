@@ -47,7 +47,7 @@ struct Workspace {
     uint32_t epoch = 0;
     void* host_res = nullptr;  // pinned result staging
     int occ_stream[2][5][7] = {};   // [generalised][policy][log2 width]
-    int occ_tile[4][8] = {};        // [policy][log2 row class - 4]
+    int occ_tile[4 * 5][8] = {};    // [policy * way classes + way class][log2 row class - 4]
     bool tile_ready = false;
     bool lds_ready = false;
     hipStream_t branch[kBranches] = {};   // capture-side streams (default priority)
