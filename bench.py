@@ -282,7 +282,7 @@ def plain_sweep_leg(torch, capi, W, args):
     stream synchronisation), batched (one captured persistent launch) vs
     plain (one ordinary launch per model)."""
     model, prow = W.plain_sweep()
-    mrow = tuple(int(v) for v in model)
+    mrow = tuple(int(v) for v in model[0])
     prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in prow]
     marr, parr = capi.models([mrow]), capi.probes(prows)
     lens = np.array([capi.pchase_trace_len(parr[i])[0] for i in range(len(prows))], dtype=np.uint64)

@@ -251,8 +251,9 @@ __global__ void __launch_bounds__(256, 4) sweep_kernel(SweepArgs args) {
         uint32_t t = 0;
         if (lane == 0) {
             t = atomicAdd(args.queue, 1u);
-            // the host flag is polled on the first pull and every 8th after it
-            if ((iter & 7) == 0 && args.abort_flag != nullptr && *args.abort_flag != 0) {
+            // the host flag (a read across PCIe) is polled on the first pull
+            // and every 64th after it
+            if ((iter & 63) == 0 && args.abort_flag != nullptr && *args.abort_flag != 0) {
                 atomicOr(args.aborted, 1u);
                 t = args.n_tasks;
             }
