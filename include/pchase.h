@@ -255,6 +255,28 @@ int cache_replay_batch(const pchase_model *models, uint32_t n_models,
                        uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
                        uint32_t mode, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cache_replay_batch in the BATCHED schedule, for the same arguments and
+ * with the same results, that allocates nothing.  Its device scratch (the
+ * models, the per-(pair, part) work items, the status word and work-queue
+ * counters) is a fixed array of 64 MiB in the library, one per GPU, set up
+ * on the first call on that GPU and held until the process ends; a call
+ * whose descriptors need more (about 56 bytes per pair or part of a split
+ * pair) returns PCHASE_ERANGE before launching anything.  Every call on one
+ * GPU uses that same array: calls that overlap on one GPU (other host
+ * threads, or other streams before this call's synchronisation) race.
+ * Everything launches on `stream`, one kernel after the other; the call
+ * synchronises `stream` before it returns.  pchase_abort() does not stop
+ * it.  Standard models only. */
+int cache_replay_batch_static(const pchase_model *models, uint32_t n_models,
+                              const int32_t *idx_dev, const uint64_t *trace_off,
+                              const uint64_t *trace_base, uint32_t elem_bytes, uint32_t n_traces,
+                              const uint32_t *pair_model, const uint32_t *pair_trace,
+                              const uint64_t *count_from, uint64_t n_pairs,
+                              uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
+                              hipStream_t stream);
+
 /* cache_replay_batch for generalised models (the declarations above):
  * same traces, pairs, outputs, ownership and errors.  A pair's state slab
  * holds n_sets 32-byte headers and 8 bytes per way; a long pair whose state
@@ -494,7 +516,7 @@ int pchase_mlp_step_count(const pchase_mlp *net, uint64_t *steps, int set);
 
 /* --------------------------------------------------------- lifecycle --- */
 /* Sets a host flag that the persistent replays of the BATCHED schedule
- * poll (each wave on its first queue pull and every 8th after it); they
+ * poll (each wave on its first queue pull and every 8th or 64th after it); they
  * drain and the call that launched them returns PCHASE_EABORTED, outputs
  * unspecified.  pchase_abort(0) clears it; later calls are unaffected. */
 void pchase_abort(int on);

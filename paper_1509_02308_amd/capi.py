@@ -92,6 +92,7 @@ def lib():
         L.pchase_trace_nu_len.argtypes = [ctypes.POINTER(PchaseNuProbe), vp, u32, vp, vp]
         L.pchase_trace_nu.argtypes = [vp, u32, vp, u32, vp, vp, u64, vp]
         L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.cache_replay_batch_static.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, vp]
         L.cache_replay_probes.argtypes = [vp, u32, vp, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
         L.infer_cache_params.argtypes = [ctypes.POINTER(PchaseObservation), vp, u32, ctypes.c_int,
                                          ctypes.c_int, u32, vp, ctypes.POINTER(PchaseResult), vp, vp, vp]
@@ -257,6 +258,19 @@ def cache_replay_batch(model_arr, idx, trace_off, trace_base, pair_model, pair_t
     check(lib().cache_replay_batch(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
                                    len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
                                    p_bo, mode, _stream(stream)))
+
+
+def cache_replay_batch_static(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
+                              misses, hitbits=None, bitoff=None, stream=None):
+    toff, p_toff = _hptr(trace_off, np.uint64)
+    tb, p_tb = _hptr(trace_base, np.uint64)
+    pm, p_pm = _hptr(pair_model, np.uint32)
+    pt, p_pt = _hptr(pair_trace, np.uint32)
+    cf, p_cf = _hptr(count_from, np.uint64)
+    bo, p_bo = _hptr(bitoff, np.uint64)
+    check(lib().cache_replay_batch_static(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
+                                          len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
+                                          p_bo, _stream(stream)))
 
 
 def general_models(rows) -> ctypes.Array:

@@ -390,17 +390,21 @@ extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t
 // Standard models: the set-partitioned tile replay.  Every pair becomes
 // one or more (pair, part) items: the fewest parts P (a power of two, at
 // most T) for which one part's sets fit a wave's LDS state of at most
-// row_cap dwords per lane.  Items are grouped by (policy, row class: the
-// state rows rounded up to a power of two, at least 16), each group one
-// launch whose LDS fits its class, longest items first; BATCHED runs each
-// group as a persistent grid pulling items from an atomic queue, the
-// groups concurrently on the workspace's replay streams; PLAIN launches one
-// block per item, group after group.
-static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, const int32_t* idx_dev,
-                        const uint64_t* trace_off, const uint64_t* trace_base, uint32_t n_traces,
-                        const uint32_t* pair_model, const uint32_t* pair_trace, const uint64_t* count_from,
-                        uint64_t n_pairs, uint64_t* misses_dev, uint32_t* hitbits_dev, const uint64_t* bitoff,
-                        uint32_t mode, hipStream_t stream) {
+// row_cap dwords per lane.  Items are grouped by (policy, way class, row
+// class: the state rows rounded up to a power of two, at least 16), each
+// group one launch whose LDS fits its class, longest items first.
+struct TileSchedule {
+    std::vector<TileItem> items;     // grouped, longest first in a group
+    std::vector<uint32_t> key;       // group key of each item
+    std::vector<float> cost;         // estimated cost of each item
+    std::vector<uint64_t> zero_cnt;  // (word, count) ranges that split pairs merge into
+    std::vector<uint64_t> zero_bits;
+};
+
+static int build_tile_schedule(const std::vector<DevModel>& dm, uint32_t n_models, const uint64_t* trace_off,
+                               const uint64_t* trace_base, uint32_t n_traces, const uint32_t* pair_model,
+                               const uint32_t* pair_trace, const uint64_t* count_from, uint64_t n_pairs,
+                               bool want_bits, const uint64_t* bitoff, TileSchedule* ts) {
     const uint32_t row_cap = 256;
     struct Key {
         uint32_t key;   // (policy * kTileWayClasses + way class) * 8 + log2(row class) - 4
@@ -411,7 +415,8 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
     items.reserve(n_pairs);
     std::vector<Key> keys;
     keys.reserve(n_pairs);
-    std::vector<uint64_t> zero_cnt, zero_bits;
+    ts->zero_cnt.clear();
+    ts->zero_bits.clear();
     for (uint64_t i = 0; i < n_pairs; ++i) {
         if (pair_model[i] >= n_models) return set_error(PCHASE_EINVAL, "pair %llu: model index out of range", (unsigned long long)i);
         if (pair_trace[i] >= n_traces) return set_error(PCHASE_EINVAL, "pair %llu: trace index out of range", (unsigned long long)i);
@@ -454,11 +459,11 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
             items.push_back(t);
         }
         if (P > 1) {
-            zero_cnt.push_back(4 * i);   // the pair's two 64-bit counters, as 32-bit words
-            zero_cnt.push_back(4);
-            if (hitbits_dev) {
-                zero_bits.push_back(bitoff[i]);
-                zero_bits.push_back((len + 31) / 32);
+            ts->zero_cnt.push_back(4 * i);   // the pair's two 64-bit counters, as 32-bit words
+            ts->zero_cnt.push_back(4);
+            if (want_bits) {
+                ts->zero_bits.push_back(bitoff[i]);
+                ts->zero_bits.push_back((len + 31) / 32);
             }
         }
     }
@@ -468,44 +473,62 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
         if (x.cost != y.cost) return x.cost > y.cost;
         return x.item < y.item;
     });
-    std::vector<TileItem> sorted(items.size());
-    for (size_t q = 0; q < keys.size(); ++q) sorted[q] = items[keys[q].item];
+    ts->items.resize(items.size());
+    ts->key.resize(items.size());
+    ts->cost.resize(items.size());
+    for (size_t q = 0; q < keys.size(); ++q) {
+        ts->items[q] = items[keys[q].item];
+        ts->key[q] = keys[q].key;
+        ts->cost[q] = keys[q].cost;
+    }
+    return PCHASE_OK;
+}
 
-    Workspace* ws;
-    std::unique_lock<std::mutex> lk;
-    int rc = workspace(&ws, &lk);
-    if (rc) return rc;
-    const size_t o_models = 0;
-    const size_t o_items = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
-    const size_t o_status = o_items + (sorted.size() * sizeof(TileItem) + 255) / 256 * 256;
-    const size_t o_zero = o_status + 512;
-    const size_t total = o_zero + (zero_cnt.size() + zero_bits.size()) * sizeof(uint64_t) + 256;
-    hipError_t e = ws->stage.ensure(total);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
-    uint8_t* sb = ws->stage.as<uint8_t>();
-    DevModel* d_models = reinterpret_cast<DevModel*>(sb + o_models);
-    TileItem* d_items = reinterpret_cast<TileItem*>(sb + o_items);
-    uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + o_status);
+// Device bytes a schedule's descriptors take in scratch.
+struct TileScratch {
+    size_t o_models, o_items, o_status, o_zero, total;
+};
+static TileScratch tile_scratch_layout(size_t n_models, const TileSchedule& ts) {
+    TileScratch L;
+    L.o_models = 0;
+    L.o_items = (n_models * sizeof(DevModel) + 255) / 256 * 256;
+    L.o_status = L.o_items + (ts.items.size() * sizeof(TileItem) + 255) / 256 * 256;
+    L.o_zero = L.o_status + 512;
+    L.total = L.o_zero + (ts.zero_cnt.size() + ts.zero_bits.size()) * sizeof(uint64_t) + 256;
+    return L;
+}
+
+// Enqueues a schedule whose descriptors go to device scratch `sb` (at least
+// tile_scratch_layout(...).total bytes), waits and reads the status.  With
+// a workspace the groups run concurrently on its replay streams; without
+// one (ws = NULL) every launch goes to `stream`, one after the other.
+// BATCHED runs each group as a persistent grid pulling items from an atomic
+// queue; PLAIN launches one block per item.  occ caches resident blocks per
+// (group, row class) (0 = unknown).
+static int run_tile_schedule(const std::vector<DevModel>& dm, const TileSchedule& ts, uint8_t* sb, Workspace* ws,
+                             int (*occ)[8], int cus, const volatile uint32_t* abort_flag, const int32_t* idx_dev,
+                             uint64_t* misses_dev, uint32_t* hitbits_dev, uint32_t mode, hipStream_t stream) {
+    const TileScratch SL = tile_scratch_layout(dm.size(), ts);
+    DevModel* d_models = reinterpret_cast<DevModel*>(sb + SL.o_models);
+    TileItem* d_items = reinterpret_cast<TileItem*>(sb + SL.o_items);
+    uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + SL.o_status);
     PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
-    PC_HIP(hipMemcpyAsync(d_items, sorted.data(), sorted.size() * sizeof(TileItem), hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_items, ts.items.data(), ts.items.size() * sizeof(TileItem), hipMemcpyHostToDevice,
+                          stream));
     PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
-    if (!zero_cnt.empty()) {
+    if (!ts.zero_cnt.empty()) {
         // split pairs merge into their outputs: zero those first
-        uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + o_zero);
-        uint64_t* d_zb = d_zc + zero_cnt.size();
-        PC_HIP(hipMemcpyAsync(d_zc, zero_cnt.data(), zero_cnt.size() * 8, hipMemcpyHostToDevice, stream));
-        PC_HIP(launch_clear_ranges(reinterpret_cast<uint32_t*>(misses_dev), d_zc, (uint32_t)(zero_cnt.size() / 2),
-                                   stream));
-        if (!zero_bits.empty()) {
-            PC_HIP(hipMemcpyAsync(d_zb, zero_bits.data(), zero_bits.size() * 8, hipMemcpyHostToDevice, stream));
-            PC_HIP(launch_clear_ranges(hitbits_dev, d_zb, (uint32_t)(zero_bits.size() / 2), stream));
+        uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + SL.o_zero);
+        uint64_t* d_zb = d_zc + ts.zero_cnt.size();
+        PC_HIP(hipMemcpyAsync(d_zc, ts.zero_cnt.data(), ts.zero_cnt.size() * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(launch_clear_ranges(reinterpret_cast<uint32_t*>(misses_dev), d_zc,
+                                   (uint32_t)(ts.zero_cnt.size() / 2), stream));
+        if (!ts.zero_bits.empty()) {
+            PC_HIP(hipMemcpyAsync(d_zb, ts.zero_bits.data(), ts.zero_bits.size() * 8, hipMemcpyHostToDevice, stream));
+            PC_HIP(launch_clear_ranges(hitbits_dev, d_zb, (uint32_t)(ts.zero_bits.size() / 2), stream));
         }
     }
-    if (!ws->tile_ready) {
-        PC_HIP(tile_prepare_lds());
-        ws->tile_ready = true;
-    }
-    // one launch per (policy, row class) group
+    // one launch per group
     struct Launch {
         int pol, wcls;
         uint32_t rows;
@@ -513,31 +536,32 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
         double cost;
     };
     std::vector<Launch> launches;
-    for (uint64_t q = 0; q < keys.size();) {
-        const uint32_t key = keys[q].key;
+    for (uint64_t q = 0; q < ts.items.size();) {
+        const uint32_t key = ts.key[q];
         uint64_t e2 = q;
         double work = 0;
-        while (e2 < keys.size() && keys[e2].key == key) work += keys[e2++].cost;
+        while (e2 < ts.items.size() && ts.key[e2] == key) work += ts.cost[e2++];
         Launch L;
         L.pol = (int)(key / 8 / kTileWayClasses);
         L.wcls = (int)(key / 8 % kTileWayClasses);
         L.rows = 16u << (key % 8);
         L.q = q;
         L.e2 = e2;
-        int& occ = ws->occ_tile[key / 8][key % 8];
-        if (occ == 0) {
-            PC_HIP(tile_occupancy(L.pol, L.wcls, L.rows, &occ));
-            if (occ < 1) occ = 1;
+        int& oc = occ[key / 8][key % 8];
+        if (oc == 0) {
+            PC_HIP(tile_occupancy(L.pol, L.wcls, L.rows, &oc));
+            if (oc < 1) oc = 1;
         }
-        L.blocks = mode == PCHASE_PLAIN ? e2 - q : std::min<uint64_t>((uint64_t)occ * ws->cus, e2 - q);
-        L.cost = std::max((double)keys[q].cost, work / (double)L.blocks);
+        L.blocks = mode == PCHASE_PLAIN ? e2 - q : std::min<uint64_t>((uint64_t)oc * cus, e2 - q);
+        L.cost = std::max((double)ts.cost[q], work / (double)L.blocks);
         launches.push_back(L);
         q = e2;
     }
+    if (launches.size() > 120) return set_error(PCHASE_ERANGE, "too many replay groups");
     std::vector<size_t> order(launches.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return launches[x].cost > launches[y].cost; });
-    const int ns = mode == PCHASE_PLAIN ? 0 : (int)std::min<size_t>(kReplayStreams, launches.size());
+    const int ns = (mode == PCHASE_PLAIN || !ws) ? 0 : (int)std::min<size_t>(kReplayStreams, launches.size());
     double load[kReplayStreams] = {};
     if (ns > 1) {
         PC_HIP(hipEventRecord(ws->rfork, stream));
@@ -563,7 +587,7 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
         a.misses = misses_dev;
         a.bits = hitbits_dev;
         a.rows = L.rows;
-        a.abort_flag = mode == PCHASE_PLAIN ? nullptr : abort_flag_dev();
+        a.abort_flag = mode == PCHASE_PLAIN ? nullptr : abort_flag;
         a.status = d_status;
         PC_HIP(launch_tile(L.pol, L.wcls, a, (uint32_t)L.blocks, st));
     }
@@ -579,6 +603,107 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
     if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
     if (status & 2u) return set_error(PCHASE_EINVAL, "a trace holds a negative element index");
     return PCHASE_OK;
+}
+
+static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, const int32_t* idx_dev,
+                        const uint64_t* trace_off, const uint64_t* trace_base, uint32_t n_traces,
+                        const uint32_t* pair_model, const uint32_t* pair_trace, const uint64_t* count_from,
+                        uint64_t n_pairs, uint64_t* misses_dev, uint32_t* hitbits_dev, const uint64_t* bitoff,
+                        uint32_t mode, hipStream_t stream) {
+    TileSchedule ts;
+    int rc = build_tile_schedule(dm, n_models, trace_off, trace_base, n_traces, pair_model, pair_trace, count_from,
+                                 n_pairs, hitbits_dev != nullptr, bitoff, &ts);
+    if (rc) return rc;
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace(&ws, &lk);
+    if (rc) return rc;
+    const TileScratch SL = tile_scratch_layout(dm.size(), ts);
+    hipError_t e = ws->stage.ensure(SL.total);
+    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    if (!ws->tile_ready) {
+        PC_HIP(tile_prepare_lds());
+        ws->tile_ready = true;
+    }
+    return run_tile_schedule(dm, ts, ws->stage.as<uint8_t>(), ws, ws->occ_tile, ws->cus, abort_flag_dev(), idx_dev,
+                             misses_dev, hitbits_dev, mode, stream);
+}
+
+// ------------------------------------------- replay without allocation ---
+// Descriptor scratch of cache_replay_batch_static: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// Host code reaches it only through the address hipGetSymbolAddress gives
+// on each device.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+struct StaticDev {
+    uint8_t* ptr = nullptr;   // device address of `scratch` on this device
+    int cus = 0;
+    int occ[4 * kTileWayClasses][8] = {};
+};
+static std::mutex g_static_mu;
+static std::map<int, StaticDev> g_static;
+
+// Set-up on the current device, once: the scratch address, the CU count and
+// the replay kernels' LDS limit.
+static int static_device(StaticDev** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(PCHASE_ENODEV, "no HIP device: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> g(g_static_mu);
+    StaticDev& sd = g_static[dev];
+    if (!sd.ptr) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return set_error(PCHASE_ENODEV, "device %d is %s, the library is built for gfx950", dev, prop.gcnArchName);
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        PC_HIP(tile_prepare_lds());
+        sd.cus = prop.multiProcessorCount;
+        sd.ptr = static_cast<uint8_t*>(p);
+    }
+    *out = &sd;
+    return PCHASE_OK;
+}
+
+extern "C" int cache_replay_batch_static(const pchase_model* models, uint32_t n_models, const int32_t* idx_dev,
+                                         const uint64_t* trace_off, const uint64_t* trace_base, uint32_t elem_bytes,
+                                         uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
+                                         const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
+                                         uint32_t* hitbits_dev, const uint64_t* bitoff, hipStream_t stream) {
+    if (elem_bytes != 4) return set_error(PCHASE_EINVAL, "elem_bytes must be 4");
+    std::vector<DevModel> dm;
+    int rc = validate_models(models, n_models, &dm);
+    if (rc) return rc;
+    if (n_pairs == 0) return PCHASE_OK;
+    if (!trace_off || !pair_model || !pair_trace) return set_error(PCHASE_EINVAL, "trace or pair arrays are NULL");
+    if (!misses_dev) return set_error(PCHASE_EINVAL, "misses_dev is NULL");
+    if (hitbits_dev && !bitoff) return set_error(PCHASE_EINVAL, "hitbits_dev needs bitoff");
+    if (n_pairs >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many pairs");
+    for (uint32_t t = 0; t < n_traces; ++t) {
+        if (trace_off[t + 1] < trace_off[t]) return set_error(PCHASE_EINVAL, "trace_off is not monotone at %u", t);
+        if (trace_base && (trace_base[t] >= (1ull << 33) || trace_base[t] % 4))
+            return set_error(PCHASE_EINVAL, "trace %u: base must be a multiple of 4 below 2^33", t);
+    }
+    if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
+    TileSchedule ts;
+    rc = build_tile_schedule(dm, n_models, trace_off, trace_base, n_traces, pair_model, pair_trace, count_from,
+                             n_pairs, hitbits_dev != nullptr, bitoff, &ts);
+    if (rc) return rc;
+    const TileScratch SL = tile_scratch_layout(dm.size(), ts);
+    if (SL.total > kStaticScratchBytes)
+        return set_error(PCHASE_ERANGE, "the call's descriptors take %zu bytes, the fixed scratch holds %zu",
+                         SL.total, kStaticScratchBytes);
+    StaticDev* sd;
+    rc = static_device(&sd);
+    if (rc) return rc;
+    // (no abort flag: the mapped page behind it would be an allocation)
+    return run_tile_schedule(dm, ts, sd->ptr, nullptr, sd->occ, sd->cus, nullptr, idx_dev, misses_dev, hitbits_dev,
+                             PCHASE_BATCHED, stream);
 }
 
 static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDesc* gd, uint32_t n_models,

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -235,3 +236,16 @@ def test_mlp_grid_matches_reference(capi):
     assert all(arr[i].base_offset == 64 and arr[i].j0 == 0 and arr[i].elem_bytes == 4 for i in range(768))
     with pytest.raises(capi.PchaseError):
         capi.pchase_mlp_grid(2)
+
+
+def test_static_replay_argument_checks(capi):
+    L = capi.lib()
+    m = capi.models([(8192, 32, 4, 0)])
+    off = np.array([0, 4], np.uint64)
+    z = np.zeros(1, np.uint32)
+    args = lambda eb: (ctypes.cast(m, ctypes.c_void_p), 1, None, off.ctypes.data, None, eb, 1, z.ctypes.data,
+                       z.ctypes.data, None, 1, None, None, None, None)
+    assert L.cache_replay_batch_static(*args(8)) == -1      # elem_bytes must be 4
+    assert L.cache_replay_batch_static(*args(4)) == -1      # misses_dev is NULL
+    bad = capi.models([(8192, 32, 3, 0)])                  # T*a*b != C
+    assert L.cache_replay_batch_static(ctypes.cast(bad, ctypes.c_void_p), *args(4)[1:]) == -1
