@@ -222,10 +222,33 @@ int pchase_plan_next_probe(const pchase_model *cands, uint32_t n_cands, const pc
                            uint32_t n_pool, const uint32_t *alive_host, uint32_t *classes_dev,
                            pchase_plan_choice *out, hipStream_t stream);
 
+/* ------------------------------------------------------------- plans --- */
+/* A caller-owned plan: the device workspace of the replay and inference
+ * calls that are given it (descriptor staging, observation bits, replay
+ * schedules, slab state of generalised caches, cached inference schedules)
+ * reserved once, as one allocation of device_bytes, when the plan is
+ * created, together with the plan's own streams, events and pinned result
+ * page.  A call given a plan allocates no device memory: it carves what it
+ * needs from the plan's memory (returning PCHASE_ERANGE, before launching
+ * anything that could write outputs, when that does not suffice), and it
+ * launches its persistent kernels directly instead of capturing a graph.
+ * The plan keeps the schedule of the last inference problem it served, so
+ * repeating infer_cache_params on the same inputs rebuilds nothing; any
+ * other call replaces what the plan held.  A plan belongs to the device
+ * that was current at creation (EINVAL on another device), and serves one
+ * call at a time (calls are serialised on it).  A NULL plan selects the
+ * library's own per-device workspace, which grows on demand. */
+typedef struct pchase_plan pchase_plan;
+int pchase_plan_create(uint64_t device_bytes, pchase_plan **plan);
+/* Waits for the plan's device, then frees everything the plan holds.
+ * NULL is a no-op. */
+void pchase_plan_destroy(pchase_plan *plan);
+
 /* ------------------------------------------------------------ replay --- */
-/* Replay scheduling: BATCHED runs every pair in one captured graph of
- * persistent kernels fed by a cost-ordered work queue; PLAIN launches one
- * ordinary kernel per model.  Results are identical. */
+/* Replay scheduling: BATCHED runs every pair in persistent kernels fed by
+ * cost-ordered work queues (captured once into a graph for probe replays
+ * and inference without a plan); PLAIN launches ordinary kernels, one
+ * block per work item.  Results are identical. */
 enum { PCHASE_BATCHED = 0, PCHASE_PLAIN = 1 };
 
 /* Replays (model, trace) pairs over materialised index traces.
@@ -253,7 +276,7 @@ int cache_replay_batch(const pchase_model *models, uint32_t n_models,
                        const uint32_t *pair_model, const uint32_t *pair_trace,
                        const uint64_t *count_from, uint64_t n_pairs,
                        uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
-                       uint32_t mode, hipStream_t stream);
+                       uint32_t mode, pchase_plan *plan, hipStream_t stream);
 
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -286,7 +309,8 @@ int cache_replay_general(const pchase_general_model *models, uint32_t n_models, 
                          const uint64_t *trace_off, const uint64_t *trace_base, uint32_t elem_bytes,
                          uint32_t n_traces, const uint32_t *pair_model, const uint32_t *pair_trace,
                          const uint64_t *count_from, uint64_t n_pairs, uint64_t *misses_dev,
-                         uint32_t *hitbits_dev, const uint64_t *bitoff, uint32_t mode, hipStream_t stream);
+                         uint32_t *hitbits_dev, const uint64_t *bitoff, uint32_t mode, pchase_plan *plan,
+                         hipStream_t stream);
 
 /* Same replay with traces given as probes instead of index arrays: pair i
  * replays probe pair_probe[i] through model pair_model[i]; the trace id of
@@ -298,7 +322,7 @@ int cache_replay_probes(const pchase_model *models, uint32_t n_models,
                         const uint32_t *pair_model, const uint32_t *pair_probe,
                         const uint64_t *count_from, uint64_t n_pairs,
                         uint64_t *misses_dev, uint32_t *hitbits_dev, const uint64_t *bitoff,
-                        uint32_t mode, hipStream_t stream);
+                        uint32_t mode, pchase_plan *plan, hipStream_t stream);
 
 /* --------------------------------------------------------- inference --- */
 enum { PCHASE_PROBES_ALL = 0, PCHASE_PROBES_OWN_SWEEP = 1 };
@@ -358,11 +382,14 @@ typedef struct pchase_result {
  * the grid it runs the exhaustive search directly (out->fallback = 2).
  * mn_dev (uint64[2*n_cands], nullable) receives (m, n) per candidate;
  * zero_host (uint32[(n_cands+31)/32], nullable) the zero-class bitmap
- * (exhaustive results only).  Synchronises `stream`. */
+ * (exhaustive results only; it passes through a 3840-byte pinned page, so
+ * with zero_host at most 30,720 candidates, ERANGE above).  With a plan the
+ * learned network's activations for one row must already exist (any
+ * earlier forward or training call made them).  Synchronises `stream`. */
 int infer_cache_params(const pchase_observation *obs, const pchase_model *cands,
                        uint32_t n_cands, int probe_select, int mode, uint32_t topk,
                        const pchase_mlp *net, pchase_result *out, uint64_t *mn_dev,
-                       uint32_t *zero_host, hipStream_t stream);
+                       uint32_t *zero_host, pchase_plan *plan, hipStream_t stream);
 
 /* ---------------------------------------------------- microbenchmarks --- */
 /* Load flavours of the single-lane chase: which cache level a load may be
@@ -516,7 +543,8 @@ int pchase_mlp_step_count(const pchase_mlp *net, uint64_t *steps, int set);
 
 /* --------------------------------------------------------- lifecycle --- */
 /* Sets a host flag that the persistent replays of the BATCHED schedule
- * poll (each wave on its first queue pull and every 8th or 64th after it); they
+ * poll (each wave on its first queue pull, then every 8th pull for
+ * materialised traces and every 64th for probe replays); they
  * drain and the call that launched them returns PCHASE_EABORTED, outputs
  * unspecified.  pchase_abort(0) clears it; later calls are unaffected. */
 void pchase_abort(int on);

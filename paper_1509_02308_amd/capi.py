@@ -87,15 +87,18 @@ def lib():
         L.pchase_last_error.restype = ctypes.c_char_p
         L.pchase_trace_len.argtypes = [ctypes.POINTER(PchaseProbe), vp, vp]
         L.pchase_trace.argtypes = [vp, u32, vp, vp, u64, vp]
-        L.cache_replay_general.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.cache_replay_general.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
+        L.pchase_plan_create.argtypes = [u64, ctypes.POINTER(vp)]
+        L.pchase_plan_destroy.argtypes = [vp]
+        L.pchase_plan_destroy.restype = None
         L.pchase_plan_next_probe.argtypes = [vp, u32, vp, u32, vp, vp, ctypes.POINTER(PchasePlanChoice), vp]
         L.pchase_trace_nu_len.argtypes = [ctypes.POINTER(PchaseNuProbe), vp, u32, vp, vp]
         L.pchase_trace_nu.argtypes = [vp, u32, vp, u32, vp, vp, u64, vp]
-        L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.cache_replay_batch.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
         L.cache_replay_batch_static.argtypes = [vp, u32, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp, vp, vp]
-        L.cache_replay_probes.argtypes = [vp, u32, vp, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp]
+        L.cache_replay_probes.argtypes = [vp, u32, vp, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
         L.infer_cache_params.argtypes = [ctypes.POINTER(PchaseObservation), vp, u32, ctypes.c_int,
-                                         ctypes.c_int, u32, vp, ctypes.POINTER(PchaseResult), vp, vp, vp]
+                                         ctypes.c_int, u32, vp, ctypes.POINTER(PchaseResult), vp, vp, vp, vp]
         L.microbench_pchase.argtypes = [ctypes.POINTER(PchaseProbe), u32, vp, u64, u64, vp, vp, vp, vp]
         L.pchase_microbench_max_k.restype = u64
         L.microbench_hbm_stream.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp, vp]
@@ -136,6 +139,32 @@ def _stream(stream=None):
         return vp(stream)
     import torch
     return vp(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A caller-owned plan (pchase_plan_create / pchase_plan_destroy):
+    device_bytes of workspace reserved once; the replay and inference calls
+    given it allocate no device memory."""
+
+    def __init__(self, device_bytes: int):
+        h = vp()
+        check(lib().pchase_plan_create(device_bytes, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().pchase_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _plan(plan):
+    return plan.handle if plan is not None else None
 
 
 def _dptr(t):
@@ -248,7 +277,7 @@ def pchase_trace_nu(probe_arr, seg_arr, idx, stream=None) -> np.ndarray:
 
 
 def cache_replay_batch(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
-                       misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None):
+                       misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None, plan=None):
     toff, p_toff = _hptr(trace_off, np.uint64)
     tb, p_tb = _hptr(trace_base, np.uint64)
     pm, p_pm = _hptr(pair_model, np.uint32)
@@ -257,7 +286,7 @@ def cache_replay_batch(model_arr, idx, trace_off, trace_base, pair_model, pair_t
     bo, p_bo = _hptr(bitoff, np.uint64)
     check(lib().cache_replay_batch(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
                                    len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
-                                   p_bo, mode, _stream(stream)))
+                                   p_bo, mode, _plan(plan), _stream(stream)))
 
 
 def cache_replay_batch_static(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
@@ -295,7 +324,7 @@ def general_models(rows) -> ctypes.Array:
 
 
 def cache_replay_general(model_arr, idx, trace_off, trace_base, pair_model, pair_trace, count_from,
-                         misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None):
+                         misses, hitbits=None, bitoff=None, mode=BATCHED, stream=None, plan=None):
     toff, p_toff = _hptr(trace_off, np.uint64)
     tb, p_tb = _hptr(trace_base, np.uint64)
     pm, p_pm = _hptr(pair_model, np.uint32)
@@ -304,23 +333,23 @@ def cache_replay_general(model_arr, idx, trace_off, trace_base, pair_model, pair
     bo, p_bo = _hptr(bitoff, np.uint64)
     check(lib().cache_replay_general(ctypes.cast(model_arr, vp), model_arr.n, _dptr(idx), p_toff, p_tb, 4,
                                      len(toff) - 1, p_pm, p_pt, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
-                                     p_bo, mode, _stream(stream)))
+                                     p_bo, mode, _plan(plan), _stream(stream)))
 
 
 def cache_replay_probes(model_arr, probe_arr, pair_model, pair_probe, count_from, misses, hitbits=None,
-                        bitoff=None, mode=BATCHED, stream=None):
+                        bitoff=None, mode=BATCHED, stream=None, plan=None):
     pm, p_pm = _hptr(pair_model, np.uint32)
     pp, p_pp = _hptr(pair_probe, np.uint32)
     cf, p_cf = _hptr(count_from, np.uint64)
     bo, p_bo = _hptr(bitoff, np.uint64)
     check(lib().cache_replay_probes(ctypes.cast(model_arr, vp), model_arr.n, ctypes.cast(probe_arr, vp),
                                     probe_arr.n, p_pm, p_pp, p_cf, len(pm), _dptr(misses), _dptr(hitbits),
-                                    p_bo, mode, _stream(stream)))
+                                    p_bo, mode, _plan(plan), _stream(stream)))
 
 
 def infer_cache_params(probe_arr, cand_arr, bits=None, bitoff=None, lat=None, lat_off=None,
                        threshold=U32_MAX, count_from=None, probe_select=PROBES_OWN_SWEEP,
-                       mode=EXHAUSTIVE, topk=8, net=None, mn=None, want_zero=False, stream=None):
+                       mode=EXHAUSTIVE, topk=8, net=None, mn=None, want_zero=False, stream=None, plan=None):
     """Returns (PchaseResult, zero-class bitmap as uint32 array or None)."""
     bo, p_bo = _hptr(bitoff, np.uint64)
     lo, p_lo = _hptr(lat_off, np.uint64)
@@ -332,7 +361,7 @@ def infer_cache_params(probe_arr, cand_arr, bits=None, bitoff=None, lat=None, la
     check(lib().infer_cache_params(ctypes.byref(obs), ctypes.cast(cand_arr, vp), cand_arr.n, probe_select,
                                    mode, topk, net.handle if net is not None else None, ctypes.byref(res), _dptr(mn),
                                    zero.ctypes.data_as(vp) if zero is not None else None,
-                                   _stream(stream)))
+                                   _plan(plan), _stream(stream)))
     return res, zero
 
 

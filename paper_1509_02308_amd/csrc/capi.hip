@@ -11,6 +11,15 @@ namespace pc {
 
 
 
+// A workspace buffer could not grow: the plan's memory is used up (ERANGE),
+// or a device allocation failed (ENOMEM).
+static int buf_fail(const Workspace* ws, hipError_t e, const char* what) {
+    if (ws->arena)
+        return set_error(PCHASE_ERANGE, "%s does not fit the plan's %llu bytes of device memory", what,
+                         (unsigned long long)ws->arena->cap);
+    return set_error(PCHASE_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+}
+
 static int validate_models(const pchase_model* models, uint32_t n, std::vector<DevModel>* out) {
     if (n && !models) return set_error(PCHASE_EINVAL, "models is NULL");
     out->resize(n);
@@ -51,12 +60,13 @@ int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vecto
         if (j.model >= dm.size() || j.probe >= dp.size() || j.bitoff + (len[j.probe] + 31) / 32 > bits_words)
             return set_error(PCHASE_EINVAL, "internal replay job outside its model, probe or bitmap bounds");
     hipError_t e = ws->aux.ensure(jobs.size() * 16);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "replay counters: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return buf_fail(ws, e, "replay counters");
     SweepPlan plan;
+    plan.dev.arena = ws->arena;
     int rc = build_sweep_plan(&plan, dm, dp, len, jobs, true);
     if (rc) return rc;
     rc = run_sweep_plan(ws, &plan, false, ws->aux.as<uint64_t>(), 2 * jobs.size(), bits, true, PCHASE_BATCHED,
-                        stream, {}, "");
+                        stream, {}, "", false, ws->arena == nullptr);
     if (rc) return rc;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;
@@ -220,7 +230,7 @@ extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models
                                    uint32_t n_probes, const uint32_t* pair_model, const uint32_t* pair_probe,
                                    const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
                                    uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode,
-                                   hipStream_t stream) {
+                                   pchase_plan* pplan, hipStream_t stream) {
     if (mode > PCHASE_PLAIN) return set_error(PCHASE_EINVAL, "unknown mode %u", mode);
     std::vector<DevModel> dm;
     std::vector<DevProbe> dp;
@@ -255,13 +265,15 @@ extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models
     }
     Workspace* ws;
     std::unique_lock<std::mutex> lk;
-    rc = workspace(&ws, &lk);
+    rc = workspace_for(pplan, &ws, &lk);
     if (rc) return rc;
+    ws->reset_arena();
     SweepPlan plan;
+    plan.dev.arena = ws->arena;
     rc = build_sweep_plan(&plan, dm, dp, len, jobs, hitbits_dev != nullptr);
     if (rc) return rc;
     rc = run_sweep_plan(ws, &plan, false, misses_dev, 2 * n_pairs, hitbits_dev, hitbits_dev != nullptr, mode,
-                        stream, {}, "");
+                        stream, {}, "", false, ws->arena == nullptr);
     if (rc) return rc;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;
@@ -354,21 +366,22 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
                                const int32_t* idx_dev, const uint64_t* trace_off, const uint64_t* trace_base,
                                uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
                                const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
-                               uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, hipStream_t stream);
+                               uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, pchase_plan* plan,
+                               hipStream_t stream);
 
 extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models, const int32_t* idx_dev,
                                   const uint64_t* trace_off, const uint64_t* trace_base, uint32_t elem_bytes,
                                   uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
                                   const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
                                   uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode,
-                                  hipStream_t stream) {
+                                  pchase_plan* plan, hipStream_t stream) {
     if (mode > PCHASE_PLAIN) return set_error(PCHASE_EINVAL, "unknown mode %u", mode);
     if (elem_bytes != 4) return set_error(PCHASE_EINVAL, "elem_bytes must be 4");
     std::vector<DevModel> dm;
     int rc = validate_models(models, n_models, &dm);
     if (rc) return rc;
     return replay_materialised(dm, nullptr, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model,
-                               pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
+                               pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, plan, stream);
 }
 
 extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t n_models, const int32_t* idx_dev,
@@ -376,7 +389,7 @@ extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t
                                     uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
                                     const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
                                     uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode,
-                                    hipStream_t stream) {
+                                    pchase_plan* plan, hipStream_t stream) {
     if (mode > PCHASE_PLAIN) return set_error(PCHASE_EINVAL, "unknown mode %u", mode);
     if (elem_bytes != 4) return set_error(PCHASE_EINVAL, "elem_bytes must be 4");
     std::vector<DevModel> dm;
@@ -384,7 +397,7 @@ extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t
     int rc = build_general(models, n_models, &dm, &gd);
     if (rc) return rc;
     return replay_materialised(dm, &gd, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model,
-                               pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
+                               pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, plan, stream);
 }
 
 // Standard models: the set-partitioned tile replay.  Every pair becomes
@@ -609,18 +622,19 @@ static int replay_tiles(const std::vector<DevModel>& dm, uint32_t n_models, cons
                         const uint64_t* trace_off, const uint64_t* trace_base, uint32_t n_traces,
                         const uint32_t* pair_model, const uint32_t* pair_trace, const uint64_t* count_from,
                         uint64_t n_pairs, uint64_t* misses_dev, uint32_t* hitbits_dev, const uint64_t* bitoff,
-                        uint32_t mode, hipStream_t stream) {
+                        uint32_t mode, pchase_plan* plan, hipStream_t stream) {
     TileSchedule ts;
     int rc = build_tile_schedule(dm, n_models, trace_off, trace_base, n_traces, pair_model, pair_trace, count_from,
                                  n_pairs, hitbits_dev != nullptr, bitoff, &ts);
     if (rc) return rc;
     Workspace* ws;
     std::unique_lock<std::mutex> lk;
-    rc = workspace(&ws, &lk);
+    rc = workspace_for(plan, &ws, &lk);
     if (rc) return rc;
+    ws->reset_arena();
     const TileScratch SL = tile_scratch_layout(dm.size(), ts);
     hipError_t e = ws->stage.ensure(SL.total);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return buf_fail(ws, e, "the replay's descriptors");
     if (!ws->tile_ready) {
         PC_HIP(tile_prepare_lds());
         ws->tile_ready = true;
@@ -710,7 +724,8 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
                                const int32_t* idx_dev, const uint64_t* trace_off, const uint64_t* trace_base,
                                uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
                                const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
-                               uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, hipStream_t stream) {
+                               uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, pchase_plan* plan,
+                               hipStream_t stream) {
     int rc = PCHASE_OK;
     if (n_pairs == 0) return PCHASE_OK;
     if (!trace_off || !pair_model || !pair_trace) return set_error(PCHASE_EINVAL, "trace or pair arrays are NULL");
@@ -725,7 +740,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
     if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
     if (!gd)
         return replay_tiles(dm, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model, pair_trace, count_from,
-                            n_pairs, misses_dev, hitbits_dev, bitoff, mode, stream);
+                            n_pairs, misses_dev, hitbits_dev, bitoff, mode, plan, stream);
 
     // generalised models: bucket pairs by (policy, group width), longest first inside a bucket;
     // a pair that is long, or whose state is large, is split by set into
@@ -810,8 +825,9 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
 
     Workspace* ws;
     std::unique_lock<std::mutex> lk;
-    rc = workspace(&ws, &lk);
+    rc = workspace_for(plan, &ws, &lk);
     if (rc) return rc;
+    ws->reset_arena();
     // descriptors
     const size_t o_models = 0;
     const size_t o_pairs = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
@@ -826,14 +842,11 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
         total = o_cum + (gd->cum.size() * sizeof(uint32_t) + 255) / 256 * 256 + 256;
     }
     hipError_t e = ws->stage.ensure(total);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "staging: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return buf_fail(ws, e, "the replay's descriptors");
     uint8_t* sb = ws->stage.as<uint8_t>();
     DevModel* d_models = reinterpret_cast<DevModel*>(sb + o_models);
     StreamPair* d_pairs = reinterpret_cast<StreamPair*>(sb + o_pairs);
     uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + o_status);
-    PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
-    PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(StreamPair), hipMemcpyHostToDevice, stream));
-    PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
     const DevGeneral* d_gen = nullptr;
     const uint2* d_info = nullptr;
     const uint32_t *d_table = nullptr, *d_cum = nullptr;
@@ -842,35 +855,20 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
         d_info = reinterpret_cast<const uint2*>(sb + o_info);
         d_table = reinterpret_cast<const uint32_t*>(sb + o_table);
         d_cum = reinterpret_cast<const uint32_t*>(sb + o_cum);
-        PC_HIP(hipMemcpyAsync(sb + o_gen, gd->gen.data(), gd->gen.size() * sizeof(DevGeneral), hipMemcpyHostToDevice,
-                              stream));
-        PC_HIP(hipMemcpyAsync(sb + o_info, gd->set_info.data(), gd->set_info.size() * sizeof(uint2),
-                              hipMemcpyHostToDevice, stream));
-        if (!gd->table.empty())
-            PC_HIP(hipMemcpyAsync(sb + o_table, gd->table.data(), gd->table.size() * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, stream));
-        if (!gd->cum.empty())
-            PC_HIP(hipMemcpyAsync(sb + o_cum, gd->cum.data(), gd->cum.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                                  stream));
-    }
-    if (!zero_cnt.empty()) {
-        // split pairs merge into their outputs: zero those first
-        uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + o_zero);
-        uint64_t* d_zb = d_zc + zero_cnt.size();
-        PC_HIP(hipMemcpyAsync(d_zc, zero_cnt.data(), zero_cnt.size() * 8, hipMemcpyHostToDevice, stream));
-        PC_HIP(launch_clear_ranges(reinterpret_cast<uint32_t*>(misses_dev), d_zc, (uint32_t)(zero_cnt.size() / 2),
-                                   stream));
-        if (!zero_bits.empty()) {
-            PC_HIP(hipMemcpyAsync(d_zb, zero_bits.data(), zero_bits.size() * 8, hipMemcpyHostToDevice, stream));
-            PC_HIP(launch_clear_ranges(hitbits_dev, d_zb, (uint32_t)(zero_bits.size() / 2), stream));
-        }
     }
 
     // state slabs: one per resident group, sized per bucket; the pool may
     // take half of the free device memory (at least 4 GiB, at most 64 GiB)
+    // (with a plan: what the plan's memory has left)
     size_t mem_free = 0, mem_total = 0;
-    PC_HIP(hipMemGetInfo(&mem_free, &mem_total));
-    const uint64_t pool_cap = std::max<uint64_t>(4ull << 30, std::min<uint64_t>((mem_free + ws->slab.cap) / 2, 64ull << 30));
+    uint64_t pool_cap;
+    if (ws->arena) {
+        const size_t at = (ws->arena->used + 255) / 256 * 256;
+        pool_cap = at < ws->arena->cap ? ws->arena->cap - at : 0;
+    } else {
+        PC_HIP(hipMemGetInfo(&mem_free, &mem_total));
+        pool_cap = std::max<uint64_t>(4ull << 30, std::min<uint64_t>((mem_free + ws->slab.cap) / 2, 64ull << 30));
+    }
     for (const auto& kv : bucket_state)
         if ((kv.second + 255) / 256 * 256 > pool_cap)
             return set_error(PCHASE_ERANGE, "model state of %llu bytes exceeds the slab pool",
@@ -946,13 +944,39 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
     }
     if (pool > ws->slab.cap) {
         e = ws->slab.ensure(pool);
-        if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "slab pool of %llu bytes: %s", (unsigned long long)pool,
-                                              hipGetErrorString(e));
+        if (e != hipSuccess) return buf_fail(ws, e, "the replay state slabs");
         ws->slab_clean = 0;
     }
     if (ws->slab_clean < ws->slab.cap) {
         PC_HIP(launch_fill_u32(ws->slab.as<uint32_t>(), ws->slab.cap / 4, 0, stream));
         ws->slab_clean = ws->slab.cap;
+    }
+    // descriptors up, and (split pairs merge into their outputs) those zeroed
+    PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(StreamPair), hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
+    if (gd) {
+        PC_HIP(hipMemcpyAsync(sb + o_gen, gd->gen.data(), gd->gen.size() * sizeof(DevGeneral), hipMemcpyHostToDevice,
+                              stream));
+        PC_HIP(hipMemcpyAsync(sb + o_info, gd->set_info.data(), gd->set_info.size() * sizeof(uint2),
+                              hipMemcpyHostToDevice, stream));
+        if (!gd->table.empty())
+            PC_HIP(hipMemcpyAsync(sb + o_table, gd->table.data(), gd->table.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, stream));
+        if (!gd->cum.empty())
+            PC_HIP(hipMemcpyAsync(sb + o_cum, gd->cum.data(), gd->cum.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                  stream));
+    }
+    if (!zero_cnt.empty()) {
+        uint64_t* d_zc = reinterpret_cast<uint64_t*>(sb + o_zero);
+        uint64_t* d_zb = d_zc + zero_cnt.size();
+        PC_HIP(hipMemcpyAsync(d_zc, zero_cnt.data(), zero_cnt.size() * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(launch_clear_ranges(reinterpret_cast<uint32_t*>(misses_dev), d_zc, (uint32_t)(zero_cnt.size() / 2),
+                                   stream));
+        if (!zero_bits.empty()) {
+            PC_HIP(hipMemcpyAsync(d_zb, zero_bits.data(), zero_bits.size() * 8, hipMemcpyHostToDevice, stream));
+            PC_HIP(launch_clear_ranges(hitbits_dev, d_zb, (uint32_t)(zero_bits.size() / 2), stream));
+        }
     }
     // longest buckets first; concurrently onto the least-loaded stream
     std::vector<size_t> order(launches.size());
@@ -1008,12 +1032,14 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
 }
 
 // ----------------------------------------------------------- inference ---
-static int build_infer_plan(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
-                            const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
+static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const pchase_model* cands,
+                            uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
                             const std::vector<uint64_t>& len, const std::vector<uint64_t>& cf,
                             const std::vector<uint64_t>& bitoff, int probe_select,
                             const std::vector<uint8_t>* allow, std::unique_ptr<InferPlan>* out) {
     std::unique_ptr<InferPlan> np(new InferPlan());
+    np->dev.arena = ws->arena;
+    np->sweep.dev.arena = ws->arena;
     np->n_cands = n_cands;
     np->n_host.assign(n_cands, 0);
     std::vector<SweepJob> jobs;
@@ -1037,7 +1063,7 @@ static int build_infer_plan(const pchase_observation* obs, const pchase_model* c
     const size_t zw = (n_cands + 31) / 32;
     const size_t bytes = 2 * n_cands * sizeof(uint64_t) + zw * 4 + 256 + sizeof(ArgminOut);
     hipError_t e = np->dev.ensure(bytes);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "inference plan: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
     uint8_t* b = np->dev.as<uint8_t>();
     np->d_m = reinterpret_cast<uint64_t*>(b);
     np->d_n = np->d_m + n_cands;
@@ -1090,7 +1116,7 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
     InferPlan* ip;
     std::unique_ptr<InferPlan> once;
     if (!cache) {
-        int rc = build_infer_plan(obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &once);
+        int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &once);
         if (rc) return rc;
         ip = once.get();
     } else {
@@ -1099,7 +1125,7 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
         auto it = ws->plans.find(key);
         if (it == ws->plans.end() || it->second->key != blob) {
             std::unique_ptr<InferPlan> np;
-            int rc = build_infer_plan(obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &np);
+            int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &np);
             if (rc) return rc;
             np->key = std::move(blob);
             np->cached = true;
@@ -1124,7 +1150,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,
-                            sched, stream, tail, "argmin", ip->cached && tune);
+                            sched, stream, tail, "argmin", ip->cached && tune, ws->arena == nullptr);
     if (rc) return rc;
     ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
     PC_HIP(hipMemcpyAsync(hr, ip->d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));
@@ -1150,7 +1176,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
 
 extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
                                   int probe_select, int mode, uint32_t topk, const pchase_mlp* net,
-                                  pchase_result* out, uint64_t* mn_dev, uint32_t* zero_host,
+                                  pchase_result* out, uint64_t* mn_dev, uint32_t* zero_host, pchase_plan* plan,
                                   hipStream_t stream) {
     if (!obs || !out) return set_error(PCHASE_EINVAL, "obs and out must not be NULL");
     if (probe_select != PCHASE_PROBES_ALL && probe_select != PCHASE_PROBES_OWN_SWEEP)
@@ -1167,7 +1193,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         // so validated, for exactly these inputs) runs without re-validation
         Workspace* ws;
         std::unique_lock<std::mutex> lk;
-        int rc = workspace(&ws, &lk);
+        int rc = workspace_for(plan, &ws, &lk);
         if (rc) return rc;
         const std::string blob = infer_key(obs, cands, n_cands, probe_select, obs->bitoff, nullptr);
         auto it = ws->plans.find(digest_of(blob));
@@ -1211,8 +1237,9 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     }
     Workspace* ws;
     std::unique_lock<std::mutex> lk;
-    rc = workspace(&ws, &lk);
+    rc = workspace_for(plan, &ws, &lk);
     if (rc) return rc;
+    ws->reset_arena();   // a plan serves one inference problem at a time
     const uint32_t* bits = obs->bits_dev;
     out->threshold_used = 0xFFFFFFFFu;
     if (have_lat) {
@@ -1225,7 +1252,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         const uint64_t present_words = (1ull << 26) / 32;
         size_t total = o_present + (obs->threshold == 0xFFFFFFFFu ? present_words * 4 : 0);
         hipError_t e = ws->obs.ensure(total);
-        if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "observation scratch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return buf_fail(ws, e, "the observed bits");
         uint8_t* b = ws->obs.as<uint8_t>();
         uint32_t* d_bits = reinterpret_cast<uint32_t*>(b + o_bits);
         uint64_t* d_latoff = reinterpret_cast<uint64_t*>(b + o_off);

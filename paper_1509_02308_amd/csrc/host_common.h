@@ -17,10 +17,22 @@ int check_model(const pchase_model& m, DevModel* d, uint64_t index);
 int check_probe(const pchase_probe& p, DevProbe* d, uint64_t* len, uint64_t index);
 
 // ----------------------------------------------------------- workspace ---
-// Growable device buffer.
+// Device memory reserved once (by a caller-owned pchase_plan): buffers are
+// carved from it front to back and never freed one by one; reset() makes
+// the whole of it available again.
+struct Arena {
+    uint8_t* base = nullptr;
+    size_t cap = 0, used = 0;
+    void reset() { used = 0; }
+};
+
+// Growable device buffer: its own hipMalloc, or a block carved from an
+// arena (then ensure() fails with hipErrorOutOfMemory instead of
+// allocating when the arena is used up).
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    Arena* arena = nullptr;
     hipError_t ensure(size_t n);
     void release();
     template <class T>
@@ -58,11 +70,21 @@ struct Workspace {
     // probe planner: class matrix of the last (candidates, pool) pair
     DevBuf planner;
     std::string planner_key;
+    // set for the workspace of a caller-owned plan: every device buffer
+    // comes from this arena, and nothing is captured into graphs
+    Arena* arena = nullptr;
+    // forgets every buffer, cached schedule and graph carved from the arena
+    void reset_arena();
     ~Workspace();
 };
 
 // Locks and returns the calling thread's current device's workspace.
 int workspace(Workspace** ws, std::unique_lock<std::mutex>* lock);
+// The plan's workspace when plan is not NULL (checked against the current
+// device), else the device's own.
+int workspace_for(pchase_plan* plan, Workspace** ws, std::unique_lock<std::mutex>* lock);
+// Creates the streams, events and pinned result page of a workspace.
+int workspace_init(Workspace* ws);
 const volatile uint32_t* abort_flag_dev();
 uint32_t abort_flag_host();
 

@@ -770,7 +770,10 @@ int infer_learned(Workspace* ws, const pchase_observation* obs, const pchase_mod
     // features of the observation, then the forward pass
     const size_t need = kIn * 8 + kIn * 4 + 256 + kIn * 4;
     hipError_t e = ws->aux.ensure(need);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "learned scratch: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        if (ws->arena) return set_error(PCHASE_ERANGE, "the learned proposal's scratch does not fit the plan's memory");
+        return set_error(PCHASE_ENOMEM, "learned scratch: %s", hipGetErrorString(e));
+    }
     uint64_t* d_pbit = ws->aux.as<uint64_t>();
     uint32_t* d_L = reinterpret_cast<uint32_t*>(d_pbit + kIn);
     float* d_x = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(d_L) + kIn * 4 + 256);

@@ -56,10 +56,12 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models,
 // enqueued after the replay, inside the same graph.
 // With autotune (plans that are cached and run again), the first batched
 // run captures every branch strategy, times each and keeps the fastest.
+// use_graph = false (the workspace of a caller-owned plan) launches the
+// batched sequence directly, nothing captured.
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
                    const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key,
-                   bool autotune = false);
+                   bool autotune = false, bool use_graph = true);
 
 // Cached schedule + score buffers of one inference problem.
 struct InferPlan {

@@ -223,7 +223,11 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     const size_t o_queues = off; off = align_up(off + (plan->batched.size() + 2) * sizeof(uint32_t), 256);
     const size_t o_clear = off; off = align_up(off + plan->clear.size() * sizeof(uint64_t), 256);
     hipError_t e = plan->dev.ensure(off);
-    if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "plan allocation of %zu bytes: %s", off, hipGetErrorString(e));
+    if (e != hipSuccess) {
+        if (plan->dev.arena)
+            return set_error(PCHASE_ERANGE, "a replay schedule of %zu bytes does not fit the plan's device memory", off);
+        return set_error(PCHASE_ENOMEM, "schedule allocation of %zu bytes: %s", off, hipGetErrorString(e));
+    }
     uint8_t* base = plan->dev.as<uint8_t>();
     plan->d_models = reinterpret_cast<DevModel*>(base + o_models);
     plan->d_probes = reinterpret_cast<DevProbe*>(base + o_probes);
@@ -263,6 +267,8 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
     PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
     if (clear_bits && bits)
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
+    uint32_t* snap = plan->d_queues + plan->batched.size() + 1;
+    PC_HIP(launch_snapshot_u32(abort_flag_dev(), snap, s));
     const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
     const int nb = (int)std::min<size_t>(want, plan->batched.size());
     if (nb > 1) {
@@ -302,6 +308,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         a.counters = counters;
         a.bits = bits;
         a.abort_flag = abort_flag_dev();
+        a.abort_snap = snap;
         a.aborted = plan->d_queues + plan->batched.size();
         a.lds_rows = bk.lds_rows;
         a.map_rows = bk.map_rows;
@@ -329,7 +336,8 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
 
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
-                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key, bool autotune) {
+                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key, bool autotune,
+                   bool use_graph) {
     if (mode == PCHASE_PLAIN) {
         const uint32_t nq = (uint32_t)plan->batched.size() + 2;
         PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, stream));
@@ -349,6 +357,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             a.counters = counters;
             a.bits = bits;
             a.abort_flag = nullptr;
+            a.abort_snap = nullptr;
             a.aborted = nullptr;
             a.lds_rows = bk.lds_rows;
             a.map_rows = bk.map_rows;
@@ -363,6 +372,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
         return PCHASE_OK;
     }
 
+    if (!use_graph) return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail);
     // batched: capture once per (outputs, tail) and replay the graph; with
     // autotune, every branch strategy is captured and timed and the fastest
     // graph is kept

@@ -105,6 +105,18 @@ int check_probe(const pchase_probe& p, DevProbe* d, uint64_t* len, uint64_t i) {
 // ------------------------------------------------------------ workspace --
 hipError_t DevBuf::ensure(size_t n) {
     if (n <= cap) return hipSuccess;
+    if (arena) {
+        const size_t at = (arena->used + 255) / 256 * 256;
+        if (at > arena->cap || n > arena->cap - at) {
+            p = nullptr;
+            cap = 0;
+            return hipErrorOutOfMemory;
+        }
+        p = arena->base + at;
+        cap = n;
+        arena->used = at + n;
+        return hipSuccess;
+    }
     size_t want = cap ? cap : 1 << 20;
     while (want < n) want *= 2;
     if (p) {
@@ -123,9 +135,18 @@ hipError_t DevBuf::ensure(size_t n) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && !arena) (void)hipFree(p);
     p = nullptr;
     cap = 0;
+}
+
+void Workspace::reset_arena() {
+    if (!arena) return;
+    plans.clear();
+    planner_key.clear();
+    for (DevBuf* b : {&stage, &aux, &obs, &slab, &mlp, &planner}) b->release();
+    slab_clean = 0;
+    arena->reset();
 }
 
 Workspace::~Workspace() {
@@ -173,6 +194,14 @@ int workspace(Workspace** out, std::unique_lock<std::mutex>* lock) {
         ws = slot.get();
     }
     *lock = std::unique_lock<std::mutex>(ws->mu);
+    int rc = workspace_init(ws);
+    if (rc) return rc;
+    *out = ws;
+    return PCHASE_OK;
+}
+
+int workspace_init(Workspace* ws) {
+    hipError_t e;
     if (!ws->host_res) {
         e = hipHostMalloc(&ws->host_res, 4096, hipHostMallocDefault);
         if (e != hipSuccess) {
@@ -202,7 +231,6 @@ int workspace(Workspace** out, std::unique_lock<std::mutex>* lock) {
         if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
         ws->lds_ready = true;
     }
-    *out = ws;
     return PCHASE_OK;
 }
 
@@ -228,6 +256,79 @@ const volatile uint32_t* abort_flag_dev() {
 uint32_t abort_flag_host() { return g_abort_host ? *g_abort_host : 0; }
 
 }  // namespace pc
+
+// A caller-owned plan: its own workspace over one device allocation.
+struct pchase_plan {
+    int device = -1;
+    void* mem = nullptr;
+    pc::Arena arena;
+    pc::Workspace ws;
+};
+
+namespace pc {
+
+int workspace_for(pchase_plan* plan, Workspace** out, std::unique_lock<std::mutex>* lock) {
+    if (!plan) return workspace(out, lock);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(PCHASE_ENODEV, "no HIP device: %s", hipGetErrorString(e));
+    if (dev != plan->device)
+        return set_error(PCHASE_EINVAL, "the plan belongs to device %d, the current device is %d", plan->device, dev);
+    *lock = std::unique_lock<std::mutex>(plan->ws.mu);
+    *out = &plan->ws;
+    return PCHASE_OK;
+}
+
+}  // namespace pc
+
+extern "C" int pchase_plan_create(uint64_t device_bytes, pchase_plan** out) {
+    using namespace pc;
+    if (!out) return set_error(PCHASE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (device_bytes == 0) return set_error(PCHASE_EINVAL, "a plan needs device memory (device_bytes = 0)");
+    Workspace* dws;
+    std::unique_lock<std::mutex> lk;
+    int rc = workspace(&dws, &lk);   // checks the device, creates the shared abort flag
+    if (rc) return rc;
+    const int dev = dws->device, cus = dws->cus;
+    lk.unlock();
+    std::unique_ptr<pchase_plan> p(new pchase_plan());
+    p->device = dev;
+    hipError_t e = hipMalloc(&p->mem, device_bytes);
+    if (e != hipSuccess) {
+        p->mem = nullptr;
+        return set_error(PCHASE_ENOMEM, "plan memory of %llu bytes: %s", (unsigned long long)device_bytes,
+                         hipGetErrorString(e));
+    }
+    p->arena.base = static_cast<uint8_t*>(p->mem);
+    p->arena.cap = device_bytes;
+    p->ws.device = dev;
+    p->ws.cus = cus;
+    p->ws.arena = &p->arena;
+    for (DevBuf* b : {&p->ws.stage, &p->ws.aux, &p->ws.obs, &p->ws.slab, &p->ws.mlp, &p->ws.planner})
+        b->arena = &p->arena;
+    rc = workspace_init(&p->ws);
+    if (rc) {
+        pchase_plan_destroy(p.release());
+        return rc;
+    }
+    *out = p.release();
+    return PCHASE_OK;
+}
+
+extern "C" void pchase_plan_destroy(pchase_plan* plan) {
+    if (!plan) return;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    const int dev = plan->device;
+    if (have && cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    plan->ws.reset_arena();
+    void* mem = plan->mem;
+    delete plan;   // the workspace's streams, events and pinned page
+    if (mem) (void)hipFree(mem);
+    if (have && cur != dev) (void)hipSetDevice(cur);
+}
 
 // ------------------------------------------------------------- C ABI ----
 extern "C" const char* pchase_last_error(void) { return pc::g_last_error.c_str(); }

@@ -86,7 +86,7 @@ def test_model_validation_before_launch(capi, row, code):
     pm = (ctypes.c_uint32 * 1)(0)
     pp = (ctypes.c_uint32 * 1)(0)
     rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
-                                        pm, pp, None, 1, ctypes.c_void_p(16), None, None, 0, None)
+                                        pm, pp, None, 1, ctypes.c_void_p(16), None, None, 0, None, None)
     assert rc == code, capi.last_error()
 
 
@@ -96,13 +96,13 @@ def test_pair_index_validation(capi):
     pm = (ctypes.c_uint32 * 1)(1)                       # model index out of range
     pp = (ctypes.c_uint32 * 1)(0)
     rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
-                                        pm, pp, None, 1, ctypes.c_void_p(16), None, None, 0, None)
+                                        pm, pp, None, 1, ctypes.c_void_p(16), None, None, 0, None, None)
     assert rc == -1 and "out of range" in capi.last_error()
     rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
-                                        pp, pp, None, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0, None)
+                                        pp, pp, None, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0, None, None)
     assert rc == -1 and "bitoff" in capi.last_error()
     rc = capi.lib().cache_replay_probes(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.cast(p, ctypes.c_void_p), 1,
-                                        pp, pp, None, 1, ctypes.c_void_p(16), None, None, 7, None)
+                                        pp, pp, None, 1, ctypes.c_void_p(16), None, None, 7, None, None)
     assert rc == -1 and "mode" in capi.last_error()
 
 
@@ -122,14 +122,14 @@ def test_infer_argument_checks(capi):
     L = capi.lib()
     # neither bits nor latencies
     rc = L.infer_cache_params(ctypes.byref(obs), ctypes.cast(cands, ctypes.c_void_p), 1, 1, 0, 8, None,
-                              ctypes.byref(res), None, None, None)
+                              ctypes.byref(res), None, None, None, None)
     assert rc == -1 and "exactly one" in capi.last_error()
     # learned without a network
     rc = L.infer_cache_params(ctypes.byref(obs), ctypes.cast(cands, ctypes.c_void_p), 1, 1, 1, 8, None,
-                              ctypes.byref(res), None, None, None)
+                              ctypes.byref(res), None, None, None, None)
     assert rc == -1
     rc = L.infer_cache_params(ctypes.byref(obs), ctypes.cast(cands, ctypes.c_void_p), 0, 1, 0, 8, None,
-                              ctypes.byref(res), None, None, None)
+                              ctypes.byref(res), None, None, None, None)
     assert rc == -1 and "candidates" in capi.last_error()
 
 
@@ -202,7 +202,7 @@ def test_general_model_validation_before_launch(capi):
     for d in bad:
         m = capi.general_models([d])
         rc = capi.lib().cache_replay_general(ctypes.cast(m, ctypes.c_void_p), 1, ctypes.c_void_p(16), off, None, 4,
-                                             1, pm, pt, None, 1, ctypes.c_void_p(16), None, None, 0, None)
+                                             1, pm, pt, None, 1, ctypes.c_void_p(16), None, None, 0, None, None)
         assert rc == -1, d
 
 
@@ -249,3 +249,16 @@ def test_static_replay_argument_checks(capi):
     assert L.cache_replay_batch_static(*args(4)) == -1      # misses_dev is NULL
     bad = capi.models([(8192, 32, 3, 0)])                  # T*a*b != C
     assert L.cache_replay_batch_static(ctypes.cast(bad, ctypes.c_void_p), *args(4)[1:]) == -1
+
+
+def test_plan_lifetime_without_device(capi):
+    """Plans are created only on a usable device: here (no GPU) creation fails
+    with ENODEV and leaves the handle NULL; a NULL out pointer or an empty
+    reservation is EINVAL; destroying NULL is a no-op."""
+    L = capi.lib()
+    h = ctypes.c_void_p(1234)
+    assert L.pchase_plan_create(1 << 20, ctypes.byref(h)) == -6
+    assert not h.value
+    assert L.pchase_plan_create(1 << 20, None) == -1
+    assert L.pchase_plan_create(0, ctypes.byref(h)) == -1
+    L.pchase_plan_destroy(None)
