@@ -391,9 +391,11 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             int rc = PCHASE_OK;
-            if (e == hipSuccess)
+            hipError_t e2 = hipSuccess;
+            if (e == hipSuccess) {   // a capture that did not begin is not ended
                 rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, cs, tail, strategy);
-            hipError_t e2 = hipStreamEndCapture(cs, &g);
+                e2 = hipStreamEndCapture(cs, &g);
+            }
             (void)hipStreamDestroy(cs);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
             if (rc) {

@@ -1,7 +1,11 @@
+import faulthandler
 import os
 import sys
 
 import pytest
+
+# a fault inside a native call prints the Python stack of every thread
+faulthandler.enable()
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
