@@ -391,14 +391,39 @@ int infer_cache_params(const pchase_observation *obs, const pchase_model *cands,
                        const pchase_mlp *net, pchase_result *out, uint64_t *mn_dev,
                        uint32_t *zero_host, pchase_plan *plan, hipStream_t stream);
 
+/* Exhaustive inference over generalised candidates (Sections 4.3-4.5: per-
+ * set associativity, set tables, shifted set mappings, weighted random
+ * replacement; pchase_general_model above).  The observation is given as
+ * for infer_cache_params (hit bits, or latencies with a threshold or the
+ * widest-gap rule); every candidate replays every observed probe
+ * (PCHASE_PROBES_ALL), the trace id of probe p being p.  m, n, best (exact
+ * rational argmin of m/n, lowest index on ties), the zero class, mn_dev
+ * (device, uint64 [2 * n_cands], (m, n) per candidate) and zero_host (at
+ * most 30,720 candidates) are as for infer_cache_params; best_m/best_n
+ * refer to best.  The probes' traces (4 bytes per access) and every
+ * candidate's hit bits (one bit per access and probe) are held in device
+ * memory during the call: ERANGE beyond 2^34 accesses or 32 GiB of hit
+ * bits, or (with a plan) when they do not fit the plan's memory.  A
+ * candidate's replay state is as for cache_replay_general.  Synchronises
+ * `stream`. */
+int infer_cache_params_general(const pchase_observation *obs, const pchase_general_model *cands,
+                               uint32_t n_cands, pchase_result *out, uint64_t *mn_dev,
+                               uint32_t *zero_host, pchase_plan *plan, hipStream_t stream);
+
 /* ---------------------------------------------------- microbenchmarks --- */
-/* Load flavours of the single-lane chase: which cache level a load may be
- * served from (gfx950 cache-policy bits of the load instruction). */
+/* Load flavours of the single-lane chase: the gfx950 cache-policy bits of
+ * the load instruction.  What each does on MI355X was measured with this
+ * chase (latency over sizes and strides): the default and the work-group
+ * scope loads may hit the per-CU vector L1 (about 100 cycles); system
+ * scope and non-temporal loads miss it and hit L2 (about 190 cycles);
+ * beyond L2, default, work-group and system scope loads see about 490
+ * cycles, non-temporal loads about 700 (they do not allocate in the
+ * memory-side cache). */
 enum {
-    PCHASE_LOAD_DEFAULT = 0, /* may hit the per-CU vector L1                    */
-    PCHASE_LOAD_L2 = 1,      /* sc0: bypasses the vector L1, served by L2      */
-    PCHASE_LOAD_SYSTEM = 2,  /* sc0 sc1: system scope, past L2 (MALL / HBM)    */
-    PCHASE_LOAD_STREAM = 3   /* nt: non-temporal hint                           */
+    PCHASE_LOAD_DEFAULT = 0, /* no policy bits                                  */
+    PCHASE_LOAD_L2 = 1,      /* sc0: work-group scope                           */
+    PCHASE_LOAD_SYSTEM = 2,  /* sc0 sc1: system scope, misses the vector L1     */
+    PCHASE_LOAD_STREAM = 3   /* nt: non-temporal, misses the vector L1          */
 };
 
 /* Fine-grained P-chase on the device (Listing 3 redesigned for one gfx950
@@ -410,8 +435,12 @@ enum {
  * at step i (the paper's s_index holds the loaded value, one step later).
  * *overhead_cycles receives the median cost of the same timed sequence
  * with the load replaced by a register move (subtract it for net latency).
- * ERANGE if k exceeds the LDS record capacity (pchase_microbench_max_k).
- * Synchronises `stream`. */
+ * idx_dev may be NULL: then no indices are recorded and each latency is
+ * kept as a 16-bit value saturated at 65535 cycles, so that up to
+ * 4 * pchase_microbench_max_k() accesses fit (long single-pass walks over
+ * caches of a few MB at line strides).
+ * ERANGE if k exceeds the LDS record capacity (pchase_microbench_max_k, or
+ * four times it without indices).  Synchronises `stream`. */
 int microbench_pchase(const pchase_probe *probe, uint32_t flavor, void *array_dev,
                       uint64_t array_bytes, uint64_t k, uint32_t *lat_dev, int32_t *idx_dev,
                       int32_t *overhead_cycles, hipStream_t stream);

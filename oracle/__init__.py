@@ -97,6 +97,8 @@ def lib():
         L.orc_auto_threshold.restype = ctypes.c_uint32
         L.orc_infer.argtypes = [p, u64, p, u64, p, p, p, ctypes.c_int, p, p]
         L.orc_infer.restype = i64
+        L.orc_infer_general.argtypes = [p, u64, p, u64, p, p, p, p, p]
+        L.orc_infer_general.restype = i64
         L.orc_in_own_sweep.argtypes = [ctypes.POINTER(OrcModel), ctypes.POINTER(OrcProbe)]
         L.orc_in_own_sweep.restype = ctypes.c_int
         _lib = L
@@ -239,6 +241,24 @@ def infer(cands, probes, obs_hits, obs_off, count_from, probe_select=1):
                            _ptr(m), _ptr(n))
     if best < -1:
         raise ValueError(f"orc_infer failed ({best})")
+    return int(best), m[:nc], n[:nc]
+
+
+def infer_general(cands, probes, obs_hits, obs_off, count_from):
+    """Exhaustive inference over General candidates, every probe for every
+    candidate.  Returns (best or -1, m uint64[n], n uint64[n])."""
+    nc, npb = len(cands), len(probes)
+    carr = (OrcGeneral * max(nc, 1))(*[g.c for g in cands])
+    parr = (OrcProbe * max(npb, 1))(*probes)
+    obs_hits = np.ascontiguousarray(obs_hits, dtype=np.uint8)
+    obs_off = np.ascontiguousarray(obs_off, dtype=np.uint64)
+    count_from = np.ascontiguousarray(count_from, dtype=np.uint64)
+    m = np.zeros(max(nc, 1), dtype=np.uint64)
+    n = np.zeros(max(nc, 1), dtype=np.uint64)
+    best = lib().orc_infer_general(ctypes.cast(carr, ctypes.c_void_p), nc, ctypes.cast(parr, ctypes.c_void_p),
+                                   npb, _ptr(obs_hits), _ptr(obs_off), _ptr(count_from), _ptr(m), _ptr(n))
+    if best < -1:
+        raise ValueError(f"orc_infer_general failed ({best})")
     return int(best), m[:nc], n[:nc]
 
 

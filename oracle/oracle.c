@@ -457,6 +457,59 @@ uint32_t orc_auto_threshold(const uint32_t *lat, uint64_t n)
  * traces; here every candidate model is replayed against the observed
  * traces and scored by the number of mismatched hit/miss decisions.       */
 /* ---------------------------------------------------------------------- */
+int64_t orc_infer_general(const orc_general *cands, uint64_t n_cands,
+                          const orc_probe *probes, uint64_t n_probes,
+                          const uint8_t *obs_hits, const uint64_t *obs_off,
+                          const uint64_t *count_from, uint64_t *m, uint64_t *n)
+{
+    uint64_t maxlen = 0;
+    for (uint64_t p = 0; p < n_probes; ++p) {
+        uint64_t len = orc_trace_len(&probes[p]);
+        if (len == 0) return -2;
+        if (len > maxlen) maxlen = len;
+    }
+    int32_t *tr = (int32_t *)malloc((maxlen ? maxlen : 1) * sizeof(int32_t));
+    uint8_t *hit = (uint8_t *)malloc(maxlen ? maxlen : 1);
+    if (!tr || !hit) {
+        free(tr);
+        free(hit);
+        return -3;
+    }
+    /* Step (iv) of Section 4.2 with generalised candidates: each candidate
+     * replays every observed probe; m counts the accesses, from count_from
+     * on, whose hit or miss differs from the observation, n those compared */
+    for (uint64_t c = 0; c < n_cands; ++c) {
+        m[c] = 0;
+        n[c] = 0;
+        if (orc_general_check(&cands[c]) != 0) continue;
+        for (uint64_t p = 0; p < n_probes; ++p) {
+            uint64_t len = orc_trace(&probes[p], tr, maxlen);
+            orc_replay_general(&cands[c], tr, len, probes[p].base, probes[p].elem, p,
+                               count_from[p], hit, NULL, NULL);
+            const uint8_t *ob = obs_hits + obs_off[p];
+            for (uint64_t k = count_from[p]; k < len; ++k) {
+                m[c] += (hit[k] != ob[k]);
+                n[c] += 1;
+            }
+        }
+    }
+    free(tr);
+    free(hit);
+
+    int64_t best = -1;
+    for (uint64_t c = 0; c < n_cands; ++c) {
+        if (n[c] == 0) continue;
+        if (best < 0) {
+            best = (int64_t)c;
+            continue;
+        }
+        unsigned __int128 lhs = (unsigned __int128)m[c] * n[best];
+        unsigned __int128 rhs = (unsigned __int128)m[best] * n[c];
+        if (lhs < rhs) best = (int64_t)c;
+    }
+    return best;
+}
+
 int orc_in_own_sweep(const orc_model *c, const orc_probe *p)
 {
     uint64_t C = c->capacity, b = c->line, N = p->n_bytes, s = p->s_bytes;

@@ -150,6 +150,16 @@ int64_t orc_infer(const orc_model *cands, uint64_t n_cands,
                   const uint64_t *count_from, int probe_select,
                   uint64_t *m, uint64_t *n);
 
+/*
+ * Exhaustive inference over generalised candidates (Sections 4.3-4.5):
+ * every candidate replays every probe; otherwise as orc_infer.  Invalid
+ * candidates get n = 0 and are skipped.
+ */
+int64_t orc_infer_general(const orc_general *cands, uint64_t n_cands,
+                          const orc_probe *probes, uint64_t n_probes,
+                          const uint8_t *obs_hits, const uint64_t *obs_off,
+                          const uint64_t *count_from, uint64_t *m, uint64_t *n);
+
 /* 1 if probe p belongs to candidate c's own sweep. */
 int orc_in_own_sweep(const orc_model *c, const orc_probe *p);
 

@@ -99,6 +99,8 @@ def lib():
         L.cache_replay_probes.argtypes = [vp, u32, vp, u32, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
         L.infer_cache_params.argtypes = [ctypes.POINTER(PchaseObservation), vp, u32, ctypes.c_int,
                                          ctypes.c_int, u32, vp, ctypes.POINTER(PchaseResult), vp, vp, vp, vp]
+        L.infer_cache_params_general.argtypes = [ctypes.POINTER(PchaseObservation), vp, u32,
+                                                 ctypes.POINTER(PchaseResult), vp, vp, vp, vp]
         L.microbench_pchase.argtypes = [ctypes.POINTER(PchaseProbe), u32, vp, u64, u64, vp, vp, vp, vp]
         L.pchase_microbench_max_k.restype = u64
         L.microbench_hbm_stream.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp, vp]
@@ -365,6 +367,25 @@ def infer_cache_params(probe_arr, cand_arr, bits=None, bitoff=None, lat=None, la
     return res, zero
 
 
+def infer_cache_params_general(probe_arr, gen_arr, bits=None, bitoff=None, lat=None, lat_off=None,
+                               threshold=U32_MAX, count_from=None, mn=None, want_zero=False, stream=None,
+                               plan=None):
+    """Generalised candidates (general_models(...)); returns (PchaseResult,
+    zero-class bitmap as uint32 array or None)."""
+    bo, p_bo = _hptr(bitoff, np.uint64)
+    lo, p_lo = _hptr(lat_off, np.uint64)
+    cf, p_cf = _hptr(count_from, np.uint64)
+    obs = PchaseObservation(ctypes.cast(probe_arr, vp), probe_arr.n, threshold, _dptr(bits), p_bo,
+                            _dptr(lat), p_lo, p_cf)
+    res = PchaseResult()
+    zero = np.zeros((gen_arr.n + 31) // 32, dtype=np.uint32) if want_zero else None
+    check(lib().infer_cache_params_general(ctypes.byref(obs), ctypes.cast(gen_arr, vp), gen_arr.n,
+                                           ctypes.byref(res), _dptr(mn),
+                                           zero.ctypes.data_as(vp) if zero is not None else None,
+                                           _plan(plan), _stream(stream)))
+    return res, zero
+
+
 def pchase_plan_next_probe(cand_arr, pool_arr, alive, classes=None, stream=None) -> PchasePlanChoice:
     """Next probe of the adaptive procedure for the surviving candidates
     (alive: uint32 bitmap words); classes (int32 CUDA tensor of
@@ -381,6 +402,7 @@ def pchase_microbench_max_k() -> int:
 
 
 def microbench_pchase(probe: PchaseProbe, flavor, array, k, lat, idx, stream=None) -> int:
+    """idx None: no index records, 16-bit latencies (4x the capacity)."""
     ovh = i32()
     check(lib().microbench_pchase(ctypes.byref(probe), flavor, _dptr(array),
                                   array.numel() * array.element_size(), k, _dptr(lat), _dptr(idx),

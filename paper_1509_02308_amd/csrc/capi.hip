@@ -90,6 +90,9 @@ static int chunk_offsets(const std::vector<uint64_t>& off, std::vector<uint64_t>
     return PCHASE_OK;
 }
 
+static int materialise_traces(Workspace* ws, const std::vector<DevProbe>& dp, const std::vector<uint64_t>& o,
+                              int32_t* idx_dev, hipStream_t stream);
+
 extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32_t* idx_dev, uint64_t* off,
                             uint64_t cap, hipStream_t stream) {
     std::vector<DevProbe> dp;
@@ -108,8 +111,17 @@ extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32
     std::unique_lock<std::mutex> lk;
     rc = workspace(&ws, &lk);
     if (rc) return rc;
+    return materialise_traces(ws, dp, o, idx_dev, stream);
+}
+
+// Writes the probes' traces to idx_dev at offsets o (n + 1 entries) through
+// the workspace's staging buffer; synchronises.
+static int materialise_traces(Workspace* ws, const std::vector<DevProbe>& dp, const std::vector<uint64_t>& o,
+                              int32_t* idx_dev, hipStream_t stream) {
+    const uint32_t n_probes = (uint32_t)dp.size();
+    if (n_probes == 0 || o[n_probes] == 0) return PCHASE_OK;
     std::vector<uint64_t> co;
-    rc = chunk_offsets(o, &co);
+    int rc = chunk_offsets(o, &co);
     if (rc) return rc;
     const size_t b_p = dp.size() * sizeof(DevProbe), b_o = o.size() * sizeof(uint64_t);
     const size_t b_c = co.back() * sizeof(ChunkRef);
@@ -120,6 +132,7 @@ extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32
     uint64_t* d_o = reinterpret_cast<uint64_t*>(st + b_p);
     uint64_t* d_co = reinterpret_cast<uint64_t*>(st + b_p + b_o);
     ChunkRef* d_c = reinterpret_cast<ChunkRef*>(st + b_p + 2 * b_o);
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(d_p, dp.data(), b_p, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_o, o.data(), b_o, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_co, co.data(), b_o, hipMemcpyHostToDevice, stream));
@@ -127,6 +140,7 @@ extern "C" int pchase_trace(const pchase_probe* probes, uint32_t n_probes, int32
     PC_HIP(launch_trace(d_p, d_o, d_c, co.back(), idx_dev, stream));
     // the staging buffer is reused by the next call: finish before releasing it
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     return PCHASE_OK;
 }
 
@@ -214,6 +228,7 @@ extern "C" int pchase_trace_nu(const pchase_nu_probe* probes, uint32_t n_probes,
     uint64_t* d_o = reinterpret_cast<uint64_t*>(st + b_p + b_s);
     uint64_t* d_co = reinterpret_cast<uint64_t*>(st + b_p + b_s + b_o);
     ChunkRef* d_c = reinterpret_cast<ChunkRef*>(st + b_p + b_s + 2 * b_o);
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(d_p, dp.data(), b_p, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_s, ds.data(), b_s, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_o, o.data(), b_o, hipMemcpyHostToDevice, stream));
@@ -222,6 +237,7 @@ extern "C" int pchase_trace_nu(const pchase_nu_probe* probes, uint32_t n_probes,
     PC_HIP(launch_trace_nu(d_p, d_s, d_o, d_c, co.back(), idx_dev, stream));
     // the staging buffer is reused by the next call: finish before releasing it
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     return PCHASE_OK;
 }
 
@@ -362,12 +378,14 @@ static int build_general(const pchase_general_model* models, uint32_t n, std::ve
     return PCHASE_OK;
 }
 
+// held: a workspace the caller has locked and laid out already (its arena
+// is not reset); NULL takes the plan's or the device's workspace.
 static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDesc* gd, uint32_t n_models,
                                const int32_t* idx_dev, const uint64_t* trace_off, const uint64_t* trace_base,
                                uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
                                const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
                                uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, pchase_plan* plan,
-                               hipStream_t stream);
+                               hipStream_t stream, Workspace* held = nullptr);
 
 extern "C" int cache_replay_batch(const pchase_model* models, uint32_t n_models, const int32_t* idx_dev,
                                   const uint64_t* trace_off, const uint64_t* trace_base, uint32_t elem_bytes,
@@ -525,6 +543,7 @@ static int run_tile_schedule(const std::vector<DevModel>& dm, const TileSchedule
     DevModel* d_models = reinterpret_cast<DevModel*>(sb + SL.o_models);
     TileItem* d_items = reinterpret_cast<TileItem*>(sb + SL.o_items);
     uint32_t* d_status = reinterpret_cast<uint32_t*>(sb + SL.o_status);
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_items, ts.items.data(), ts.items.size() * sizeof(TileItem), hipMemcpyHostToDevice,
                           stream));
@@ -611,6 +630,7 @@ static int run_tile_schedule(const std::vector<DevModel>& dm, const TileSchedule
         }
     }
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     uint32_t status = 0;
     PC_HIP(hipMemcpy(&status, d_status, sizeof status, hipMemcpyDeviceToHost));
     if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
@@ -725,7 +745,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
                                uint32_t n_traces, const uint32_t* pair_model, const uint32_t* pair_trace,
                                const uint64_t* count_from, uint64_t n_pairs, uint64_t* misses_dev,
                                uint32_t* hitbits_dev, const uint64_t* bitoff, uint32_t mode, pchase_plan* plan,
-                               hipStream_t stream) {
+                               hipStream_t stream, Workspace* held) {
     int rc = PCHASE_OK;
     if (n_pairs == 0) return PCHASE_OK;
     if (!trace_off || !pair_model || !pair_trace) return set_error(PCHASE_EINVAL, "trace or pair arrays are NULL");
@@ -738,9 +758,11 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
             return set_error(PCHASE_EINVAL, "trace %u: base must be a multiple of 4 below 2^33", t);
     }
     if (trace_off[n_traces] && !idx_dev) return set_error(PCHASE_EINVAL, "idx_dev is NULL");
-    if (!gd)
+    if (!gd) {
+        if (held) return set_error(PCHASE_EINVAL, "internal: standard replay in a held workspace");
         return replay_tiles(dm, n_models, idx_dev, trace_off, trace_base, n_traces, pair_model, pair_trace, count_from,
                             n_pairs, misses_dev, hitbits_dev, bitoff, mode, plan, stream);
+    }
 
     // generalised models: bucket pairs by (policy, group width), longest first inside a bucket;
     // a pair that is long, or whose state is large, is split by set into
@@ -823,11 +845,13 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
         p.pad = items[q].parts > 1 ? (items[q].parts << 16) | items[q].part : 0;
     }
 
-    Workspace* ws;
+    Workspace* ws = held;
     std::unique_lock<std::mutex> lk;
-    rc = workspace_for(plan, &ws, &lk);
-    if (rc) return rc;
-    ws->reset_arena();
+    if (!ws) {
+        rc = workspace_for(plan, &ws, &lk);
+        if (rc) return rc;
+        ws->reset_arena();
+    }
     // descriptors
     const size_t o_models = 0;
     const size_t o_pairs = (dm.size() * sizeof(DevModel) + 255) / 256 * 256;
@@ -952,6 +976,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
         ws->slab_clean = ws->slab.cap;
     }
     // descriptors up, and (split pairs merge into their outputs) those zeroed
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(d_models, dm.data(), dm.size() * sizeof(DevModel), hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(StreamPair), hipMemcpyHostToDevice, stream));
     PC_HIP(launch_fill_u32(d_status, 128, 0, stream));
@@ -1024,6 +1049,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
     }
     ws->epoch += (uint32_t)n_items + 1;
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     uint32_t status = 0;
     PC_HIP(hipMemcpy(&status, d_status, sizeof status, hipMemcpyDeviceToHost));
     if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
@@ -1174,6 +1200,93 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
 }
 
 
+// Layout of an observation's hit bits (Section 4.2, steps 3-4): probe p's
+// bits at word bitoff[p] of bits_dev as given, or, for latencies, packed
+// back to back (words in total) in the bitmap observation_bits writes;
+// cf[p] = the first access compared (one cycle L unless given).
+static int observation_layout(const pchase_observation* obs, const std::vector<DevProbe>& dp,
+                              const std::vector<uint64_t>& len, std::vector<uint64_t>* cf_out,
+                              std::vector<uint64_t>* bitoff_out, uint64_t* words_out, uint64_t* maxlen_out) {
+    const bool have_bits = obs->bits_dev != nullptr, have_lat = obs->lat_dev != nullptr;
+    if (have_bits == have_lat) return set_error(PCHASE_EINVAL, "give exactly one of bits_dev and lat_dev");
+    if (have_bits && !obs->bitoff) return set_error(PCHASE_EINVAL, "bits_dev needs bitoff");
+    if (have_lat && !obs->lat_off) return set_error(PCHASE_EINVAL, "lat_dev needs lat_off");
+    std::vector<uint64_t>& cf = *cf_out;
+    std::vector<uint64_t>& bitoff = *bitoff_out;
+    cf.assign(obs->n_probes, 0);
+    bitoff.assign(obs->n_probes, 0);
+    uint64_t words = 0, maxlen = 0;
+    for (uint32_t p = 0; p < obs->n_probes; ++p) {
+        cf[p] = obs->count_from ? obs->count_from[p] : dp[p].L;
+        maxlen = std::max(maxlen, len[p]);
+        if (have_bits) {
+            bitoff[p] = obs->bitoff[p];
+        } else {
+            if (obs->lat_off[p + 1] - obs->lat_off[p] != len[p])
+                return set_error(PCHASE_EINVAL, "probe %u: %llu latencies for a trace of %llu accesses", p,
+                                 (unsigned long long)(obs->lat_off[p + 1] - obs->lat_off[p]),
+                                 (unsigned long long)len[p]);
+            bitoff[p] = words;
+            words += (len[p] + 31) / 32;
+        }
+    }
+    *words_out = words;
+    *maxlen_out = maxlen;
+    return PCHASE_OK;
+}
+
+// The observation's hit bits on the device: bits_dev as given, or the
+// latencies classified (the given threshold, or the widest gap) into
+// ws->obs.  *threshold_used = the threshold applied (0xFFFFFFFF for bits).
+static int observation_bits(Workspace* ws, const pchase_observation* obs, const std::vector<uint64_t>& bitoff,
+                            uint64_t words, uint64_t maxlen, const uint32_t** bits_out, uint32_t* threshold_used,
+                            hipStream_t stream) {
+    const uint32_t* bits = obs->bits_dev;
+    *threshold_used = 0xFFFFFFFFu;
+    if (!obs->bits_dev) {
+        // latency -> hit bits on the device
+        const uint64_t n_lat = obs->lat_off[obs->n_probes] - obs->lat_off[0];
+        const size_t o_bits = 0;
+        const size_t o_off = (words * 4 + 255) / 256 * 256;
+        const size_t o_mm = o_off + ((2 * (size_t)obs->n_probes + 1) * 8 + 255) / 256 * 256;
+        const size_t o_present = o_mm + 256;
+        const uint64_t present_words = (1ull << 26) / 32;
+        size_t total = o_present + (obs->threshold == 0xFFFFFFFFu ? present_words * 4 : 0);
+        hipError_t e = ws->obs.ensure(total);
+        if (e != hipSuccess) return buf_fail(ws, e, "the observed bits");
+        uint8_t* b = ws->obs.as<uint8_t>();
+        uint32_t* d_bits = reinterpret_cast<uint32_t*>(b + o_bits);
+        uint64_t* d_latoff = reinterpret_cast<uint64_t*>(b + o_off);
+        uint64_t* d_bitoff = d_latoff + obs->n_probes + 1;
+        uint32_t* d_mm = reinterpret_cast<uint32_t*>(b + o_mm);
+        uint32_t mm_init[4] = {0xFFFFFFFFu, 0u, obs->threshold, 0u};
+        uint32_t mmh[3] = {}, th = 0;   // copy targets live as long as the fence
+        CopyFence fence(stream);
+        PC_HIP(hipMemcpyAsync(d_latoff, obs->lat_off, (obs->n_probes + 1) * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(hipMemcpyAsync(d_bitoff, bitoff.data(), obs->n_probes * 8, hipMemcpyHostToDevice, stream));
+        PC_HIP(hipMemcpyAsync(d_mm, mm_init, sizeof mm_init, hipMemcpyHostToDevice, stream));
+        if (obs->threshold == 0xFFFFFFFFu) {
+            PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(b + o_present), present_words, 0, stream));
+            // the presence bitmap covers 2^26 distinct values above the minimum
+            PC_HIP(launch_auto_threshold(obs->lat_dev + obs->lat_off[0], n_lat, d_mm,
+                                         reinterpret_cast<uint32_t*>(b + o_present), present_words * 32,
+                                         d_mm + 2, stream));
+            PC_HIP(hipMemcpyAsync(mmh, d_mm, sizeof mmh, hipMemcpyDeviceToHost, stream));
+            PC_HIP(hipStreamSynchronize(stream));
+            if ((uint64_t)mmh[1] - mmh[0] >= present_words * 32 || mmh[2] == 0xFFFFFFFFu)
+                return set_error(PCHASE_ERANGE, "latency range %u..%u too wide for the automatic threshold", mmh[0], mmh[1]);
+        }
+        PC_HIP(launch_classify(obs->lat_dev, d_latoff, d_bitoff, obs->n_probes, maxlen, d_mm + 2, d_bits, stream));
+        PC_HIP(hipMemcpyAsync(&th, d_mm + 2, 4, hipMemcpyDeviceToHost, stream));
+        PC_HIP(hipStreamSynchronize(stream));
+        fence.done();
+        *threshold_used = th;
+        bits = d_bits;
+    }
+    *bits_out = bits;
+    return PCHASE_OK;
+}
+
 extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
                                   int probe_select, int mode, uint32_t topk, const pchase_mlp* net,
                                   pchase_result* out, uint64_t* mn_dev, uint32_t* zero_host, pchase_plan* plan,
@@ -1215,72 +1328,18 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     rc = validate_probes(obs->probes, obs->n_probes, &dp, &len);
     if (rc) return rc;
     if (obs->n_probes == 0) return set_error(PCHASE_EINVAL, "no observed probes");
-    const bool have_bits = obs->bits_dev != nullptr, have_lat = obs->lat_dev != nullptr;
-    if (have_bits == have_lat) return set_error(PCHASE_EINVAL, "give exactly one of bits_dev and lat_dev");
-    if (have_bits && !obs->bitoff) return set_error(PCHASE_EINVAL, "bits_dev needs bitoff");
-    if (have_lat && !obs->lat_off) return set_error(PCHASE_EINVAL, "lat_dev needs lat_off");
-    std::vector<uint64_t> cf(obs->n_probes), bitoff(obs->n_probes);
+    std::vector<uint64_t> cf, bitoff;
     uint64_t words = 0, maxlen = 0;
-    for (uint32_t p = 0; p < obs->n_probes; ++p) {
-        cf[p] = obs->count_from ? obs->count_from[p] : dp[p].L;
-        maxlen = std::max(maxlen, len[p]);
-        if (have_bits) {
-            bitoff[p] = obs->bitoff[p];
-        } else {
-            if (obs->lat_off[p + 1] - obs->lat_off[p] != len[p])
-                return set_error(PCHASE_EINVAL, "probe %u: %llu latencies for a trace of %llu accesses", p,
-                                 (unsigned long long)(obs->lat_off[p + 1] - obs->lat_off[p]),
-                                 (unsigned long long)len[p]);
-            bitoff[p] = words;
-            words += (len[p] + 31) / 32;
-        }
-    }
+    rc = observation_layout(obs, dp, len, &cf, &bitoff, &words, &maxlen);
+    if (rc) return rc;
     Workspace* ws;
     std::unique_lock<std::mutex> lk;
     rc = workspace_for(plan, &ws, &lk);
     if (rc) return rc;
     ws->reset_arena();   // a plan serves one inference problem at a time
-    const uint32_t* bits = obs->bits_dev;
-    out->threshold_used = 0xFFFFFFFFu;
-    if (have_lat) {
-        // latency -> hit bits on the device
-        const uint64_t n_lat = obs->lat_off[obs->n_probes] - obs->lat_off[0];
-        const size_t o_bits = 0;
-        const size_t o_off = (words * 4 + 255) / 256 * 256;
-        const size_t o_mm = o_off + ((2 * (size_t)obs->n_probes + 1) * 8 + 255) / 256 * 256;
-        const size_t o_present = o_mm + 256;
-        const uint64_t present_words = (1ull << 26) / 32;
-        size_t total = o_present + (obs->threshold == 0xFFFFFFFFu ? present_words * 4 : 0);
-        hipError_t e = ws->obs.ensure(total);
-        if (e != hipSuccess) return buf_fail(ws, e, "the observed bits");
-        uint8_t* b = ws->obs.as<uint8_t>();
-        uint32_t* d_bits = reinterpret_cast<uint32_t*>(b + o_bits);
-        uint64_t* d_latoff = reinterpret_cast<uint64_t*>(b + o_off);
-        uint64_t* d_bitoff = d_latoff + obs->n_probes + 1;
-        uint32_t* d_mm = reinterpret_cast<uint32_t*>(b + o_mm);
-        PC_HIP(hipMemcpyAsync(d_latoff, obs->lat_off, (obs->n_probes + 1) * 8, hipMemcpyHostToDevice, stream));
-        PC_HIP(hipMemcpyAsync(d_bitoff, bitoff.data(), obs->n_probes * 8, hipMemcpyHostToDevice, stream));
-        uint32_t mm_init[4] = {0xFFFFFFFFu, 0u, obs->threshold, 0u};
-        PC_HIP(hipMemcpyAsync(d_mm, mm_init, sizeof mm_init, hipMemcpyHostToDevice, stream));
-        if (obs->threshold == 0xFFFFFFFFu) {
-            PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(b + o_present), present_words, 0, stream));
-            // the presence bitmap covers 2^26 distinct values above the minimum
-            uint32_t mmh[3];
-            PC_HIP(launch_auto_threshold(obs->lat_dev + obs->lat_off[0], n_lat, d_mm,
-                                         reinterpret_cast<uint32_t*>(b + o_present), present_words * 32,
-                                         d_mm + 2, stream));
-            PC_HIP(hipMemcpyAsync(mmh, d_mm, sizeof mmh, hipMemcpyDeviceToHost, stream));
-            PC_HIP(hipStreamSynchronize(stream));
-            if ((uint64_t)mmh[1] - mmh[0] >= present_words * 32 || mmh[2] == 0xFFFFFFFFu)
-                return set_error(PCHASE_ERANGE, "latency range %u..%u too wide for the automatic threshold", mmh[0], mmh[1]);
-        }
-        PC_HIP(launch_classify(obs->lat_dev, d_latoff, d_bitoff, obs->n_probes, maxlen, d_mm + 2, d_bits, stream));
-        uint32_t th = 0;
-        PC_HIP(hipMemcpyAsync(&th, d_mm + 2, 4, hipMemcpyDeviceToHost, stream));
-        PC_HIP(hipStreamSynchronize(stream));
-        out->threshold_used = th;
-        bits = d_bits;
-    }
+    const uint32_t* bits = nullptr;
+    rc = observation_bits(ws, obs, bitoff, words, maxlen, &bits, &out->threshold_used, stream);
+    if (rc) return rc;
 
     out->fallback = 0;
     uint64_t replayed = 0;
@@ -1306,5 +1365,129 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     if (rc) return rc;
     out->replayed_accesses += replayed;
     if (mode == PCHASE_EXHAUSTIVE) out->replayed_accesses = replayed;
+    return PCHASE_OK;
+}
+
+// ------------------------------------------- generalised-candidate search --
+// Sections 4.3-4.5 widen the candidates beyond (C, b, a, policy): per-set
+// associativity, set tables, shifted set mappings, weighted replacement.
+// Such a candidate has no closed-form trace per set, so each observed probe
+// is materialised once and every (candidate, probe) pair replayed through
+// the generalised engine into a hit bitmap, which one wave per pair then
+// compares with the observation (step (iv) of Section 4.2).
+extern "C" int infer_cache_params_general(const pchase_observation* obs, const pchase_general_model* cands,
+                                          uint32_t n_cands, pchase_result* out, uint64_t* mn_dev,
+                                          uint32_t* zero_host, pchase_plan* plan, hipStream_t stream) {
+    if (!obs || !out) return set_error(PCHASE_EINVAL, "obs and out must not be NULL");
+    if (n_cands == 0) return set_error(PCHASE_EINVAL, "no candidates");
+    if (zero_host && (n_cands + 31) / 32 * 4 > 4096 - 256) return set_error(PCHASE_ERANGE, "zero-class bitmap too large");
+    std::vector<DevModel> dm;
+    GeneralDesc gd;
+    int rc = build_general(cands, n_cands, &dm, &gd);
+    if (rc) return rc;
+    std::vector<DevProbe> dp;
+    std::vector<uint64_t> len;
+    rc = validate_probes(obs->probes, obs->n_probes, &dp, &len);
+    if (rc) return rc;
+    if (obs->n_probes == 0) return set_error(PCHASE_EINVAL, "no observed probes");
+    std::vector<uint64_t> cf, obits;
+    uint64_t words = 0, maxlen = 0;
+    rc = observation_layout(obs, dp, len, &cf, &obits, &words, &maxlen);
+    if (rc) return rc;
+    const uint32_t np = obs->n_probes;
+    const uint64_t n_pairs = (uint64_t)n_cands * np;
+    if (n_pairs >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many (candidate, probe) pairs");
+    // traces back to back; hit words of one candidate: every probe's, word aligned
+    std::vector<uint64_t> toff(np + 1, 0), hoff(np), base(np), n_cmp(n_cands, 0);
+    uint64_t cand_words = 0, compared = 0;
+    for (uint32_t p = 0; p < np; ++p) {
+        toff[p + 1] = toff[p] + len[p];
+        hoff[p] = cand_words;
+        cand_words += (len[p] + 31) / 32;
+        base[p] = obs->probes[p].base_offset;
+        compared += len[p] > cf[p] ? len[p] - cf[p] : 0;
+    }
+    for (uint32_t c = 0; c < n_cands; ++c) n_cmp[c] = compared;
+    const uint64_t hit_bytes = (uint64_t)n_cands * cand_words * 4;
+    if (toff[np] >= (1ull << 34) || hit_bytes >= (32ull << 30))
+        return set_error(PCHASE_ERANGE, "the search needs %llu accesses and %llu bytes of hit bits",
+                         (unsigned long long)toff[np], (unsigned long long)hit_bytes);
+    std::vector<uint32_t> pm(n_pairs), pt(n_pairs);
+    std::vector<uint64_t> pcf(n_pairs), pbit(n_pairs);
+    for (uint64_t i = 0; i < n_pairs; ++i) {
+        const uint32_t c = (uint32_t)(i / np), p = (uint32_t)(i % np);
+        pm[i] = c;
+        pt[i] = p;
+        pcf[i] = cf[p];
+        pbit[i] = (uint64_t)c * cand_words + hoff[p];
+    }
+
+    Workspace* ws;
+    std::unique_lock<std::mutex> lk;
+    rc = workspace_for(plan, &ws, &lk);
+    if (rc) return rc;
+    ws->reset_arena();
+    const uint32_t* bits = nullptr;
+    rc = observation_bits(ws, obs, obits, words, maxlen, &bits, &out->threshold_used, stream);
+    if (rc) return rc;
+    // idx | hits | misses | m | n | zero | argmin | hoff | obits | cf | len
+    auto up = [](uint64_t b) { return (b + 255) / 256 * 256; };
+    const size_t zw = (n_cands + 31) / 32;
+    const size_t o_hits = up(toff[np] * 4);
+    const size_t o_miss = o_hits + up(hit_bytes);
+    const size_t o_m = o_miss + up(n_pairs * 16);
+    const size_t o_n = o_m + up((uint64_t)n_cands * 8);
+    const size_t o_zero = o_n + up((uint64_t)n_cands * 8);
+    const size_t o_out = o_zero + up(zw * 4);
+    const size_t o_tab = o_out + up(sizeof(ArgminOut));
+    const size_t total = o_tab + 4 * up((uint64_t)np * 8);
+    hipError_t e = ws->gsearch.ensure(total);
+    if (e != hipSuccess) return buf_fail(ws, e, "the generalised search's buffers");
+    uint8_t* g = ws->gsearch.as<uint8_t>();
+    int32_t* d_idx = reinterpret_cast<int32_t*>(g);
+    uint32_t* d_hits = reinterpret_cast<uint32_t*>(g + o_hits);
+    uint64_t* d_miss = reinterpret_cast<uint64_t*>(g + o_miss);
+    uint64_t* d_m = reinterpret_cast<uint64_t*>(g + o_m);
+    uint64_t* d_n = reinterpret_cast<uint64_t*>(g + o_n);
+    uint32_t* d_zero = reinterpret_cast<uint32_t*>(g + o_zero);
+    ArgminOut* d_out = reinterpret_cast<ArgminOut*>(g + o_out);
+    uint64_t* d_hoff = reinterpret_cast<uint64_t*>(g + o_tab);
+    uint64_t* d_obits = reinterpret_cast<uint64_t*>(g + o_tab + up((uint64_t)np * 8));
+    uint64_t* d_cf = reinterpret_cast<uint64_t*>(g + o_tab + 2 * up((uint64_t)np * 8));
+    uint64_t* d_len = reinterpret_cast<uint64_t*>(g + o_tab + 3 * up((uint64_t)np * 8));
+
+    rc = materialise_traces(ws, dp, toff, d_idx, stream);
+    if (rc) return rc;
+    rc = replay_materialised(dm, &gd, n_cands, d_idx, toff.data(), base.data(), np, pm.data(), pt.data(), pcf.data(),
+                             n_pairs, d_miss, d_hits, pbit.data(), PCHASE_BATCHED, plan, stream, ws);
+    if (rc) return rc;
+    ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
+    CopyFence fence(stream);
+    PC_HIP(hipMemcpyAsync(d_hoff, hoff.data(), np * 8, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_obits, obits.data(), np * 8, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_cf, cf.data(), np * 8, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_len, len.data(), np * 8, hipMemcpyHostToDevice, stream));
+    PC_HIP(hipMemcpyAsync(d_n, n_cmp.data(), (size_t)n_cands * 8, hipMemcpyHostToDevice, stream));
+    PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(d_m), 2 * (uint64_t)n_cands, 0, stream));
+    PC_HIP(launch_fill_u32(d_zero, zw, 0, stream));
+    PC_HIP(launch_mismatch(d_hits, cand_words, bits, d_hoff, d_obits, d_cf, d_len, np, n_pairs, d_m, stream));
+    PC_HIP(launch_argmin(d_m, d_n, n_cands, d_zero, d_out, stream));
+    PC_HIP(hipMemcpyAsync(hr, d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));
+    if (zero_host)
+        PC_HIP(hipMemcpyAsync(static_cast<uint8_t*>(ws->host_res) + 256, d_zero, zw * 4, hipMemcpyDeviceToHost,
+                              stream));
+    if (mn_dev) {
+        PC_HIP(hipMemcpy2DAsync(mn_dev, 16, d_m, 8, 8, n_cands, hipMemcpyDeviceToDevice, stream));
+        PC_HIP(hipMemcpy2DAsync(mn_dev + 1, 16, d_n, 8, 8, n_cands, hipMemcpyDeviceToDevice, stream));
+    }
+    PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
+    out->best = hr->best;
+    out->best_m = hr->m;
+    out->best_n = hr->n;
+    out->n_zero = hr->n_zero;
+    out->fallback = 0;
+    out->replayed_accesses = (uint64_t)n_cands * toff[np];
+    if (zero_host) std::memcpy(zero_host, static_cast<uint8_t*>(ws->host_res) + 256, zw * 4);
     return PCHASE_OK;
 }

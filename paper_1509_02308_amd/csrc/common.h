@@ -215,6 +215,12 @@ hipError_t launch_classify(const uint32_t* lat, const uint64_t* lat_off, const u
                            uint32_t n_probes, uint64_t maxlen, const uint32_t* theta, uint32_t* bits,
                            hipStream_t stream);
 hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t n, hipStream_t stream);
+// m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from
+// cf[p] to len[p], whose hit bit in hits + c * cand_words + hoff[p] differs
+// from the observation's in obs + obits[p] (word offsets).
+hipError_t launch_mismatch(const uint32_t* hits, uint64_t cand_words, const uint32_t* obs, const uint64_t* hoff,
+                           const uint64_t* obits, const uint64_t* cf, const uint64_t* len, uint32_t n_probes,
+                           uint64_t n_pairs, uint64_t* m, hipStream_t stream);
 
 // ------------------------------------------------------------ Philox ----
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two

@@ -55,6 +55,7 @@ struct Workspace {
     DevBuf obs;        // derived observed bitmaps
     DevBuf slab;       // stream-replay set state
     DevBuf mlp;        // grid replay bank of the learned proposer
+    DevBuf gsearch;    // generalised-candidate search: traces, hit bits, scores
     size_t slab_clean = 0;  // bytes of `slab` known to hold epoch 0 or older epochs
     uint32_t epoch = 0;
     void* host_res = nullptr;  // pinned result staging
@@ -76,6 +77,24 @@ struct Workspace {
     // forgets every buffer, cached schedule and graph carved from the arena
     void reset_arena();
     ~Workspace();
+};
+
+// Guards host memory that queued copies read: declared after the host
+// buffers of a scope and before its first asynchronous copy out of them, it
+// makes any return that has not synchronised `stream` (an error return)
+// wait for the stream before those buffers are destroyed, so that no copy
+// still in the queue reads freed memory.  done() once the scope has
+// synchronised the stream itself.
+struct CopyFence {
+    hipStream_t stream;
+    bool armed = true;
+    explicit CopyFence(hipStream_t s) : stream(s) {}
+    CopyFence(const CopyFence&) = delete;
+    CopyFence& operator=(const CopyFence&) = delete;
+    ~CopyFence() {
+        if (armed) (void)hipStreamSynchronize(stream);
+    }
+    void done() { armed = false; }
 };
 
 // Locks and returns the calling thread's current device's workspace.

@@ -94,10 +94,13 @@ __device__ __forceinline__ void timed_nothing(int32_t& j, uint64_t& t0, uint64_t
         : "memory");
 }
 
-template <int FLAVOR>
+// COMPACT: no index records, latencies as 16-bit values saturated at 65535
+// cycles, so that four times as many accesses fit the LDS record store.
+template <int FLAVOR, bool COMPACT>
 __global__ void __launch_bounds__(64) pchase_walk_kernel(const int32_t* arr, uint32_t j0, uint64_t warm, uint64_t k,
                                                          uint32_t* lat_out, int32_t* idx_out, int32_t* ovh_out) {
-    extern __shared__ uint32_t rec[];  // [k] latencies then [k] indices
+    extern __shared__ uint32_t rec[];  // [k] latencies then [k] indices, or [k] 16-bit latencies
+    uint16_t* rec16 = reinterpret_cast<uint16_t*>(rec);
     if (threadIdx.x != 0) return;
     int32_t j = (int32_t)j0;
     // preheat: one untimed walk over the cycle
@@ -112,8 +115,13 @@ __global__ void __launch_bounds__(64) pchase_walk_kernel(const int32_t* arr, uin
         uint64_t t0, t1;
         int32_t nj;
         timed_load<FLAVOR>(arr + j, nj, t0, t1);
-        rec[i] = (uint32_t)(t1 - t0);
-        rec[k + i] = (uint32_t)j;
+        if constexpr (COMPACT) {
+            const uint64_t d = t1 - t0;
+            rec16[i] = (uint16_t)(d < 65535 ? d : 65535);
+        } else {
+            rec[i] = (uint32_t)(t1 - t0);
+            rec[k + i] = (uint32_t)j;
+        }
         j = nj;
     }
     // timer overhead: median of 63 empty segments
@@ -132,19 +140,27 @@ __global__ void __launch_bounds__(64) pchase_walk_kernel(const int32_t* arr, uin
         }
     *ovh_out = (int32_t)o[31];
     for (uint64_t i = 0; i < k; ++i) {
-        lat_out[i] = rec[i];
-        idx_out[i] = (int32_t)rec[k + i];
+        if constexpr (COMPACT) {
+            lat_out[i] = rec16[i];
+        } else {
+            lat_out[i] = rec[i];
+            idx_out[i] = (int32_t)rec[k + i];
+        }
     }
 }
 
 using WalkFn = void (*)(const int32_t*, uint32_t, uint64_t, uint64_t, uint32_t*, int32_t*, int32_t*);
-static WalkFn walk_fn(uint32_t flavor) {
+template <bool COMPACT>
+static WalkFn walk_fn_t(uint32_t flavor) {
     switch (flavor) {
-        case PCHASE_LOAD_DEFAULT: return pchase_walk_kernel<PCHASE_LOAD_DEFAULT>;
-        case PCHASE_LOAD_L2: return pchase_walk_kernel<PCHASE_LOAD_L2>;
-        case PCHASE_LOAD_SYSTEM: return pchase_walk_kernel<PCHASE_LOAD_SYSTEM>;
-        default: return pchase_walk_kernel<PCHASE_LOAD_STREAM>;
+        case PCHASE_LOAD_DEFAULT: return pchase_walk_kernel<PCHASE_LOAD_DEFAULT, COMPACT>;
+        case PCHASE_LOAD_L2: return pchase_walk_kernel<PCHASE_LOAD_L2, COMPACT>;
+        case PCHASE_LOAD_SYSTEM: return pchase_walk_kernel<PCHASE_LOAD_SYSTEM, COMPACT>;
+        default: return pchase_walk_kernel<PCHASE_LOAD_STREAM, COMPACT>;
     }
+}
+static WalkFn walk_fn(uint32_t flavor, bool compact) {
+    return compact ? walk_fn_t<true>(flavor) : walk_fn_t<false>(flavor);
 }
 
 static uint64_t lds_record_bytes() {
@@ -396,8 +412,8 @@ extern "C" uint64_t pchase_microbench_max_k(void) { return lds_record_bytes() / 
 extern "C" int microbench_pchase(const pchase_probe* probe, uint32_t flavor, void* array_dev, uint64_t array_bytes,
                                  uint64_t k, uint32_t* lat_dev, int32_t* idx_dev, int32_t* overhead_cycles,
                                  hipStream_t stream) {
-    if (!probe || !array_dev || !lat_dev || !idx_dev || !overhead_cycles)
-        return set_error(PCHASE_EINVAL, "NULL argument");
+    if (!probe || !array_dev || !lat_dev || !overhead_cycles) return set_error(PCHASE_EINVAL, "NULL argument");
+    const bool compact = idx_dev == nullptr;
     if (flavor > PCHASE_LOAD_STREAM) return set_error(PCHASE_EINVAL, "unknown load flavour %u", flavor);
     DevProbe dp;
     uint64_t len = 0;
@@ -407,7 +423,7 @@ extern "C" int microbench_pchase(const pchase_probe* probe, uint32_t flavor, voi
         return set_error(PCHASE_ERANGE, "array of %llu bytes is smaller than base_offset + N",
                          (unsigned long long)array_bytes);
     if ((uintptr_t)array_dev % 4) return set_error(PCHASE_EINVAL, "array_dev must be 4-byte aligned");
-    const uint64_t maxk = pchase_microbench_max_k();
+    const uint64_t maxk = compact ? lds_record_bytes() / 2 : pchase_microbench_max_k();
     if (k == 0 || k > maxk)
         return set_error(PCHASE_ERANGE, "k = %llu outside [1, %llu] (LDS record capacity)", (unsigned long long)k,
                          (unsigned long long)maxk);
@@ -418,8 +434,8 @@ extern "C" int microbench_pchase(const pchase_probe* probe, uint32_t flavor, voi
     int32_t* arr = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(array_dev) + probe->base_offset);
     hipLaunchKernelGGL(pchase_init_kernel, dim3(1024), dim3(256), 0, stream, arr, dp.ne, dp.se);
     PC_HIP(hipGetLastError());
-    const size_t lds = (size_t)k * 8;
-    WalkFn fn = walk_fn(flavor);
+    const size_t lds = (size_t)k * (compact ? 2 : 8);
+    WalkFn fn = walk_fn(flavor, compact);
     PC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_record_bytes()));
     hipError_t e = ws->aux.ensure(256);
     if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "aux: %s", hipGetErrorString(e));
@@ -427,8 +443,10 @@ extern "C" int microbench_pchase(const pchase_probe* probe, uint32_t flavor, voi
     const uint64_t warm = dp.L < k ? (uint64_t)dp.L : k;
     hipLaunchKernelGGL(fn, dim3(1), dim3(64), lds, stream, arr, dp.j0, warm, k, lat_dev, idx_dev, d_ovh);
     PC_HIP(hipGetLastError());
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(overhead_cycles, d_ovh, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     return PCHASE_OK;
 }
 

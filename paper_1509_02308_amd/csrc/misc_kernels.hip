@@ -261,6 +261,46 @@ hipError_t launch_argmin(const uint64_t* m, const uint64_t* n, uint32_t nc, uint
     return hipGetLastError();
 }
 
+// ------------------------------------------ generalised-candidate scoring --
+// Step (iv) of Section 4.2 over replayed hit bitmaps: one wave per (candidate,
+// probe) pair, lanes over the pair's words, XOR with the observation,
+// population count of the compared bits, one atomic per pair.
+__global__ void __launch_bounds__(256) mismatch_kernel(const uint32_t* hits, uint64_t cand_words, const uint32_t* obs,
+                                                       const uint64_t* hoff, const uint64_t* obits,
+                                                       const uint64_t* cf, const uint64_t* len, uint32_t n_probes,
+                                                       uint64_t n_pairs, unsigned long long* m) {
+    const uint64_t pair = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    if (pair >= n_pairs) return;
+    const uint64_t c = pair / n_probes;
+    const uint32_t p = (uint32_t)(pair % n_probes);
+    const uint32_t* h = hits + c * cand_words + hoff[p];
+    const uint32_t* o = obs + obits[p];
+    const uint64_t a0 = cf[p], a1 = len[p];
+    unsigned long long cnt = 0;
+    if (a0 < a1) {
+        const uint64_t w0 = a0 >> 5, w1 = (a1 + 31) >> 5;
+        for (uint64_t w = w0 + lane; w < w1; w += 64) {
+            uint32_t x = h[w] ^ o[w];
+            if (w == w0) x &= ~0u << (a0 & 31);
+            if (w == w1 - 1 && (a1 & 31)) x &= (1u << (a1 & 31)) - 1u;
+            cnt += (unsigned long long)__popc(x);
+        }
+    }
+    for (int s = 32; s > 0; s >>= 1) cnt += __shfl_xor(cnt, s);
+    if (lane == 0 && cnt) atomicAdd(m + c, cnt);
+}
+
+hipError_t launch_mismatch(const uint32_t* hits, uint64_t cand_words, const uint32_t* obs, const uint64_t* hoff,
+                           const uint64_t* obits, const uint64_t* cf, const uint64_t* len, uint32_t n_probes,
+                           uint64_t n_pairs, uint64_t* m, hipStream_t stream) {
+    if (n_pairs == 0) return hipSuccess;
+    const uint64_t blocks = (n_pairs + 3) / 4;
+    hipLaunchKernelGGL(mismatch_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, hits, cand_words, obs, hoff,
+                       obits, cf, len, n_probes, n_pairs, reinterpret_cast<unsigned long long*>(m));
+    return hipGetLastError();
+}
+
 // ------------------------------------------------ latency classification --
 // Automatic threshold: the lower end of the widest gap between consecutive
 // distinct latency values.  Values are marked in a presence bitmap over

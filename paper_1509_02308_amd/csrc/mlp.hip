@@ -783,6 +783,7 @@ int infer_learned(Workspace* ws, const pchase_observation* obs, const pchase_mod
         L[p] = dp[p].L;
         pbit[p] = bitoff[p] * 32;   // observation offsets are in words
     }
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(d_pbit, pbit.data(), kIn * 8, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_L, L.data(), kIn * 4, hipMemcpyHostToDevice, stream));
     FeatArgs fa{};
@@ -800,6 +801,7 @@ int infer_learned(Workspace* ws, const pchase_observation* obs, const pchase_mod
     int32_t* hr = static_cast<int32_t*>(ws->host_res);
     PC_HIP(hipMemcpyAsync(hr, net->idx, topk * 4, hipMemcpyDeviceToHost, stream));
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     allow->assign(n_cands, 0);
     for (uint32_t j = 0; j < topk; ++j)
         if (hr[j] >= 0 && (uint32_t)hr[j] < n_cands) (*allow)[hr[j]] = 1;
@@ -893,17 +895,19 @@ extern "C" int pchase_mlp_features(const pchase_model* models, uint32_t n, float
     rc = workspace(&ws, &lk);
     if (rc) return rc;
     const uint32_t per = (uint32_t)std::max<uint64_t>(1, kBankBytesMax / (gt.slot_bits / 8));
+    CopyFence fence(stream);   // the grid table's arrays
     for (uint32_t c0 = 0; c0 < n; c0 += per) {
         const uint32_t cn = std::min(per, n - c0);
-        BankLayout bl;
-        rc = bank_alloc(ws, gt, cn, (size_t)cn * 8 + 256, &bl, stream);
-        if (rc) return rc;
         std::vector<Slot> slots(cn);
         std::vector<uint64_t> bit0(cn);
         for (uint32_t i = 0; i < cn; ++i) {
             slots[i] = {c0 + i, 0};
             bit0[i] = i * gt.slot_bits;
         }
+        CopyFence chunk(stream);
+        BankLayout bl;
+        rc = bank_alloc(ws, gt, cn, (size_t)cn * 8 + 256, &bl, stream);
+        if (rc) return rc;
         rc = replay_slots(ws, gt, dm, slots, bl.bank, stream);
         if (rc) return rc;
         uint64_t* d_bit0 = reinterpret_cast<uint64_t*>(bl.rows);
@@ -918,7 +922,9 @@ extern "C" int pchase_mlp_features(const pchase_model* models, uint32_t n, float
         fa.x = x_dev + (uint64_t)c0 * kIn;
         PC_HIP(launch_features(fa, stream));
         PC_HIP(hipStreamSynchronize(stream));   // the bank is reused by the next chunk
+        chunk.done();
     }
+    fence.done();
     return PCHASE_OK;
 }
 
@@ -939,6 +945,8 @@ extern "C" int pchase_mlp_labels(const pchase_model* models, uint32_t n, int32_t
     std::unique_lock<std::mutex> lk;
     rc = workspace(&ws, &lk);
     if (rc) return rc;
+    std::vector<uint64_t> sig(n);
+    CopyFence fence(stream);
     BankLayout bl;
     rc = bank_alloc(ws, gt, n, (size_t)n * 8 + 256, &bl, stream);
     if (rc) return rc;
@@ -949,7 +957,6 @@ extern "C" int pchase_mlp_labels(const pchase_model* models, uint32_t n, int32_t
     uint64_t* d_sig = reinterpret_cast<uint64_t*>(bl.rows);
     hipLaunchKernelGGL(signature_kernel, dim3(n), dim3(256), 0, stream, bl.bank, gt.slot_bits, bl.pbit, bl.L, kIn, d_sig);
     PC_HIP(hipGetLastError());
-    std::vector<uint64_t> sig(n);
     PC_HIP(hipMemcpyAsync(sig.data(), d_sig, n * 8, hipMemcpyDeviceToHost, stream));
     PC_HIP(hipStreamSynchronize(stream));
     // exact check of every earlier model with the same signature
@@ -970,13 +977,15 @@ extern "C" int pchase_mlp_labels(const pchase_model* models, uint32_t n, int32_t
         if (e != hipSuccess) return set_error(PCHASE_ENOMEM, "label pairs: %s", hipGetErrorString(e));
         uint32_t* d_pairs = ws->aux.as<uint32_t>();
         uint32_t* d_diff = d_pairs + 2 * (size_t)np;
+        std::vector<uint32_t> diff(np);
+        CopyFence block(stream);
         PC_HIP(hipMemcpyAsync(d_pairs, pairs.data(), (size_t)np * 8, hipMemcpyHostToDevice, stream));
         hipLaunchKernelGGL(pair_differ_kernel, dim3(np), dim3(256), 0, stream, bl.bank, gt.slot_bits, bl.pbit, bl.L, kIn,
                            d_pairs, d_diff);
         PC_HIP(hipGetLastError());
-        std::vector<uint32_t> diff(np);
         PC_HIP(hipMemcpyAsync(diff.data(), d_diff, (size_t)np * 4, hipMemcpyDeviceToHost, stream));
         PC_HIP(hipStreamSynchronize(stream));
+        block.done();
         for (uint32_t k = 0; k < np; ++k) {
             const uint32_t i = pairs[2 * k], j = pairs[2 * k + 1];
             if (!diff[k] && (int32_t)j < labels[i]) labels[i] = (int32_t)j;
@@ -1027,6 +1036,7 @@ extern "C" int pchase_mlp_samples(const pchase_model* models, uint32_t n_models,
     std::unique_lock<std::mutex> lk;
     rc = workspace(&ws, &lk);
     if (rc) return rc;
+    CopyFence fence(stream);   // the labels and the grid table's arrays
     PC_HIP(hipMemcpyAsync(labels_dev, lab.data(), (size_t)n * 4, hipMemcpyHostToDevice, stream));
     const uint32_t per = (uint32_t)std::max<uint64_t>(1, kBankBytesMax / (gt.slot_bits / 8));
     size_t r0 = 0;
@@ -1049,6 +1059,7 @@ extern "C" int pchase_mlp_samples(const pchase_model* models, uint32_t n_models,
             ++r;
         }
         const size_t rows = r - r0;
+        CopyFence chunk(stream);
         BankLayout bl;
         rc = bank_alloc(ws, gt, slots.size(), rows * 24 + 1024, &bl, stream);
         if (rc) return rc;
@@ -1077,8 +1088,10 @@ extern "C" int pchase_mlp_samples(const pchase_model* models, uint32_t n_models,
         fa.x = x_dev;
         PC_HIP(launch_features(fa, stream));
         PC_HIP(hipStreamSynchronize(stream));
+        chunk.done();
         r0 = r;
     }
+    fence.done();
     return PCHASE_OK;
 }
 
@@ -1095,8 +1108,10 @@ extern "C" int pchase_mlp_train_step(pchase_mlp* net, const float* x_dev, const 
     if (rc) return rc;
     net->steps += 1;
     if (loss) {
+        CopyFence fence(stream);
         PC_HIP(hipMemcpyAsync(loss, net->loss, 4, hipMemcpyDeviceToHost, stream));
         PC_HIP(hipStreamSynchronize(stream));
+        fence.done();
     }
     return PCHASE_OK;
 }
@@ -1149,10 +1164,10 @@ extern "C" int pchase_mlp_train(pchase_mlp* net, const float* x_dev, const int32
     for (uint32_t ep = 0; ep < epochs; ++ep)
         for (uint64_t s = 0; s < steps; ++s) PC_HIP(hipGraphLaunch(net->gexec, stream));
     net->steps += steps * epochs;
-    if (last_loss) {
-        PC_HIP(hipMemcpyAsync(last_loss, net->loss, 4, hipMemcpyDeviceToHost, stream));
-    }
+    CopyFence fence(stream);
+    if (last_loss) PC_HIP(hipMemcpyAsync(last_loss, net->loss, 4, hipMemcpyDeviceToHost, stream));
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     return PCHASE_OK;
 }
 

@@ -207,6 +207,7 @@ extern "C" int pchase_plan_next_probe(const pchase_model* cands, uint32_t n_cand
             bank.release();
             return set_error(PCHASE_ENOMEM, "planner classes: %s", hipGetErrorString(e));
         }
+        CopyFence fence(stream);
         hipError_t he = hipMemcpyAsync(d_pp, pp.data(), pp.size() * sizeof(PlanProbe), hipMemcpyHostToDevice, stream);
         const uint64_t n = (uint64_t)n_pool * n_cands;
         const uint32_t blocks = (uint32_t)((n + 255) / 256);
@@ -219,7 +220,11 @@ extern "C" int pchase_plan_next_probe(const pchase_model* cands, uint32_t n_cand
                                n_cands, ws->planner.as<uint32_t>());
             he = hipGetLastError();
         }
-        if (he == hipSuccess) he = hipStreamSynchronize(stream);   // the bank is freed below
+        if (he == hipSuccess)
+            he = hipStreamSynchronize(stream);   // the bank is freed below
+        else
+            (void)hipStreamSynchronize(stream);  // nothing queued may outlive the bank or pp
+        fence.done();
         bank.release();
         if (he != hipSuccess) return hip_fail(he, "planner classes");
         ws->planner_key = key;
@@ -229,6 +234,8 @@ extern "C" int pchase_plan_next_probe(const pchase_model* cands, uint32_t n_cand
     unsigned long long* d_best =
         reinterpret_cast<unsigned long long*>(ws->planner.as<uint8_t>() + (cls_bytes + aw * 4 + 7) / 8 * 8);
     const unsigned long long init = ~0ull;
+    unsigned long long best = 0;
+    CopyFence fence(stream);
     PC_HIP(hipMemcpyAsync(d_alive, alive_host, aw * 4, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_best, &init, sizeof init, hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(plan_score_kernel, dim3(n_pool), dim3(256), n_cands * sizeof(uint32_t), stream, d_cls, d_alive,
@@ -236,9 +243,9 @@ extern "C" int pchase_plan_next_probe(const pchase_model* cands, uint32_t n_cand
     PC_HIP(hipGetLastError());
     if (classes_dev)
         PC_HIP(hipMemcpyAsync(classes_dev, d_cls, cls_bytes, hipMemcpyDeviceToDevice, stream));
-    unsigned long long best = 0;
     PC_HIP(hipMemcpyAsync(&best, d_best, sizeof best, hipMemcpyDeviceToHost, stream));
     PC_HIP(hipStreamSynchronize(stream));
+    fence.done();
     const uint32_t worst = (uint32_t)(best >> 42), probe = (uint32_t)(best & ((1u << 21) - 1));
     const uint32_t classes = n_cands - (uint32_t)((best >> 21) & ((1u << 21) - 1));
     out->n_alive = n_alive;

@@ -144,7 +144,7 @@ void Workspace::reset_arena() {
     if (!arena) return;
     plans.clear();
     planner_key.clear();
-    for (DevBuf* b : {&stage, &aux, &obs, &slab, &mlp, &planner}) b->release();
+    for (DevBuf* b : {&stage, &aux, &obs, &slab, &mlp, &planner, &gsearch}) b->release();
     slab_clean = 0;
     arena->reset();
 }
@@ -166,6 +166,7 @@ Workspace::~Workspace() {
     slab.release();
     mlp.release();
     planner.release();
+    gsearch.release();
     if (host_res) (void)hipHostFree(host_res);
 }
 
@@ -305,7 +306,8 @@ extern "C" int pchase_plan_create(uint64_t device_bytes, pchase_plan** out) {
     p->ws.device = dev;
     p->ws.cus = cus;
     p->ws.arena = &p->arena;
-    for (DevBuf* b : {&p->ws.stage, &p->ws.aux, &p->ws.obs, &p->ws.slab, &p->ws.mlp, &p->ws.planner})
+    for (DevBuf* b : {&p->ws.stage, &p->ws.aux, &p->ws.obs, &p->ws.slab, &p->ws.mlp, &p->ws.planner,
+                       &p->ws.gsearch})
         b->arena = &p->arena;
     rc = workspace_init(&p->ws);
     if (rc) {

@@ -226,3 +226,64 @@ def random_general(n: int, seed: int = 7):
             d["weights"] = w
         out.append(d)
     return out
+
+
+# --------------------------------------------------------------------------
+# Generalised-candidate search (Sections 4.3-4.5): around each paper-shaped
+# target, a family of neighbours that differ in one structural choice (set
+# mapping bits, ways per set, set table, replacement weights, policy), and
+# the fine-grained probes that observe it.
+# --------------------------------------------------------------------------
+def general_family(target: dict, seed: int = 1509):
+    """Candidate dicts around a paper_general_targets() entry, the target
+    itself included (at a seeded position).  Returns (family, index)."""
+    rng = np.random.default_rng(seed)
+    name = target["name"]
+    fam = []
+    if name == "texture_l1":
+        for sh in (5, 6, 7, 8, 9):
+            for pol in (LRU, FIFO):
+                for w in (88, 96, 104):
+                    fam.append({"line": 32, "ways": [w] * 4, "policy": pol, "set_shift": sh})
+                fam.append({"line": 32, "ways": [48] * 8, "policy": pol, "set_shift": sh})
+    elif name == "readonly_table":
+        tables = [list(target["table"])] + [[int(x) for x in rng.permutation(np.arange(64) % 4)] for _ in range(7)]
+        for sh in (6, 7, 8):
+            for t in tables:
+                fam.append({"line": 32, "ways": [96] * 4, "policy": LRU, "set_shift": sh, "table": t})
+    elif name == "l2_tlb":
+        plain = [r % 7 for r in range(7)]
+        for pol in (LRU, FIFO):
+            for big in (15, 16, 17, 18, 19):
+                for small in (7, 8, 9):
+                    for t in (list(target["table"]), plain):
+                        fam.append({"line": 2 << 20, "ways": [big] + [small] * 6, "policy": pol, "table": t})
+    elif name == "fermi_l1":
+        for wts in ([1, 3, 1, 1], [1, 1, 1, 1], [3, 1, 1, 1], [1, 1, 3, 1], [1, 1, 1, 3]):
+            for sd in (1509, 1510):
+                fam.append({"line": 128, "ways": [4] * 32, "policy": WRANDOM, "weights": wts, "seed": sd})
+        for pol in (LRU, FIFO, PLRU):
+            fam.append({"line": 128, "ways": [4] * 32, "policy": pol})
+    else:
+        raise ValueError(f"no family for {name}")
+    key = {k: v for k, v in target.items() if k != "name"}
+    fam = [d for d in fam if d != key]
+    at = int(rng.integers(0, len(fam) + 1))
+    fam.insert(at, key)
+    return fam, at
+
+
+def general_probe_rows(target: dict, n_per_stride: int = 48, passes: int = 2):
+    """Fine-grained probes (N, s, passes) for a generalised target: strides of
+    half a line, a line, two lines and the set-mapping unit, N ramping from
+    half to twice the capacity in n_per_stride steps of a line multiple."""
+    b = int(target["line"])
+    C = b * int(sum(target["ways"]))
+    unit = 1 << int(target["set_shift"]) if target.get("set_shift") else b
+    strides = sorted({s for s in (b // 2, b, 2 * b, unit) if s >= 4})
+    rows = []
+    for s in strides:
+        step = max(b, (3 * C // 2) // n_per_stride // b * b)
+        for N in range(C // 2, 2 * C + 1, step):
+            rows.append((N, s, passes))
+    return rows

@@ -206,6 +206,30 @@ def test_general_model_validation_before_launch(capi):
         assert rc == -1, d
 
 
+def test_general_infer_argument_checks(capi):
+    """The generalised search validates its candidates and observation on
+    the host before it touches a device."""
+    good = capi.general_models([{"line": 32, "ways": [4, 4]}])
+    probes = capi.probes([(4096, 32, 2)])
+    obs = capi.PchaseObservation(ctypes.cast(probes, ctypes.c_void_p), 1, capi.U32_MAX, None, None, None,
+                                 None, None)
+    res = capi.PchaseResult()
+    L = capi.lib()
+    rc = L.infer_cache_params_general(None, ctypes.cast(good, ctypes.c_void_p), 1, ctypes.byref(res), None, None,
+                                      None, None)
+    assert rc == -1
+    rc = L.infer_cache_params_general(ctypes.byref(obs), ctypes.cast(good, ctypes.c_void_p), 0, ctypes.byref(res),
+                                      None, None, None, None)
+    assert rc == -1 and "candidates" in capi.last_error()
+    rc = L.infer_cache_params_general(ctypes.byref(obs), ctypes.cast(good, ctypes.c_void_p), 1, ctypes.byref(res),
+                                      None, None, None, None)
+    assert rc == -1 and "exactly one" in capi.last_error()
+    bad = capi.general_models([{"line": 32, "ways": [4, 3], "policy": 2}])
+    rc = L.infer_cache_params_general(ctypes.byref(obs), ctypes.cast(bad, ctypes.c_void_p), 1, ctypes.byref(res),
+                                      None, None, None, None)
+    assert rc == -1 and "PLRU" in capi.last_error()
+
+
 def test_planner_argument_checks(capi):
     """Planner arguments are checked on the host before any launch."""
     L = capi.lib()

@@ -106,3 +106,85 @@ def test_general_equal_sets_match_standard_replay():
         torch.cuda.synchronize()
         out.append((bits.cpu().numpy(), misses.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+# ------------------------------------------------ generalised-candidate search --
+def _observe(target, rows):
+    """The target's hit bits per probe (oracle replay, trace id = probe
+    index), packed at word offsets, plus the flat bytes the oracle scores."""
+    g = _orc_general(target)
+    hits, words, off, cf = [], [], [], []
+    pos = 0
+    for i, r in enumerate(rows):
+        p = orc.make_probe(*r)
+        h, _, _ = orc.replay_general(g, orc.trace(p), trace_id=i)
+        hits.append(h)
+        off.append(pos)
+        pos += len(h)
+        cf.append(orc.cycle_len(p))
+        n = (len(h) + 31) // 32
+        pad = np.zeros(n * 32, np.uint8)
+        pad[:len(h)] = h
+        words.append((pad.reshape(n, 32).astype(np.uint64) << np.arange(32, dtype=np.uint64)).sum(1).astype(np.uint32))
+    bitoff = np.concatenate([[0], np.cumsum([len(w) for w in words])[:-1]]).astype(np.uint64)
+    return (np.concatenate(hits), np.array(off, np.uint64), np.array(cf, np.uint64),
+            np.concatenate(words + [np.zeros(1, np.uint32)]), bitoff)
+
+
+def _zero_list(zero, n):
+    return [i for i in range(n) if (int(zero[i // 32]) >> (i % 32)) & 1]
+
+
+@pytest.mark.parametrize("name", ["texture_l1", "readonly_table", "l2_tlb", "fermi_l1"])
+def test_general_search_recovers_paper_targets(name):
+    """Sections 4.3-4.5: the search over each paper-shaped target's family
+    gives the oracle's (m, n) for every candidate, its best and its zero
+    class, and the target is in that class."""
+    torch, capi = need_gpu()
+    target = [t for t in W.paper_general_targets() if t["name"] == name][0]
+    fam, at = W.general_family(target)
+    rows = W.general_probe_rows(target)
+    flat, off, cf, packed, bitoff = _observe(target, rows)
+    best, m, n = orc.infer_general([_orc_general(d) for d in fam], [orc.make_probe(*r) for r in rows], flat, off, cf)
+    mn = torch.zeros(2 * len(fam), dtype=torch.int64, device="cuda")
+    say(f"generalised search {name}: {len(fam)} candidates x {len(rows)} probes")
+    res, zero = capi.infer_cache_params_general(capi.probes(rows), capi.general_models(fam),
+                                                bits=torch.from_numpy(packed.view(np.int32)).cuda(), bitoff=bitoff,
+                                                mn=mn, want_zero=True)
+    got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    assert np.array_equal(got[:, 0], m) and np.array_equal(got[:, 1], n)
+    zc = [int(i) for i in np.nonzero(m == 0)[0]]
+    assert res.best == best and (res.best_m, res.best_n) == (int(m[best]), int(n[best]))
+    assert _zero_list(zero, len(fam)) == zc and res.n_zero == len(zc)
+    assert at in zc and len(zc) < len(fam)
+
+
+def test_general_search_from_latencies_and_with_a_plan():
+    """The same search fed with latencies (hits fast, misses slow, jittered;
+    the widest gap classifies them) and run inside a caller-owned plan."""
+    torch, capi = need_gpu()
+    target = [t for t in W.paper_general_targets() if t["name"] == "fermi_l1"][0]
+    fam, at = W.general_family(target)
+    rows = W.general_probe_rows(target)[::3]
+    flat, off, cf, packed, bitoff = _observe(target, rows)
+    rng = np.random.default_rng(5)
+    lat = np.where(flat == 1, 90 + rng.integers(0, 20, flat.size), 400 + rng.integers(0, 60, flat.size)).astype(np.uint32)
+    lat_off = np.concatenate([off, [flat.size]]).astype(np.uint64)
+    best, m, n = orc.infer_general([_orc_general(d) for d in fam], [orc.make_probe(*r) for r in rows], flat, off, cf)
+    say(f"generalised search from latencies: {len(fam)} x {len(rows)}")
+    res, zero = capi.infer_cache_params_general(capi.probes(rows), capi.general_models(fam),
+                                                lat=torch.from_numpy(lat.view(np.int32)).cuda(), lat_off=lat_off,
+                                                want_zero=True)
+    assert 90 <= res.threshold_used < 400
+    assert res.best == best and _zero_list(zero, len(fam)) == [int(i) for i in np.nonzero(m == 0)[0]]
+    plan = capi.Plan(256 << 20)
+    try:
+        mn = torch.zeros(2 * len(fam), dtype=torch.int64, device="cuda")
+        res2, zero2 = capi.infer_cache_params_general(capi.probes(rows), capi.general_models(fam),
+                                                      bits=torch.from_numpy(packed.view(np.int32)).cuda(),
+                                                      bitoff=bitoff, mn=mn, want_zero=True, plan=plan)
+        got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        assert np.array_equal(got[:, 0], m) and np.array_equal(got[:, 1], n)
+        assert res2.best == best and np.array_equal(zero2, zero)
+    finally:
+        plan.close()

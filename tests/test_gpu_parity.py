@@ -374,6 +374,27 @@ def test_microbench_pchase_records_the_chase():
     assert ovh > 0 and (l > 0).all() and np.median(l) > ovh
 
 
+def test_microbench_pchase_compact_records():
+    """Without index records the latencies are 16-bit and four times as many
+    fit: a walk of exactly that capacity runs, one more access is refused;
+    an L1-resident chase and one far past L2 keep their order of cost."""
+    torch, capi = need_gpu()
+    kmax = 4 * capi.pchase_microbench_max_k()
+    N, s = 64 << 20, 256
+    arr = torch.zeros(N // 4 + 16, dtype=torch.int32, device="cuda")
+    lat = torch.zeros(kmax + 1, dtype=torch.int32, device="cuda")
+    say(f"microbench_pchase compact, k = {kmax}")
+    far = capi.microbench_pchase(capi.PchaseProbe(N, s, 0, 0, 4, 1), 2, arr, kmax, lat, None)
+    lf = lat[:kmax].cpu().numpy().view(np.uint32)
+    assert (lf > 0).all() and (lf <= 65535).all() and int(lat[kmax:].cpu().numpy()[0]) == 0
+    with pytest.raises(capi.PchaseError) as ei:
+        capi.microbench_pchase(capi.PchaseProbe(N, s, 0, 0, 4, 1), 2, arr, kmax + 1, lat, None)
+    assert ei.value.code == -2
+    near = capi.microbench_pchase(capi.PchaseProbe(4096, 128, 0, 0, 4, 1), 0, arr, 1024, lat, None)
+    ln = lat[:1024].cpu().numpy().view(np.uint32)
+    assert np.median(ln) - near < np.median(lf) - far
+
+
 def test_microbench_lds_bank_conflicts_grow_with_even_strides():
     torch, capi = need_gpu()
     cyc = torch.zeros(64, dtype=torch.int32, device="cuda")
