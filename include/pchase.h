@@ -246,9 +246,9 @@ void pchase_plan_destroy(pchase_plan *plan);
 
 /* ------------------------------------------------------------ replay --- */
 /* Replay scheduling: BATCHED runs every pair in persistent kernels fed by
- * cost-ordered work queues (captured once into a graph for probe replays
- * and inference without a plan); PLAIN launches ordinary kernels, one
- * block per work item.  Results are identical. */
+ * cost-ordered work queues (for inference without a plan, captured once
+ * into a graph that later calls on the same inputs replay); PLAIN launches
+ * ordinary kernels, one block per work item.  Results are identical. */
 enum { PCHASE_BATCHED = 0, PCHASE_PLAIN = 1 };
 
 /* Replays (model, trace) pairs over materialised index traces.

@@ -65,8 +65,9 @@ int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vecto
     plan.dev.arena = ws->arena;
     int rc = build_sweep_plan(&plan, dm, dp, len, jobs, true);
     if (rc) return rc;
+    // a one-off plan: launched directly (a graph would be captured, run once and destroyed)
     rc = run_sweep_plan(ws, &plan, false, ws->aux.as<uint64_t>(), 2 * jobs.size(), bits, true, PCHASE_BATCHED,
-                        stream, {}, "", false, ws->arena == nullptr);
+                        stream, {}, "", false, false);
     if (rc) return rc;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;
@@ -288,8 +289,9 @@ extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models
     plan.dev.arena = ws->arena;
     rc = build_sweep_plan(&plan, dm, dp, len, jobs, hitbits_dev != nullptr);
     if (rc) return rc;
+    // a one-off plan: launched directly (a graph would be captured, run once and destroyed)
     rc = run_sweep_plan(ws, &plan, false, misses_dev, 2 * n_pairs, hitbits_dev, hitbits_dev != nullptr, mode,
-                        stream, {}, "", false, ws->arena == nullptr);
+                        stream, {}, "", false, false);
     if (rc) return rc;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;

@@ -66,6 +66,7 @@ struct Workspace {
     hipStream_t branch[kBranches] = {};   // capture-side streams (default priority)
     hipEvent_t fork = nullptr, join[kBranches] = {};
     hipStream_t rstream[kReplayStreams] = {};   // default priority
+    hipStream_t capture = nullptr;   // the stream graphs are captured on (never runs work itself)
     hipEvent_t rfork = nullptr, rjoin[kReplayStreams] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
     // probe planner: class matrix of the last (candidates, pool) pair

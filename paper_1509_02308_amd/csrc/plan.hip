@@ -386,8 +386,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             plan->gexec = nullptr;
         }
         auto capture = [&](int strategy, hipGraphExec_t* out) -> int {
-            hipStream_t cs;
-            PC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipStream_t cs = ws->capture;   // the workspace's capture stream, reused
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             int rc = PCHASE_OK;
@@ -396,7 +395,6 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
                 rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, cs, tail, strategy);
                 e2 = hipStreamEndCapture(cs, &g);
             }
-            (void)hipStreamDestroy(cs);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
             if (rc) {
                 if (g) (void)hipGraphDestroy(g);
