@@ -150,13 +150,22 @@ def main():
         return capi.infer_cache_params(parr, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_OWN_SWEEP,
                                        mode=capi.EXHAUSTIVE | sched | tune_flag, mn=mn)[0]
 
-    log("inference sweep: cold step (plan, capture" + ("" if args.no_autotune else ", autotune") + ")")
+    log("inference sweep: cold step (plan, capture with the default branch strategy)")
     t_cold0 = time.perf_counter()
     res = step()
     cold_ms = (time.perf_counter() - t_cold0) * 1e3
     assert res.replayed_accesses == accesses, (res.replayed_accesses, accesses)
+    warm_done = 1
+    tune_ms = None
+    if not args.no_autotune:
+        # the second call on the same inputs times the branch strategies
+        t_tune0 = time.perf_counter()
+        res = step()
+        tune_ms = (time.perf_counter() - t_tune0) * 1e3
+        warm_done = 2
+        log(f"inference sweep: tuning step {tune_ms:.1f} ms")
     log(f"inference sweep: cold step {cold_ms:.1f} ms; {args.warmup} warm-up, {args.steps} timed steps")
-    for _ in range(max(0, args.warmup - 1)):
+    for _ in range(max(0, args.warmup - warm_done)):
         res = step()
 
     # timed region: K steps, HIP events on the launch stream around each step
@@ -258,6 +267,7 @@ def main():
                    "accesses_per_step": accesses, "target": target, "schedule": "batched"},
         "time_to_params_ms": float(np.median(lat_ms)),
         "time_to_params_cold_ms": cold_ms,
+        "tuning_step_ms": tune_ms,
         "exact": exact,
         "best": int(res.best),
         "zero_class": int(res.n_zero),

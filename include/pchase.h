@@ -30,8 +30,9 @@
  *     return values to host memory synchronise `stream` before returning;
  *     the others return as soon as the work is enqueued;
  *   - the library keeps per-device workspace (descriptor staging, replay
- *     state, work queues, captured graphs) that it allocates on first use
- *     and grows on demand; pchase_release() frees it.
+ *     state, work queues, cached inference schedules) that it allocates on
+ *     first use and grows on demand; pchase_release() frees it (or a
+ *     caller-owned pchase_plan takes its place, below).
  */
 #ifndef PCHASE_H
 #define PCHASE_H
@@ -230,8 +231,7 @@ int pchase_plan_next_probe(const pchase_model *cands, uint32_t n_cands, const pc
  * created, together with the plan's own streams, events and pinned result
  * page.  A call given a plan allocates no device memory: it carves what it
  * needs from the plan's memory (returning PCHASE_ERANGE, before launching
- * anything that could write outputs, when that does not suffice), and it
- * launches its persistent kernels directly instead of capturing a graph.
+ * anything that could write outputs, when that does not suffice).
  * The plan keeps the schedule of the last inference problem it served, so
  * repeating infer_cache_params on the same inputs rebuilds nothing; any
  * other call replaces what the plan held.  A plan belongs to the device
@@ -246,8 +246,7 @@ void pchase_plan_destroy(pchase_plan *plan);
 
 /* ------------------------------------------------------------ replay --- */
 /* Replay scheduling: BATCHED runs every pair in persistent kernels fed by
- * cost-ordered work queues (for inference without a plan, captured once
- * into a graph that later calls on the same inputs replay); PLAIN launches
+ * cost-ordered work queues, spread over parallel streams; PLAIN launches
  * ordinary kernels, one block per work item.  Results are identical. */
 enum { PCHASE_BATCHED = 0, PCHASE_PLAIN = 1 };
 
@@ -328,12 +327,14 @@ int cache_replay_probes(const pchase_model *models, uint32_t n_models,
 enum { PCHASE_PROBES_ALL = 0, PCHASE_PROBES_OWN_SWEEP = 1 };
 enum { PCHASE_EXHAUSTIVE = 0, PCHASE_LEARNED = 1 };
 /* OR into infer_cache_params' mode to replay with the PLAIN schedule (one
- * launch per candidate) instead of the captured persistent batch. */
+ * launch per candidate) instead of the persistent batch. */
 #define PCHASE_SCHED_PLAIN 0x100
-/* OR into infer_cache_params' mode to capture the batched schedule with its
- * default branch assignment instead of timing every assignment on the first
- * call of a problem (for profiling runs, where the timing loop would be
- * serialised by the profiler). */
+/* The first call of a problem answers with the batched schedule's default
+ * assignment of kernels to streams; the second call on the same inputs
+ * times every assignment and keeps the fastest for the calls after it.  OR
+ * this flag into infer_cache_params' mode to keep the default assignment
+ * (for profiling runs, where the timing loop would be serialised by the
+ * profiler). */
 #define PCHASE_SCHED_UNTUNED 0x200
 
 /* Observed fine-grained P-chase runs (Listing 3 outputs): probe p's trace
@@ -571,11 +572,13 @@ int pchase_mlp_param(const pchase_mlp *net, uint32_t which, uint32_t slot, void 
 int pchase_mlp_step_count(const pchase_mlp *net, uint64_t *steps, int set);
 
 /* --------------------------------------------------------- lifecycle --- */
-/* Sets a host flag that the persistent replays of the BATCHED schedule
- * poll (each wave on its first queue pull, then every 8th pull for
- * materialised traces and every 64th for probe replays); they
- * drain and the call that launched them returns PCHASE_EABORTED, outputs
- * unspecified.  pchase_abort(0) clears it; later calls are unaffected. */
+/* Sets a host flag that stops the BATCHED schedule's replays: a probe
+ * replay or inference that starts while it is set returns PCHASE_EABORTED
+ * before launching anything; running persistent replays poll it (every 8th
+ * queue pull, the first included, for materialised traces; every 64th for
+ * probe replays), drain, and the call that launched them returns
+ * PCHASE_EABORTED, outputs unspecified.  pchase_abort(0) clears it; later
+ * calls are unaffected. */
 void pchase_abort(int on);
 /* Frees the calling thread's current device workspace. */
 int pchase_release(void);

@@ -65,9 +65,8 @@ int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vecto
     plan.dev.arena = ws->arena;
     int rc = build_sweep_plan(&plan, dm, dp, len, jobs, true);
     if (rc) return rc;
-    // a one-off plan: launched directly (a graph would be captured, run once and destroyed)
     rc = run_sweep_plan(ws, &plan, false, ws->aux.as<uint64_t>(), 2 * jobs.size(), bits, true, PCHASE_BATCHED,
-                        stream, {}, "", false, false);
+                        stream, {});
     if (rc) return rc;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;
@@ -289,9 +288,8 @@ extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models
     plan.dev.arena = ws->arena;
     rc = build_sweep_plan(&plan, dm, dp, len, jobs, hitbits_dev != nullptr);
     if (rc) return rc;
-    // a one-off plan: launched directly (a graph would be captured, run once and destroyed)
     rc = run_sweep_plan(ws, &plan, false, misses_dev, 2 * n_pairs, hitbits_dev, hitbits_dev != nullptr, mode,
-                        stream, {}, "", false, false);
+                        stream, {});
     if (rc) return rc;
     PC_HIP(hipStreamSynchronize(stream));
     uint32_t status = 0;
@@ -439,15 +437,12 @@ static int build_tile_schedule(const std::vector<DevModel>& dm, uint32_t n_model
                                const uint32_t* pair_trace, const uint64_t* count_from, uint64_t n_pairs,
                                bool want_bits, const uint64_t* bitoff, TileSchedule* ts) {
     const uint32_t row_cap = 256;
-    struct Key {
-        uint32_t key;   // (policy * kTileWayClasses + way class) * 8 + log2(row class) - 4
-        float cost;
-        uint32_t item;
-    };
     std::vector<TileItem> items;
     items.reserve(n_pairs);
-    std::vector<Key> keys;
-    keys.reserve(n_pairs);
+    std::vector<uint32_t> key;   // group key | cost bucket << 8 of each item
+    std::vector<float> cost;
+    key.reserve(n_pairs);
+    cost.reserve(n_pairs);
     ts->zero_cnt.clear();
     ts->zero_bits.clear();
     for (uint64_t i = 0; i < n_pairs; ++i) {
@@ -487,8 +482,13 @@ static int build_tile_schedule(const std::vector<DevModel>& dm, uint32_t n_model
             t.out = (uint32_t)i;
             t.part = p | (lp << 16);
             const uint32_t grp = m.policy * kTileWayClasses + (uint32_t)tile_way_class(ly.kw);
-            keys.push_back(Key{grp * 8u + cls, (float)((double)len * (8.0 + (double)ly.kw * (1u << ly.lw) / P)),
-                               (uint32_t)items.size()});
+            const float c = (float)((double)len * (8.0 + (double)ly.kw * (1u << ly.lw) / P));
+            // cost bucket: the float's exponent and top 4 mantissa bits, so
+            // that larger costs come first at 1/16-octave resolution
+            uint32_t cb;
+            std::memcpy(&cb, &c, 4);
+            key.push_back((grp * 8u + cls) | ((4095u - ((cb >> 19) & 4095u)) << 8));
+            cost.push_back(c);
             items.push_back(t);
         }
         if (P > 1) {
@@ -501,18 +501,22 @@ static int build_tile_schedule(const std::vector<DevModel>& dm, uint32_t n_model
         }
     }
     if (items.size() >= (1ull << 32)) return set_error(PCHASE_ERANGE, "too many pairs");
-    std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
-        if (x.key != y.key) return x.key < y.key;
-        if (x.cost != y.cost) return x.cost > y.cost;
-        return x.item < y.item;
-    });
-    ts->items.resize(items.size());
-    ts->key.resize(items.size());
-    ts->cost.resize(items.size());
-    for (size_t q = 0; q < keys.size(); ++q) {
-        ts->items[q] = items[keys[q].item];
-        ts->key[q] = keys[q].key;
-        ts->cost[q] = keys[q].cost;
+    // counting sort by (group key, cost bucket), stable: groups contiguous,
+    // longest items first within a group (to the bucket's resolution)
+    const uint32_t n_keys = 4 * kTileWayClasses * 8;
+    auto rank = [&](uint32_t k) { return (k & 0xFFu) * 4096u + (k >> 8); };
+    std::vector<uint32_t> start((size_t)n_keys * 4096 + 1, 0);
+    for (uint32_t k : key) ++start[rank(k) + 1];
+    for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+    const size_t n_items = items.size();
+    ts->items.resize(n_items);
+    ts->key.resize(n_items);
+    ts->cost.resize(n_items);
+    for (size_t q = 0; q < n_items; ++q) {
+        const uint32_t pos = start[rank(key[q])]++;
+        ts->items[pos] = items[q];
+        ts->key[pos] = key[q] & 0xFFu;
+        ts->cost[pos] = cost[q];
     }
     return PCHASE_OK;
 }
@@ -1177,8 +1181,10 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
         if (e != hipSuccess) return e;
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
+    // the first run of a cached plan answers at once with the default branch
+    // strategy; the next run times the strategies and keeps the fastest
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,
-                            sched, stream, tail, "argmin", ip->cached && tune, ws->arena == nullptr);
+                            sched, stream, tail, ip->cached && tune, ip->runs == 0);
     if (rc) return rc;
     ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
     PC_HIP(hipMemcpyAsync(hr, ip->d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));
@@ -1198,6 +1204,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     out->n_zero = hr->n_zero;
     if (zero_host && zw * 4 <= 4096 - 256) std::memcpy(zero_host, static_cast<uint8_t*>(ws->host_res) + 256, zw * 4);
     *replayed = ip->sweep.accesses;
+    ++ip->runs;
     return PCHASE_OK;
 }
 

@@ -122,7 +122,6 @@ struct SweepArgs {
     uint64_t* counters;       // replay: (total, steady) per out; score: m per out
     uint32_t* bits;           // replay: output bitmap or null; score: observed bitmap
     const volatile uint32_t* abort_flag;
-    const uint32_t* abort_snap;   // the flag copied to device memory when the run starts
     uint32_t* aborted;
     uint32_t lds_rows;        // LDS classes: dwords per lane column
     uint32_t map_rows;        // map class: dwords of the map in a column
@@ -205,8 +204,6 @@ struct DevNuProbe {
 hipError_t launch_trace_nu(const DevNuProbe* probes, const DevNuSeg* segs, const uint64_t* off,
                            const ChunkRef* chunks, uint64_t n_chunks, int32_t* idx, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
-// *dst = *src by one thread (a host flag copied into device memory).
-hipError_t launch_snapshot_u32(const volatile uint32_t* src, uint32_t* dst, hipStream_t stream);
 hipError_t launch_argmin(const uint64_t* m, const uint64_t* n, uint32_t nc, uint32_t* zero_bits,
                          ArgminOut* out, hipStream_t stream);
 hipError_t launch_auto_threshold(const uint32_t* lat, uint64_t n, uint32_t* mm, uint32_t* present,

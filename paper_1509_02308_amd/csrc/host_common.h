@@ -41,7 +41,7 @@ struct DevBuf {
 
 struct InferPlan;
 
-// Parallel graph branches of a batched replay.
+// Parallel branch streams of a batched replay.
 constexpr int kBranches = 4;
 // Streams of the materialised-trace replay's concurrent buckets.
 constexpr int kReplayStreams = 8;
@@ -63,19 +63,18 @@ struct Workspace {
     int occ_tile[4 * 5][8] = {};    // [policy * way classes + way class][log2 row class - 4]
     bool tile_ready = false;
     bool lds_ready = false;
-    hipStream_t branch[kBranches] = {};   // capture-side streams (default priority)
+    hipStream_t branch[kBranches] = {};   // branch streams of a batched sweep (default priority)
     hipEvent_t fork = nullptr, join[kBranches] = {};
     hipStream_t rstream[kReplayStreams] = {};   // default priority
-    hipStream_t capture = nullptr;   // the stream graphs are captured on (never runs work itself)
     hipEvent_t rfork = nullptr, rjoin[kReplayStreams] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
     // probe planner: class matrix of the last (candidates, pool) pair
     DevBuf planner;
     std::string planner_key;
     // set for the workspace of a caller-owned plan: every device buffer
-    // comes from this arena, and nothing is captured into graphs
+    // comes from this arena
     Arena* arena = nullptr;
-    // forgets every buffer, cached schedule and graph carved from the arena
+    // forgets every buffer and cached schedule carved from the arena
     void reset_arena();
     ~Workspace();
 };

@@ -182,15 +182,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stre
     return hipGetLastError();
 }
 
-__global__ void snapshot_u32_kernel(const volatile uint32_t* src, uint32_t* dst) {
-    if (threadIdx.x == 0) *dst = *src;
-}
-
-hipError_t launch_snapshot_u32(const volatile uint32_t* src, uint32_t* dst, hipStream_t stream) {
-    hipLaunchKernelGGL(snapshot_u32_kernel, dim3(1), dim3(64), 0, stream, src, dst);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------- argmin ---
 // best = argmin over candidates with n > 0 of m/n, compared exactly as
 // m_i * n_j < m_j * n_i in 128 bits, ties to the lower index.

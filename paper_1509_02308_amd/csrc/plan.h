@@ -1,7 +1,7 @@
 // plan.h -- schedules of the probe-replay kernels: jobs (model x probe)
 // split into wave tasks, grouped by (policy, way class), ordered longest
-// first for the persistent batched launch, and the captured graph that
-// replays a schedule.
+// first for the persistent batched launch, with the branch strategy the
+// autotuner chose for them.
 #pragma once
 
 #include <functional>
@@ -36,10 +36,8 @@ struct SweepPlan {
     SweepTask* d_plain = nullptr;
     uint32_t* d_queues = nullptr;    // one per batched bucket, + status word
     uint64_t* d_clear = nullptr;
-    // captured batched run
-    hipGraphExec_t gexec = nullptr;
-    std::string gkey;
-    int strategy = 0;                // branch strategy of gexec
+    int strategy = 0;                // branch strategy of the batched runs
+    bool tuned = false;              // strategy chosen by timing
     SweepPlan() = default;
     SweepPlan(const SweepPlan&) = delete;
     SweepPlan& operator=(const SweepPlan&) = delete;
@@ -51,17 +49,17 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models,
                      const std::vector<DevProbe>& probes, const std::vector<uint64_t>& probe_len,
                      const std::vector<SweepJob>& jobs, bool want_clear);
 
-// Runs the plan: zeroes `counters` (n_counters words) and the bitmap ranges
-// (when clear_bits), then replays every job.  `tail` (may be empty) is
-// enqueued after the replay, inside the same graph.
-// With autotune (plans that are cached and run again), the first batched
-// run captures every branch strategy, times each and keeps the fastest.
-// use_graph = false (the workspace of a caller-owned plan) launches the
-// batched sequence directly, nothing captured.
+// Runs the plan on `stream` (launches only; the caller synchronises):
+// zeroes `counters` (n_counters words) and the bitmap ranges (when
+// clear_bits), then replays every job; `tail` (may be empty) is enqueued
+// after the replay.  With autotune (plans that are cached and run again),
+// the first batched run that is not deferred times every branch strategy
+// and keeps the fastest for the plan's later runs; defer_tuning leaves the
+// tuning to a later run (a problem's first answer does not wait for it).
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
-                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key,
-                   bool autotune = false, bool use_graph = true);
+                   const std::function<hipError_t(hipStream_t)>& tail, bool autotune = false,
+                   bool defer_tuning = false);
 
 // Cached schedule + score buffers of one inference problem.
 struct InferPlan {
@@ -69,6 +67,7 @@ struct InferPlan {
     bool cached = false;            // kept for later calls (worth autotuning)
     SweepPlan sweep;
     std::vector<uint64_t> n_host;   // compared accesses per candidate
+    uint32_t runs = 0;              // completed runs (the first one is not tuned)
     DevBuf dev;                     // m | n | zero bits | argmin out
     uint64_t* d_m = nullptr;
     uint64_t* d_n = nullptr;

@@ -8,8 +8,7 @@
 // PLAIN runs one ordinary launch per model, tasks in natural order.
 // BATCHED runs one persistent launch per group, each wave pulling tasks
 // from an atomic queue in longest-first order (a counting sort on a
-// log-scale cost estimate), with the whole sequence captured once into a
-// graph and replayed afterwards.
+// log-scale cost estimate), the groups spread over parallel branch streams.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -45,10 +44,7 @@ std::string Digest::str() const {
     return buf;
 }
 
-SweepPlan::~SweepPlan() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    dev.release();
-}
+SweepPlan::~SweepPlan() { dev.release(); }
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -248,10 +244,10 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     return PCHASE_OK;
 }
 
-// Enqueues the batched sequence on `s` (under capture): the buckets, one
-// persistent kernel each, are spread over parallel branches (least-loaded
-// branch first, largest bucket first) so that one bucket's tail overlaps the
-// next bucket's work; the branches join before the tail.
+// Enqueues the batched sequence on `s`: the buckets, one persistent kernel
+// each, are spread over parallel branch streams (least-loaded branch first,
+// largest bucket first) so that one bucket's tail overlaps the next
+// bucket's work; the branches join `s` again before the tail.
 // Branch assignment strategies the autotuner tries (strategy 0 is the
 // untuned default): 0 greedy over 4 branches by estimated cost; 1 the same
 // with LDS-class buckets weighted 3x (their occupancy is LDS-bound); 2 greedy
@@ -267,8 +263,6 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
     PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
     if (clear_bits && bits)
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
-    uint32_t* snap = plan->d_queues + plan->batched.size() + 1;
-    PC_HIP(launch_snapshot_u32(abort_flag_dev(), snap, s));
     const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
     const int nb = (int)std::min<size_t>(want, plan->batched.size());
     if (nb > 1) {
@@ -308,7 +302,6 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         a.counters = counters;
         a.bits = bits;
         a.abort_flag = abort_flag_dev();
-        a.abort_snap = snap;
         a.aborted = plan->d_queues + plan->batched.size();
         a.lds_rows = bk.lds_rows;
         a.map_rows = bk.map_rows;
@@ -336,8 +329,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
 
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
-                   const std::function<hipError_t(hipStream_t)>& tail, const std::string& tail_key, bool autotune,
-                   bool use_graph) {
+                   const std::function<hipError_t(hipStream_t)>& tail, bool autotune, bool defer_tuning) {
     if (mode == PCHASE_PLAIN) {
         const uint32_t nq = (uint32_t)plan->batched.size() + 2;
         PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, stream));
@@ -357,7 +349,6 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             a.counters = counters;
             a.bits = bits;
             a.abort_flag = nullptr;
-            a.abort_snap = nullptr;
             a.aborted = nullptr;
             a.lds_rows = bk.lds_rows;
             a.map_rows = bk.map_rows;
@@ -372,97 +363,51 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
         return PCHASE_OK;
     }
 
-    if (!use_graph) return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail);
-    // batched: capture once per (outputs, tail) and replay the graph; with
-    // autotune, every branch strategy is captured and timed and the fastest
-    // graph is kept
-    char kb[160];
-    snprintf(kb, sizeof kb, "%d|%p|%llu|%p|%d|", (int)score, (void*)counters, (unsigned long long)n_counters,
-             (void*)bits, (int)clear_bits);
-    const std::string key = std::string(kb) + tail_key;
-    if (plan->gexec == nullptr || plan->gkey != key) {
-        if (plan->gexec) {
-            (void)hipGraphExecDestroy(plan->gexec);
-            plan->gexec = nullptr;
+    // a flag already set when the run starts stops it before anything is
+    // launched (the persistent kernels only poll it every 64th pull)
+    if (abort_flag_host() != 0) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
+    // batched: the sequence is launched directly on every run (about twenty
+    // launches against milliseconds of kernel time).  With autotune, a run
+    // of a plan that has not been tuned yet times every branch strategy on
+    // the stream and keeps the fastest for the later runs; the last timed
+    // run uses the chosen strategy, so its outputs are this run's.  With
+    // defer_tuning the run uses the current strategy and leaves the tuning
+    // to the next one (a problem's first answer does not wait for it).
+    const bool tunable = autotune && plan->batched.size() >= 2 && !plan->tuned;
+    if (!tunable || defer_tuning)
+        return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, plan->strategy);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    int best = 0;
+    float best_ms = 0;
+    int rc = PCHASE_OK;
+    for (int st = 0; st < kStrategies && e == hipSuccess && rc == PCHASE_OK; ++st) {
+        float ms = 0;
+        for (int r = 0; r < 2 && e == hipSuccess && rc == PCHASE_OK; ++r) {   // the first run warms up
+            e = hipEventRecord(t0, stream);
+            if (e == hipSuccess)
+                rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, st);
+            if (e == hipSuccess && rc == PCHASE_OK) e = hipEventRecord(t1, stream);
+            if (e == hipSuccess && rc == PCHASE_OK) e = hipEventSynchronize(t1);
+            if (e == hipSuccess && rc == PCHASE_OK) e = hipEventElapsedTime(&ms, t0, t1);
         }
-        auto capture = [&](int strategy, hipGraphExec_t* out) -> int {
-            hipStream_t cs = ws->capture;   // the workspace's capture stream, reused
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-            int rc = PCHASE_OK;
-            hipError_t e2 = hipSuccess;
-            if (e == hipSuccess) {   // a capture that did not begin is not ended
-                rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, cs, tail, strategy);
-                e2 = hipStreamEndCapture(cs, &g);
-            }
-            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            if (rc) {
-                if (g) (void)hipGraphDestroy(g);
-                return rc;
-            }
-            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-            e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                *out = nullptr;
-                return hip_fail(e, "hipGraphInstantiate");
-            }
-            return PCHASE_OK;
-        };
-        // timings of replays that pchase_abort cut short say nothing: with
-        // the flag set the default strategy runs untuned, and the key is
-        // marked so that the next call captures and tunes again
-        const bool aborting = abort_flag_host() != 0;
-        if (!autotune || plan->batched.size() < 2 || aborting) {
-            int rc = capture(0, &plan->gexec);
-            if (rc) return rc;
-            plan->strategy = 0;
-        } else {
-            hipEvent_t t0, t1;
-            PC_HIP(hipEventCreate(&t0));
-            PC_HIP(hipEventCreate(&t1));
-            float best_ms = 0;
-            for (int st = 0; st < kStrategies; ++st) {
-                hipGraphExec_t ge = nullptr;
-                int rc = capture(st, &ge);
-                if (rc) {
-                    (void)hipEventDestroy(t0);
-                    (void)hipEventDestroy(t1);
-                    return rc;
-                }
-                float ms = 0;
-                hipError_t e = hipGraphLaunch(ge, stream);   // warm
-                for (int r = 0; r < 2 && e == hipSuccess; ++r) {
-                    e = hipEventRecord(t0, stream);
-                    if (e == hipSuccess) e = hipGraphLaunch(ge, stream);
-                    if (e == hipSuccess) e = hipEventRecord(t1, stream);
-                    if (e == hipSuccess) e = hipEventSynchronize(t1);
-                    float m = 0;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&m, t0, t1);
-                    if (e == hipSuccess && (r == 0 || m < ms)) ms = m;
-                }
-                if (e != hipSuccess) {
-                    (void)hipGraphExecDestroy(ge);
-                    (void)hipEventDestroy(t0);
-                    (void)hipEventDestroy(t1);
-                    return hip_fail(e, "autotune run");
-                }
-                if (!plan->gexec || ms < best_ms) {
-                    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
-                    plan->gexec = ge;
-                    plan->strategy = st;
-                    best_ms = ms;
-                } else {
-                    (void)hipGraphExecDestroy(ge);
-                }
-            }
-            (void)hipEventDestroy(t0);
-            (void)hipEventDestroy(t1);
+        if (e == hipSuccess && rc == PCHASE_OK && (st == 0 || ms < best_ms)) {
+            best = st;
+            best_ms = ms;
         }
-        plan->gkey = (autotune && aborting) ? key + "|untuned" : key;
     }
-    PC_HIP(hipGraphLaunch(plan->gexec, stream));
-    return PCHASE_OK;
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune run");
+    // timings of replays that pchase_abort cut short say nothing: the plan
+    // stays untuned and the next run tunes again
+    if (abort_flag_host() == 0) {
+        plan->strategy = best;
+        plan->tuned = true;
+    }
+    return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, plan->strategy);
 }
 
 }  // namespace pc

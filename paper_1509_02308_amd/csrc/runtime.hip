@@ -159,7 +159,6 @@ Workspace::~Workspace() {
         if (rjoin[b]) (void)hipEventDestroy(rjoin[b]);
     }
     if (rfork) (void)hipEventDestroy(rfork);
-    if (capture) (void)hipStreamDestroy(capture);
     if (fork) (void)hipEventDestroy(fork);
     stage.release();
     aux.release();
@@ -231,8 +230,6 @@ int workspace_init(Workspace* ws) {
         }
         e = hipEventCreateWithFlags(&ws->rfork, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
-        e = hipStreamCreateWithFlags(&ws->capture, hipStreamNonBlocking);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
         ws->lds_ready = true;
     }
     return PCHASE_OK;

@@ -251,11 +251,9 @@ __global__ void __launch_bounds__(256, 4) sweep_kernel(SweepArgs args) {
         uint32_t t = 0;
         if (lane == 0) {
             t = atomicAdd(args.queue, 1u);
-            // abort: the flag as it stood when the run started (a device
-            // copy) on the first pull, the host flag itself (a read across
-            // PCIe) on every 64th
-            if ((iter == 0 && args.abort_snap != nullptr && *args.abort_snap != 0) ||
-                ((iter & 63) == 63 && args.abort_flag != nullptr && *args.abort_flag != 0)) {
+            // abort: the host flag (a read across PCIe) on every 64th pull;
+            // a flag already set when the call starts is seen by the host
+            if ((iter & 63) == 63 && args.abort_flag != nullptr && *args.abort_flag != 0) {
                 atomicOr(args.aborted, 1u);
                 t = args.n_tasks;
             }

@@ -1,8 +1,8 @@
-"""pchase_abort: with the host flag set before a batched call, every
-persistent kernel leaves the queue on its first pull (each wave polls the
-flag itself, so every kernel exits normally), the call returns
-PCHASE_EABORTED, and once the flag is cleared the very next call on the
-same cached plan is exact against the oracle again."""
+"""pchase_abort: with the host flag set before a batched call, the call
+returns PCHASE_EABORTED (an inference before it launches anything; a
+materialised replay when its persistent kernels, which poll the flag on
+their first queue pull, have drained), and once the flag is cleared the
+very next call on the same inputs is exact against the oracle again."""
 import numpy as np
 import pytest
 
