@@ -1090,18 +1090,33 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
         }
     }
-    int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false);
+    int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false, false);
     if (rc) return rc;
     const size_t zw = (n_cands + 31) / 32;
-    const size_t bytes = 2 * n_cands * sizeof(uint64_t) + zw * 4 + 256 + sizeof(ArgminOut);
+    const uint32_t n_probes = (uint32_t)obs->n_probes;
+    const size_t o_out = (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256;
+    const size_t o_pinfo = (o_out + sizeof(ArgminOut) + 255) / 256 * 256;
+    const size_t o_zeros = o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t);
+    const size_t bytes = o_zeros + (size_t)n_probes * sizeof(uint64_t);
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
     uint8_t* b = np->dev.as<uint8_t>();
     np->d_m = reinterpret_cast<uint64_t*>(b);
     np->d_n = np->d_m + n_cands;
     np->d_zero = reinterpret_cast<uint32_t*>(np->d_n + n_cands);
-    np->d_out = reinterpret_cast<ArgminOut*>(b + (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256);
+    np->d_out = reinterpret_cast<ArgminOut*>(b + o_out);
+    np->d_pinfo = reinterpret_cast<uint64_t*>(b + o_pinfo);
+    np->d_zeros = reinterpret_cast<uint64_t*>(b + o_zeros);
+    np->n_probes = n_probes;
+    np->sweep.zeros = np->d_zeros;
+    std::vector<uint64_t> pinfo(3 * (size_t)n_probes);
+    for (uint32_t p = 0; p < n_probes; ++p) {
+        pinfo[3 * (size_t)p] = bitoff[p];
+        pinfo[3 * (size_t)p + 1] = std::min(cf[p], len[p]);
+        pinfo[3 * (size_t)p + 2] = len[p];
+    }
     PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (n_probes) PC_HIP(hipMemcpy(np->d_pinfo, pinfo.data(), pinfo.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     *out = std::move(np);
     return PCHASE_OK;
 }
@@ -1181,6 +1196,8 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
         if (e != hipSuccess) return e;
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
+    // the observed misses of each probe, the constant part of every score
+    PC_HIP(launch_obs_zeros(bits, ip->d_pinfo, ip->n_probes, ip->d_zeros, stream));
     // the first run of a cached plan answers at once with the default branch
     // strategy; the next run times the strategies and keeps the fastest
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,

@@ -121,6 +121,9 @@ struct SweepArgs {
     const DevProbe* probes;
     uint64_t* counters;       // replay: (total, steady) per out; score: m per out
     uint32_t* bits;           // replay: output bitmap or null; score: observed bitmap
+    const uint64_t* zeros;    // score: per probe, 0 bits (observed misses) of its
+                              // observed bitmap from count_from on; every job of
+                              // a probe compares with that bitmap from that index
     const volatile uint32_t* abort_flag;
     uint32_t* aborted;
     uint32_t lds_rows;        // LDS classes: dwords per lane column
@@ -212,6 +215,10 @@ hipError_t launch_classify(const uint32_t* lat, const uint64_t* lat_off, const u
                            uint32_t n_probes, uint64_t maxlen, const uint32_t* theta, uint32_t* bits,
                            hipStream_t stream);
 hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t n, hipStream_t stream);
+// zeros[p] = number of 0 bits of bits + pinfo[3p] (a word offset) over bit
+// indices [pinfo[3p+1], pinfo[3p+2]) (count_from, length), for p < n.
+hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
+                            hipStream_t stream);
 // m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from
 // cf[p] to len[p], whose hit bit in hits + c * cand_words + hoff[p] differs
 // from the observation's in obs + obits[p] (word offsets).

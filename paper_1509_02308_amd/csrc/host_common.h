@@ -63,8 +63,9 @@ struct Workspace {
     int occ_tile[4 * 5][8] = {};    // [policy * way classes + way class][log2 row class - 4]
     bool tile_ready = false;
     bool lds_ready = false;
-    hipStream_t branch[kBranches] = {};   // branch streams of a batched sweep (default priority)
-    hipEvent_t fork = nullptr, join[kBranches] = {};
+    // branch streams of a batched sweep beyond the caller's own (default priority)
+    hipStream_t branch[kBranches - 1] = {};
+    hipEvent_t fork = nullptr, join[kBranches - 1] = {};
     hipStream_t rstream[kReplayStreams] = {};   // default priority
     hipEvent_t rfork = nullptr, rjoin[kReplayStreams] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;

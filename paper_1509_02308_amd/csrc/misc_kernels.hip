@@ -420,4 +420,35 @@ hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t 
     return hipGetLastError();
 }
 
+// Observed misses per probe, the constant term of the mismatch count (one
+// wave per probe; lanes take words in turn).
+__global__ void obs_zeros_kernel(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t p = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (p >= n) return;
+    const uint32_t* w = bits + pinfo[3 * (uint64_t)p];
+    const uint64_t lo = pinfo[3 * (uint64_t)p + 1], hi = pinfo[3 * (uint64_t)p + 2];
+    uint64_t z = 0;
+    if (lo < hi) {
+        const uint64_t w_lo = lo >> 5, w_hi = (hi - 1) >> 5;
+        for (uint64_t i = w_lo + lane; i <= w_hi; i += kWave) {
+            uint32_t mask = 0xFFFFFFFFu;
+            if (i == w_lo) mask &= 0xFFFFFFFFu << (lo & 31);
+            if (i == w_hi && (hi & 31)) mask &= (1u << (hi & 31)) - 1u;
+            z += (uint64_t)__popc(~w[i] & mask);
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) z += __shfl_xor(z, off, kWave);
+    if (lane == 0) zeros[p] = z;
+}
+
+hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
+                            hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint32_t wpb = 256 / kWave;
+    hipLaunchKernelGGL(obs_zeros_kernel, dim3((n + wpb - 1) / wpb), dim3(256), 0, stream, bits, pinfo, n, zeros);
+    return hipGetLastError();
+}
+
 }  // namespace pc

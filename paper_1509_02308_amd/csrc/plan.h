@@ -36,6 +36,7 @@ struct SweepPlan {
     SweepTask* d_plain = nullptr;
     uint32_t* d_queues = nullptr;    // one per batched bucket, + status word
     uint64_t* d_clear = nullptr;
+    const uint64_t* zeros = nullptr; // scoring: observed misses per probe (SweepArgs::zeros)
     int strategy = 0;                // branch strategy of the batched runs
     bool tuned = false;              // strategy chosen by timing
     SweepPlan() = default;
@@ -44,10 +45,13 @@ struct SweepPlan {
     ~SweepPlan();
 };
 
-// jobs must be grouped by model (each model's jobs contiguous).
+// jobs must be grouped by model (each model's jobs contiguous).  With
+// lds_bitmaps, tasks whose jobs' hit bits fit a wave's LDS bitmap gather
+// them there and store them coalesced (replays that write hit bits);
+// scoring plans need no bitmap.
 int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models,
                      const std::vector<DevProbe>& probes, const std::vector<uint64_t>& probe_len,
-                     const std::vector<SweepJob>& jobs, bool want_clear);
+                     const std::vector<SweepJob>& jobs, bool want_clear, bool lds_bitmaps = true);
 
 // Runs the plan on `stream` (launches only; the caller synchronises):
 // zeroes `counters` (n_counters words) and the bitmap ranges (when
@@ -68,7 +72,10 @@ struct InferPlan {
     SweepPlan sweep;
     std::vector<uint64_t> n_host;   // compared accesses per candidate
     uint32_t runs = 0;              // completed runs (the first one is not tuned)
-    DevBuf dev;                     // m | n | zero bits | argmin out
+    DevBuf dev;                     // m | n | zero bits | argmin out | probe info | observed misses
+    uint64_t* d_pinfo = nullptr;    // per probe: bitmap word offset, count_from, length
+    uint64_t* d_zeros = nullptr;    // per probe: observed misses from count_from on
+    uint32_t n_probes = 0;
     uint64_t* d_m = nullptr;
     uint64_t* d_n = nullptr;
     uint32_t* d_zero = nullptr;

@@ -50,7 +50,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const std::vector<DevProbe>& probes,
                      const std::vector<uint64_t>& probe_len, const std::vector<SweepJob>& jobs_in,
-                     bool want_clear) {
+                     bool want_clear, bool lds_bitmaps) {
     plan->n_models = (uint32_t)models.size();
     plan->n_probes = (uint32_t)probes.size();
     plan->n_jobs = jobs_in.size();
@@ -75,7 +75,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         // at most as many jobs per task as the LDS bitmap holds
         uint64_t maxw = 1;
         for (size_t q = j; q < e; ++q) maxw = std::max<uint64_t>(maxw, (probe_len[jobs[q].probe] + 31) / 32);
-        const uint64_t jpt_bm = std::max<uint64_t>(1, kBmMaxWords / maxw);
+        const uint64_t jpt_bm = lds_bitmaps ? std::max<uint64_t>(1, kBmMaxWords / maxw) : kWave;
         const uint64_t T = m.sets;
         uint64_t G = std::min<uint64_t>(T, kWave);
         double best = -1;
@@ -107,7 +107,7 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
                 jobs[q].bm_off = (uint32_t)words;
                 words += (len + 31) / 32;
             }
-            t.bm_words = words <= kBmMaxWords ? (uint32_t)words : 0u;
+            t.bm_words = (lds_bitmaps && words <= kBmMaxWords) ? (uint32_t)words : 0u;
             int cls = base_cls;
             double wcost = 1.0;
             if (base_cls == kALds) {
@@ -265,9 +265,12 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
     const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
     const int nb = (int)std::min<size_t>(want, plan->batched.size());
+    // branch 0 is `s` itself; branch b > 0 is workspace stream b - 1, forked
+    // from `s` and joined back into it
+    auto branch_stream = [&](int b) { return b == 0 ? s : ws->branch[b - 1]; };
     if (nb > 1) {
         PC_HIP(hipEventRecord(ws->fork, s));
-        for (int b = 0; b < nb; ++b) PC_HIP(hipStreamWaitEvent(ws->branch[b], ws->fork, 0));
+        for (int b = 1; b < nb; ++b) PC_HIP(hipStreamWaitEvent(ws->branch[b - 1], ws->fork, 0));
     }
     auto lds_class = [](const Bucket& bk) { return bk.cls == kAMap || bk.cls == kALds; };
     auto weight = [&](const Bucket& bk) { return (strategy == 1 && lds_class(bk)) ? 3.0 * bk.cost : bk.cost; };
@@ -290,7 +293,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
                 if (load[b] < load[br]) br = b;
         }
         load[br] += weight(bk);
-        hipStream_t bs = nb > 1 ? ws->branch[br] : s;
+        hipStream_t bs = branch_stream(br);
         SweepArgs a;
         a.tasks = plan->d_lpt + bk.first;
         a.n_tasks = bk.count;
@@ -301,6 +304,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         a.probes = plan->d_probes;
         a.counters = counters;
         a.bits = bits;
+        a.zeros = plan->zeros;
         a.abort_flag = abort_flag_dev();
         a.aborted = plan->d_queues + plan->batched.size();
         a.lds_rows = bk.lds_rows;
@@ -317,11 +321,9 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         if (need < blocks) blocks = need;
         PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, blocks, bs));
     }
-    if (nb > 1) {
-        for (int b = 0; b < nb; ++b) {
-            PC_HIP(hipEventRecord(ws->join[b], ws->branch[b]));
-            PC_HIP(hipStreamWaitEvent(s, ws->join[b], 0));
-        }
+    for (int b = 1; b < nb; ++b) {
+        PC_HIP(hipEventRecord(ws->join[b - 1], ws->branch[b - 1]));
+        PC_HIP(hipStreamWaitEvent(s, ws->join[b - 1], 0));
     }
     if (tail) PC_HIP(tail(s));
     return PCHASE_OK;
@@ -348,6 +350,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
             a.probes = plan->d_probes;
             a.counters = counters;
             a.bits = bits;
+            a.zeros = plan->zeros;
             a.abort_flag = nullptr;
             a.aborted = nullptr;
             a.lds_rows = bk.lds_rows;

@@ -150,7 +150,7 @@ void Workspace::reset_arena() {
 }
 
 Workspace::~Workspace() {
-    for (int b = 0; b < kBranches; ++b) {
+    for (int b = 0; b < kBranches - 1; ++b) {
         if (branch[b]) (void)hipStreamDestroy(branch[b]);
         if (join[b]) (void)hipEventDestroy(join[b]);
     }
@@ -214,7 +214,7 @@ int workspace_init(Workspace* ws) {
     if (!ws->lds_ready) {
         e = sweep_prepare_lds();
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-        for (int b = 0; b < kBranches; ++b) {
+        for (int b = 0; b < kBranches - 1; ++b) {
             e = hipStreamCreateWithFlags(&ws->branch[b], hipStreamNonBlocking);
             if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
             e = hipEventCreateWithFlags(&ws->join[b], hipEventDisableTiming);

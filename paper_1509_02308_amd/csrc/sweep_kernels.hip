@@ -18,7 +18,11 @@
 // with a segmented wave reduction; per-access hit bits, when requested, are
 // or-ed into a caller bitmap.  In scoring mode the lane compares its
 // decisions with an observed bitmap instead and accumulates mismatches per
-// candidate model.
+// candidate model.  Every access of a run after its first is a hit, so the
+// mismatch count over [cf, len) is the observed misses there (a per-probe
+// constant) plus, per modelled miss at k >= cf, +1 if the observation says
+// hit and -1 if it says miss: scoring reads the observation only at the
+// model's misses.
 #include <type_traits>
 
 #include "sweep_lane.h"
@@ -37,19 +41,6 @@ __device__ __forceinline__ void or_bits(uint32_t* w, uint32_t lo, uint32_t hi) {
         atomicOr(w + word, mask);
         lo += n;
     }
-}
-
-__device__ __forceinline__ uint32_t ones_in(const uint32_t* w, uint32_t lo, uint32_t hi) {
-    uint32_t c = 0;
-    while (lo < hi) {
-        const uint32_t word = lo >> 5;
-        const uint32_t b0 = lo & 31;
-        const uint32_t n = (hi - lo < 32 - b0) ? hi - lo : 32 - b0;
-        const uint32_t mask = (n == 32) ? 0xFFFFFFFFu : (((1u << n) - 1u) << b0);
-        c += __popc(w[word] & mask);
-        lo += n;
-    }
-    return c;
 }
 
 // ---------------------------------------------------------------- kernel --
@@ -82,24 +73,23 @@ struct Visitor {
     uint32_t cf;
     uint32_t* bits;   // memory bitmap of the job (observed or output), or null
     uint32_t* bm;     // LDS bitmap of the job (BM)
-    uint32_t mt = 0, ms = 0, mm = 0;
+    uint32_t mt = 0;  // replay: misses
+    uint32_t ms = 0;  // misses at k >= cf
+    uint32_t mp = 0;  // score: misses at k >= cf that the observation calls hits
     __device__ __forceinline__ void operator()(uint32_t line, uint32_t q, uint32_t k0, uint32_t r) {
         const bool hit = st->access(line, q, *m, k0, trace_id);
-        if (!hit) {
-            ++mt;
-            ms += (k0 >= cf) ? 1u : 0u;
-        }
-        if constexpr (BM) {
-            or_run(bm, k0, r, hit);
-        } else if constexpr (SCORE) {
-            if (k0 >= cf) {
-                const uint32_t ob = (bits[k0 >> 5] >> (k0 & 31)) & 1u;
-                mm += (ob != (hit ? 1u : 0u)) ? 1u : 0u;
+        if constexpr (SCORE) {
+            if (!hit && k0 >= cf) {
+                ++ms;
+                mp += (bits[k0 >> 5] >> (k0 & 31)) & 1u;
             }
-            const uint32_t lo = (k0 + 1 > cf) ? k0 + 1 : cf, hi = k0 + r;
-            if (lo < hi) mm += (hi - lo) - ones_in(bits, lo, hi);
-        } else if (bits != nullptr) {
-            or_bits(bits, hit ? k0 : k0 + 1, k0 + r);
+        } else {
+            if (!hit) {
+                ++mt;
+                ms += (k0 >= cf) ? 1u : 0u;
+            }
+            if constexpr (BM) or_run(bm, k0, r, hit);
+            else if (bits != nullptr) or_bits(bits, hit ? k0 : k0 + 1, k0 + r);
         }
     }
 };
@@ -124,7 +114,7 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
                                          uint32_t* bm) {
     const DevModel m = args.models[task.model];
     const bool active = (uint32_t)lane < task.n;
-    const bool use_bm = task.bm_words != 0 && (SCORE || args.bits != nullptr);
+    const bool use_bm = !SCORE && task.bm_words != 0 && args.bits != nullptr;
     const uint32_t T = m.sets;
     const uint32_t G = task.lanes;
     if (use_bm) {
@@ -134,7 +124,8 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     uint32_t key = kInvalidTag;
-    uint32_t mt = 0, ms = 0, mm = 0;   // per lane: below the trace length < 2^32
+    uint32_t mt = 0, ms = 0, mp = 0;   // per lane: below the trace length < 2^32
+    uint64_t z = 0;                    // score: the job's observed misses, on its lane g = 0
     if (active) {
         // G lanes per replay (chosen by the plan); lane g of a replay owns
         // the sets g, g+G, g+2G, ... and replays them one after the other
@@ -144,6 +135,7 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         const SweepJob job = args.jobs[task.job + jrel];
         const DevProbe p = args.probes[job.probe];
         key = job.out;
+        if (SCORE && g == 0) z = args.zeros[job.probe];
         uint32_t* bits = (args.bits == nullptr || use_bm) ? nullptr : args.bits + job.bitoff;
         uint32_t* jbm = use_bm ? bm + job.bm_off : nullptr;
         const uint32_t len = p.L * p.passes;
@@ -159,19 +151,19 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
                     st.init(col, args.map_rows, m.ways);
                     Visitor<MapSet<POL>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
                     cached_runs(sc, p, m, set, v);
-                    mt += v.mt; ms += v.ms; mm += v.mm;
+                    mt += v.mt; ms += v.ms; mp += v.mp;
                 } else if constexpr (A == kClassScan) {
                     ScanSet<POL> st;
                     st.init(col, m.ways);
                     Visitor<ScanSet<POL>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
                     cached_runs(sc, p, m, set, v);
-                    mt += v.mt; ms += v.ms; mm += v.mm;
+                    mt += v.mt; ms += v.ms; mp += v.mp;
                 } else {
                     RegSet<POL, A> st;
                     st.init();
                     Visitor<RegSet<POL, A>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
                     cached_runs(sc, p, m, set, v);
-                    mt += v.mt; ms += v.ms; mm += v.mm;
+                    mt += v.mt; ms += v.ms; mp += v.mp;
                 }
             }
         };
@@ -179,8 +171,8 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         else sets(std::false_type{});
     }
     if (use_bm) {
-        // every lane's runs are in the LDS bitmap: compare it with the
-        // observation (score) or store it (replay), word by word, coalesced
+        // every lane's runs are in the LDS bitmap: store it, word by word,
+        // coalesced
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -188,22 +180,9 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         for (uint32_t jr = jlo; jr <= jhi; ++jr) {
             const SweepJob job = args.jobs[task.job + jr];
             const DevProbe p = args.probes[job.probe];
-            const uint32_t len = p.L * p.passes;
-            const uint32_t words = (len + 31) / 32;
-            if constexpr (SCORE) {
-                key = job.out;  // one candidate per task when scoring
-                const uint32_t cf = job.count_from < len ? (uint32_t)job.count_from : len;
-                for (uint32_t w = (cf >> 5) + (uint32_t)lane; w < words; w += kWave) {
-                    uint32_t mask = 0xFFFFFFFFu;
-                    if (w == (cf >> 5)) mask &= ~((1u << (cf & 31)) - 1u);
-                    if (w == words - 1 && (len & 31)) mask &= (1u << (len & 31)) - 1u;
-                    const uint32_t diff = (bm[job.bm_off + w] ^ args.bits[job.bitoff + w]) & mask;
-                    mm += __popc(diff);
-                }
-            } else {
-                for (uint32_t w = (uint32_t)lane; w < words; w += kWave)
-                    args.bits[job.bitoff + w] = bm[job.bm_off + w];
-            }
+            const uint32_t words = (p.L * p.passes + 31) / 32;
+            for (uint32_t w = (uint32_t)lane; w < words; w += kWave)
+                args.bits[job.bitoff + w] = bm[job.bm_off + w];
         }
     }
     // every lane takes part in the shuffle (a shuffle from an inactive lane
@@ -211,7 +190,10 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
     const uint32_t key_up = __shfl_up(key, 1, kWave);
     const bool head = (lane == 0) || (key_up != key);
     if (SCORE) {
-        const uint64_t sm = seg_sum(mm, key, lane);
+        // z + 2 mp - ms, summed modulo 2^64: a lane's part may be negative,
+        // a candidate's total is not
+        const uint64_t part = z + 2 * (uint64_t)mp - (uint64_t)ms;
+        const uint64_t sm = seg_sum(part, key, lane);
         if (head && key != kInvalidTag && sm) atomicAdd((unsigned long long*)&args.counters[key], sm);
     } else {
         const uint64_t st = seg_sum(mt, key, lane);
