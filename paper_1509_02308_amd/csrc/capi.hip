@@ -42,6 +42,25 @@ static int validate_probes(const pchase_probe* probes, uint32_t n, std::vector<D
     return PCHASE_OK;
 }
 
+// Every set of model m holds at most a lines of probe p's array: no access
+// of the probe evicts (a bound: the set's units in the array's address range
+// times the lines per unit).
+static bool no_eviction(const DevModel& m, const DevProbe& p) {
+    const uint64_t xlo = p.base, xhi = p.base + ((uint64_t)(p.ne - 1) << p.elem_shift);
+    const uint64_t units = (xhi >> m.unit_shift) - (xlo >> m.unit_shift) + 1;
+    const uint64_t per_set = ((units + m.sets - 1) / m.sets) << (m.unit_shift - m.line_shift);
+    return per_set <= m.ways;
+}
+
+// Every pass of probe p is one increasing sweep of the array (the chase
+// does not wrap around inside a pass): the first sweep from j0 holds all L
+// accesses of the pass.
+static bool one_sweep_per_pass(const DevProbe& p) {
+    if (p.se == 0) return true;
+    const uint64_t first = ((uint64_t)p.ne - p.j0 + p.se - 1) / p.se;
+    return first >= p.L;
+}
+
 static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     const uint64_t C = c.capacity_bytes, b = c.line_bytes, N = p.n_bytes, s = p.s_bytes;
     if (2 * N < C || N > 2 * C) return false;
@@ -1075,10 +1094,21 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->n_cands = n_cands;
     np->n_host.assign(n_cands, 0);
     std::vector<SweepJob> jobs;
+    std::vector<uint32_t> skip_off(n_cands + 1, 0), skip_probe;
     for (uint32_t c = 0; c < n_cands; ++c) {
+        skip_off[c] = (uint32_t)skip_probe.size();
         if (allow && !(*allow)[c]) continue;
         for (uint32_t p = 0; p < obs->n_probes; ++p) {
             if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
+            if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
+            // no access evicts and nothing before the second pass is
+            // compared: the only misses are first touches, all in the first
+            // pass, so the score is the observed misses alone
+            if (cf[p] >= dp[p].L && no_eviction(dm[c], dp[p])) {
+                skip_probe.push_back(p);
+                np->decided_accesses += len[p];
+                continue;
+            }
             SweepJob j;
             j.model = c;
             j.probe = p;
@@ -1086,10 +1116,12 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             j.trace_id = p;
             j.count_from = cf[p];
             j.bitoff = bitoff[p];
+            j.bm_off = 0;
+            j.cyc = (dm[c].policy == PCHASE_LRU || dm[c].policy == PCHASE_FIFO) && one_sweep_per_pass(dp[p]) ? 1u : 0u;
             jobs.push_back(j);
-            if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
         }
     }
+    skip_off[n_cands] = (uint32_t)skip_probe.size();
     int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false, false);
     if (rc) return rc;
     const size_t zw = (n_cands + 31) / 32;
@@ -1097,7 +1129,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_out = (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256;
     const size_t o_pinfo = (o_out + sizeof(ArgminOut) + 255) / 256 * 256;
     const size_t o_zeros = o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t);
-    const size_t bytes = o_zeros + (size_t)n_probes * sizeof(uint64_t);
+    const size_t o_skip = o_zeros + (size_t)n_probes * sizeof(uint64_t);
+    const size_t bytes = o_skip + (skip_off.size() + skip_probe.size()) * sizeof(uint32_t);
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
     uint8_t* b = np->dev.as<uint8_t>();
@@ -1109,6 +1142,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->d_zeros = reinterpret_cast<uint64_t*>(b + o_zeros);
     np->n_probes = n_probes;
     np->sweep.zeros = np->d_zeros;
+    np->d_skip_off = reinterpret_cast<uint32_t*>(b + o_skip);
+    np->d_skip_probe = np->d_skip_off + skip_off.size();
     std::vector<uint64_t> pinfo(3 * (size_t)n_probes);
     for (uint32_t p = 0; p < n_probes; ++p) {
         pinfo[3 * (size_t)p] = bitoff[p];
@@ -1117,6 +1152,10 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     }
     PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
     if (n_probes) PC_HIP(hipMemcpy(np->d_pinfo, pinfo.data(), pinfo.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(np->d_skip_off, skip_off.data(), skip_off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!skip_probe.empty())
+        PC_HIP(hipMemcpy(np->d_skip_probe, skip_probe.data(), skip_probe.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
     *out = std::move(np);
     return PCHASE_OK;
 }
@@ -1192,7 +1231,9 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
-        hipError_t e = launch_fill_u32(pp->d_zero, zw, 0, s);
+        hipError_t e = launch_add_zeros(pp->d_skip_off, pp->d_skip_probe, pp->n_cands, pp->d_zeros, pp->d_m, s);
+        if (e != hipSuccess) return e;
+        e = launch_fill_u32(pp->d_zero, zw, 0, s);
         if (e != hipSuccess) return e;
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
@@ -1220,7 +1261,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     out->best_n = hr->n;
     out->n_zero = hr->n_zero;
     if (zero_host && zw * 4 <= 4096 - 256) std::memcpy(zero_host, static_cast<uint8_t*>(ws->host_res) + 256, zw * 4);
-    *replayed = ip->sweep.accesses;
+    *replayed = ip->sweep.accesses + ip->decided_accesses;
     ++ip->runs;
     return PCHASE_OK;
 }

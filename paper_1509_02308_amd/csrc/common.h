@@ -17,8 +17,9 @@ constexpr int kWave = 64;
 // Replay classes: ways held in registers (unrolled up to the class bound) or
 // in an LDS column per lane for the large associativities.
 // Large associativities use an LDS map (when the set's lines fit it) or an
-// LDS scan.
-enum WayClass : int { kA1 = 0, kA2, kA4, kA8, kA16, kAMap, kALds, kNumClasses };
+// LDS scan.  kACyc (scoring only) holds no ways: LRU or FIFO jobs whose
+// every pass is one increasing sweep, decided per set in closed form.
+enum WayClass : int { kA1 = 0, kA2, kA4, kA8, kA16, kAMap, kALds, kACyc, kNumClasses };
 constexpr uint32_t kMapMaxEntries = 448;   // map rows + ways <= 240 dwords per lane
 __host__ __device__ inline int way_class(uint32_t a) {
     return a <= 1 ? kA1 : a <= 2 ? kA2 : a <= 4 ? kA4 : a <= 8 ? kA8 : a <= 16 ? kA16 : kALds;
@@ -80,7 +81,7 @@ struct SweepJob {
     uint64_t count_from;
     uint64_t bitoff;      // word offset of the output / observed bitmap
     uint32_t bm_off;      // word offset of the job's bits in its task's LDS bitmap
-    uint32_t pad;
+    uint32_t cyc;         // scoring: 1 if the job is decided in closed form (kACyc)
 };
 
 // A wave's worth of (job, set) items: items item0 .. item0+n-1 of the run of
@@ -217,6 +218,10 @@ hipError_t launch_classify(const uint32_t* lat, const uint64_t* lat_off, const u
 hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t n, hipStream_t stream);
 // zeros[p] = number of 0 bits of bits + pinfo[3p] (a word offset) over bit
 // indices [pinfo[3p+1], pinfo[3p+2]) (count_from, length), for p < n.
+// m[c] += zeros[probe[i]] for i in [off[c], off[c+1]), c < n: the scores of
+// jobs decided without a replay.
+hipError_t launch_add_zeros(const uint32_t* off, const uint32_t* probe, uint32_t n, const uint64_t* zeros,
+                            uint64_t* m, hipStream_t stream);
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
                             hipStream_t stream);
 // m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from

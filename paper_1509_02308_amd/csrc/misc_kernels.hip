@@ -443,6 +443,22 @@ __global__ void obs_zeros_kernel(const uint32_t* bits, const uint64_t* pinfo, ui
     if (lane == 0) zeros[p] = z;
 }
 
+__global__ void add_zeros_kernel(const uint32_t* off, const uint32_t* probe, uint32_t n, const uint64_t* zeros,
+                                 uint64_t* m) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    uint64_t z = 0;
+    for (uint32_t i = off[c]; i < off[c + 1]; ++i) z += zeros[probe[i]];
+    m[c] += z;
+}
+
+hipError_t launch_add_zeros(const uint32_t* off, const uint32_t* probe, uint32_t n, const uint64_t* zeros,
+                            uint64_t* m, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_zeros_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, off, probe, n, zeros, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
                             hipStream_t stream) {
     if (n == 0) return hipSuccess;

@@ -70,54 +70,64 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         size_t e = j;
         while (e < jobs.size() && jobs[e].model == mi) ++e;
         const DevModel& m = models[mi];
-        // G lanes per job: the choice that keeps most lanes busy, counting
-        // lanes left idle (64 mod G) and sets shared unevenly (T mod G), with
-        // at most as many jobs per task as the LDS bitmap holds
-        uint64_t maxw = 1;
-        for (size_t q = j; q < e; ++q) maxw = std::max<uint64_t>(maxw, (probe_len[jobs[q].probe] + 31) / 32);
-        const uint64_t jpt_bm = lds_bitmaps ? std::max<uint64_t>(1, kBmMaxWords / maxw) : kWave;
-        const uint64_t T = m.sets;
-        uint64_t G = std::min<uint64_t>(T, kWave);
-        double best = -1;
-        for (uint64_t d = std::min<uint64_t>(T, kWave); d >= 1; --d) {
-            const uint64_t jp = std::min<uint64_t>(std::max<uint64_t>(1, kWave / d), jpt_bm);
-            const double sets_per_lane = std::ceil((double)T / (double)d);
-            const double eff = (double)(jp * d) / kWave * ((double)T / (double)d) / sets_per_lane;
-            if (eff > best + 0.03) {
-                best = eff;
-                G = d;
+        // closed-form jobs (scoring) first: each group forms tasks of its own
+        const size_t mid = (size_t)(std::stable_partition(jobs.begin() + j, jobs.begin() + e,
+                                                          [](const SweepJob& x) { return x.cyc != 0; }) -
+                                    jobs.begin());
+        for (int grp = 0; grp < 2; ++grp) {
+            const size_t gb = grp == 0 ? j : mid, ge = grp == 0 ? mid : e;
+            if (gb == ge) continue;
+            // G lanes per job: the choice that keeps most lanes busy, counting
+            // lanes left idle (64 mod G) and sets shared unevenly (T mod G), with
+            // at most as many jobs per task as the LDS bitmap holds
+            uint64_t maxw = 1;
+            for (size_t q = gb; q < ge; ++q) maxw = std::max<uint64_t>(maxw, (probe_len[jobs[q].probe] + 31) / 32);
+            const uint64_t jpt_bm = lds_bitmaps ? std::max<uint64_t>(1, kBmMaxWords / maxw) : kWave;
+            const uint64_t T = m.sets;
+            uint64_t G = std::min<uint64_t>(T, kWave);
+            double best = -1;
+            for (uint64_t d = std::min<uint64_t>(T, kWave); d >= 1; --d) {
+                const uint64_t jp = std::min<uint64_t>(std::max<uint64_t>(1, kWave / d), jpt_bm);
+                const double sets_per_lane = std::ceil((double)T / (double)d);
+                const double eff = (double)(jp * d) / kWave * ((double)T / (double)d) / sets_per_lane;
+                if (eff > best + 0.03) {
+                    best = eff;
+                    G = d;
+                }
             }
-        }
-        const uint64_t jpt = std::min<uint64_t>(std::max<uint64_t>(1, kWave / G), jpt_bm);  // jobs per task
-        const double per_set = std::ceil((double)m.sets / (double)G) / (double)m.sets;
-        const int base_cls = way_class(m.ways);
-        for (uint64_t q0 = j; q0 < e; q0 += jpt) {
-            const uint64_t q1 = std::min<uint64_t>(e, q0 + jpt);
-            SweepTask t;
-            t.job = (uint32_t)j;
-            t.item0 = (uint32_t)((q0 - j) * G);
-            t.n = (uint32_t)((q1 - q0) * G);
-            t.model = mi;
-            t.lanes = (uint32_t)G;
-            uint64_t ml = 0, me = 0, words = 0;
-            for (uint64_t q = q0; q < q1; ++q) {
-                const uint64_t len = probe_len[jobs[q].probe];
-                ml = std::max(ml, len);
-                if (base_cls == kALds) me = std::max(me, map_entries(probes[jobs[q].probe], m));
-                jobs[q].bm_off = (uint32_t)words;
-                words += (len + 31) / 32;
+            const uint64_t jpt = std::min<uint64_t>(std::max<uint64_t>(1, kWave / G), jpt_bm);  // jobs per task
+            const double per_set = std::ceil((double)m.sets / (double)G) / (double)m.sets;
+            const int base_cls = grp == 0 ? (int)kACyc : way_class(m.ways);
+            for (uint64_t q0 = gb; q0 < ge; q0 += jpt) {
+                const uint64_t q1 = std::min<uint64_t>(ge, q0 + jpt);
+                SweepTask t;
+                t.job = (uint32_t)gb;
+                t.item0 = (uint32_t)((q0 - gb) * G);
+                t.n = (uint32_t)((q1 - q0) * G);
+                t.model = mi;
+                t.lanes = (uint32_t)G;
+                uint64_t ml = 0, me = 0, words = 0;
+                for (uint64_t q = q0; q < q1; ++q) {
+                    const uint64_t len = probe_len[jobs[q].probe];
+                    ml = std::max(ml, len);
+                    if (base_cls == kALds) me = std::max(me, map_entries(probes[jobs[q].probe], m));
+                    jobs[q].bm_off = (uint32_t)words;
+                    words += (len + 31) / 32;
+                }
+                t.bm_words = (lds_bitmaps && words <= kBmMaxWords) ? (uint32_t)words : 0u;
+                int cls = base_cls;
+                double wcost = 1.0;
+                if (base_cls == kALds) {
+                    if (me <= kMapMaxEntries) cls = kAMap;
+                    else wcost = (double)m.ways;
+                } else if (base_cls == kACyc) {
+                    wcost = 0.5;   // the first pass only, no way state
+                }
+                tasks.push_back(t);
+                tcls.push_back((uint8_t)cls);
+                tmap.push_back((uint16_t)(cls == kAMap ? (me + 3) / 4 : 0));
+                cost.push_back((float)((double)ml * per_set * wcost + 64.0));
             }
-            t.bm_words = (lds_bitmaps && words <= kBmMaxWords) ? (uint32_t)words : 0u;
-            int cls = base_cls;
-            double wcost = 1.0;
-            if (base_cls == kALds) {
-                if (me <= kMapMaxEntries) cls = kAMap;
-                else wcost = (double)m.ways;
-            }
-            tasks.push_back(t);
-            tcls.push_back((uint8_t)cls);
-            tmap.push_back((uint16_t)(cls == kAMap ? (me + 3) / 4 : 0));
-            cost.push_back((float)((double)ml * per_set * wcost + 64.0));
         }
         for (size_t q = j; q < e; ++q) plan->accesses += probe_len[jobs[q].probe];
         j = e;
@@ -165,7 +175,9 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
         std::vector<uint32_t> key(tasks.size());
         for (size_t i = 0; i < tasks.size(); ++i) {
             const DevModel& m = models[tasks[i].model];
-            const int grp = (int)m.policy * kNumClasses + tcls[i];
+            // closed-form tasks of LRU and FIFO models share one kernel
+            const int pol = tcls[i] == kACyc ? (int)PCHASE_LRU : (int)m.policy;
+            const int grp = pol * kNumClasses + tcls[i];
             int cb = (int)std::floor(std::log2((double)cost[i] + 1.0) * 8.0);
             cb = std::max(0, std::min(255, cb));
             key[i] = (uint32_t)(grp * 256 + (255 - cb));
@@ -180,7 +192,8 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     for (size_t i = 0; i < order.size(); ++i) {
         lpt[i] = tasks[order[i]];
         const DevModel& m = models[lpt[i].model];
-        const int pol = (int)m.policy, cls = tcls[order[i]];
+        const int cls = tcls[order[i]];
+        const int pol = cls == kACyc ? (int)PCHASE_LRU : (int)m.policy;
         if (plan->batched.empty() || plan->batched.back().pol != pol || plan->batched.back().cls != cls) {
             plan->batched.push_back(Bucket{pol, cls, (uint32_t)i, 0, 0, 0, 0.0, 0});
             bucket_amax.push_back(0);

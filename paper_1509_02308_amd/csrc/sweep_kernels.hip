@@ -94,6 +94,39 @@ struct Visitor {
     }
 };
 
+// Scoring of an LRU or FIFO job whose every pass is one increasing sweep
+// (Section 4.1's cyclic P-chase): each line of a set is visited by one run
+// per pass, in the same order in every pass.  With n lines in the set and a
+// ways, the first pass's run starts miss (cold), and when n > a so does
+// every later run start: since a line's last use all n - 1 other lines of
+// the set were used, which evicts it under LRU (its reuse distance is at
+// least a), and under FIFO (every access so far missed and inserted, so the
+// a lines held are the a used just before it).  When n <= a nothing is ever
+// evicted.  Every other access hits.  The lane walks the first pass only and
+// looks the observation up at every pass's copy of each run start.
+struct CycVisitor {
+    uint32_t cf, L, passes;
+    const uint32_t* bits;
+    uint32_t n = 0;               // runs (lines) of the set in a pass
+    uint32_t ms1 = 0, mp1 = 0;    // first pass: counted misses, of which the observation calls hits
+    uint32_t ms2 = 0, mp2 = 0;    // the later passes, if n > a
+    __device__ __forceinline__ void operator()(uint32_t, uint32_t, uint32_t k0, uint32_t) {
+        ++n;
+        if (k0 >= cf) {
+            ++ms1;
+            mp1 += (bits[k0 >> 5] >> (k0 & 31)) & 1u;
+        }
+        uint32_t k = k0;
+        for (uint32_t q = 1; q < passes; ++q) {
+            k += L;
+            if (k >= cf) {
+                ++ms2;
+                mp2 += (bits[k >> 5] >> (k & 31)) & 1u;
+            }
+        }
+    }
+};
+
 __device__ __forceinline__ uint64_t seg_sum(uint64_t v, uint32_t key, int lane) {
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -107,6 +140,7 @@ __device__ __forceinline__ uint64_t seg_sum(uint64_t v, uint32_t key, int lane) 
 // Way classes of the kernel template: 1..16 are register classes.
 constexpr int kClassMap = 1000;
 constexpr int kClassScan = 2000;
+constexpr int kClassCyc = 3000;   // closed form (CycVisitor), scoring only
 constexpr uint32_t kMaxLdsRows = 240;  // with the bitmap, 64 KB per one-wave block at most
 
 template <int POL, int A, bool SCORE>
@@ -146,7 +180,19 @@ __device__ __forceinline__ void run_task(const SweepArgs& args, const SweepTask&
         auto sets = [&](auto bm_tag) {
             constexpr bool BM = decltype(bm_tag)::value;
             for (uint32_t set = g; set < T; set += G) {
-                if constexpr (A == kClassMap) {
+                if constexpr (A == kClassCyc) {
+                    CycVisitor v{cf, p.L, p.passes, bits};
+                    if (sc.n <= kCachedSweeps) {
+                        for (uint32_t i = 0; i < sc.n; ++i)
+                            sweep_walk(pick_sweep(i != 0, sc.w1, sc.w0), 0, sc.sb, m, p, set, sc.qlo, v);
+                    } else {
+                        auto f = [&](const Sweep& w) { sweep_walk(w, 0, sc.sb, m, p, set, sc.qlo, v); };
+                        pass_sweeps(p, m, f);
+                    }
+                    const bool thrash = v.n > m.ways;
+                    ms += v.ms1 + (thrash ? v.ms2 : 0u);
+                    mp += v.mp1 + (thrash ? v.mp2 : 0u);
+                } else if constexpr (A == kClassMap) {
                     MapSet<POL> st;
                     st.init(col, args.map_rows, m.ways);
                     Visitor<MapSet<POL>, SCORE, BM> v{&st, &m, job.trace_id, cf, bits, jbm};
@@ -251,6 +297,11 @@ using SweepFn = void (*)(SweepArgs);
 
 template <bool SCORE>
 static SweepFn pick(int pol, int cls) {
+    if (cls == kACyc) {
+        // one kernel for LRU and FIFO; replays that write bits never use it
+        if constexpr (SCORE) return sweep_kernel<PCHASE_LRU, kClassCyc, true>;
+        else return nullptr;
+    }
 #define PC_CASE(P)                                           \
     switch (cls) {                                           \
         case kA1: return sweep_kernel<P, 1, SCORE>;          \
@@ -289,6 +340,7 @@ hipError_t launch_sweep(bool score, int pol, int cls, const SweepArgs& args, uin
     size_t lds;
     sweep_geometry(cls, args.lds_rows, args.bm_words, &threads, &lds);
     SweepFn fn = score ? pick<true>(pol, cls) : pick<false>(pol, cls);
+    if (fn == nullptr) return hipErrorInvalidDeviceFunction;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, stream, args);
     return hipGetLastError();
 }
@@ -299,6 +351,7 @@ hipError_t sweep_occupancy(bool score, int pol, int cls, uint32_t lds_rows, uint
     size_t lds;
     sweep_geometry(cls, lds_rows, bm_words, &threads, &lds);
     SweepFn fn = score ? pick<true>(pol, cls) : pick<false>(pol, cls);
+    if (fn == nullptr) return hipErrorInvalidDeviceFunction;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)fn, threads, lds);
 }
 

@@ -324,6 +324,39 @@ def test_inference_all_probes_mode():
     assert res.best == best
 
 
+def test_inference_scores_any_observation_and_count_from():
+    """Every scoring path against the oracle on an arbitrary (random)
+    observation: every way class and policy, set_shift mappings, probes of
+    1 to 4 passes, chases that wrap inside a pass, j0 and base offsets, and
+    count_from anywhere from 0 to past the first pass (jobs with no eviction
+    and nothing of the first pass compared are decided without a replay;
+    LRU and FIFO jobs whose passes are single sweeps in closed form)."""
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(2024)
+    lens = [orc.trace_len(orc_probe(r)) for r in PROBES]
+    L = [orc.cycle_len(orc_probe(r)) for r in PROBES]
+    for trial, density in enumerate((0.5, 0.9)):
+        hits_all = [(rng.random(n) < density).astype(np.uint8) for n in lens]
+        off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+        choices = [lambda i: 0, lambda i: L[i] // 2, lambda i: L[i], lambda i: L[i] + 1,
+                   lambda i: min(2 * L[i] - 1, lens[i]), lambda i: lens[i]]
+        cfs = np.array([choices[(i + trial) % len(choices)](i) for i in range(len(PROBES))], np.uint64)
+        best, m, n = orc.infer([orc_model(r) for r in MODELS], [orc_probe(r) for r in PROBES],
+                               np.concatenate(hits_all), off, cfs, probe_select=0)
+        packed, bitoff = _bits_layout(hits_all)
+        mn = torch.zeros(2 * len(MODELS), dtype=torch.int64, device="cuda")
+        say(f"infer_cache_params random observation, trial {trial}")
+        for sched in (0, capi.SCHED_PLAIN):
+            res, _ = capi.infer_cache_params(capi.probes(PROBES), capi.models(MODELS),
+                                             bits=torch.from_numpy(packed.view(np.int32)).cuda(), bitoff=bitoff,
+                                             count_from=cfs, probe_select=0, mn=mn, mode=sched)
+            got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+            bad = np.nonzero((got[:, 0] != m) | (got[:, 1] != n))[0]
+            assert len(bad) == 0, [(MODELS[int(c)], tuple(got[c]), (int(m[c]), int(n[c]))) for c in bad[:5]]
+            assert res.best == best and res.best_m == m[best]
+            assert res.replayed_accesses == len(MODELS) * sum(lens)
+
+
 @pytest.mark.timeout(600)
 def test_inference_full_candidate_grid():
     """The full search: 438 candidates (C 8..64 KB, b 32..128 B, a 1..64,

@@ -199,6 +199,62 @@ def test_overflow_by_lines_closed_form(orc, policy, C, b, a):
                 assert ms == ((N - C) // b) * (a + 1)
 
 
+# ---------------------- cyclic chases: closed forms per set, Section 4.1 --
+def test_cyclic_chase_closed_forms(orc):
+    """Two closed forms of the replay (the scoring kernels use both):
+    (1) when every set holds at most a of the array's lines, any policy
+    misses exactly on the first touch of each line; (2) LRU and FIFO on a
+    chase whose every pass is one increasing sweep: each set's run starts
+    (first access of each line visit) miss in the first pass, and in every
+    later pass exactly when the set holds more lines than ways.  Random
+    models with set_shift mappings, non-power-of-two sets and ways, j0 and
+    base offsets, 1 to 3 passes."""
+    rng = np.random.default_rng(5)
+    checked = [0, 0]
+    for _ in range(1500):
+        b = int(rng.choice([4, 8, 16, 32]))
+        a = int(rng.choice([1, 2, 3, 4, 8]))
+        T = int(rng.choice([1, 2, 3, 4, 8]))
+        pol = int(rng.choice([0, 1, 2, 3]))
+        if pol == orc.PLRU and a & (a - 1):
+            continue
+        lb = b.bit_length() - 1
+        ss = lb + int(rng.integers(0, 3)) if rng.random() < 0.3 else 0
+        C = a * b * T
+        N = int(rng.integers(1, 6 * C // 4 + 2)) * 4
+        s = int(rng.integers(1, 3 * b // 4 + 2)) * 4
+        passes = int(rng.integers(1, 4))
+        j0 = int(rng.integers(0, N // 4)) if rng.random() < 0.3 else 0
+        base = int(rng.integers(0, 64)) * 4 if rng.random() < 0.3 else 0
+        m = orc.make_model(C, b, a, pol, set_shift=ss, seed=7)
+        p = orc.make_probe(N, s, passes=passes, j0=j0, base=base)
+        idx = np.asarray(orc.trace(p), np.int64)
+        L = orc.cycle_len(p)
+        hits, _, _ = orc.replay(m, idx, base=base, trace_id=3, count_from=0)
+        miss = 1 - np.asarray(hits)
+        addr = base + 4 * idx
+        us = ss if ss else lb
+        sets, lines = (addr >> us) % T, addr >> lb
+        units = ((base + (N // 4 - 1) * 4) >> us) - (base >> us) + 1
+        if (-(-units // T)) << (us - lb) <= a:
+            first = np.zeros(len(idx), np.uint8)
+            first[np.unique(lines, return_index=True)[1]] = 1
+            assert np.array_equal(miss, first), (C, b, a, pol, ss, N, s, passes, j0, base)
+            checked[0] += 1
+        ne, se = N // 4, (s // 4) % (N // 4)
+        if pol in (orc.LRU, orc.FIFO) and (se == 0 or (ne - j0 + se - 1) // se >= L):
+            expect = np.zeros(len(idx), np.uint8)
+            for t in range(T):
+                ks = np.nonzero(sets[:L] == t)[0]
+                starts = [k for i, k in enumerate(ks) if i == 0 or lines[k] != lines[ks[i - 1]]]
+                n_lines = len({int(lines[k]) for k in ks})
+                for q in range(passes if n_lines > a else 1):
+                    expect[np.asarray(starts, np.int64) + q * L] = 1
+            assert np.array_equal(miss, expect), (C, b, a, pol, ss, N, s, passes, j0, base)
+            checked[1] += 1
+    assert min(checked) > 100, checked
+
+
 # ------------------------------------ I4: Eq. (1), Section 4.1 ---------
 @pytest.mark.parametrize("C,b,a", [(4096, 32, 4), (16384, 64, 8), (8192, 128, 2), (32768, 32, 16)])
 def test_eq1_stride_special_cases(orc, C, b, a):
