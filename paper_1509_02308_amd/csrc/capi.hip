@@ -61,6 +61,36 @@ static bool one_sweep_per_pass(const DevProbe& p) {
     return first >= p.L;
 }
 
+// Runs of one pass under line size 2^ls when the pass is one increasing
+// sweep whose visited lines form an arithmetic progression (step d lines):
+// every line of the swept range when the stride is at most a line, one line
+// per access when the stride is a multiple of the line.  Returns 0 otherwise.
+static uint64_t sweep_runs(const DevProbe& p, uint32_t ls, uint64_t* d) {
+    if (!one_sweep_per_pass(p)) return 0;
+    *d = 1;
+    if (p.se == 0 || p.L == 1) return 1;
+    const uint64_t sb = (uint64_t)p.se << p.elem_shift, b = 1ull << ls;
+    const uint64_t x0 = p.base + ((uint64_t)p.j0 << p.elem_shift);
+    if (sb <= b) return ((x0 + (uint64_t)(p.L - 1) * sb) >> ls) - (x0 >> ls) + 1;
+    if (sb % b == 0) {
+        *d = sb >> ls;
+        return p.L;
+    }
+    return 0;
+}
+
+static uint64_t gcd64(uint64_t x, uint64_t y) {
+    while (y) {
+        const uint64_t t = x % y;
+        x = y;
+        y = t;
+    }
+    return x;
+}
+
+// Largest run table (entries of 8 bytes) an inference plan builds.
+constexpr uint64_t kMaxTableEntries = 1ull << 24;
+
 static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     const uint64_t C = c.capacity_bytes, b = c.line_bytes, N = p.n_bytes, s = p.s_bytes;
     if (2 * N < C || N > 2 * C) return false;
@@ -1094,20 +1124,61 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->n_cands = n_cands;
     np->n_host.assign(n_cands, 0);
     std::vector<SweepJob> jobs;
-    std::vector<uint32_t> skip_off(n_cands + 1, 0), skip_probe;
+    std::vector<uint32_t> dec_off(n_cands + 1, 0);
+    std::vector<DecidedJob> decided;
+    std::vector<RunTable> tables;
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> table_of;   // (probe, line shift) -> table
+    uint64_t entries = 0;
     for (uint32_t c = 0; c < n_cands; ++c) {
-        skip_off[c] = (uint32_t)skip_probe.size();
+        dec_off[c] = (uint32_t)decided.size();
         if (allow && !(*allow)[c]) continue;
+        const DevModel& md = dm[c];
+        const bool lru_fifo = md.policy == PCHASE_LRU || md.policy == PCHASE_FIFO;
         for (uint32_t p = 0; p < obs->n_probes; ++p) {
             if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
             if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
             // no access evicts and nothing before the second pass is
             // compared: the only misses are first touches, all in the first
             // pass, so the score is the observed misses alone
-            if (cf[p] >= dp[p].L && no_eviction(dm[c], dp[p])) {
-                skip_probe.push_back(p);
+            if (cf[p] >= dp[p].L && no_eviction(md, dp[p])) {
+                decided.push_back(DecidedJob{p, 0, 0, 0, 1});
                 np->decided_accesses += len[p];
                 continue;
+            }
+            // single-sweep passes over an arithmetic progression of lines
+            // (one line per set-mapping unit): run i of a pass lies in set
+            // (l0 + i d) mod T, so runs i and i + T' (T' = T / gcd(d, T))
+            // share a set and the runs of one period are in distinct sets;
+            // a visited set holds q0 or q0 + 1 lines (the latter for
+            // i mod T' < r, with U runs = q0 T' + r)
+            uint64_t d = 1;
+            const uint64_t U = md.unit_shift == md.line_shift ? sweep_runs(dp[p], md.line_shift, &d) : 0;
+            if (U) {
+                const uint64_t Tp = md.sets / gcd64(d % md.sets, md.sets);
+                const uint64_t q0 = U / Tp, r = U % Tp;
+                const bool none = q0 + (r ? 1 : 0) <= md.ways;   // no eviction
+                const int kind = none ? (cf[p] >= dp[p].L ? 0 : 1) : !lru_fifo ? -1 : q0 > md.ways ? 2 : 3;
+                uint32_t tid = 0;
+                bool ok = kind >= 0;
+                if (kind >= 1) {
+                    auto key = std::make_pair(p, md.line_shift);
+                    auto it = table_of.find(key);
+                    if (it != table_of.end()) {
+                        tid = it->second;
+                    } else if (entries + U + 1 <= kMaxTableEntries) {
+                        tid = (uint32_t)tables.size();
+                        tables.push_back(RunTable{p, md.line_shift, U, entries});
+                        table_of.emplace(key, tid);
+                        entries += U + 1;
+                    } else {
+                        ok = false;
+                    }
+                }
+                if (ok) {
+                    decided.push_back(DecidedJob{p, tid, (uint32_t)kind, (uint32_t)r, Tp});
+                    np->decided_accesses += len[p];
+                    continue;
+                }
             }
             SweepJob j;
             j.model = c;
@@ -1117,11 +1188,11 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             j.count_from = cf[p];
             j.bitoff = bitoff[p];
             j.bm_off = 0;
-            j.cyc = (dm[c].policy == PCHASE_LRU || dm[c].policy == PCHASE_FIFO) && one_sweep_per_pass(dp[p]) ? 1u : 0u;
+            j.cyc = lru_fifo && one_sweep_per_pass(dp[p]) ? 1u : 0u;
             jobs.push_back(j);
         }
     }
-    skip_off[n_cands] = (uint32_t)skip_probe.size();
+    dec_off[n_cands] = (uint32_t)decided.size();
     int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false, false);
     if (rc) return rc;
     const size_t zw = (n_cands + 31) / 32;
@@ -1129,8 +1200,13 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_out = (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256;
     const size_t o_pinfo = (o_out + sizeof(ArgminOut) + 255) / 256 * 256;
     const size_t o_zeros = o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t);
-    const size_t o_skip = o_zeros + (size_t)n_probes * sizeof(uint64_t);
-    const size_t bytes = o_skip + (skip_off.size() + skip_probe.size()) * sizeof(uint32_t);
+    auto up256 = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_dec = up256(o_zeros + (size_t)n_probes * sizeof(uint64_t));
+    const size_t o_doff = up256(o_dec + decided.size() * sizeof(DecidedJob));
+    const size_t o_tab = up256(o_doff + dec_off.size() * sizeof(uint32_t));
+    const size_t o_s1 = up256(o_tab + tables.size() * sizeof(RunTable));
+    const size_t o_pre = up256(o_s1 + tables.size() * sizeof(int64_t));
+    const size_t bytes = o_pre + entries * sizeof(int64_t);
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
     uint8_t* b = np->dev.as<uint8_t>();
@@ -1142,8 +1218,12 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->d_zeros = reinterpret_cast<uint64_t*>(b + o_zeros);
     np->n_probes = n_probes;
     np->sweep.zeros = np->d_zeros;
-    np->d_skip_off = reinterpret_cast<uint32_t*>(b + o_skip);
-    np->d_skip_probe = np->d_skip_off + skip_off.size();
+    np->d_decided = reinterpret_cast<DecidedJob*>(b + o_dec);
+    np->d_dec_off = reinterpret_cast<uint32_t*>(b + o_doff);
+    np->d_tables = reinterpret_cast<RunTable*>(b + o_tab);
+    np->d_s1 = reinterpret_cast<int64_t*>(b + o_s1);
+    np->d_prefix = reinterpret_cast<int64_t*>(b + o_pre);
+    np->n_tables = (uint32_t)tables.size();
     std::vector<uint64_t> pinfo(3 * (size_t)n_probes);
     for (uint32_t p = 0; p < n_probes; ++p) {
         pinfo[3 * (size_t)p] = bitoff[p];
@@ -1152,10 +1232,11 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     }
     PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
     if (n_probes) PC_HIP(hipMemcpy(np->d_pinfo, pinfo.data(), pinfo.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    PC_HIP(hipMemcpy(np->d_skip_off, skip_off.data(), skip_off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    if (!skip_probe.empty())
-        PC_HIP(hipMemcpy(np->d_skip_probe, skip_probe.data(), skip_probe.size() * sizeof(uint32_t),
-                         hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(np->d_dec_off, dec_off.data(), dec_off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!decided.empty())
+        PC_HIP(hipMemcpy(np->d_decided, decided.data(), decided.size() * sizeof(DecidedJob), hipMemcpyHostToDevice));
+    if (!tables.empty())
+        PC_HIP(hipMemcpy(np->d_tables, tables.data(), tables.size() * sizeof(RunTable), hipMemcpyHostToDevice));
     *out = std::move(np);
     return PCHASE_OK;
 }
@@ -1231,14 +1312,18 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
-        hipError_t e = launch_add_zeros(pp->d_skip_off, pp->d_skip_probe, pp->n_cands, pp->d_zeros, pp->d_m, s);
+        hipError_t e = launch_decided(pp->d_dec_off, pp->d_decided, pp->n_cands, pp->d_zeros, pp->d_tables,
+                                      pp->d_prefix, pp->d_s1, pp->d_m, s);
         if (e != hipSuccess) return e;
         e = launch_fill_u32(pp->d_zero, zw, 0, s);
         if (e != hipSuccess) return e;
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
-    // the observed misses of each probe, the constant part of every score
+    // the observed misses of each probe, the constant part of every score,
+    // and the run tables of the jobs decided without a replay
     PC_HIP(launch_obs_zeros(bits, ip->d_pinfo, ip->n_probes, ip->d_zeros, stream));
+    PC_HIP(launch_run_tables(ip->d_tables, ip->n_tables, ip->sweep.d_probes, ip->d_pinfo, bits, ip->d_prefix,
+                             ip->d_s1, stream));
     // the first run of a cached plan answers at once with the default branch
     // strategy; the next run times the strategies and keeps the fastest
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,

@@ -218,10 +218,41 @@ hipError_t launch_classify(const uint32_t* lat, const uint64_t* lat_off, const u
 hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t n, hipStream_t stream);
 // zeros[p] = number of 0 bits of bits + pinfo[3p] (a word offset) over bit
 // indices [pinfo[3p+1], pinfo[3p+2]) (count_from, length), for p < n.
-// m[c] += zeros[probe[i]] for i in [off[c], off[c+1]), c < n: the scores of
-// jobs decided without a replay.
-hipError_t launch_add_zeros(const uint32_t* off, const uint32_t* probe, uint32_t n, const uint64_t* zeros,
-                            uint64_t* m, hipStream_t stream);
+// Scoring without a replay.  A run table lists the runs (line visits) of one
+// pass of a probe whose every pass is one increasing sweep and whose visited
+// lines (line size 2^line_shift) form an arithmetic progression: run i is
+// the i-th line visited, d lines after run i-1.  Per call, the prefix over
+// runs of the later passes' signed weights w(k) = [k >= count_from] *
+// (2 obs(k) - 1) at the run's start k goes to prefix[off .. off + runs] and
+// the first pass's total to s1[table].
+struct RunTable {
+    uint32_t probe;
+    uint32_t line_shift;
+    uint64_t runs;
+    uint64_t off;
+};
+// A job decided without a replay, by kind:
+//   0  no eviction, nothing of the first pass compared: the observed misses;
+//   1  no eviction (first-pass run starts are the only misses): + s1;
+//   2  LRU or FIFO, every visited set holds more lines than ways (every run
+//      start misses): + s1 + all later-pass weights;
+//   3  LRU or FIFO, the sets of runs i with i mod period < rem hold more
+//      lines than ways and the others do not: + s1 + the later-pass weights
+//      of those runs.
+struct DecidedJob {
+    uint32_t probe;
+    uint32_t table;
+    uint32_t kind;
+    uint32_t rem;
+    uint64_t period;
+};
+hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
+                             const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix, int64_t* s1,
+                             hipStream_t stream);
+// m[c] += the scores of candidate c's decided jobs dj[off[c] .. off[c+1]), c < n.
+hipError_t launch_decided(const uint32_t* off, const DecidedJob* dj, uint32_t n, const uint64_t* zeros,
+                          const RunTable* tables, const int64_t* prefix, const int64_t* s1, uint64_t* m,
+                          hipStream_t stream);
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
                             hipStream_t stream);
 // m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from

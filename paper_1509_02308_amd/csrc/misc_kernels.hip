@@ -443,19 +443,103 @@ __global__ void obs_zeros_kernel(const uint32_t* bits, const uint64_t* pinfo, ui
     if (lane == 0) zeros[p] = z;
 }
 
-__global__ void add_zeros_kernel(const uint32_t* off, const uint32_t* probe, uint32_t n, const uint64_t* zeros,
-                                 uint64_t* m) {
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    uint64_t z = 0;
-    for (uint32_t i = off[c]; i < off[c + 1]; ++i) z += zeros[probe[i]];
-    m[c] += z;
+__device__ __forceinline__ int64_t obs_weight(const uint32_t* ob, uint64_t k, uint64_t cf) {
+    return k >= cf ? 2 * (int64_t)((ob[k >> 5] >> (k & 31)) & 1u) - 1 : 0;
 }
 
-hipError_t launch_add_zeros(const uint32_t* off, const uint32_t* probe, uint32_t n, const uint64_t* zeros,
-                            uint64_t* m, hipStream_t stream) {
+// One wave per run table; lanes take 64 runs at a time and carry the prefix.
+__global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
+                                 const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix, int64_t* s1) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (w >= n_tables) return;
+    const RunTable t = tables[w];
+    const DevProbe p = probes[t.probe];
+    const uint32_t* ob = bits + pinfo[3 * (uint64_t)t.probe];
+    const uint64_t cf = pinfo[3 * (uint64_t)t.probe + 1];
+    const uint64_t sb = (uint64_t)p.se << p.elem_shift;
+    const uint64_t x0 = p.base + ((uint64_t)p.j0 << p.elem_shift);
+    const uint64_t l0 = x0 >> t.line_shift;
+    // runs are single accesses unless the stride is below the line
+    const bool per_line = t.runs > 1 && sb < (1ull << t.line_shift);
+    int64_t* out = prefix + t.off;
+    int64_t carry = 0, first = 0;
+    for (uint64_t i0 = 0; i0 < t.runs; i0 += kWave) {
+        const uint64_t i = i0 + lane;
+        int64_t w2 = 0;
+        if (i < t.runs) {
+            // first access of line l0 + i: ceil((line start - x0) / stride)
+            const uint64_t k = (per_line && i > 0) ? udiv64(((l0 + i) << t.line_shift) - x0 + sb - 1, sb) : i;
+            first += obs_weight(ob, k, cf);
+            uint64_t kk = k;
+            for (uint32_t q = 1; q < p.passes; ++q) {
+                kk += p.L;
+                w2 += obs_weight(ob, kk, cf);
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t o = __shfl_up(w2, d, kWave);
+            if ((int)lane >= d) w2 += o;
+        }
+        if (i < t.runs) out[i + 1] = carry + w2;
+        carry += __shfl(w2, kWave - 1, kWave);
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) first += __shfl_xor(first, d, kWave);
+    if (lane == 0) {
+        out[0] = 0;
+        s1[w] = first;
+    }
+}
+
+hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
+                             const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix, int64_t* s1,
+                             hipStream_t stream) {
+    if (n_tables == 0) return hipSuccess;
+    const uint32_t wpb = 256 / kWave;
+    hipLaunchKernelGGL(run_table_kernel, dim3((n_tables + wpb - 1) / wpb), dim3(256), 0, stream, tables, n_tables,
+                       probes, pinfo, bits, prefix, s1);
+    return hipGetLastError();
+}
+
+// One wave per candidate; lanes take its decided jobs in turn.
+__global__ void decided_kernel(const uint32_t* off, const DecidedJob* dj, uint32_t n, const uint64_t* zeros,
+                               const RunTable* tables, const int64_t* prefix, const int64_t* s1, uint64_t* m) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (c >= n) return;
+    int64_t acc = 0;
+    for (uint32_t i = off[c] + lane; i < off[c + 1]; i += kWave) {
+        const DecidedJob j = dj[i];
+        int64_t v = (int64_t)zeros[j.probe];
+        if (j.kind >= 1) v += s1[j.table];
+        if (j.kind >= 2) {
+            const RunTable t = tables[j.table];
+            const int64_t* P = prefix + t.off;
+            if (j.kind == 2) {
+                v += P[t.runs];
+            } else {
+                for (uint64_t st = 0; st < t.runs; st += j.period) {
+                    const uint64_t hi = st + j.rem < t.runs ? st + j.rem : t.runs;
+                    v += P[hi] - P[st];
+                }
+            }
+        }
+        acc += v;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+    if (lane == 0) m[c] += (uint64_t)acc;
+}
+
+hipError_t launch_decided(const uint32_t* off, const DecidedJob* dj, uint32_t n, const uint64_t* zeros,
+                          const RunTable* tables, const int64_t* prefix, const int64_t* s1, uint64_t* m,
+                          hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(add_zeros_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, off, probe, n, zeros, m);
+    const uint32_t wpb = 256 / kWave;
+    hipLaunchKernelGGL(decided_kernel, dim3((n + wpb - 1) / wpb), dim3(256), 0, stream, off, dj, n, zeros, tables,
+                       prefix, s1, m);
     return hipGetLastError();
 }
 

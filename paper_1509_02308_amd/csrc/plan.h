@@ -72,15 +72,19 @@ struct InferPlan {
     SweepPlan sweep;
     std::vector<uint64_t> n_host;   // compared accesses per candidate
     uint32_t runs = 0;              // completed runs (the first one is not tuned)
-    DevBuf dev;                     // m | n | zero bits | argmin out | probe info | observed misses | skip lists
+    DevBuf dev;                     // m | n | zero bits | argmin out | probe info | observed misses |
+                                    // decided jobs | run tables
     uint64_t* d_pinfo = nullptr;    // per probe: bitmap word offset, count_from, length
     uint64_t* d_zeros = nullptr;    // per probe: observed misses from count_from on
     uint32_t n_probes = 0;
-    // jobs decided without a replay (no eviction, nothing of the first pass
-    // compared): candidate c's probes are d_skip_probe[d_skip_off[c] ..
-    // d_skip_off[c+1]), each scoring its observed misses
-    uint32_t* d_skip_off = nullptr;
-    uint32_t* d_skip_probe = nullptr;
+    // jobs decided without a replay: candidate c's are d_decided[d_dec_off[c]
+    // .. d_dec_off[c+1]), scored from the observed misses and the run tables
+    DecidedJob* d_decided = nullptr;
+    uint32_t* d_dec_off = nullptr;
+    RunTable* d_tables = nullptr;
+    int64_t* d_s1 = nullptr;
+    int64_t* d_prefix = nullptr;
+    uint32_t n_tables = 0;
     uint64_t decided_accesses = 0;  // their accesses
     uint64_t* d_m = nullptr;
     uint64_t* d_n = nullptr;
