@@ -85,6 +85,55 @@ def lane_ops_per_access(a: int, policy: int) -> float:
     return a + 8
 
 
+def closed_form(C: int, b: int, a: int, pol: int, N: int, s: int, L: int) -> bool:
+    """Whether the library scores the job (candidate, probe) of this
+    workload (base 0, j0 0, 4-byte elements, count_from one pass) without a
+    replay through way state, by the rules include/pchase.h states: no
+    eviction possible (every set holds at most a lines of the array); or an
+    LRU-like model (LRU, FIFO, one way, two-way tree-PLRU) on a chase that
+    visits every line at most once per pass; or a pass that is one
+    increasing sweep over an arithmetic progression of lines whose sets
+    never evict.  The benchmark checks the total against the library's
+    closed_form_accesses."""
+    ls = b.bit_length() - 1
+    T = C // (a * b)
+    ne, se = N // 4, (s // 4) % (N // 4)
+    if -(-(((N - 4) >> ls) + 1) // T) <= a:
+        return True
+    sb = 4 * se
+    single = se == 0 or -(-ne // se) >= L
+    lru_like = pol in (0, 1) or a == 1 or (a == 2 and pol == 2)
+    if lru_like:
+        if single:
+            return True
+        if sb % b:
+            return False
+        # sweeps visit lines l, l + d, ...: disjoint when their first lines differ modulo d
+        d, firsts, r, k = sb // b, set(), 0, 0
+        while k < L:
+            f = ((4 * r) >> ls) % d
+            if f in firsts or len(firsts) == 64:
+                return False
+            firsts.add(f)
+            cnt = min(-(-(ne - r) // se), L - k)
+            k += cnt
+            r = r + cnt * se - ne
+        return True
+    if not single:
+        return False
+    if se == 0 or L == 1:
+        U, d = 1, 1
+    elif sb <= b:
+        U, d = (((L - 1) * sb) >> ls) + 1, 1
+    elif sb % b == 0:
+        U, d = L, sb // b
+    else:
+        return False
+    Tp = T // math.gcd(d % T, T)
+    q0, r = divmod(U, Tp)
+    return q0 + (1 if r else 0) <= a
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +151,7 @@ def main():
     ap.add_argument("--adaptive-targets", type=int, default=50)
     ap.add_argument("--plain-sweep-calls", type=int, default=50)
     ap.add_argument("--no-autotune", action="store_true",
-                    help="capture the batched step with its default branch assignment (profiling runs)")
+                    help="run the batched step with its default branch assignment (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the replay would shard by "
@@ -135,14 +184,19 @@ def main():
                              np.arange(len(prows), dtype=np.uint32), None, misses, bits, bitoff)
     torch.cuda.synchronize()
 
-    # algorithmic work of one step
-    accesses, lane_ops = 0, 0.0
+    # algorithmic work of one step: lane-ops of the accesses replayed
+    # through way state; jobs scored in closed form count none
+    accesses, lane_ops, closed = 0, 0.0, 0
     for C, b, a, pol, _, _ in crows:
-        own = [i for i, (N, s, _) in enumerate(prows)
-               if C <= 2 * N <= 4 * C and N % b == 0 and s in (b // 2, b, 2 * b)]
-        acc = int(lens[own].sum())
-        accesses += acc
-        lane_ops += acc * lane_ops_per_access(a, pol)
+        for i, (N, s, passes) in enumerate(prows):
+            if not (C <= 2 * N <= 4 * C and N % b == 0 and s in (b // 2, b, 2 * b)):
+                continue
+            acc = int(lens[i])
+            accesses += acc
+            if closed_form(C, b, a, pol, N, s, acc // passes):
+                closed += acc
+            else:
+                lane_ops += acc * lane_ops_per_access(a, pol)
 
     tune_flag = capi.SCHED_UNTUNED if args.no_autotune else 0
 
@@ -150,11 +204,12 @@ def main():
         return capi.infer_cache_params(parr, carr, bits=bits, bitoff=bitoff, probe_select=capi.PROBES_OWN_SWEEP,
                                        mode=capi.EXHAUSTIVE | sched | tune_flag, mn=mn)[0]
 
-    log("inference sweep: cold step (plan, capture with the default branch strategy)")
+    log("inference sweep: cold step (plan, default branch strategy)")
     t_cold0 = time.perf_counter()
     res = step()
     cold_ms = (time.perf_counter() - t_cold0) * 1e3
     assert res.replayed_accesses == accesses, (res.replayed_accesses, accesses)
+    assert res.closed_form_accesses == closed, (res.closed_form_accesses, closed)
     warm_done = 1
     tune_ms = None
     if not args.no_autotune:
@@ -190,7 +245,7 @@ def main():
     step(mn=mn)
     gpu_mn = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
 
-    # plain schedule: one launch per candidate, no persistent queue, no graph
+    # plain schedule: one launch per candidate, no persistent queue
     plain = None
     if args.plain_steps > 0:
         log("inference sweep: plain schedule")
@@ -214,8 +269,11 @@ def main():
                 "traffic_note": "HBM bytes per step (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed "
                                 "profile when it matches the current kernel sources, else null",
                 "algorithmic_bytes_per_step": accesses / 8,
-                "kernel": "sweep_kernel<policy, way class, score> (all instantiations of one captured step)",
+                "kernel": "sweep_kernel<policy, way class, score> (every bucket of one step, with the run-table and "
+                          "closed-form scoring kernels beside them)",
                 "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms,
+                "accesses_replayed_through_way_state": accesses - closed,
+                "accesses_scored_in_closed_form": closed,
                 "measured_valu_peak": measured_peak / 1e12, "frac_of_measured_peak": achieved / measured_peak,
                 "hbm_frac_algorithmic": accesses / 8 / (gpu_step_ms * 1e-3) / 8e12}
 
@@ -289,7 +347,7 @@ def plain_sweep_leg(torch, capi, W, args):
     150,320 accesses) with per-access hit bits and both miss counts, as one
     cache_replay_probes call.  It is launch-bound: the figure is the latency
     of one call (median over calls, host clock around the call and a
-    stream synchronisation), batched (one captured persistent launch) vs
+    stream synchronisation), batched (persistent launches on branch streams) vs
     plain (one ordinary launch per model)."""
     model, prow = W.plain_sweep()
     mrow = tuple(int(v) for v in model[0])

@@ -363,7 +363,9 @@ typedef struct pchase_result {
     int64_t best;               /* candidate index, -1 if none compared */
     uint64_t best_m, best_n;    /* mismatches / compared accesses of best */
     uint64_t n_zero;            /* candidates with m == 0 (zero class) */
-    uint64_t replayed_accesses; /* accesses replayed by this call */
+    uint64_t replayed_accesses; /* accesses whose hit or miss the call determined */
+    uint64_t closed_form_accesses; /* of those, accesses of jobs scored in closed
+                                      form, without a replay through way state */
     uint32_t fallback;          /* LEARNED: 1 no exact top-k match, 2 not the grid */
     uint32_t threshold_used;    /* latency threshold applied (UINT32_MAX: none) */
 } pchase_result;

@@ -66,7 +66,8 @@ class PchaseObservation(ctypes.Structure):
 
 class PchaseResult(ctypes.Structure):
     _fields_ = [("best", i64), ("best_m", u64), ("best_n", u64), ("n_zero", u64),
-                ("replayed_accesses", u64), ("fallback", u32), ("threshold_used", u32)]
+                ("replayed_accesses", u64), ("closed_form_accesses", u64), ("fallback", u32),
+                ("threshold_used", u32)]
 
 
 class PchaseError(RuntimeError):

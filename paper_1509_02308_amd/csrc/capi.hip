@@ -79,6 +79,32 @@ static uint64_t sweep_runs(const DevProbe& p, uint32_t ls, uint64_t* d) {
     return 0;
 }
 
+// Every line is visited by at most one run in a pass (so every pass visits
+// each set's lines once, in the same order): one increasing sweep, or at most
+// 64 sweeps whose stride is a multiple of the line (each sweep visits lines
+// l, l + d, l + 2d, ..., d the stride in lines) and whose first lines differ
+// modulo d.
+static bool lines_once_per_pass(const DevProbe& p, uint32_t ls) {
+    if (one_sweep_per_pass(p)) return true;
+    const uint64_t sb = (uint64_t)p.se << p.elem_shift;
+    if (sb & ((1ull << ls) - 1)) return false;
+    const uint64_t d = sb >> ls;
+    std::vector<uint64_t> first;
+    uint64_t r = p.j0, kpos = 0;
+    while (kpos < p.L) {
+        if (first.size() == 64) return false;
+        const uint64_t res = ((p.base + (r << p.elem_shift)) >> ls) % d;
+        for (uint64_t f : first)
+            if (f == res) return false;
+        first.push_back(res);
+        uint64_t cnt = ((uint64_t)p.ne - r + p.se - 1) / p.se;
+        if (cnt > p.L - kpos) cnt = p.L - kpos;
+        kpos += cnt;
+        r = r + cnt * p.se - p.ne;
+    }
+    return true;
+}
+
 static uint64_t gcd64(uint64_t x, uint64_t y) {
     while (y) {
         const uint64_t t = x % y;
@@ -89,7 +115,7 @@ static uint64_t gcd64(uint64_t x, uint64_t y) {
 }
 
 // Largest run table (entries of 8 bytes) an inference plan builds.
-constexpr uint64_t kMaxTableEntries = 1ull << 24;
+constexpr uint64_t kMaxTableEntries = 1ull << 26;
 
 static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     const uint64_t C = c.capacity_bytes, b = c.line_bytes, N = p.n_bytes, s = p.s_bytes;
@@ -1133,7 +1159,10 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
         dec_off[c] = (uint32_t)decided.size();
         if (allow && !(*allow)[c]) continue;
         const DevModel& md = dm[c];
-        const bool lru_fifo = md.policy == PCHASE_LRU || md.policy == PCHASE_FIFO;
+        // the closed forms hold for LRU and FIFO; with one way every policy
+        // replaces as LRU does, and two-way tree-PLRU is LRU
+        const bool lru_fifo = md.policy == PCHASE_LRU || md.policy == PCHASE_FIFO || md.ways == 1 ||
+                              (md.ways == 2 && md.policy == PCHASE_PLRU);
         for (uint32_t p = 0; p < obs->n_probes; ++p) {
             if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
             if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
@@ -1188,7 +1217,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             j.count_from = cf[p];
             j.bitoff = bitoff[p];
             j.bm_off = 0;
-            j.cyc = lru_fifo && one_sweep_per_pass(dp[p]) ? 1u : 0u;
+            j.cyc = lru_fifo && lines_once_per_pass(dp[p], md.line_shift) ? 1u : 0u;
+            if (j.cyc) np->cyc_accesses += len[p];
             jobs.push_back(j);
         }
     }
@@ -1347,6 +1377,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     out->n_zero = hr->n_zero;
     if (zero_host && zw * 4 <= 4096 - 256) std::memcpy(zero_host, static_cast<uint8_t*>(ws->host_res) + 256, zw * 4);
     *replayed = ip->sweep.accesses + ip->decided_accesses;
+    out->closed_form_accesses += ip->decided_accesses + ip->cyc_accesses;
     ++ip->runs;
     return PCHASE_OK;
 }
@@ -1453,6 +1484,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
     if (mode == PCHASE_LEARNED && (!net || topk == 0)) return set_error(PCHASE_EINVAL, "LEARNED needs a network and topk >= 1");
     if (n_cands == 0) return set_error(PCHASE_EINVAL, "no candidates");
     if (zero_host && (n_cands + 31) / 32 * 4 > 4096 - 256) return set_error(PCHASE_ERANGE, "zero-class bitmap too large");
+    out->closed_form_accesses = 0;
     if (mode == PCHASE_EXHAUSTIVE && obs->bits_dev && !obs->lat_dev && obs->bitoff && obs->probes && obs->n_probes) {
         // repeated inference on the same inputs: the cached plan (built, and
         // so validated, for exactly these inputs) runs without re-validation
@@ -1640,6 +1672,7 @@ extern "C" int infer_cache_params_general(const pchase_observation* obs, const p
     out->n_zero = hr->n_zero;
     out->fallback = 0;
     out->replayed_accesses = (uint64_t)n_cands * toff[np];
+    out->closed_form_accesses = 0;
     if (zero_host) std::memcpy(zero_host, static_cast<uint8_t*>(ws->host_res) + 256, zw * 4);
     return PCHASE_OK;
 }

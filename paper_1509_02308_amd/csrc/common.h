@@ -315,4 +315,4 @@ static_assert(sizeof(pchase_segment) == 16, "pchase_segment layout");
 static_assert(sizeof(pchase_nu_probe) == 40, "pchase_nu_probe layout");
 static_assert(sizeof(pchase_general_model) == 56, "pchase_general_model layout");
 static_assert(sizeof(pchase_plan_choice) == 24, "pchase_plan_choice layout");
-static_assert(sizeof(pchase_result) == 48, "pchase_result layout");
+static_assert(sizeof(pchase_result) == 56, "pchase_result layout");

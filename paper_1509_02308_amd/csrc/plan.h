@@ -86,6 +86,7 @@ struct InferPlan {
     int64_t* d_prefix = nullptr;
     uint32_t n_tables = 0;
     uint64_t decided_accesses = 0;  // their accesses
+    uint64_t cyc_accesses = 0;      // accesses of the plan's closed-form (kACyc) jobs
     uint64_t* d_m = nullptr;
     uint64_t* d_n = nullptr;
     uint32_t* d_zero = nullptr;

@@ -40,7 +40,7 @@ def test_header_functions_exported(capi):
 def test_struct_layouts_match_header(capi):
     assert ctypes.sizeof(capi.PchaseModel) == 40
     assert ctypes.sizeof(capi.PchaseProbe) == 40
-    assert ctypes.sizeof(capi.PchaseResult) == 48
+    assert ctypes.sizeof(capi.PchaseResult) == 56
     assert ctypes.sizeof(capi.PchaseSegment) == 16
     assert ctypes.sizeof(capi.PchaseNuProbe) == 40
     assert ctypes.sizeof(capi.PchaseGeneralModel) == 56

@@ -38,6 +38,7 @@ PROBES = [
     (4096, 8192 + 64, 2),                     # s > N
     (30000, 4, 1, 123), (8192, 36, 2, 5, 64),  # j0 and base offsets
     (1 << 20, 65536, 2), (1 << 18, 2048, 2), (40960, 4092, 2), (128, 4, 3),
+    (4128, 64, 2), (12352, 128, 3), (4160, 96, 2),   # 2 and 3 sweeps a pass, each line once at 32 B
 ]
 
 
