@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--nu-probes", type=int, default=4096)
     ap.add_argument("--adaptive-targets", type=int, default=50)
     ap.add_argument("--plain-sweep-calls", type=int, default=50)
+    ap.add_argument("--full-replay-steps", type=int, default=10,
+                    help="timed steps with the closed forms off (every access through the per-set replay)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the batched step with its default branch assignment (profiling runs)")
     args = ap.parse_args()
@@ -186,13 +188,14 @@ def main():
 
     # algorithmic work of one step: lane-ops of the accesses replayed
     # through way state; jobs scored in closed form count none
-    accesses, lane_ops, closed = 0, 0.0, 0
+    accesses, lane_ops, lane_ops_all, closed = 0, 0.0, 0.0, 0
     for C, b, a, pol, _, _ in crows:
         for i, (N, s, passes) in enumerate(prows):
             if not (C <= 2 * N <= 4 * C and N % b == 0 and s in (b // 2, b, 2 * b)):
                 continue
             acc = int(lens[i])
             accesses += acc
+            lane_ops_all += acc * lane_ops_per_access(a, pol)
             if closed_form(C, b, a, pol, N, s, acc // passes):
                 closed += acc
             else:
@@ -260,6 +263,38 @@ def main():
         plain = {"value": accesses / pw, "unit": "accesses/s", "time_to_params_ms": pw * 1e3,
                  "steps": args.plain_steps}
 
+    # the same step with every access replayed through the per-set state:
+    # the replay engine's own rate, and the same (m, n) for every candidate
+    full = None
+    if args.full_replay_steps > 0:
+        log("inference sweep: full replay (closed forms off)")
+        step(capi.SCHED_FULL_REPLAY)
+        rf = step(capi.SCHED_FULL_REPLAY)
+        assert rf.closed_form_accesses == 0 and rf.replayed_accesses == accesses
+        evf = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.full_replay_steps)]
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        for k in range(args.full_replay_steps):
+            evf[k][0].record(stream)
+            rf = step(capi.SCHED_FULL_REPLAY)
+            evf[k][1].record(stream)
+        torch.cuda.synchronize()
+        fw = (time.perf_counter() - tf) / args.full_replay_steps
+        fms = float(np.median([a.elapsed_time(b) for a, b in evf]))
+        mnf = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+        step(capi.SCHED_FULL_REPLAY, mn=mnf)
+        same = bool(np.array_equal(mnf.cpu().numpy().astype(np.uint64).reshape(-1, 2), gpu_mn))
+        assert same and rf.best == res.best and rf.best_m == res.best_m
+        fach = lane_ops_all / (fms * 1e-3)
+        full = {"ms_per_step": fw * 1e3, "value": accesses / fw, "unit": "accesses/s",
+                "steps": args.full_replay_steps, "kernel_ms_per_step": fms, "same_m_n_as_default": same,
+                "roofline": {"bound": "alu", "achieved": fach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                             "unit": "Tlane-op/s", "frac": fach / PEAK_LANE_OPS,
+                             "algorithmic_lane_ops_per_step": lane_ops_all,
+                             "kernel": "sweep_kernel<policy, way class, score> (every access of the step)"}}
+        log(f"inference sweep: full replay {fw * 1e3:.2f} ms per step")
+
     gpu_step_ms = float(np.median(gpu_ms))
     achieved = lane_ops / (gpu_step_ms * 1e-3)
     measured_peak = capi.microbench_valu(8, 20000)
@@ -322,7 +357,12 @@ def main():
                                "LRU/FIFO/PLRU) x own N sweep (C/2..2C step b, s in {b/2,b,2b}, 2 passes), "
                                "one seeded target",
                    "candidates": len(crows), "probes": len(prows), "replays": 1079586,
-                   "accesses_per_step": accesses, "target": target, "schedule": "batched"},
+                   "accesses_per_step": accesses, "target": target, "schedule": "batched",
+                   "closed_form_accesses_per_step": closed,
+                   "scoring": "default: jobs with a closed form (no eviction possible; LRU-like policies on "
+                              "chases that visit each line once per pass) are scored without a per-access "
+                              "replay, the rest replayed through per-set state; full_replay: every access "
+                              "replayed; both give the same (m, n) for every candidate"},
         "time_to_params_ms": float(np.median(lat_ms)),
         "time_to_params_cold_ms": cold_ms,
         "tuning_step_ms": tune_ms,
@@ -330,6 +370,7 @@ def main():
         "best": int(res.best),
         "zero_class": int(res.n_zero),
         "plain": plain,
+        "full_replay": full,
         "plain_sweep": plain_sweep,
         "learned": learned,
         "large_batch": large,

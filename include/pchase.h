@@ -336,6 +336,23 @@ enum { PCHASE_EXHAUSTIVE = 0, PCHASE_LEARNED = 1 };
  * (for profiling runs, where the timing loop would be serialised by the
  * profiler). */
 #define PCHASE_SCHED_UNTUNED 0x200
+/* By default the scores of (candidate, probe) jobs whose outcome has a
+ * closed form are computed without a replay through way state (results are
+ * identical; pchase_result.closed_form_accesses counts their accesses):
+ *  - no set of the candidate can hold more than a lines of the probe's array
+ *    (Section 4.2 step 1: nothing is ever evicted, so only first touches
+ *    miss);
+ *  - LRU and FIFO (and one-way caches, and two-way tree-PLRU, which is LRU)
+ *    on a chase whose every pass visits each line at most once (Section
+ *    4.1: every pass visits a set's n lines in the same cyclic order, so
+ *    after the first pass every run start misses when n > a and none does
+ *    when n <= a);
+ * single-sweep passes whose visited lines form an arithmetic progression
+ * (one line per set-mapping unit) are scored from per-probe prefix sums of
+ * the observation, the others by a walk over the first pass's runs.  OR
+ * this flag into infer_cache_params' mode to replay every access through
+ * the per-set state instead (to measure or check the replay engine). */
+#define PCHASE_SCHED_FULL_REPLAY 0x400
 
 /* Observed fine-grained P-chase runs (Listing 3 outputs): probe p's trace
  * is known from the probe; its hit bits are either given (bits_dev, layout

@@ -22,6 +22,7 @@ PROBES_ALL, PROBES_OWN_SWEEP = 0, 1
 EXHAUSTIVE, LEARNED = 0, 1
 SCHED_PLAIN = 0x100
 SCHED_UNTUNED = 0x200
+SCHED_FULL_REPLAY = 0x400
 LOAD_DEFAULT, LOAD_L2, LOAD_SYSTEM, LOAD_STREAM = 0, 1, 2, 3
 MLP_IN, MLP_HIDDEN = 768, 256
 U32_MAX = 0xFFFFFFFF

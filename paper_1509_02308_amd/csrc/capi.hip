@@ -1143,7 +1143,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                             uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
                             const std::vector<uint64_t>& len, const std::vector<uint64_t>& cf,
                             const std::vector<uint64_t>& bitoff, int probe_select,
-                            const std::vector<uint8_t>* allow, std::unique_ptr<InferPlan>* out) {
+                            const std::vector<uint8_t>* allow, bool closed, std::unique_ptr<InferPlan>* out) {
     std::unique_ptr<InferPlan> np(new InferPlan());
     np->dev.arena = ws->arena;
     np->sweep.dev.arena = ws->arena;
@@ -1169,7 +1169,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // no access evicts and nothing before the second pass is
             // compared: the only misses are first touches, all in the first
             // pass, so the score is the observed misses alone
-            if (cf[p] >= dp[p].L && no_eviction(md, dp[p])) {
+            if (closed && cf[p] >= dp[p].L && no_eviction(md, dp[p])) {
                 decided.push_back(DecidedJob{p, 0, 0, 0, 1});
                 np->decided_accesses += len[p];
                 continue;
@@ -1181,7 +1181,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // a visited set holds q0 or q0 + 1 lines (the latter for
             // i mod T' < r, with U runs = q0 T' + r)
             uint64_t d = 1;
-            const uint64_t U = md.unit_shift == md.line_shift ? sweep_runs(dp[p], md.line_shift, &d) : 0;
+            const uint64_t U = closed && md.unit_shift == md.line_shift ? sweep_runs(dp[p], md.line_shift, &d) : 0;
             if (U) {
                 const uint64_t Tp = md.sets / gcd64(d % md.sets, md.sets);
                 const uint64_t q0 = U / Tp, r = U % Tp;
@@ -1217,7 +1217,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             j.count_from = cf[p];
             j.bitoff = bitoff[p];
             j.bm_off = 0;
-            j.cyc = lru_fifo && lines_once_per_pass(dp[p], md.line_shift) ? 1u : 0u;
+            j.cyc = closed && lru_fifo && lines_once_per_pass(dp[p], md.line_shift) ? 1u : 0u;
             if (j.cyc) np->cyc_accesses += len[p];
             jobs.push_back(j);
         }
@@ -1274,9 +1274,11 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
 // The exact inputs that shape an inference plan, as bytes: a cached plan is
 // used only when its stored inputs equal these (the digest only finds it).
 static std::string infer_key(const pchase_observation* obs, const pchase_model* cands, uint32_t n_cands,
-                             int probe_select, const uint64_t* bitoff, const std::vector<uint8_t>* allow) {
+                             int probe_select, const uint64_t* bitoff, const std::vector<uint8_t>* allow,
+                             bool closed) {
     std::string k;
     auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    k.push_back(closed ? 'c' : 'r');
     put(&n_cands, sizeof n_cands);
     put(&obs->n_probes, sizeof obs->n_probes);
     put(&probe_select, sizeof probe_select);
@@ -1309,20 +1311,22 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
                             const std::vector<uint64_t>& bitoff, const uint32_t* bits, int probe_select,
                             const std::vector<uint8_t>* allow, pchase_result* out, uint64_t* mn_dev,
                             uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched,
-                            bool cache = true, bool tune = true) {
+                            bool closed, bool cache = true, bool tune = true) {
     InferPlan* ip;
     std::unique_ptr<InferPlan> once;
     if (!cache) {
-        int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &once);
+        int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, closed,
+                                  &once);
         if (rc) return rc;
         ip = once.get();
     } else {
-        std::string blob = infer_key(obs, cands, n_cands, probe_select, bitoff.data(), allow);
+        std::string blob = infer_key(obs, cands, n_cands, probe_select, bitoff.data(), allow, closed);
         const std::string key = digest_of(blob);
         auto it = ws->plans.find(key);
         if (it == ws->plans.end() || it->second->key != blob) {
             std::unique_ptr<InferPlan> np;
-            int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, &np);
+            int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, closed,
+                                      &np);
             if (rc) return rc;
             np->key = std::move(blob);
             np->cached = true;
@@ -1479,7 +1483,8 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         return set_error(PCHASE_EINVAL, "unknown probe_select %d", probe_select);
     const uint32_t sched = (mode & PCHASE_SCHED_PLAIN) ? PCHASE_PLAIN : PCHASE_BATCHED;
     const bool tune = !(mode & PCHASE_SCHED_UNTUNED);
-    mode &= ~(PCHASE_SCHED_PLAIN | PCHASE_SCHED_UNTUNED);
+    const bool closed = !(mode & PCHASE_SCHED_FULL_REPLAY);
+    mode &= ~(PCHASE_SCHED_PLAIN | PCHASE_SCHED_UNTUNED | PCHASE_SCHED_FULL_REPLAY);
     if (mode != PCHASE_EXHAUSTIVE && mode != PCHASE_LEARNED) return set_error(PCHASE_EINVAL, "unknown mode %d", mode);
     if (mode == PCHASE_LEARNED && (!net || topk == 0)) return set_error(PCHASE_EINVAL, "LEARNED needs a network and topk >= 1");
     if (n_cands == 0) return set_error(PCHASE_EINVAL, "no candidates");
@@ -1492,7 +1497,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         std::unique_lock<std::mutex> lk;
         int rc = workspace_for(plan, &ws, &lk);
         if (rc) return rc;
-        const std::string blob = infer_key(obs, cands, n_cands, probe_select, obs->bitoff, nullptr);
+        const std::string blob = infer_key(obs, cands, n_cands, probe_select, obs->bitoff, nullptr, closed);
         auto it = ws->plans.find(digest_of(blob));
         if (it != ws->plans.end() && it->second->key == blob) {
             out->threshold_used = 0xFFFFFFFFu;
@@ -1535,7 +1540,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         if (on_grid) {
             // confirm the proposals exactly: one-off plan, eager launches
             rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, &allow, out,
-                                  nullptr, nullptr, stream, &replayed, PCHASE_PLAIN, false);
+                                  nullptr, nullptr, stream, &replayed, PCHASE_PLAIN, closed, false);
             if (rc) return rc;
             out->replayed_accesses = replayed;
             if (out->best >= 0 && out->best_m == 0) return PCHASE_OK;
@@ -1545,7 +1550,7 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         }
     }
     rc = infer_exhaustive(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, bits, probe_select, nullptr, out, mn_dev,
-                          zero_host, stream, &replayed, sched, true, tune);
+                          zero_host, stream, &replayed, sched, closed, true, tune);
     if (rc) return rc;
     out->replayed_accesses += replayed;
     if (mode == PCHASE_EXHAUSTIVE) out->replayed_accesses = replayed;

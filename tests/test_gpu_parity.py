@@ -347,15 +347,18 @@ def test_inference_scores_any_observation_and_count_from():
         packed, bitoff = _bits_layout(hits_all)
         mn = torch.zeros(2 * len(MODELS), dtype=torch.int64, device="cuda")
         say(f"infer_cache_params random observation, trial {trial}")
-        for sched in (0, capi.SCHED_PLAIN):
+        closed = []
+        for sched in (0, capi.SCHED_PLAIN, capi.SCHED_FULL_REPLAY, capi.SCHED_FULL_REPLAY | capi.SCHED_PLAIN):
             res, _ = capi.infer_cache_params(capi.probes(PROBES), capi.models(MODELS),
                                              bits=torch.from_numpy(packed.view(np.int32)).cuda(), bitoff=bitoff,
                                              count_from=cfs, probe_select=0, mn=mn, mode=sched)
             got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
             bad = np.nonzero((got[:, 0] != m) | (got[:, 1] != n))[0]
-            assert len(bad) == 0, [(MODELS[int(c)], tuple(got[c]), (int(m[c]), int(n[c]))) for c in bad[:5]]
+            assert len(bad) == 0, [(sched, MODELS[int(c)], tuple(got[c]), (int(m[c]), int(n[c]))) for c in bad[:5]]
             assert res.best == best and res.best_m == m[best]
             assert res.replayed_accesses == len(MODELS) * sum(lens)
+            closed.append(res.closed_form_accesses)
+        assert closed[0] == closed[1] > 0 and closed[2] == closed[3] == 0
 
 
 @pytest.mark.timeout(600)
@@ -390,6 +393,12 @@ def test_inference_full_candidate_grid():
     assert res.n_zero == len(zc)
     got_zero = [c for c in range(len(crows)) if (zero[c // 32] >> (c % 32)) & 1]
     assert got_zero == zc.tolist()
+    say("infer_cache_params full grid, every access replayed")
+    res_f, _ = capi.infer_cache_params(capi.probes(prows), capi.models(crows), bits=bits, bitoff=bitoff,
+                                       probe_select=1, mn=mn, mode=capi.SCHED_FULL_REPLAY)
+    got_f = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    assert res_f.closed_form_accesses == 0 and res.closed_form_accesses > 0
+    assert np.array_equal(got_f, got) and res_f.best == best
 
 
 # -------------------------------------------------------- microbenches ---
