@@ -674,12 +674,9 @@ static int run_tile_schedule(const std::vector<DevModel>& dm, const TileSchedule
     std::vector<size_t> order(launches.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return launches[x].cost > launches[y].cost; });
-    const int ns = (mode == PCHASE_PLAIN || !ws) ? 0 : (int)std::min<size_t>(kReplayStreams, launches.size());
-    double load[kReplayStreams] = {};
-    if (ns > 1) {
-        PC_HIP(hipEventRecord(ws->rfork, stream));
-        for (int b = 0; b < ns; ++b) PC_HIP(hipStreamWaitEvent(ws->rstream[b], ws->rfork, 0));
-    }
+    const int ns = (mode == PCHASE_PLAIN || !ws) ? 0 : (int)std::min<size_t>(kBranches, launches.size());
+    double load[kBranches] = {};
+    if (ns > 1) PC_HIP(fork_branches(ws, stream, ns));
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const Launch& L = launches[order[oi]];
         hipStream_t st = stream;
@@ -688,7 +685,7 @@ static int run_tile_schedule(const std::vector<DevModel>& dm, const TileSchedule
             for (int c = 1; c < ns; ++c)
                 if (load[c] < load[b]) b = c;
             load[b] += L.cost;
-            st = ws->rstream[b];
+            st = branch_stream(ws, stream, b);
         }
         TileArgs a;
         a.items = d_items + L.q;
@@ -704,12 +701,7 @@ static int run_tile_schedule(const std::vector<DevModel>& dm, const TileSchedule
         a.status = d_status;
         PC_HIP(launch_tile(L.pol, L.wcls, a, (uint32_t)L.blocks, st));
     }
-    if (ns > 1) {
-        for (int b = 0; b < ns; ++b) {
-            PC_HIP(hipEventRecord(ws->rjoin[b], ws->rstream[b]));
-            PC_HIP(hipStreamWaitEvent(stream, ws->rjoin[b], 0));
-        }
-    }
+    if (ns > 1) PC_HIP(join_branches(ws, stream, ns));
     PC_HIP(hipStreamSynchronize(stream));
     fence.done();
     uint32_t status = 0;
@@ -1088,21 +1080,18 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
     std::vector<size_t> order(launches.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return launches[x].cost > launches[y].cost; });
-    const int ns = concurrent ? (int)std::min<size_t>(kReplayStreams, launches.size()) : 0;
-    double load[kReplayStreams] = {};
-    if (ns) {
-        PC_HIP(hipEventRecord(ws->rfork, stream));
-        for (int b = 0; b < ns; ++b) PC_HIP(hipStreamWaitEvent(ws->rstream[b], ws->rfork, 0));
-    }
+    const int ns = concurrent ? (int)std::min<size_t>(kBranches, launches.size()) : 0;
+    double load[kBranches] = {};
+    if (ns > 1) PC_HIP(fork_branches(ws, stream, ns));
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const Launch& L = launches[order[oi]];
         hipStream_t st = stream;
-        if (ns) {
+        if (ns > 1) {
             int b = 0;
             for (int c = 1; c < ns; ++c)
                 if (load[c] < load[b]) b = c;
             load[b] += L.cost;
-            st = ws->rstream[b];
+            st = branch_stream(ws, stream, b);
         }
         StreamArgs a;
         a.pairs = d_pairs + L.q;
@@ -1124,10 +1113,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
         a.cum_w = d_cum;
         PC_HIP(launch_stream(L.pol, L.W, L.gen, a, (uint32_t)L.blocks, st));
     }
-    for (int b = 0; b < ns; ++b) {
-        PC_HIP(hipEventRecord(ws->rjoin[b], ws->rstream[b]));
-        PC_HIP(hipStreamWaitEvent(stream, ws->rjoin[b], 0));
-    }
+    if (ns > 1) PC_HIP(join_branches(ws, stream, ns));
     ws->epoch += (uint32_t)n_items + 1;
     PC_HIP(hipStreamSynchronize(stream));
     fence.done();

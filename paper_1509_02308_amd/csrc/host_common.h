@@ -41,10 +41,11 @@ struct DevBuf {
 
 struct InferPlan;
 
-// Parallel branch streams of a batched replay.
+// Streams of a concurrent launch sequence: the caller's stream and three
+// workspace streams, one per hardware queue of the process (the runtime's
+// default of four queues; a fifth stream would share a queue with another
+// and its kernels would wait for that stream's).
 constexpr int kBranches = 4;
-// Streams of the materialised-trace replay's concurrent buckets.
-constexpr int kReplayStreams = 8;
 
 struct Workspace {
     int device = -1;
@@ -66,8 +67,6 @@ struct Workspace {
     // branch streams of a batched sweep beyond the caller's own (default priority)
     hipStream_t branch[kBranches - 1] = {};
     hipEvent_t fork = nullptr, join[kBranches - 1] = {};
-    hipStream_t rstream[kReplayStreams] = {};   // default priority
-    hipEvent_t rfork = nullptr, rjoin[kReplayStreams] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
     // probe planner: class matrix of the last (candidates, pool) pair
     DevBuf planner;
@@ -97,6 +96,14 @@ struct CopyFence {
     }
     void done() { armed = false; }
 };
+
+// Branch b of a concurrent sequence on `s`: `s` itself for b = 0, else
+// workspace stream b - 1.
+inline hipStream_t branch_stream(Workspace* ws, hipStream_t s, int b) { return b == 0 ? s : ws->branch[b - 1]; }
+// Branches 1 .. n-1 wait for the work enqueued on `s` so far.
+hipError_t fork_branches(Workspace* ws, hipStream_t s, int n);
+// `s` waits for the work enqueued on branches 1 .. n-1.
+hipError_t join_branches(Workspace* ws, hipStream_t s, int n);
 
 // Locks and returns the calling thread's current device's workspace.
 int workspace(Workspace** ws, std::unique_lock<std::mutex>* lock);

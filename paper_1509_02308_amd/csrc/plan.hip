@@ -278,13 +278,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
     const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
     const int nb = (int)std::min<size_t>(want, plan->batched.size());
-    // branch 0 is `s` itself; branch b > 0 is workspace stream b - 1, forked
-    // from `s` and joined back into it
-    auto branch_stream = [&](int b) { return b == 0 ? s : ws->branch[b - 1]; };
-    if (nb > 1) {
-        PC_HIP(hipEventRecord(ws->fork, s));
-        for (int b = 1; b < nb; ++b) PC_HIP(hipStreamWaitEvent(ws->branch[b - 1], ws->fork, 0));
-    }
+    PC_HIP(fork_branches(ws, s, nb));
     auto lds_class = [](const Bucket& bk) { return bk.cls == kAMap || bk.cls == kALds; };
     auto weight = [&](const Bucket& bk) { return (strategy == 1 && lds_class(bk)) ? 3.0 * bk.cost : bk.cost; };
     std::vector<size_t> idx(plan->batched.size());
@@ -306,7 +300,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
                 if (load[b] < load[br]) br = b;
         }
         load[br] += weight(bk);
-        hipStream_t bs = branch_stream(br);
+        hipStream_t bs = branch_stream(ws, s, br);
         SweepArgs a;
         a.tasks = plan->d_lpt + bk.first;
         a.n_tasks = bk.count;
@@ -334,10 +328,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         if (need < blocks) blocks = need;
         PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, blocks, bs));
     }
-    for (int b = 1; b < nb; ++b) {
-        PC_HIP(hipEventRecord(ws->join[b - 1], ws->branch[b - 1]));
-        PC_HIP(hipStreamWaitEvent(s, ws->join[b - 1], 0));
-    }
+    PC_HIP(join_branches(ws, s, nb));
     if (tail) PC_HIP(tail(s));
     return PCHASE_OK;
 }

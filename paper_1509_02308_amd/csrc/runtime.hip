@@ -154,11 +154,6 @@ Workspace::~Workspace() {
         if (branch[b]) (void)hipStreamDestroy(branch[b]);
         if (join[b]) (void)hipEventDestroy(join[b]);
     }
-    for (int b = 0; b < kReplayStreams; ++b) {
-        if (rstream[b]) (void)hipStreamDestroy(rstream[b]);
-        if (rjoin[b]) (void)hipEventDestroy(rjoin[b]);
-    }
-    if (rfork) (void)hipEventDestroy(rfork);
     if (fork) (void)hipEventDestroy(fork);
     stage.release();
     aux.release();
@@ -168,6 +163,22 @@ Workspace::~Workspace() {
     planner.release();
     gsearch.release();
     if (host_res) (void)hipHostFree(host_res);
+}
+
+hipError_t fork_branches(Workspace* ws, hipStream_t s, int n) {
+    if (n < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(ws->fork, s);
+    for (int b = 1; b < n && e == hipSuccess; ++b) e = hipStreamWaitEvent(ws->branch[b - 1], ws->fork, 0);
+    return e;
+}
+
+hipError_t join_branches(Workspace* ws, hipStream_t s, int n) {
+    hipError_t e = hipSuccess;
+    for (int b = 1; b < n && e == hipSuccess; ++b) {
+        e = hipEventRecord(ws->join[b - 1], ws->branch[b - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ws->join[b - 1], 0);
+    }
+    return e;
 }
 
 static std::mutex g_ws_mu;
@@ -221,14 +232,6 @@ int workspace_init(Workspace* ws) {
             if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
         }
         e = hipEventCreateWithFlags(&ws->fork, hipEventDisableTiming);
-        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
-        for (int b = 0; b < kReplayStreams; ++b) {
-            e = hipStreamCreateWithFlags(&ws->rstream[b], hipStreamNonBlocking);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
-            e = hipEventCreateWithFlags(&ws->rjoin[b], hipEventDisableTiming);
-            if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
-        }
-        e = hipEventCreateWithFlags(&ws->rfork, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
         ws->lds_ready = true;
     }
