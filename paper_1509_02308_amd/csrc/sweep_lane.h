@@ -410,13 +410,42 @@ struct Sweep {
     uint32_t rem;    // uf mod T
     uint32_t unit_mode;  // 1: walk units (stride below T units), 0: walk accesses
     uint32_t fast;   // unit mode: offsets fit 32 bits, divide by the stride's multiplier
-    // aligned unit mode (a unit is one line, the stride divides it and the
-    // sweep starts on a stride boundary): every full unit holds R accesses
-    // and the first access of unit uf + d is d*R - off0, no division needed
+    // aligned (1): a unit is one line, the stride divides it and the sweep
+    // starts on a stride boundary: every full unit holds R accesses and the
+    // first access of unit uf + d is d*R - off0, no division needed.
+    // strided (2): the stride is dd units: access i lies in unit uf + i dd,
+    // so set rem + c (mod T) holds the accesses i = i0 + j R with R =
+    // T / g, g = gcd(dd, T), when g divides c, and i0 = (c / g) off0 mod R,
+    // off0 the inverse of dd / g modulo R.
     uint32_t aligned;
     uint32_t R;
     uint32_t off0;
 };
+
+// Inverse of x modulo n (gcd(x, n) = 1, n >= 1) by the extended Euclidean
+// algorithm; 0 when n == 1.
+__device__ __forceinline__ uint32_t inv_mod(uint32_t x, uint32_t n) {
+    int64_t r0 = n, r1 = x % n, t0 = 0, t1 = 1;
+    while (r1 != 0) {
+        const int64_t q = r0 / r1;
+        const int64_t r2 = r0 - q * r1, t2 = t0 - q * t1;
+        r0 = r1;
+        r1 = r2;
+        t0 = t1;
+        t1 = t2;
+    }
+    if (t0 < 0) t0 += n;
+    return n == 1 ? 0u : (uint32_t)t0;
+}
+
+__device__ __forceinline__ uint32_t gcd_u32(uint32_t x, uint32_t y) {
+    while (y) {
+        const uint32_t t = x % y;
+        x = y;
+        y = t;
+    }
+    return x;
+}
 
 __device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, uint32_t cnt, uint32_t kin,
                                           const DevModel& m, const DevProbe& p) {
@@ -442,6 +471,17 @@ __device__ __forceinline__ void sweep_geo(Sweep& w, uint64_t xf, uint64_t sb, ui
             w.R = (uint32_t)R;
             w.off0 = (uint32_t)((xf - (uf << us)) / sb);
         }
+    } else if (sb > 0 && (sb & (U - 1)) == 0 && cnt > 1 && cnt < (1u << 30)) {
+        const uint64_t dd = sb >> us;
+        const uint32_t T = m.sets;
+        const uint32_t dm = (uint32_t)(dd % T);
+        const uint32_t g = gcd_u32(dm, T);   // gcd(0, T) = T
+        const uint32_t P = T / g;
+        if (dd < (1ull << 32)) {
+            w.aligned = 2;
+            w.R = P;
+            w.off0 = inv_mod((uint32_t)((dd / g) % P), P);
+        }
     }
 }
 
@@ -459,6 +499,26 @@ __device__ __forceinline__ void sweep_walk(const Sweep& w, uint32_t kpass, uint6
     const uint64_t U = 1ull << us;
     const uint64_t xf = w.xf;
     const uint32_t cnt = w.cnt, kstart = kpass + w.kin;
+    if (w.aligned == 2) {
+        // strided: only this set's accesses i0, i0 + P, ...; the unit grows
+        // by P dd = T (dd / g), so its quotient by T grows by dd / g, and
+        // the line by P (sb >> ls) (the stride is a multiple of the line)
+        const uint32_t c = set >= w.rem ? set - w.rem : set + T - w.rem;
+        const uint32_t P = w.R, g = T / P;
+        if (c % g) return;
+        const uint32_t i0 = (uint32_t)(((uint64_t)(c / g) * w.off0) % P);
+        if (i0 >= cnt) return;
+        const uint32_t n = (cnt - 1 - i0) / P + 1;
+        const uint64_t dd = sb >> us, lb = sb >> ls;
+        const uint32_t sdg = (uint32_t)(dd / g);
+        uint32_t Q = w.qf + (uint32_t)(((uint64_t)w.rem + (uint64_t)i0 * dd) / T) - qlo;
+        uint32_t line = (uint32_t)((xf >> ls) + (uint64_t)i0 * lb);
+        const uint32_t lstep = (uint32_t)((uint64_t)P * lb);   // wraps only past the last access
+        uint32_t k = kstart + i0;
+        for (uint32_t j = 0; j < n; ++j, line += lstep, Q += sdg, k += P)
+            visit(line, (Q << rsh) + (line & ((1u << rsh) - 1)), k, 1);
+        return;
+    }
     if (w.aligned) {
         // unit u = uf + d starts at access d*R - off0; units advance by T
         const uint32_t d = set >= w.rem ? set - w.rem : set + T - w.rem;
