@@ -105,6 +105,45 @@ static bool lines_once_per_pass(const DevProbe& p, uint32_t ls) {
     return true;
 }
 
+// Runs of one pass that visits every line of a range [lo, hi] exactly once
+// with d sweeps of stride d lines (d <= 64): sweep o (after sorting) starts at
+// line lo + o, at access (*ks)[o] of the pass.  Returns hi - lo + 1, or 0
+// when the pass is not of that shape.
+static uint64_t multi_sweep_runs(const DevProbe& p, uint32_t ls, std::vector<uint64_t>* ks) {
+    if (p.se == 0 || one_sweep_per_pass(p)) return 0;
+    const uint64_t sb = (uint64_t)p.se << p.elem_shift;
+    if (sb & ((1ull << ls) - 1)) return 0;
+    const uint64_t d = sb >> ls;
+    if (d > 64) return 0;
+    struct Sw {
+        uint64_t first, last, k;
+    };
+    std::vector<Sw> sw;
+    uint64_t r = p.j0, kpos = 0;
+    while (kpos < p.L) {
+        if (sw.size() == d) return 0;   // more sweeps than residues: some line repeats
+        uint64_t cnt = ((uint64_t)p.ne - r + p.se - 1) / p.se;
+        if (cnt > p.L - kpos) cnt = p.L - kpos;
+        const uint64_t f = (p.base + (r << p.elem_shift)) >> ls;
+        sw.push_back(Sw{f, f + (cnt - 1) * d, kpos});
+        kpos += cnt;
+        r = r + cnt * p.se - p.ne;
+    }
+    if (sw.size() != d) return 0;
+    uint64_t lo = ~0ull, hi = 0;
+    for (const Sw& x : sw) {
+        lo = std::min(lo, x.first);
+        hi = std::max(hi, x.last);
+    }
+    ks->assign(d, ~0ull);
+    for (const Sw& x : sw) {
+        const uint64_t o = x.first - lo;
+        if (o >= d || hi - x.last >= d || (*ks)[o] != ~0ull) return 0;
+        (*ks)[o] = x.k;
+    }
+    return hi - lo + 1;
+}
+
 static uint64_t gcd64(uint64_t x, uint64_t y) {
     while (y) {
         const uint64_t t = x % y;
@@ -1136,13 +1175,12 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->n_cands = n_cands;
     np->n_host.assign(n_cands, 0);
     std::vector<SweepJob> jobs;
-    std::vector<uint32_t> dec_off(n_cands + 1, 0);
     std::vector<DecidedJob> decided;
     std::vector<RunTable> tables;
+    std::vector<uint64_t> table_ks;   // first access of each sweep of the multi-sweep tables
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> table_of;   // (probe, line shift) -> table
     uint64_t entries = 0;
     for (uint32_t c = 0; c < n_cands; ++c) {
-        dec_off[c] = (uint32_t)decided.size();
         if (allow && !(*allow)[c]) continue;
         const DevModel& md = dm[c];
         // the closed forms hold for LRU and FIFO; with one way every policy
@@ -1156,7 +1194,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // compared: the only misses are first touches, all in the first
             // pass, so the score is the observed misses alone
             if (closed && cf[p] >= dp[p].L && no_eviction(md, dp[p])) {
-                decided.push_back(DecidedJob{p, 0, 0, 0, 1});
+                decided.push_back(DecidedJob{p, 0, 0, 0, 1, c, 0});
                 np->decided_accesses += len[p];
                 continue;
             }
@@ -1166,8 +1204,15 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // share a set and the runs of one period are in distinct sets;
             // a visited set holds q0 or q0 + 1 lines (the latter for
             // i mod T' < r, with U runs = q0 T' + r)
+            // (several sweeps that visit every line of a range once: the
+            // runs in line order, d = 1)
             uint64_t d = 1;
-            const uint64_t U = closed && md.unit_shift == md.line_shift ? sweep_runs(dp[p], md.line_shift, &d) : 0;
+            std::vector<uint64_t> ks;
+            uint64_t U = 0;
+            if (closed && md.unit_shift == md.line_shift) {
+                U = sweep_runs(dp[p], md.line_shift, &d);
+                if (!U) U = multi_sweep_runs(dp[p], md.line_shift, &ks);
+            }
             if (U) {
                 const uint64_t Tp = md.sets / gcd64(d % md.sets, md.sets);
                 const uint64_t q0 = U / Tp, r = U % Tp;
@@ -1182,7 +1227,9 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                         tid = it->second;
                     } else if (entries + U + 1 <= kMaxTableEntries) {
                         tid = (uint32_t)tables.size();
-                        tables.push_back(RunTable{p, md.line_shift, U, entries});
+                        tables.push_back(RunTable{p, md.line_shift, U, entries, (uint32_t)ks.size(), 0,
+                                                  (uint64_t)table_ks.size()});
+                        table_ks.insert(table_ks.end(), ks.begin(), ks.end());
                         table_of.emplace(key, tid);
                         entries += U + 1;
                     } else {
@@ -1190,7 +1237,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                     }
                 }
                 if (ok) {
-                    decided.push_back(DecidedJob{p, tid, (uint32_t)kind, (uint32_t)r, Tp});
+                    decided.push_back(DecidedJob{p, tid, (uint32_t)kind, (uint32_t)r, Tp, c, 0});
                     np->decided_accesses += len[p];
                     continue;
                 }
@@ -1208,7 +1255,6 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             jobs.push_back(j);
         }
     }
-    dec_off[n_cands] = (uint32_t)decided.size();
     int rc = build_sweep_plan(&np->sweep, dm, dp, len, jobs, false, false);
     if (rc) return rc;
     const size_t zw = (n_cands + 31) / 32;
@@ -1218,10 +1264,10 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_zeros = o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t);
     auto up256 = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t o_dec = up256(o_zeros + (size_t)n_probes * sizeof(uint64_t));
-    const size_t o_doff = up256(o_dec + decided.size() * sizeof(DecidedJob));
-    const size_t o_tab = up256(o_doff + dec_off.size() * sizeof(uint32_t));
+    const size_t o_tab = up256(o_dec + decided.size() * sizeof(DecidedJob));
     const size_t o_s1 = up256(o_tab + tables.size() * sizeof(RunTable));
-    const size_t o_pre = up256(o_s1 + tables.size() * sizeof(int64_t));
+    const size_t o_ks = up256(o_s1 + tables.size() * sizeof(int64_t));
+    const size_t o_pre = up256(o_ks + table_ks.size() * sizeof(uint64_t));
     const size_t bytes = o_pre + entries * sizeof(int64_t);
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
@@ -1235,11 +1281,12 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->n_probes = n_probes;
     np->sweep.zeros = np->d_zeros;
     np->d_decided = reinterpret_cast<DecidedJob*>(b + o_dec);
-    np->d_dec_off = reinterpret_cast<uint32_t*>(b + o_doff);
     np->d_tables = reinterpret_cast<RunTable*>(b + o_tab);
     np->d_s1 = reinterpret_cast<int64_t*>(b + o_s1);
     np->d_prefix = reinterpret_cast<int64_t*>(b + o_pre);
+    np->d_table_ks = reinterpret_cast<uint64_t*>(b + o_ks);
     np->n_tables = (uint32_t)tables.size();
+    np->n_decided = (uint32_t)decided.size();
     std::vector<uint64_t> pinfo(3 * (size_t)n_probes);
     for (uint32_t p = 0; p < n_probes; ++p) {
         pinfo[3 * (size_t)p] = bitoff[p];
@@ -1248,11 +1295,12 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     }
     PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
     if (n_probes) PC_HIP(hipMemcpy(np->d_pinfo, pinfo.data(), pinfo.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    PC_HIP(hipMemcpy(np->d_dec_off, dec_off.data(), dec_off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     if (!decided.empty())
         PC_HIP(hipMemcpy(np->d_decided, decided.data(), decided.size() * sizeof(DecidedJob), hipMemcpyHostToDevice));
     if (!tables.empty())
         PC_HIP(hipMemcpy(np->d_tables, tables.data(), tables.size() * sizeof(RunTable), hipMemcpyHostToDevice));
+    if (!table_ks.empty())
+        PC_HIP(hipMemcpy(np->d_table_ks, table_ks.data(), table_ks.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     *out = std::move(np);
     return PCHASE_OK;
 }
@@ -1332,8 +1380,8 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
-        hipError_t e = launch_decided(pp->d_dec_off, pp->d_decided, pp->n_cands, pp->d_zeros, pp->d_tables,
-                                      pp->d_prefix, pp->d_s1, pp->d_m, s);
+        hipError_t e = launch_decided(pp->d_decided, pp->n_decided, pp->d_zeros, pp->d_tables, pp->d_prefix,
+                                      pp->d_s1, pp->d_m, s);
         if (e != hipSuccess) return e;
         e = launch_fill_u32(pp->d_zero, zw, 0, s);
         if (e != hipSuccess) return e;
@@ -1342,8 +1390,8 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     // the observed misses of each probe, the constant part of every score,
     // and the run tables of the jobs decided without a replay
     PC_HIP(launch_obs_zeros(bits, ip->d_pinfo, ip->n_probes, ip->d_zeros, stream));
-    PC_HIP(launch_run_tables(ip->d_tables, ip->n_tables, ip->sweep.d_probes, ip->d_pinfo, bits, ip->d_prefix,
-                             ip->d_s1, stream));
+    PC_HIP(launch_run_tables(ip->d_tables, ip->n_tables, ip->sweep.d_probes, ip->d_table_ks, ip->d_pinfo, bits,
+                             ip->d_prefix, ip->d_s1, stream));
     // the first run of a cached plan answers at once with the default branch
     // strategy; the next run times the strategies and keeps the fastest
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,

@@ -219,17 +219,24 @@ hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t 
 // zeros[p] = number of 0 bits of bits + pinfo[3p] (a word offset) over bit
 // indices [pinfo[3p+1], pinfo[3p+2]) (count_from, length), for p < n.
 // Scoring without a replay.  A run table lists the runs (line visits) of one
-// pass of a probe whose every pass is one increasing sweep and whose visited
-// lines (line size 2^line_shift) form an arithmetic progression: run i is
-// the i-th line visited, d lines after run i-1.  Per call, the prefix over
-// runs of the later passes' signed weights w(k) = [k >= count_from] *
-// (2 obs(k) - 1) at the run's start k goes to prefix[off .. off + runs] and
-// the first pass's total to s1[table].
+// pass of a probe whose visited lines (line size 2^line_shift) form an
+// arithmetic progression, each line visited once per pass, in the order of
+// the lines: either one increasing sweep (nsw == 0; run i is the i-th line
+// visited, first access per the stride) or nsw sweeps of stride nsw lines
+// that together visit every line of a range once (run i is the range's
+// i-th line, visited by the sweep starting at access ks[koff + i mod nsw],
+// as its (i / nsw)-th access).  Per call, the prefix over runs of the later
+// passes' signed weights w(k) = [k >= count_from] * (2 obs(k) - 1) at the
+// run's start k goes to prefix[off .. off + runs] and the first pass's total
+// to s1[table].
 struct RunTable {
     uint32_t probe;
     uint32_t line_shift;
     uint64_t runs;
     uint64_t off;
+    uint32_t nsw;
+    uint32_t pad;
+    uint64_t koff;
 };
 // A job decided without a replay, by kind:
 //   0  no eviction, nothing of the first pass compared: the observed misses;
@@ -245,14 +252,15 @@ struct DecidedJob {
     uint32_t kind;
     uint32_t rem;
     uint64_t period;
+    uint32_t cand;        // score slot
+    uint32_t pad;
 };
 hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
-                             const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix, int64_t* s1,
-                             hipStream_t stream);
-// m[c] += the scores of candidate c's decided jobs dj[off[c] .. off[c+1]), c < n.
-hipError_t launch_decided(const uint32_t* off, const DecidedJob* dj, uint32_t n, const uint64_t* zeros,
-                          const RunTable* tables, const int64_t* prefix, const int64_t* s1, uint64_t* m,
-                          hipStream_t stream);
+                             const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
+                             int64_t* s1, hipStream_t stream);
+// m[dj[i].cand] += the score of decided job i, i < n (jobs grouped by cand).
+hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
+                          const int64_t* prefix, const int64_t* s1, uint64_t* m, hipStream_t stream);
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
                             hipStream_t stream);
 // m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from

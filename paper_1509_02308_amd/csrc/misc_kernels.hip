@@ -449,7 +449,8 @@ __device__ __forceinline__ int64_t obs_weight(const uint32_t* ob, uint64_t k, ui
 
 // One wave per run table; lanes take 64 runs at a time and carry the prefix.
 __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
-                                 const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix, int64_t* s1) {
+                                 const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
+                                 int64_t* s1) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (w >= n_tables) return;
@@ -461,15 +462,18 @@ __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, cons
     const uint64_t x0 = p.base + ((uint64_t)p.j0 << p.elem_shift);
     const uint64_t l0 = x0 >> t.line_shift;
     // runs are single accesses unless the stride is below the line
-    const bool per_line = t.runs > 1 && sb < (1ull << t.line_shift);
+    const bool per_line = t.nsw == 0 && t.runs > 1 && sb < (1ull << t.line_shift);
     int64_t* out = prefix + t.off;
     int64_t carry = 0, first = 0;
     for (uint64_t i0 = 0; i0 < t.runs; i0 += kWave) {
         const uint64_t i = i0 + lane;
         int64_t w2 = 0;
         if (i < t.runs) {
-            // first access of line l0 + i: ceil((line start - x0) / stride)
-            const uint64_t k = (per_line && i > 0) ? udiv64(((l0 + i) << t.line_shift) - x0 + sb - 1, sb) : i;
+            // first access of line l0 + i: ceil((line start - x0) / stride);
+            // several sweeps: the (i / nsw)-th access of sweep i mod nsw
+            uint64_t k;
+            if (t.nsw) k = ks[t.koff + (uint32_t)i % t.nsw] + (uint32_t)i / t.nsw;
+            else k = (per_line && i > 0) ? udiv64(((l0 + i) << t.line_shift) - x0 + sb - 1, sb) : i;
             first += obs_weight(ob, k, cf);
             uint64_t kk = k;
             for (uint32_t q = 1; q < p.passes; ++q) {
@@ -494,25 +498,27 @@ __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, cons
 }
 
 hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
-                             const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix, int64_t* s1,
-                             hipStream_t stream) {
+                             const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
+                             int64_t* s1, hipStream_t stream) {
     if (n_tables == 0) return hipSuccess;
     const uint32_t wpb = 256 / kWave;
     hipLaunchKernelGGL(run_table_kernel, dim3((n_tables + wpb - 1) / wpb), dim3(256), 0, stream, tables, n_tables,
-                       probes, pinfo, bits, prefix, s1);
+                       probes, ks, pinfo, bits, prefix, s1);
     return hipGetLastError();
 }
 
-// One wave per candidate; lanes take its decided jobs in turn.
-__global__ void decided_kernel(const uint32_t* off, const DecidedJob* dj, uint32_t n, const uint64_t* zeros,
-                               const RunTable* tables, const int64_t* prefix, const int64_t* s1, uint64_t* m) {
+// One lane per decided job; jobs of one candidate are contiguous, so a
+// segmented wave sum and one atomic per candidate run of the wave follow.
+__global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
+                               const int64_t* prefix, const int64_t* s1, uint64_t* m) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (c >= n) return;
-    int64_t acc = 0;
-    for (uint32_t i = off[c] + lane; i < off[c + 1]; i += kWave) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t key = 0xFFFFFFFFu;
+    int64_t v = 0;
+    if (i < n) {
         const DecidedJob j = dj[i];
-        int64_t v = (int64_t)zeros[j.probe];
+        key = j.cand;
+        v = (int64_t)zeros[j.probe];
         if (j.kind >= 1) v += s1[j.table];
         if (j.kind >= 2) {
             const RunTable t = tables[j.table];
@@ -526,20 +532,23 @@ __global__ void decided_kernel(const uint32_t* off, const DecidedJob* dj, uint32
                 }
             }
         }
-        acc += v;
     }
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
-    if (lane == 0) m[c] += (uint64_t)acc;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t o = __shfl_down(v, off, kWave);
+        const uint32_t ok = __shfl_down(key, off, kWave);
+        if ((int)lane + off < kWave && ok == key) v += o;
+    }
+    const uint32_t up = __shfl_up(key, 1, kWave);
+    if (key != 0xFFFFFFFFu && (lane == 0 || up != key) && v != 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(m + key), (unsigned long long)v);
 }
 
-hipError_t launch_decided(const uint32_t* off, const DecidedJob* dj, uint32_t n, const uint64_t* zeros,
-                          const RunTable* tables, const int64_t* prefix, const int64_t* s1, uint64_t* m,
-                          hipStream_t stream) {
+hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
+                          const int64_t* prefix, const int64_t* s1, uint64_t* m, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    const uint32_t wpb = 256 / kWave;
-    hipLaunchKernelGGL(decided_kernel, dim3((n + wpb - 1) / wpb), dim3(256), 0, stream, off, dj, n, zeros, tables,
-                       prefix, s1, m);
+    hipLaunchKernelGGL(decided_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, dj, n, zeros, tables, prefix,
+                       s1, m);
     return hipGetLastError();
 }
 

@@ -77,14 +77,15 @@ struct InferPlan {
     uint64_t* d_pinfo = nullptr;    // per probe: bitmap word offset, count_from, length
     uint64_t* d_zeros = nullptr;    // per probe: observed misses from count_from on
     uint32_t n_probes = 0;
-    // jobs decided without a replay: candidate c's are d_decided[d_dec_off[c]
-    // .. d_dec_off[c+1]), scored from the observed misses and the run tables
+    // jobs decided without a replay (grouped by candidate), scored from the
+    // observed misses and the run tables
     DecidedJob* d_decided = nullptr;
-    uint32_t* d_dec_off = nullptr;
     RunTable* d_tables = nullptr;
     int64_t* d_s1 = nullptr;
     int64_t* d_prefix = nullptr;
+    uint64_t* d_table_ks = nullptr;
     uint32_t n_tables = 0;
+    uint32_t n_decided = 0;
     uint64_t decided_accesses = 0;  // their accesses
     uint64_t cyc_accesses = 0;      // accesses of the plan's closed-form (kACyc) jobs
     uint64_t* d_m = nullptr;
