@@ -85,7 +85,7 @@ def lane_ops_per_access(a: int, policy: int) -> float:
     return a + 8
 
 
-def closed_form(C: int, b: int, a: int, pol: int, N: int, s: int, L: int) -> bool:
+def closed_form(C: int, b: int, a: int, pol: int, N: int, s: int, L: int, passes: int) -> bool:
     """Whether the library scores the job (candidate, probe) of this
     workload (base 0, j0 0, 4-byte elements, count_from one pass) without a
     replay through way state, by the rules include/pchase.h states: no
@@ -93,8 +93,9 @@ def closed_form(C: int, b: int, a: int, pol: int, N: int, s: int, L: int) -> boo
     LRU-like model (LRU, FIFO, one way, two-way tree-PLRU) on a chase that
     visits every line at most once per pass; or a pass that is one
     increasing sweep over an arithmetic progression of lines whose sets
-    never evict.  The benchmark checks the total against the library's
-    closed_form_accesses."""
+    never evict or that tree-PLRU replays over two passes (a second-pass
+    pattern per (a, lines of the set)).  The benchmark checks the total
+    against the library's closed_form_accesses."""
     ls = b.bit_length() - 1
     T = C // (a * b)
     ne, se = N // 4, (s // 4) % (N // 4)
@@ -119,19 +120,39 @@ def closed_form(C: int, b: int, a: int, pol: int, N: int, s: int, L: int) -> boo
             k += cnt
             r = r + cnt * se - ne
         return True
-    if not single:
-        return False
-    if se == 0 or L == 1:
-        U, d = 1, 1
-    elif sb <= b:
-        U, d = (((L - 1) * sb) >> ls) + 1, 1
-    elif sb % b == 0:
-        U, d = L, sb // b
+    nsw = 0
+    if single:
+        if se == 0 or L == 1:
+            U, d = 1, 1
+        elif sb <= b:
+            U, d = (((L - 1) * sb) >> ls) + 1, 1
+        elif sb % b == 0:
+            U, d = L, sb // b
+        else:
+            return False
     else:
-        return False
+        # sweeps of stride nsw lines that visit every line of a range once
+        if sb % b or sb // b > 64:
+            return False
+        nsw, sweeps, r, k = sb // b, [], 0, 0
+        while k < L:
+            if len(sweeps) == nsw:
+                return False
+            cnt = min(-(-(ne - r) // se), L - k)
+            f = (4 * r) >> ls
+            sweeps.append((f, f + (cnt - 1) * nsw))
+            k += cnt
+            r = r + cnt * se - ne
+        lo, hi = min(f for f, _ in sweeps), max(l for _, l in sweeps)
+        offs = {f - lo for f, _ in sweeps}
+        if len(sweeps) != nsw or len(offs) != nsw or max(offs) >= nsw or min(hi - l for _, l in sweeps) < 0 \
+                or max(hi - l for _, l in sweeps) >= nsw:
+            return False
+        U, d = hi - lo + 1, 1
     Tp = T // math.gcd(d % T, T)
     q0, r = divmod(U, Tp)
-    return q0 + (1 if r else 0) <= a
+    return q0 + (1 if r else 0) <= a or \
+        (pol == 2 and passes == 2 and (nsw == 0 or T % nsw == 0) and q0 + 1 <= 4096)
 
 
 def main():
@@ -196,7 +217,7 @@ def main():
             acc = int(lens[i])
             accesses += acc
             lane_ops_all += acc * lane_ops_per_access(a, pol)
-            if closed_form(C, b, a, pol, N, s, acc // passes):
+            if closed_form(C, b, a, pol, N, s, acc // passes, passes):
                 closed += acc
             else:
                 lane_ops += acc * lane_ops_per_access(a, pol)

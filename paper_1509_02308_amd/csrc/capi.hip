@@ -155,6 +155,8 @@ static uint64_t gcd64(uint64_t x, uint64_t y) {
 
 // Largest run table (entries of 8 bytes) an inference plan builds.
 constexpr uint64_t kMaxTableEntries = 1ull << 26;
+// Largest set (lines) a tree-PLRU pattern is tabulated for.
+constexpr uint64_t kMaxPatternLines = 4096;
 
 static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     const uint64_t C = c.capacity_bytes, b = c.line_bytes, N = p.n_bytes, s = p.s_bytes;
@@ -1180,6 +1182,9 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     std::vector<uint64_t> table_ks;   // first access of each sweep of the multi-sweep tables
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> table_of;   // (probe, line shift) -> table
     uint64_t entries = 0;
+    std::vector<PlruPattern> patterns;
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> pattern_of;   // (ways, lines) -> pattern
+    uint64_t pat_bits = 0, pat_scratch = 0;
     for (uint32_t c = 0; c < n_cands; ++c) {
         if (allow && !(*allow)[c]) continue;
         const DevModel& md = dm[c];
@@ -1194,7 +1199,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // compared: the only misses are first touches, all in the first
             // pass, so the score is the observed misses alone
             if (closed && cf[p] >= dp[p].L && no_eviction(md, dp[p])) {
-                decided.push_back(DecidedJob{p, 0, 0, 0, 1, c, 0});
+                decided.push_back(DecidedJob{p, 0, 0, 0, 1, c, 0, 0, 0});
                 np->decided_accesses += len[p];
                 continue;
             }
@@ -1217,8 +1222,30 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                 const uint64_t Tp = md.sets / gcd64(d % md.sets, md.sets);
                 const uint64_t q0 = U / Tp, r = U % Tp;
                 const bool none = q0 + (r ? 1 : 0) <= md.ways;   // no eviction
-                const int kind = none ? (cf[p] >= dp[p].L ? 0 : 1) : !lru_fifo ? -1 : q0 > md.ways ? 2 : 3;
-                uint32_t tid = 0;
+                // tree-PLRU: per-(a, n) second-pass patterns, for two-pass
+                // chases that visit each set's lines in line order (one
+                // sweep; or sweeps of stride nsw lines with nsw dividing T,
+                // so that a set's lines all lie in one sweep)
+                const bool plru_pat = md.policy == PCHASE_PLRU && dp[p].passes == 2 &&
+                                      (ks.empty() || md.sets % ks.size() == 0) && q0 + 1 <= kMaxPatternLines;
+                const int kind = none ? (cf[p] >= dp[p].L ? 0 : 1)
+                                 : lru_fifo ? (q0 > md.ways ? 2 : 3) : plru_pat ? 4 : -1;
+                uint32_t tid = 0, pb = 0, ps = 0;
+                if (kind == 4) {
+                    auto pattern = [&](uint32_t n) -> uint32_t {
+                        auto key = std::make_pair(md.ways, n);
+                        auto it = pattern_of.find(key);
+                        if (it != pattern_of.end()) return it->second;
+                        const uint32_t id = (uint32_t)patterns.size();
+                        patterns.push_back(PlruPattern{md.ways, md.log2_ways, n, (uint32_t)pat_scratch, pat_bits});
+                        pat_scratch += n + md.ways;
+                        pat_bits += (n + 31) / 32 * 32;
+                        pattern_of.emplace(key, id);
+                        return id;
+                    };
+                    ps = pattern((uint32_t)q0);
+                    pb = r ? pattern((uint32_t)q0 + 1) : ps;
+                }
                 bool ok = kind >= 0;
                 if (kind >= 1) {
                     auto key = std::make_pair(p, md.line_shift);
@@ -1237,7 +1264,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                     }
                 }
                 if (ok) {
-                    decided.push_back(DecidedJob{p, tid, (uint32_t)kind, (uint32_t)r, Tp, c, 0});
+                    decided.push_back(DecidedJob{p, tid, (uint32_t)kind, (uint32_t)r, Tp, c, pb, ps, 0});
                     np->decided_accesses += len[p];
                     continue;
                 }
@@ -1267,7 +1294,10 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_tab = up256(o_dec + decided.size() * sizeof(DecidedJob));
     const size_t o_s1 = up256(o_tab + tables.size() * sizeof(RunTable));
     const size_t o_ks = up256(o_s1 + tables.size() * sizeof(int64_t));
-    const size_t o_pre = up256(o_ks + table_ks.size() * sizeof(uint64_t));
+    const size_t o_pat = up256(o_ks + table_ks.size() * sizeof(uint64_t));
+    const size_t o_pbits = up256(o_pat + patterns.size() * sizeof(PlruPattern));
+    const size_t o_pscr = up256(o_pbits + pat_bits / 8);
+    const size_t o_pre = up256(o_pscr + pat_scratch * sizeof(uint32_t));
     const size_t bytes = o_pre + entries * sizeof(int64_t);
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
@@ -1285,6 +1315,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->d_s1 = reinterpret_cast<int64_t*>(b + o_s1);
     np->d_prefix = reinterpret_cast<int64_t*>(b + o_pre);
     np->d_table_ks = reinterpret_cast<uint64_t*>(b + o_ks);
+    np->d_patterns = reinterpret_cast<PlruPattern*>(b + o_pat);
+    np->d_pat_bits = reinterpret_cast<uint32_t*>(b + o_pbits);
     np->n_tables = (uint32_t)tables.size();
     np->n_decided = (uint32_t)decided.size();
     std::vector<uint64_t> pinfo(3 * (size_t)n_probes);
@@ -1301,6 +1333,14 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
         PC_HIP(hipMemcpy(np->d_tables, tables.data(), tables.size() * sizeof(RunTable), hipMemcpyHostToDevice));
     if (!table_ks.empty())
         PC_HIP(hipMemcpy(np->d_table_ks, table_ks.data(), table_ks.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (!patterns.empty()) {
+        // the patterns depend on the plan only: computed once, here
+        PC_HIP(hipMemcpy(np->d_patterns, patterns.data(), patterns.size() * sizeof(PlruPattern),
+                         hipMemcpyHostToDevice));
+        PC_HIP(launch_plru_patterns(np->d_patterns, (uint32_t)patterns.size(), np->d_pat_bits,
+                                    reinterpret_cast<uint32_t*>(b + o_pscr), nullptr));
+        PC_HIP(hipStreamSynchronize(nullptr));
+    }
     *out = std::move(np);
     return PCHASE_OK;
 }
@@ -1381,7 +1421,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
         hipError_t e = launch_decided(pp->d_decided, pp->n_decided, pp->d_zeros, pp->d_tables, pp->d_prefix,
-                                      pp->d_s1, pp->d_m, s);
+                                      pp->d_s1, pp->d_patterns, pp->d_pat_bits, pp->d_m, s);
         if (e != hipSuccess) return e;
         e = launch_fill_u32(pp->d_zero, zw, 0, s);
         if (e != hipSuccess) return e;

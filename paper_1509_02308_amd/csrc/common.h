@@ -245,7 +245,12 @@ struct RunTable {
 //      start misses): + s1 + all later-pass weights;
 //   3  LRU or FIFO, the sets of runs i with i mod period < rem hold more
 //      lines than ways and the others do not: + s1 + the later-pass weights
-//      of those runs.
+//      of those runs;
+//   4  tree-PLRU, two passes, one sweep: the set of run i holds q0 + 1
+//      lines if i mod period < rem, else q0, and run i is its set's
+//      (i / period)-th line; + s1 + the second-pass weights of the runs
+//      whose position misses in the second pass of a cyclic chase over
+//      that many lines (pattern pat_big, pat_small).
 struct DecidedJob {
     uint32_t probe;
     uint32_t table;
@@ -253,14 +258,29 @@ struct DecidedJob {
     uint32_t rem;
     uint64_t period;
     uint32_t cand;        // score slot
+    uint32_t pat_big;     // kind 4: pattern of the sets with q0 + 1 lines
+    uint32_t pat_small;   // kind 4: pattern of the sets with q0 lines
     uint32_t pad;
 };
+// Second-pass miss pattern of a cyclic chase over n distinct lines through
+// one a-way tree-PLRU set (ways filled in order, all node bits 0 at the
+// start): bit i of bits[off ..] = the visit of the i-th line misses.
+struct PlruPattern {
+    uint32_t ways;
+    uint32_t log2_ways;
+    uint32_t lines;
+    uint32_t scr;         // scratch offset (lines + ways words)
+    uint64_t off;         // bit offset, a multiple of 32
+};
+hipError_t launch_plru_patterns(const PlruPattern* pd, uint32_t n, uint32_t* bits, uint32_t* scratch,
+                                hipStream_t stream);
 hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
                              const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
                              int64_t* s1, hipStream_t stream);
 // m[dj[i].cand] += the score of decided job i, i < n (jobs grouped by cand).
 hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
-                          const int64_t* prefix, const int64_t* s1, uint64_t* m, hipStream_t stream);
+                          const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
+                          const uint32_t* pat_bits, uint64_t* m, hipStream_t stream);
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
                             hipStream_t stream);
 // m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from

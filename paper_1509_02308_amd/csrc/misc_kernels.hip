@@ -1,7 +1,7 @@
 // misc_kernels.hip -- trace generation (Listing 1 + Listing 2), latency
 // classification (Section 4.1, t = t0 + tm*r), exact argmin over candidate
 // scores and small fill kernels.
-#include "common.h"
+#include "sweep_lane.h"
 
 namespace pc {
 
@@ -510,7 +510,8 @@ hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const De
 // One lane per decided job; jobs of one candidate are contiguous, so a
 // segmented wave sum and one atomic per candidate run of the wave follow.
 __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
-                               const int64_t* prefix, const int64_t* s1, uint64_t* m) {
+                               const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
+                               const uint32_t* pat_bits, uint64_t* m) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t key = 0xFFFFFFFFu;
@@ -525,10 +526,26 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
             const int64_t* P = prefix + t.off;
             if (j.kind == 2) {
                 v += P[t.runs];
-            } else {
+            } else if (j.kind == 3) {
                 for (uint64_t st = 0; st < t.runs; st += j.period) {
                     const uint64_t hi = st + j.rem < t.runs ? st + j.rem : t.runs;
                     v += P[hi] - P[st];
+                }
+            } else {
+                // position i (a set bit of the pattern): runs [i T', i T' +
+                // rem) of the big sets, [i T' + rem, (i + 1) T') of the small
+                for (int part = 0; part < 2; ++part) {
+                    if (part == 0 && j.rem == 0) continue;
+                    const PlruPattern pt = pats[part == 0 ? j.pat_big : j.pat_small];
+                    const uint32_t* pw = pat_bits + (pt.off >> 5);
+                    for (uint32_t w = 0; w < (pt.lines + 31) / 32; ++w) {
+                        for (uint32_t bits = pw[w]; bits != 0; bits &= bits - 1) {
+                            const uint64_t st = (uint64_t)(w * 32 + (uint32_t)__ffs(bits) - 1) * j.period;
+                            const uint64_t mid = st + j.rem < t.runs ? st + j.rem : t.runs;
+                            const uint64_t end = st + j.period < t.runs ? st + j.period : t.runs;
+                            v += part == 0 ? P[mid] - P[st] : P[end] - P[mid];
+                        }
+                    }
                 }
             }
         }
@@ -545,10 +562,49 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
 }
 
 hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
-                          const int64_t* prefix, const int64_t* s1, uint64_t* m, hipStream_t stream) {
+                          const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
+                          const uint32_t* pat_bits, uint64_t* m, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(decided_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, dj, n, zeros, tables, prefix,
-                       s1, m);
+                       s1, pats, pat_bits, m);
+    return hipGetLastError();
+}
+
+// One lane per pattern: the set's way -> line and line -> way maps live in
+// the lane's scratch words; the tree bits in registers.
+__global__ void plru_pattern_kernel(const PlruPattern* pd, uint32_t n, uint32_t* bits, uint32_t* scratch) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const PlruPattern p = pd[t];
+    uint32_t* way_line = scratch + p.scr;
+    uint32_t* line_way = way_line + p.ways;
+    uint32_t* out = bits + (p.off >> 5);
+    for (uint32_t w = 0; w < p.ways; ++w) way_line[w] = kInvalidTag;
+    for (uint32_t x = 0; x < p.lines; ++x) line_way[x] = kInvalidTag;
+    for (uint32_t w = 0; w < (p.lines + 31) / 32; ++w) out[w] = 0;
+    PlruBits tree;
+    uint32_t nvalid = 0;
+    for (uint32_t pass = 0; pass < 2; ++pass) {
+        for (uint32_t x = 0; x < p.lines; ++x) {
+            uint32_t w = line_way[x];
+            const bool hit = w != kInvalidTag;
+            if (!hit) {
+                w = nvalid < p.ways ? nvalid++ : tree.victim(p.log2_ways, p.ways);
+                const uint32_t old = way_line[w];
+                if (old != kInvalidTag) line_way[old] = kInvalidTag;
+                way_line[w] = x;
+                line_way[x] = w;
+                if (pass == 1) out[x >> 5] |= 1u << (x & 31);
+            }
+            tree.touch(w, p.log2_ways);
+        }
+    }
+}
+
+hipError_t launch_plru_patterns(const PlruPattern* pd, uint32_t n, uint32_t* bits, uint32_t* scratch,
+                                hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(plru_pattern_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, pd, n, bits, scratch);
     return hipGetLastError();
 }
 

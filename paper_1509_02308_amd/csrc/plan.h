@@ -84,6 +84,8 @@ struct InferPlan {
     int64_t* d_s1 = nullptr;
     int64_t* d_prefix = nullptr;
     uint64_t* d_table_ks = nullptr;
+    PlruPattern* d_patterns = nullptr;
+    uint32_t* d_pat_bits = nullptr;
     uint32_t n_tables = 0;
     uint32_t n_decided = 0;
     uint64_t decided_accesses = 0;  // their accesses
