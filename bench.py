@@ -8,6 +8,14 @@ accesses -- scored against one seeded synthetic observation, exact argmin
 and zero class returned to the host.  The observation is the replay of a
 seeded target candidate; inputs are resident in HBM before timing.
 
+The default step scores the jobs that have a closed form (no eviction
+possible; LRU, FIFO and tree-PLRU on chases that visit each set's lines in
+the same order every pass) without replaying their accesses, and replays
+the rest; the full-replay step (PCHASE_SCHED_FULL_REPLAY) replays every
+access through per-set state.  Both give the same (m, n) for every
+candidate, which the benchmark checks; the roofline is the replay
+engine's, on the full-replay step.
+
 Prints one JSON line (see the repository's benchmark contract).
 """
 from __future__ import annotations
@@ -281,8 +289,18 @@ def main():
         torch.cuda.synchronize()
         pw = (time.perf_counter() - tp) / args.plain_steps
         assert rp.best == res.best and rp.best_m == res.best_m
+        # the schedules compared on the replay engine: every access replayed
+        step(capi.SCHED_PLAIN | capi.SCHED_FULL_REPLAY)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        for _ in range(args.plain_steps):
+            rq = step(capi.SCHED_PLAIN | capi.SCHED_FULL_REPLAY)
+        torch.cuda.synchronize()
+        qw = (time.perf_counter() - tq) / args.plain_steps
+        assert rq.best == res.best and rq.best_m == res.best_m
         plain = {"value": accesses / pw, "unit": "accesses/s", "time_to_params_ms": pw * 1e3,
-                 "steps": args.plain_steps}
+                 "steps": args.plain_steps, "full_replay_value": accesses / qw,
+                 "full_replay_time_to_params_ms": qw * 1e3}
 
     # the same step with every access replayed through the per-set state:
     # the replay engine's own rate, and the same (m, n) for every candidate
@@ -318,20 +336,33 @@ def main():
 
     gpu_step_ms = float(np.median(gpu_ms))
     achieved = lane_ops / (gpu_step_ms * 1e-3)
+    closed_info = {"ms_per_step": wall * 1e3 / args.steps, "kernel_ms_per_step": gpu_step_ms,
+                   "accesses_scored_in_closed_form": closed,
+                   "accesses_replayed_through_way_state": accesses - closed,
+                   "way_state_lane_ops_per_step": lane_ops,
+                   "way_state_frac_of_valu_peak": achieved / PEAK_LANE_OPS,
+                   "note": "the default step: run tables (per-probe prefix sums of the observation), one lane per "
+                           "decided job (O(a) range sums), and the sweep kernels for the few jobs left; the "
+                           "roofline above is the replay engine's, on the full-replay step"}
+    # roofline of the replay engine: the sweep kernels replaying every access
+    # of the step (full replay); the default step decides almost all of them
+    # in closed form (closed_form above)
     measured_peak = capi.microbench_valu(8, 20000)
     traffic = measured_traffic()
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                "traffic_note": "HBM bytes per step (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed "
-                                "profile when it matches the current kernel sources, else null",
+    r_ms, r_ops, r_step = gpu_step_ms, lane_ops, "default"
+    if full is not None:
+        r_ms, r_ops, r_step = full["kernel_ms_per_step"], lane_ops_all, "full_replay"
+    r_ach = r_ops / (r_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": r_ach / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                "frac": r_ach / PEAK_LANE_OPS, "traffic": traffic if r_step == "full_replay" else None,
+                "traffic_note": "HBM bytes per full-replay step (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from "
+                                "the committed profile when it matches the current kernel sources, else null",
                 "algorithmic_bytes_per_step": accesses / 8,
-                "kernel": "sweep_kernel<policy, way class, score> (every bucket of one step, with the run-table and "
-                          "closed-form scoring kernels beside them)",
-                "algorithmic_lane_ops_per_step": lane_ops, "kernel_ms_per_step": gpu_step_ms,
-                "accesses_replayed_through_way_state": accesses - closed,
-                "accesses_scored_in_closed_form": closed,
-                "measured_valu_peak": measured_peak / 1e12, "frac_of_measured_peak": achieved / measured_peak,
-                "hbm_frac_algorithmic": accesses / 8 / (gpu_step_ms * 1e-3) / 8e12}
+                "kernel": "sweep_kernel<policy, way class, score> (every bucket of one step)",
+                "step": r_step,
+                "algorithmic_lane_ops_per_step": r_ops, "kernel_ms_per_step": r_ms,
+                "measured_valu_peak": measured_peak / 1e12, "frac_of_measured_peak": r_ach / measured_peak,
+                "hbm_frac_algorithmic": accesses / 8 / (r_ms * 1e-3) / 8e12}
 
     plain_sweep = None
     if args.plain_sweep_calls > 0:
@@ -380,10 +411,11 @@ def main():
                    "candidates": len(crows), "probes": len(prows), "replays": 1079586,
                    "accesses_per_step": accesses, "target": target, "schedule": "batched",
                    "closed_form_accesses_per_step": closed,
-                   "scoring": "default: jobs with a closed form (no eviction possible; LRU-like policies on "
-                              "chases that visit each line once per pass) are scored without a per-access "
-                              "replay, the rest replayed through per-set state; full_replay: every access "
-                              "replayed; both give the same (m, n) for every candidate"},
+                   "scoring": "default: jobs with a closed form (no eviction possible; LRU, FIFO and "
+                              "tree-PLRU on chases that visit each set's lines in the same order every pass) "
+                              "are scored without a per-access replay, the rest replayed through per-set "
+                              "state; full_replay: every access replayed; both give the same (m, n) for "
+                              "every candidate"},
         "time_to_params_ms": float(np.median(lat_ms)),
         "time_to_params_cold_ms": cold_ms,
         "tuning_step_ms": tune_ms,
@@ -392,6 +424,7 @@ def main():
         "zero_class": int(res.n_zero),
         "plain": plain,
         "full_replay": full,
+        "closed_form": closed_info,
         "plain_sweep": plain_sweep,
         "learned": learned,
         "large_batch": large,
@@ -482,6 +515,7 @@ def learned_leg(torch, capi, W, crows, args):
     capi.cache_replay_probes(carr, g, pm, pp, None, misses, all_bits, bo)
     obs = torch.zeros(tw, dtype=torch.int32, device="cuda")
     t_l, t_e, acc_l, acc_e, fb, exact, agree = [], [], 0, 0, 0, 0, 0
+    t_lf, t_ef, agree_f = [], [], 0   # every 10th target again with the closed forms off
     log(f"learned: {len(targets)} held-out targets")
     for k, t in enumerate(targets):
         if k and k % 250 == 0:
@@ -502,6 +536,17 @@ def learned_leg(torch, capi, W, crows, args):
         fb += rl.fallback != 0
         exact += rl.best_m == 0 and bool((zero[rl.best // 32] >> (rl.best % 32)) & 1)
         agree += rl.best == re.best
+        if k % 10 == 0:
+            d = time.perf_counter()
+            rlf, _ = capi.infer_cache_params(g, carr, bits=obs, bitoff=off, probe_select=capi.PROBES_ALL,
+                                             mode=capi.LEARNED | capi.SCHED_FULL_REPLAY, topk=8, net=net)
+            e = time.perf_counter()
+            ref, _ = capi.infer_cache_params(g, carr, bits=obs, bitoff=off, probe_select=capi.PROBES_ALL,
+                                             mode=capi.EXHAUSTIVE | capi.SCHED_FULL_REPLAY)
+            f = time.perf_counter()
+            t_lf.append(e - d)
+            t_ef.append(f - e)
+            agree_f += rlf.best == ref.best == re.best
     net.close()
     return {"samples": ns, "epochs": args.learned_epochs, "batch": 1024, "train_steps": steps,
             "labels_s": t_labels, "samples_s": t_samples, "train_s": t_train,
@@ -512,7 +557,11 @@ def learned_leg(torch, capi, W, crows, args):
             "time_to_params_ms": float(np.median(t_l) * 1e3),
             "exhaustive_time_to_params_ms": float(np.median(t_e) * 1e3),
             "replayed_accesses_per_target": acc_l / len(targets),
-            "exhaustive_replayed_accesses_per_target": acc_e / len(targets)}
+            "exhaustive_replayed_accesses_per_target": acc_e / len(targets),
+            "full_replay_targets": len(t_lf),
+            "full_replay_time_to_params_ms": float(np.median(t_lf) * 1e3) if t_lf else None,
+            "full_replay_exhaustive_time_to_params_ms": float(np.median(t_ef) * 1e3) if t_ef else None,
+            "full_replay_same_best": agree_f / max(1, len(t_lf))}
 
 
 def large_batch_leg(torch, capi, W, args, stream):

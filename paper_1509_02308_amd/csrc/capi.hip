@@ -1199,7 +1199,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // compared: the only misses are first touches, all in the first
             // pass, so the score is the observed misses alone
             if (closed && cf[p] >= dp[p].L && no_eviction(md, dp[p])) {
-                decided.push_back(DecidedJob{p, 0, 0, 0, 1, c, 0, 0, 0});
+                decided.push_back(DecidedJob{p, 0, 0, 0, 1, c, 0, 0, 0});   // slot set below
                 np->decided_accesses += len[p];
                 continue;
             }
@@ -1291,7 +1291,24 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_zeros = o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t);
     auto up256 = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t o_dec = up256(o_zeros + (size_t)n_probes * sizeof(uint64_t));
-    const size_t o_tab = up256(o_dec + decided.size() * sizeof(DecidedJob));
+    // jobs in table order for the gathers, slots in candidate order for the sums
+    std::vector<uint32_t> dec_cand(decided.size());
+    for (size_t q = 0; q < decided.size(); ++q) {
+        decided[q].slot = (uint32_t)q;
+        dec_cand[q] = decided[q].cand;
+    }
+    {
+        // counting sort by table, stable
+        std::vector<uint32_t> cnt(tables.size() + 2, 0);
+        for (const DecidedJob& x : decided) ++cnt[x.table + 1];
+        for (size_t t = 1; t < cnt.size(); ++t) cnt[t] += cnt[t - 1];
+        std::vector<DecidedJob> by_table(decided.size());
+        for (const DecidedJob& x : decided) by_table[cnt[x.table]++] = x;
+        decided.swap(by_table);
+    }
+    const size_t o_dval = up256(o_dec + decided.size() * sizeof(DecidedJob));
+    const size_t o_dcand = up256(o_dval + decided.size() * sizeof(int64_t));
+    const size_t o_tab = up256(o_dcand + decided.size() * sizeof(uint32_t));
     const size_t o_s1 = up256(o_tab + tables.size() * sizeof(RunTable));
     const size_t o_ks = up256(o_s1 + tables.size() * sizeof(int64_t));
     const size_t o_pat = up256(o_ks + table_ks.size() * sizeof(uint64_t));
@@ -1311,6 +1328,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->n_probes = n_probes;
     np->sweep.zeros = np->d_zeros;
     np->d_decided = reinterpret_cast<DecidedJob*>(b + o_dec);
+    np->d_dec_vals = reinterpret_cast<int64_t*>(b + o_dval);
+    np->d_dec_cand = reinterpret_cast<uint32_t*>(b + o_dcand);
     np->d_tables = reinterpret_cast<RunTable*>(b + o_tab);
     np->d_s1 = reinterpret_cast<int64_t*>(b + o_s1);
     np->d_prefix = reinterpret_cast<int64_t*>(b + o_pre);
@@ -1327,8 +1346,10 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     }
     PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
     if (n_probes) PC_HIP(hipMemcpy(np->d_pinfo, pinfo.data(), pinfo.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    if (!decided.empty())
+    if (!decided.empty()) {
         PC_HIP(hipMemcpy(np->d_decided, decided.data(), decided.size() * sizeof(DecidedJob), hipMemcpyHostToDevice));
+        PC_HIP(hipMemcpy(np->d_dec_cand, dec_cand.data(), dec_cand.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
     if (!tables.empty())
         PC_HIP(hipMemcpy(np->d_tables, tables.data(), tables.size() * sizeof(RunTable), hipMemcpyHostToDevice));
     if (!table_ks.empty())
@@ -1421,7 +1442,8 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
         hipError_t e = launch_decided(pp->d_decided, pp->n_decided, pp->d_zeros, pp->d_tables, pp->d_prefix,
-                                      pp->d_s1, pp->d_patterns, pp->d_pat_bits, pp->d_m, s);
+                                      pp->d_s1, pp->d_patterns, pp->d_pat_bits, pp->d_dec_vals, pp->d_dec_cand,
+                                      pp->d_m, s);
         if (e != hipSuccess) return e;
         e = launch_fill_u32(pp->d_zero, zw, 0, s);
         if (e != hipSuccess) return e;

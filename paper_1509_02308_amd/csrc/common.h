@@ -260,7 +260,7 @@ struct DecidedJob {
     uint32_t cand;        // score slot
     uint32_t pat_big;     // kind 4: pattern of the sets with q0 + 1 lines
     uint32_t pat_small;   // kind 4: pattern of the sets with q0 lines
-    uint32_t pad;
+    uint32_t slot;        // position of the job in candidate order
 };
 // Second-pass miss pattern of a cyclic chase over n distinct lines through
 // one a-way tree-PLRU set (ways filled in order, all node bits 0 at the
@@ -277,10 +277,13 @@ hipError_t launch_plru_patterns(const PlruPattern* pd, uint32_t n, uint32_t* bit
 hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
                              const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
                              int64_t* s1, hipStream_t stream);
-// m[dj[i].cand] += the score of decided job i, i < n (jobs grouped by cand).
+// vals[dj[i].slot] = the score of decided job i, i < n (jobs in table order,
+// so that lanes next to each other gather from the same run table); then
+// m[cand[q]] += vals[q] (slots in candidate order, a candidate's contiguous).
 hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
                           const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
-                          const uint32_t* pat_bits, uint64_t* m, hipStream_t stream);
+                          const uint32_t* pat_bits, int64_t* vals, const uint32_t* cand, uint64_t* m,
+                          hipStream_t stream);
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,
                             hipStream_t stream);
 // m[c] += accesses of pair (c, p) = (pair / n_probes, pair % n_probes), from

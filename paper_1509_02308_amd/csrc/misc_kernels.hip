@@ -507,19 +507,14 @@ hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const De
     return hipGetLastError();
 }
 
-// One lane per decided job; jobs of one candidate are contiguous, so a
-// segmented wave sum and one atomic per candidate run of the wave follow.
+// One lane per decided job (table order); the score goes to its slot.
 __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
                                const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
-                               const uint32_t* pat_bits, uint64_t* m) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
+                               const uint32_t* pat_bits, int64_t* vals) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t key = 0xFFFFFFFFu;
-    int64_t v = 0;
     if (i < n) {
         const DecidedJob j = dj[i];
-        key = j.cand;
-        v = (int64_t)zeros[j.probe];
+        int64_t v = (int64_t)zeros[j.probe];
         if (j.kind >= 1) v += s1[j.table];
         if (j.kind >= 2) {
             const RunTable t = tables[j.table];
@@ -549,6 +544,20 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
                 }
             }
         }
+        vals[j.slot] = v;
+    }
+}
+
+// One lane per slot (candidate order): a segmented wave sum over runs of one
+// candidate, one atomic per run.
+__global__ void decided_sum_kernel(const int64_t* vals, const uint32_t* cand, uint32_t n, uint64_t* m) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t key = 0xFFFFFFFFu;
+    int64_t v = 0;
+    if (q < n) {
+        key = cand[q];
+        v = vals[q];
     }
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -563,10 +572,14 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
 
 hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
                           const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
-                          const uint32_t* pat_bits, uint64_t* m, hipStream_t stream) {
+                          const uint32_t* pat_bits, int64_t* vals, const uint32_t* cand, uint64_t* m,
+                          hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(decided_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, dj, n, zeros, tables, prefix,
-                       s1, pats, pat_bits, m);
+                       s1, pats, pat_bits, vals);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(decided_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, vals, cand, n, m);
     return hipGetLastError();
 }
 

@@ -79,7 +79,9 @@ struct InferPlan {
     uint32_t n_probes = 0;
     // jobs decided without a replay (grouped by candidate), scored from the
     // observed misses and the run tables
-    DecidedJob* d_decided = nullptr;
+    DecidedJob* d_decided = nullptr;   // in table order
+    int64_t* d_dec_vals = nullptr;     // per job score, candidate order
+    uint32_t* d_dec_cand = nullptr;    // candidate of each slot
     RunTable* d_tables = nullptr;
     int64_t* d_s1 = nullptr;
     int64_t* d_prefix = nullptr;
