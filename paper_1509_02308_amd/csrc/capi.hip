@@ -1180,11 +1180,27 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     std::vector<DecidedJob> decided;
     std::vector<RunTable> tables;
     std::vector<uint64_t> table_ks;   // first access of each sweep of the multi-sweep tables
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> table_of;   // (probe, line shift) -> table
     uint64_t entries = 0;
     std::vector<PlruPattern> patterns;
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> pattern_of;   // (ways, lines) -> pattern
     uint64_t pat_bits = 0, pat_scratch = 0;
+    // own sweeps: probes indexed by stride, sorted by array size
+    std::map<uint64_t, std::vector<std::pair<uint64_t, uint32_t>>> by_stride;
+    if (probe_select == PCHASE_PROBES_OWN_SWEEP) {
+        for (uint32_t p = 0; p < obs->n_probes; ++p)
+            by_stride[obs->probes[p].s_bytes].push_back({obs->probes[p].n_bytes, p});
+        for (auto& kv : by_stride) std::sort(kv.second.begin(), kv.second.end());
+    }
+    // sweep geometry per (probe, line shift), computed once
+    struct Geo {
+        uint64_t U = 0, d = 1;
+        uint32_t ks_off = 0, nsw = 0;
+        int32_t table = -1;   // its run table, once one is built
+        bool done = false;
+    };
+    std::vector<Geo> geo;
+    std::vector<uint64_t> geo_ks;
+    std::vector<uint32_t> mine;
     for (uint32_t c = 0; c < n_cands; ++c) {
         if (allow && !(*allow)[c]) continue;
         const DevModel& md = dm[c];
@@ -1192,8 +1208,24 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
         // replaces as LRU does, and two-way tree-PLRU is LRU
         const bool lru_fifo = md.policy == PCHASE_LRU || md.policy == PCHASE_FIFO || md.ways == 1 ||
                               (md.ways == 2 && md.policy == PCHASE_PLRU);
-        for (uint32_t p = 0; p < obs->n_probes; ++p) {
-            if (probe_select == PCHASE_PROBES_OWN_SWEEP && !own_sweep(cands[c], obs->probes[p])) continue;
+        mine.clear();
+        if (probe_select == PCHASE_PROBES_OWN_SWEEP) {
+            const uint64_t C = cands[c].capacity_bytes, b = cands[c].line_bytes;
+            const uint64_t strides[3] = {b / 2, b, 2 * b};
+            for (int si = 0; si < 3; ++si) {
+                if (si == 0 && (b & 1)) continue;   // no half-line stride
+                auto it = by_stride.find(strides[si]);
+                if (it == by_stride.end()) continue;
+                const auto& v = it->second;
+                auto lo = std::lower_bound(v.begin(), v.end(), std::make_pair((C + 1) / 2, 0u));
+                for (; lo != v.end() && lo->first <= 2 * C; ++lo)
+                    if (own_sweep(cands[c], obs->probes[lo->second])) mine.push_back(lo->second);
+            }
+            std::sort(mine.begin(), mine.end());
+        } else {
+            for (uint32_t p = 0; p < obs->n_probes; ++p) mine.push_back(p);
+        }
+        for (uint32_t p : mine) {
             if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
             // no access evicts and nothing before the second pass is
             // compared: the only misses are first touches, all in the first
@@ -1211,12 +1243,28 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             // i mod T' < r, with U runs = q0 T' + r)
             // (several sweeps that visit every line of a range once: the
             // runs in line order, d = 1)
-            uint64_t d = 1;
-            std::vector<uint64_t> ks;
-            uint64_t U = 0;
+            uint64_t d = 1, U = 0;
+            uint32_t nsw = 0, ks_off = 0;
             if (closed && md.unit_shift == md.line_shift) {
-                U = sweep_runs(dp[p], md.line_shift, &d);
-                if (!U) U = multi_sweep_runs(dp[p], md.line_shift, &ks);
+                if (geo.empty()) geo.resize((size_t)obs->n_probes * 64);
+                Geo& gg = geo[(size_t)p * 64 + md.line_shift];
+                if (!gg.done) {
+                    gg.done = true;
+                    gg.U = sweep_runs(dp[p], md.line_shift, &gg.d);
+                    if (!gg.U) {
+                        std::vector<uint64_t> ks;
+                        gg.U = multi_sweep_runs(dp[p], md.line_shift, &ks);
+                        if (gg.U) {
+                            gg.ks_off = (uint32_t)geo_ks.size();
+                            gg.nsw = (uint32_t)ks.size();
+                            geo_ks.insert(geo_ks.end(), ks.begin(), ks.end());
+                        }
+                    }
+                }
+                U = gg.U;
+                d = gg.d;
+                nsw = gg.nsw;
+                ks_off = gg.ks_off;
             }
             if (U) {
                 const uint64_t Tp = md.sets / gcd64(d % md.sets, md.sets);
@@ -1227,7 +1275,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                 // sweep; or sweeps of stride nsw lines with nsw dividing T,
                 // so that a set's lines all lie in one sweep)
                 const bool plru_pat = md.policy == PCHASE_PLRU && dp[p].passes == 2 &&
-                                      (ks.empty() || md.sets % ks.size() == 0) && q0 + 1 <= kMaxPatternLines;
+                                      (nsw == 0 || md.sets % nsw == 0) && q0 + 1 <= kMaxPatternLines;
                 const int kind = none ? (cf[p] >= dp[p].L ? 0 : 1)
                                  : lru_fifo ? (q0 > md.ways ? 2 : 3) : plru_pat ? 4 : -1;
                 uint32_t tid = 0, pb = 0, ps = 0;
@@ -1248,16 +1296,14 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                 }
                 bool ok = kind >= 0;
                 if (kind >= 1) {
-                    auto key = std::make_pair(p, md.line_shift);
-                    auto it = table_of.find(key);
-                    if (it != table_of.end()) {
-                        tid = it->second;
+                    Geo& gg = geo[(size_t)p * 64 + md.line_shift];
+                    if (gg.table >= 0) {
+                        tid = (uint32_t)gg.table;
                     } else if (entries + U + 1 <= kMaxTableEntries) {
                         tid = (uint32_t)tables.size();
-                        tables.push_back(RunTable{p, md.line_shift, U, entries, (uint32_t)ks.size(), 0,
-                                                  (uint64_t)table_ks.size()});
-                        table_ks.insert(table_ks.end(), ks.begin(), ks.end());
-                        table_of.emplace(key, tid);
+                        tables.push_back(RunTable{p, md.line_shift, U, entries, nsw, 0, (uint64_t)table_ks.size()});
+                        table_ks.insert(table_ks.end(), geo_ks.begin() + ks_off, geo_ks.begin() + ks_off + nsw);
+                        gg.table = (int32_t)tid;
                         entries += U + 1;
                     } else {
                         ok = false;
