@@ -121,6 +121,13 @@ struct RegSet {
 
     __device__ __forceinline__ bool access(uint32_t line, uint32_t, const DevModel& m, uint32_t k,
                                            uint32_t trace_id) {
+        if constexpr (A == 1) {
+            // one way: every policy keeps the last line (an empty way holds
+            // kInvalidTag, above every line: addresses stay below 2^34 - 8)
+            const bool hit = tag[0] == line;
+            tag[0] = line;
+            return hit;
+        }
         const uint32_t a = m.ways;
         int hw = -1;
 #pragma unroll
