@@ -1487,23 +1487,28 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
     auto tail = [pp, zw](hipStream_t s) -> hipError_t {
-        hipError_t e = launch_decided(pp->d_decided, pp->n_decided, pp->d_zeros, pp->d_tables, pp->d_prefix,
-                                      pp->d_s1, pp->d_patterns, pp->d_pat_bits, pp->d_dec_vals, pp->d_dec_cand,
-                                      pp->d_m, s);
-        if (e != hipSuccess) return e;
-        e = launch_fill_u32(pp->d_zero, zw, 0, s);
+        hipError_t e = launch_fill_u32(pp->d_zero, zw, 0, s);
         if (e != hipSuccess) return e;
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
-    // the observed misses of each probe, the constant part of every score,
-    // and the run tables of the jobs decided without a replay
+    // the jobs decided without a replay, beside the replay: their run
+    // tables, then their scores into the cleared counters
+    auto side = [pp, bits](hipStream_t s) -> hipError_t {
+        hipError_t e = launch_run_tables(pp->d_tables, pp->n_tables, pp->sweep.d_probes, pp->d_table_ks, pp->d_pinfo,
+                                         bits, pp->d_prefix, pp->d_s1, s);
+        if (e != hipSuccess) return e;
+        return launch_decided(pp->d_decided, pp->n_decided, pp->d_zeros, pp->d_tables, pp->d_prefix, pp->d_s1,
+                              pp->d_patterns, pp->d_pat_bits, pp->d_dec_vals, pp->d_dec_cand, pp->d_m, s);
+    };
+    const bool has_side = ip->n_decided != 0;
+    // the observed misses of each probe, the constant part of every score
     PC_HIP(launch_obs_zeros(bits, ip->d_pinfo, ip->n_probes, ip->d_zeros, stream));
-    PC_HIP(launch_run_tables(ip->d_tables, ip->n_tables, ip->sweep.d_probes, ip->d_table_ks, ip->d_pinfo, bits,
-                             ip->d_prefix, ip->d_s1, stream));
     // the first run of a cached plan answers at once with the default branch
     // strategy; the next run times the strategies and keeps the fastest
     int rc = run_sweep_plan(ws, &ip->sweep, true, ip->d_m, n_cands, const_cast<uint32_t*>(bits), false,
-                            sched, stream, tail, ip->cached && tune, ip->runs == 0);
+                            sched, stream, tail, ip->cached && tune, ip->runs == 0,
+                            has_side ? std::function<hipError_t(hipStream_t)>(side)
+                                     : std::function<hipError_t(hipStream_t)>());
     if (rc) return rc;
     ArgminOut* hr = static_cast<ArgminOut*>(ws->host_res);
     PC_HIP(hipMemcpyAsync(hr, ip->d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));

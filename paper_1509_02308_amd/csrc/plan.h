@@ -60,10 +60,12 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models,
 // the first batched run that is not deferred times every branch strategy
 // and keeps the fastest for the plan's later runs; defer_tuning leaves the
 // tuning to a later run (a problem's first answer does not wait for it).
+// `side` (may be empty) is work that needs the cleared counters but not the
+// replay: it runs on a branch stream beside the replay (PLAIN: before it).
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
                    const std::function<hipError_t(hipStream_t)>& tail, bool autotune = false,
-                   bool defer_tuning = false);
+                   bool defer_tuning = false, const std::function<hipError_t(hipStream_t)>& side = {});
 
 // Cached schedule + score buffers of one inference problem.
 struct InferPlan {

@@ -270,7 +270,8 @@ constexpr int kStrategies = 5;
 
 static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters,
                            uint64_t n_counters, uint32_t* bits, bool clear_bits, hipStream_t s,
-                           const std::function<hipError_t(hipStream_t)>& tail, int strategy = 0) {
+                           const std::function<hipError_t(hipStream_t)>& tail,
+                           const std::function<hipError_t(hipStream_t)>& side, int strategy = 0) {
     const uint32_t nq = (uint32_t)plan->batched.size() + 2;
     PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, s));
     PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
@@ -278,7 +279,11 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
     const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
     const int nb = (int)std::min<size_t>(want, plan->batched.size());
-    PC_HIP(fork_branches(ws, s, nb));
+    // work independent of the buckets (after the fills) goes first onto a
+    // branch of its own when one is free, else onto the last one
+    const int ns = side ? std::min(kBranches, std::max(nb, 1) + 1) : nb;
+    PC_HIP(fork_branches(ws, s, ns));
+    if (side) PC_HIP(side(branch_stream(ws, s, ns - 1)));
     auto lds_class = [](const Bucket& bk) { return bk.cls == kAMap || bk.cls == kALds; };
     auto weight = [&](const Bucket& bk) { return (strategy == 1 && lds_class(bk)) ? 3.0 * bk.cost : bk.cost; };
     std::vector<size_t> idx(plan->batched.size());
@@ -328,20 +333,22 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
         if (need < blocks) blocks = need;
         PC_HIP(launch_sweep(score, bk.pol, bk.cls, a, blocks, bs));
     }
-    PC_HIP(join_branches(ws, s, nb));
+    PC_HIP(join_branches(ws, s, ns));
     if (tail) PC_HIP(tail(s));
     return PCHASE_OK;
 }
 
 int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counters, uint64_t n_counters,
                    uint32_t* bits, bool clear_bits, uint32_t mode, hipStream_t stream,
-                   const std::function<hipError_t(hipStream_t)>& tail, bool autotune, bool defer_tuning) {
+                   const std::function<hipError_t(hipStream_t)>& tail, bool autotune, bool defer_tuning,
+                   const std::function<hipError_t(hipStream_t)>& side) {
     if (mode == PCHASE_PLAIN) {
         const uint32_t nq = (uint32_t)plan->batched.size() + 2;
         PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, stream));
         PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, stream));
         if (clear_bits && bits)
             PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), stream));
+        if (side) PC_HIP(side(stream));
         for (const Bucket& bk : plan->plain) {
             if (bk.count == 0) continue;
             SweepArgs a;
@@ -382,7 +389,8 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
     // to the next one (a problem's first answer does not wait for it).
     const bool tunable = autotune && plan->batched.size() >= 2 && !plan->tuned;
     if (!tunable || defer_tuning)
-        return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, plan->strategy);
+        return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, side,
+                               plan->strategy);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -394,7 +402,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
         for (int r = 0; r < 2 && e == hipSuccess && rc == PCHASE_OK; ++r) {   // the first run warms up
             e = hipEventRecord(t0, stream);
             if (e == hipSuccess)
-                rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, st);
+                rc = enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, side, st);
             if (e == hipSuccess && rc == PCHASE_OK) e = hipEventRecord(t1, stream);
             if (e == hipSuccess && rc == PCHASE_OK) e = hipEventSynchronize(t1);
             if (e == hipSuccess && rc == PCHASE_OK) e = hipEventElapsedTime(&ms, t0, t1);
@@ -414,7 +422,8 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
         plan->strategy = best;
         plan->tuned = true;
     }
-    return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, plan->strategy);
+    return enqueue_batched(ws, plan, score, counters, n_counters, bits, clear_bits, stream, tail, side,
+                           plan->strategy);
 }
 
 }  // namespace pc
