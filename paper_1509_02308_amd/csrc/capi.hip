@@ -153,7 +153,7 @@ static uint64_t gcd64(uint64_t x, uint64_t y) {
     return x;
 }
 
-// Largest run table (entries of 8 bytes) an inference plan builds.
+// Largest run table (entries of 4 bytes) an inference plan builds.
 constexpr uint64_t kMaxTableEntries = 1ull << 26;
 // Largest set (lines) a tree-PLRU pattern is tabulated for.
 constexpr uint64_t kMaxPatternLines = 4096;
@@ -1299,7 +1299,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                     Geo& gg = geo[(size_t)p * 64 + md.line_shift];
                     if (gg.table >= 0) {
                         tid = (uint32_t)gg.table;
-                    } else if (entries + U + 1 <= kMaxTableEntries) {
+                    } else if (entries + U + 1 <= kMaxTableEntries &&
+                               U * (uint64_t)(dp[p].passes - 1) < (1ull << 31)) {
                         tid = (uint32_t)tables.size();
                         tables.push_back(RunTable{p, md.line_shift, U, entries, nsw, 0, (uint64_t)table_ks.size()});
                         table_ks.insert(table_ks.end(), geo_ks.begin() + ks_off, geo_ks.begin() + ks_off + nsw);
@@ -1361,7 +1362,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_pbits = up256(o_pat + patterns.size() * sizeof(PlruPattern));
     const size_t o_pscr = up256(o_pbits + pat_bits / 8);
     const size_t o_pre = up256(o_pscr + pat_scratch * sizeof(uint32_t));
-    const size_t bytes = o_pre + entries * sizeof(int64_t);
+    const size_t bytes = o_pre + entries * sizeof(int32_t);
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
     uint8_t* b = np->dev.as<uint8_t>();
@@ -1378,7 +1379,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->d_dec_cand = reinterpret_cast<uint32_t*>(b + o_dcand);
     np->d_tables = reinterpret_cast<RunTable*>(b + o_tab);
     np->d_s1 = reinterpret_cast<int64_t*>(b + o_s1);
-    np->d_prefix = reinterpret_cast<int64_t*>(b + o_pre);
+    np->d_prefix = reinterpret_cast<int32_t*>(b + o_pre);
     np->d_table_ks = reinterpret_cast<uint64_t*>(b + o_ks);
     np->d_patterns = reinterpret_cast<PlruPattern*>(b + o_pat);
     np->d_pat_bits = reinterpret_cast<uint32_t*>(b + o_pbits);

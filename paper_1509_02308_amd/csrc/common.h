@@ -227,8 +227,9 @@ hipError_t launch_clear_ranges(uint32_t* bits, const uint64_t* ranges, uint32_t 
 // i-th line, visited by the sweep starting at access ks[koff + i mod nsw],
 // as its (i / nsw)-th access).  Per call, the prefix over runs of the later
 // passes' signed weights w(k) = [k >= count_from] * (2 obs(k) - 1) at the
-// run's start k goes to prefix[off .. off + runs] and the first pass's total
-// to s1[table].
+// run's start k goes to prefix[off .. off + runs] (32-bit: tables are built
+// only when runs * (passes - 1) < 2^31) and the first pass's total to
+// s1[table].
 struct RunTable {
     uint32_t probe;
     uint32_t line_shift;
@@ -275,13 +276,13 @@ struct PlruPattern {
 hipError_t launch_plru_patterns(const PlruPattern* pd, uint32_t n, uint32_t* bits, uint32_t* scratch,
                                 hipStream_t stream);
 hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
-                             const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
+                             const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int32_t* prefix,
                              int64_t* s1, hipStream_t stream);
 // vals[dj[i].slot] = the score of decided job i, i < n (jobs in table order,
 // so that lanes next to each other gather from the same run table); then
 // m[cand[q]] += vals[q] (slots in candidate order, a candidate's contiguous).
 hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
-                          const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
+                          const int32_t* prefix, const int64_t* s1, const PlruPattern* pats,
                           const uint32_t* pat_bits, int64_t* vals, const uint32_t* cand, uint64_t* m,
                           hipStream_t stream);
 hipError_t launch_obs_zeros(const uint32_t* bits, const uint64_t* pinfo, uint32_t n, uint64_t* zeros,

@@ -449,7 +449,7 @@ __device__ __forceinline__ int64_t obs_weight(const uint32_t* ob, uint64_t k, ui
 
 // One wave per run table; lanes take 64 runs at a time and carry the prefix.
 __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
-                                 const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
+                                 const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int32_t* prefix,
                                  int64_t* s1) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -463,7 +463,7 @@ __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, cons
     const uint64_t l0 = x0 >> t.line_shift;
     // runs are single accesses unless the stride is below the line
     const bool per_line = t.nsw == 0 && t.runs > 1 && sb < (1ull << t.line_shift);
-    int64_t* out = prefix + t.off;
+    int32_t* out = prefix + t.off;
     int64_t carry = 0, first = 0;
     for (uint64_t i0 = 0; i0 < t.runs; i0 += kWave) {
         const uint64_t i = i0 + lane;
@@ -486,7 +486,7 @@ __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, cons
             const int64_t o = __shfl_up(w2, d, kWave);
             if ((int)lane >= d) w2 += o;
         }
-        if (i < t.runs) out[i + 1] = carry + w2;
+        if (i < t.runs) out[i + 1] = (int32_t)(carry + w2);
         carry += __shfl(w2, kWave - 1, kWave);
     }
 #pragma unroll
@@ -498,7 +498,7 @@ __global__ void run_table_kernel(const RunTable* tables, uint32_t n_tables, cons
 }
 
 hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const DevProbe* probes,
-                             const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int64_t* prefix,
+                             const uint64_t* ks, const uint64_t* pinfo, const uint32_t* bits, int32_t* prefix,
                              int64_t* s1, hipStream_t stream) {
     if (n_tables == 0) return hipSuccess;
     const uint32_t wpb = 256 / kWave;
@@ -509,7 +509,7 @@ hipError_t launch_run_tables(const RunTable* tables, uint32_t n_tables, const De
 
 // One lane per decided job (table order); the score goes to its slot.
 __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
-                               const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
+                               const int32_t* prefix, const int64_t* s1, const PlruPattern* pats,
                                const uint32_t* pat_bits, int64_t* vals) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -518,13 +518,13 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
         if (j.kind >= 1) v += s1[j.table];
         if (j.kind >= 2) {
             const RunTable t = tables[j.table];
-            const int64_t* P = prefix + t.off;
+            const int32_t* P = prefix + t.off;
             if (j.kind == 2) {
-                v += P[t.runs];
+                v += (int64_t)P[t.runs];
             } else if (j.kind == 3) {
                 for (uint64_t st = 0; st < t.runs; st += j.period) {
                     const uint64_t hi = st + j.rem < t.runs ? st + j.rem : t.runs;
-                    v += P[hi] - P[st];
+                    v += (int64_t)P[hi] - (int64_t)P[st];
                 }
             } else {
                 // position i (a set bit of the pattern): runs [i T', i T' +
@@ -538,7 +538,7 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
                             const uint64_t st = (uint64_t)(w * 32 + (uint32_t)__ffs(bits) - 1) * j.period;
                             const uint64_t mid = st + j.rem < t.runs ? st + j.rem : t.runs;
                             const uint64_t end = st + j.period < t.runs ? st + j.period : t.runs;
-                            v += part == 0 ? P[mid] - P[st] : P[end] - P[mid];
+                            v += part == 0 ? (int64_t)P[mid] - (int64_t)P[st] : (int64_t)P[end] - (int64_t)P[mid];
                         }
                     }
                 }
@@ -571,7 +571,7 @@ __global__ void decided_sum_kernel(const int64_t* vals, const uint32_t* cand, ui
 }
 
 hipError_t launch_decided(const DecidedJob* dj, uint32_t n, const uint64_t* zeros, const RunTable* tables,
-                          const int64_t* prefix, const int64_t* s1, const PlruPattern* pats,
+                          const int32_t* prefix, const int64_t* s1, const PlruPattern* pats,
                           const uint32_t* pat_bits, int64_t* vals, const uint32_t* cand, uint64_t* m,
                           hipStream_t stream) {
     if (n == 0) return hipSuccess;

@@ -86,7 +86,7 @@ struct InferPlan {
     uint32_t* d_dec_cand = nullptr;    // candidate of each slot
     RunTable* d_tables = nullptr;
     int64_t* d_s1 = nullptr;
-    int64_t* d_prefix = nullptr;
+    int32_t* d_prefix = nullptr;
     uint64_t* d_table_ks = nullptr;
     PlruPattern* d_patterns = nullptr;
     uint32_t* d_pat_bits = nullptr;
