@@ -188,3 +188,42 @@ def test_general_search_from_latencies_and_with_a_plan():
         assert res2.best == best and np.array_equal(zero2, zero)
     finally:
         plan.close()
+
+
+def test_general_many_pairs_with_long_traces_split_by_length():
+    """A call of at least 65,536 pairs (the schedule then splits a pair by
+    length only above 131,072 accesses) with a few traces above that length:
+    every policy of the generalised engine, all totals and the long pairs'
+    bitmaps (and a sample of the short ones) against the oracle."""
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(4096)
+    models = W.random_general(10, seed=77)
+    short = [rng.integers(0, int(rng.integers(16, 4000)), size=int(rng.integers(8, 64))).astype(np.int32)
+             for _ in range(6560)]
+    long_ = [rng.integers(0, 30000, size=140000 + 1000 * i).astype(np.int32) for i in range(3)]
+    long_.append(orc.trace(orc.make_probe(36864 + 64, 64, passes=250)))   # 144,250 accesses
+    traces = short + long_
+    assert len(models) * len(traces) >= 65536 and min(len(t) for t in long_) > 131072
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    idx = torch.from_numpy(np.concatenate(traces + [np.zeros(1, np.int32)])).cuda()
+    pm = np.repeat(np.arange(len(models), dtype=np.uint32), len(traces))
+    pt = np.tile(np.arange(len(traces), dtype=np.uint32), len(models))
+    cf = np.array([len(traces[t]) // 2 for t in pt], dtype=np.uint64)
+    words = np.array([(len(traces[t]) + 31) // 32 for t in pt], dtype=np.uint64)
+    bitoff = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    bits = torch.full((int(words.sum()) + 1,), 0x55, dtype=torch.int32, device="cuda")
+    misses = torch.full((2 * len(pm),), -1, dtype=torch.int64, device="cuda")
+    bases = [4 * int(rng.integers(0, 4096)) for _ in traces]
+    say(f"cache_replay_general: {len(models)} models x {len(traces)} traces = {len(pm)} pairs")
+    capi.cache_replay_general(capi.general_models(models), idx, off, bases, pm, pt, cf, misses, bits, bitoff, 0)
+    torch.cuda.synchronize()
+    mis = misses.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+    b = bits.cpu().numpy().view(np.uint32)
+    oms = [_orc_general(d) for d in models]
+    n_long = len(long_)
+    for i in range(len(pm)):
+        m, t = int(pm[i]), int(pt[i])
+        hits, mt, ms = orc.replay_general(oms[m], traces[t], base=bases[t], trace_id=t, count_from=int(cf[i]))
+        assert (mis[i, 0], mis[i, 1]) == (mt, ms), (models[m], t)
+        if t >= len(traces) - n_long or i % 97 == 0:
+            assert np.array_equal(unpack_bits(b[bitoff[i]:], len(traces[t])), hits), (models[m], t)
