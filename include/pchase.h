@@ -234,7 +234,12 @@ int pchase_plan_next_probe(const pchase_model *cands, uint32_t n_cands, const pc
  * anything that could write outputs, when that does not suffice).
  * The plan keeps the schedule of the last inference problem it served, so
  * repeating infer_cache_params on the same inputs rebuilds nothing; any
- * other call replaces what the plan held.  A plan belongs to the device
+ * other call replaces what the plan held.  An inference schedule holds the
+ * replay descriptors and, for the closed-form scoring (see
+ * PCHASE_SCHED_FULL_REPLAY), 52 bytes per job scored without a replay and
+ * 4 bytes per run of every run table (at most 2^26 entries): about 160 MB
+ * for 438 candidates on their own N sweeps (1.08 million jobs, 24.7
+ * million table entries).  A plan belongs to the device
  * that was current at creation (EINVAL on another device), and serves one
  * call at a time (calls are serialised on it).  A NULL plan selects the
  * library's own per-device workspace, which grows on demand. */
