@@ -1198,6 +1198,11 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
         int32_t table = -1;   // its run table, once one is built
         bool done = false;
     };
+    // indexed by (probe, the candidates' distinct line shifts)
+    std::vector<int32_t> ls_slot(64, -1);
+    uint32_t n_ls = 0;
+    for (uint32_t c = 0; c < n_cands; ++c)
+        if (ls_slot[dm[c].line_shift] < 0) ls_slot[dm[c].line_shift] = (int32_t)n_ls++;
     std::vector<Geo> geo;
     std::vector<uint64_t> geo_ks;
     std::vector<uint32_t> mine;
@@ -1246,8 +1251,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
             uint64_t d = 1, U = 0;
             uint32_t nsw = 0, ks_off = 0;
             if (closed && md.unit_shift == md.line_shift) {
-                if (geo.empty()) geo.resize((size_t)obs->n_probes * 64);
-                Geo& gg = geo[(size_t)p * 64 + md.line_shift];
+                if (geo.empty()) geo.resize((size_t)obs->n_probes * n_ls);
+                Geo& gg = geo[(size_t)p * n_ls + (uint32_t)ls_slot[md.line_shift]];
                 if (!gg.done) {
                     gg.done = true;
                     gg.U = sweep_runs(dp[p], md.line_shift, &gg.d);
@@ -1296,7 +1301,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                 }
                 bool ok = kind >= 0;
                 if (kind >= 1) {
-                    Geo& gg = geo[(size_t)p * 64 + md.line_shift];
+                    Geo& gg = geo[(size_t)p * n_ls + (uint32_t)ls_slot[md.line_shift]];
                     if (gg.table >= 0) {
                         tid = (uint32_t)gg.table;
                     } else if (entries + U + 1 <= kMaxTableEntries &&

@@ -527,20 +527,41 @@ __global__ void decided_kernel(const DecidedJob* dj, uint32_t n, const uint64_t*
                     v += (int64_t)P[hi] - (int64_t)P[st];
                 }
             } else {
-                // position i (a set bit of the pattern): runs [i T', i T' +
-                // rem) of the big sets, [i T' + rem, (i + 1) T') of the small
-                for (int part = 0; part < 2; ++part) {
-                    if (part == 0 && j.rem == 0) continue;
-                    const PlruPattern pt = pats[part == 0 ? j.pat_big : j.pat_small];
-                    const uint32_t* pw = pat_bits + (pt.off >> 5);
-                    for (uint32_t w = 0; w < (pt.lines + 31) / 32; ++w) {
-                        for (uint32_t bits = pw[w]; bits != 0; bits &= bits - 1) {
-                            const uint64_t st = (uint64_t)(w * 32 + (uint32_t)__ffs(bits) - 1) * j.period;
-                            const uint64_t mid = st + j.rem < t.runs ? st + j.rem : t.runs;
-                            const uint64_t end = st + j.period < t.runs ? st + j.period : t.runs;
-                            v += part == 0 ? (int64_t)P[mid] - (int64_t)P[st] : (int64_t)P[end] - (int64_t)P[mid];
-                        }
+                // position i covers runs [i T', i T' + rem) of the big sets
+                // (pattern pat_big) then [i T' + rem, (i + 1) T') of the
+                // small ones (pat_small): in run order the missing ranges
+                // are merged, and the prefix is read at their ends only
+                const PlruPattern pb = pats[j.pat_big], ps = pats[j.pat_small];
+                const uint32_t* wb = pat_bits + (pb.off >> 5);
+                const uint32_t* wsm = pat_bits + (ps.off >> 5);
+                const uint32_t nb = j.rem ? pb.lines : 0u, nsm = ps.lines;
+                const uint32_t npos = nb > nsm ? nb : nsm;
+                bool open = false;
+                uint64_t from = 0;
+                uint32_t bw = 0, sw = 0;
+                for (uint32_t i = 0; i < npos; ++i) {
+                    if ((i & 31) == 0) {
+                        bw = i < nb ? wb[i >> 5] : 0u;
+                        sw = i < nsm ? wsm[i >> 5] : 0u;
                     }
+                    const uint64_t st = (uint64_t)i * j.period;
+                    const uint64_t mid = st + j.rem < t.runs ? st + j.rem : t.runs;
+                    const bool mb = i < nb && ((bw >> (i & 31)) & 1u);
+                    const bool ms = i < nsm && ((sw >> (i & 31)) & 1u);
+                    if (mb != open) {   // a range opens or closes at st
+                        if (mb) from = st;
+                        else v += (int64_t)P[st] - (int64_t)P[from];
+                        open = mb;
+                    }
+                    if (ms != open) {   // ... or at mid
+                        if (ms) from = mid;
+                        else v += (int64_t)P[mid] - (int64_t)P[from];
+                        open = ms;
+                    }
+                }
+                if (open) {
+                    const uint64_t end = (uint64_t)npos * j.period < t.runs ? (uint64_t)npos * j.period : t.runs;
+                    v += (int64_t)P[end] - (int64_t)P[from];
                 }
             }
         }
