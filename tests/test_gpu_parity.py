@@ -361,6 +361,56 @@ def test_inference_scores_any_observation_and_count_from():
         assert closed[0] == closed[1] > 0 and closed[2] == closed[3] == 0
 
 
+def test_inference_random_geometries_every_scoring_path():
+    """Seeded random candidates (sets 1..12 incl. non-powers of two, lines 4..64 B,
+    ways 1..16, LRU/FIFO/PLRU/RANDOM, some with set_shift) and random probes
+    (arrays around the capacities, strides below, at and several lines above
+    the line, 1..3 passes, j0 and base offsets), a random observation and
+    count_from from 0 to past the first pass: every (m, n) against the
+    oracle, with the closed forms on and off, batched and plain."""
+    torch, capi = need_gpu()
+    rng = np.random.default_rng(31337)
+    crows = []
+    while len(crows) < 48:
+        b = int(rng.choice([4, 8, 16, 32, 64]))
+        pol = int(rng.choice([W.LRU, W.FIFO, W.PLRU, W.RANDOM]))
+        a = int(rng.choice([1, 2, 4, 8, 16])) if pol == W.PLRU else int(rng.integers(1, 17))
+        T = int(rng.integers(1, 13))
+        ss = int(np.log2(b)) + int(rng.integers(1, 3)) if rng.random() < 0.2 else 0
+        crows.append((a * b * T, b, a, pol, ss, int(rng.integers(1, 1 << 30))))
+    prows = []
+    for _ in range(40):
+        C, b = crows[int(rng.integers(len(crows)))][:2]
+        N = 4 * int(rng.integers(max(1, C // 8), 3 * C // 4 + 2))
+        s = int(rng.choice([4 * int(rng.integers(1, max(2, b // 4))), b, 2 * b, 3 * b, 4 * int(rng.integers(1, 64))]))
+        passes = int(rng.integers(1, 4))
+        j0 = int(rng.integers(0, N // 4)) if rng.random() < 0.3 else 0
+        base = 4 * int(rng.integers(0, 512)) if rng.random() < 0.3 else 0
+        prows.append((N, s, passes, j0, base))
+    lens = [orc.trace_len(orc_probe(r)) for r in prows]
+    L = [orc.cycle_len(orc_probe(r)) for r in prows]
+    hits_all = [(rng.random(n) < 0.7).astype(np.uint8) for n in lens]
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    cfs = np.array([int(rng.choice([0, L[i] // 3, L[i], min(L[i] + 5, lens[i]), lens[i]])) for i in range(len(prows))],
+                   np.uint64)
+    best, m, n = orc.infer([orc_model(r) for r in crows], [orc_probe(r) for r in prows], np.concatenate(hits_all),
+                           off, cfs, probe_select=0)
+    packed, bitoff = _bits_layout(hits_all)
+    bits = torch.from_numpy(packed.view(np.int32)).cuda()
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+    closed = []
+    for sched in (0, capi.SCHED_PLAIN, capi.SCHED_FULL_REPLAY, capi.SCHED_FULL_REPLAY | capi.SCHED_PLAIN):
+        say(f"infer_cache_params random geometries, mode {sched:#x}")
+        res, _ = capi.infer_cache_params(capi.probes(prows), capi.models(crows), bits=bits, bitoff=bitoff,
+                                         count_from=cfs, probe_select=0, mn=mn, mode=sched)
+        got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        bad = np.nonzero((got[:, 0] != m) | (got[:, 1] != n))[0]
+        assert len(bad) == 0, [(sched, crows[int(c)], tuple(got[c]), (int(m[c]), int(n[c]))) for c in bad[:5]]
+        assert res.best == best and res.best_m == m[best]
+        closed.append(res.closed_form_accesses)
+    assert closed[0] == closed[1] > 0 and closed[2] == closed[3] == 0
+
+
 @pytest.mark.timeout(600)
 def test_inference_full_candidate_grid():
     """The full search: 438 candidates (C 8..64 KB, b 32..128 B, a 1..64,
