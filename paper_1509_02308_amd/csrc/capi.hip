@@ -1170,10 +1170,18 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                             uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
                             const std::vector<uint64_t>& len, const std::vector<uint64_t>& cf,
                             const std::vector<uint64_t>& bitoff, int probe_select,
-                            const std::vector<uint8_t>* allow, bool closed, std::unique_ptr<InferPlan>* out) {
+                            const std::vector<uint8_t>* allow, bool closed, std::unique_ptr<InferPlan>* out,
+                            InferPlan* reuse = nullptr) {
     std::unique_ptr<InferPlan> np(new InferPlan());
     np->dev.arena = ws->arena;
     np->sweep.dev.arena = ws->arena;
+    if (reuse && !ws->arena) {
+        // take over the device buffers of a plan that is no longer needed
+        std::swap(np->dev.p, reuse->dev.p);
+        std::swap(np->dev.cap, reuse->dev.cap);
+        std::swap(np->sweep.dev.p, reuse->sweep.dev.p);
+        std::swap(np->sweep.dev.cap, reuse->sweep.dev.cap);
+    }
     np->n_cands = n_cands;
     np->n_host.assign(n_cands, 0);
     std::vector<SweepJob> jobs;
@@ -1460,12 +1468,14 @@ static int infer_exhaustive(Workspace* ws, const pchase_observation* obs, const 
                             uint32_t* zero_host, hipStream_t stream, uint64_t* replayed, uint32_t sched,
                             bool closed, bool cache = true, bool tune = true) {
     InferPlan* ip;
-    std::unique_ptr<InferPlan> once;
     if (!cache) {
+        std::unique_ptr<InferPlan> once, prev = std::move(ws->oneoff);
         int rc = build_infer_plan(ws, obs, cands, n_cands, dm, dp, len, cf, bitoff, probe_select, allow, closed,
-                                  &once);
+                                  &once, prev.get());
         if (rc) return rc;
-        ip = once.get();
+        prev.reset();
+        ws->oneoff = std::move(once);
+        ip = ws->oneoff.get();
     } else {
         std::string blob = infer_key(obs, cands, n_cands, probe_select, bitoff.data(), allow, closed);
         const std::string key = digest_of(blob);

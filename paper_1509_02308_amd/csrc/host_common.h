@@ -68,6 +68,10 @@ struct Workspace {
     hipStream_t branch[kBranches - 1] = {};
     hipEvent_t fork = nullptr, join[kBranches - 1] = {};
     std::map<std::string, std::unique_ptr<InferPlan>> plans;
+    // the last one-off inference plan (the learned proposer's confirmation):
+    // its device buffers serve the next one, which grows them only when
+    // needed (not with an arena)
+    std::unique_ptr<InferPlan> oneoff;
     // probe planner: class matrix of the last (candidates, pool) pair
     DevBuf planner;
     std::string planner_key;

@@ -143,6 +143,7 @@ void DevBuf::release() {
 void Workspace::reset_arena() {
     if (!arena) return;
     plans.clear();
+    oneoff.reset();
     planner_key.clear();
     for (DevBuf* b : {&stage, &aux, &obs, &slab, &mlp, &planner, &gsearch}) b->release();
     slab_clean = 0;
