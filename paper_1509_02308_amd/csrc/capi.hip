@@ -1346,42 +1346,58 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     if (rc) return rc;
     const size_t zw = (n_cands + 31) / 32;
     const uint32_t n_probes = (uint32_t)obs->n_probes;
-    const size_t o_out = (2 * n_cands * sizeof(uint64_t) + zw * 4 + 255) / 256 * 256;
-    const size_t o_pinfo = (o_out + sizeof(ArgminOut) + 255) / 256 * 256;
-    const size_t o_zeros = o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t);
     auto up256 = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t o_dec = up256(o_zeros + (size_t)n_probes * sizeof(uint64_t));
-    // jobs in table order for the gathers, slots in candidate order for the sums
-    std::vector<uint32_t> dec_cand(decided.size());
-    for (size_t q = 0; q < decided.size(); ++q) {
-        decided[q].slot = (uint32_t)q;
-        dec_cand[q] = decided[q].cand;
-    }
-    {
-        // counting sort by table, stable
-        std::vector<uint32_t> cnt(tables.size() + 2, 0);
-        for (const DecidedJob& x : decided) ++cnt[x.table + 1];
-        for (size_t t = 1; t < cnt.size(); ++t) cnt[t] += cnt[t - 1];
-        std::vector<DecidedJob> by_table(decided.size());
-        for (const DecidedJob& x : decided) by_table[cnt[x.table]++] = x;
-        decided.swap(by_table);
-    }
-    const size_t o_dval = up256(o_dec + decided.size() * sizeof(DecidedJob));
-    const size_t o_dcand = up256(o_dval + decided.size() * sizeof(int64_t));
+    // what the host writes first, as one image uploaded in one copy; then
+    // what the kernels write
+    const size_t o_n = 0;
+    const size_t o_pinfo = up256(o_n + n_cands * sizeof(uint64_t));
+    const size_t o_dec = up256(o_pinfo + 3 * (size_t)n_probes * sizeof(uint64_t));
+    const size_t o_dcand = up256(o_dec + decided.size() * sizeof(DecidedJob));
     const size_t o_tab = up256(o_dcand + decided.size() * sizeof(uint32_t));
-    const size_t o_s1 = up256(o_tab + tables.size() * sizeof(RunTable));
-    const size_t o_ks = up256(o_s1 + tables.size() * sizeof(int64_t));
+    const size_t o_ks = up256(o_tab + tables.size() * sizeof(RunTable));
     const size_t o_pat = up256(o_ks + table_ks.size() * sizeof(uint64_t));
-    const size_t o_pbits = up256(o_pat + patterns.size() * sizeof(PlruPattern));
+    const size_t o_img = o_pat + patterns.size() * sizeof(PlruPattern);
+    const size_t o_m = up256(o_img);
+    const size_t o_zero = o_m + n_cands * sizeof(uint64_t);
+    const size_t o_out = up256(o_zero + zw * 4);
+    const size_t o_zeros = up256(o_out + sizeof(ArgminOut));
+    const size_t o_dval = up256(o_zeros + (size_t)n_probes * sizeof(uint64_t));
+    const size_t o_s1 = up256(o_dval + decided.size() * sizeof(int64_t));
+    const size_t o_pbits = up256(o_s1 + tables.size() * sizeof(int64_t));
     const size_t o_pscr = up256(o_pbits + pat_bits / 8);
     const size_t o_pre = up256(o_pscr + pat_scratch * sizeof(uint32_t));
     const size_t bytes = o_pre + entries * sizeof(int32_t);
+    std::vector<uint8_t> img(o_img);
+    auto put = [&](size_t at, const void* src, size_t n) {
+        if (n) std::memcpy(img.data() + at, src, n);
+    };
+    put(o_n, np->n_host.data(), n_cands * sizeof(uint64_t));
+    for (uint32_t p = 0; p < n_probes; ++p) {
+        const uint64_t row[3] = {bitoff[p], std::min(cf[p], len[p]), len[p]};
+        put(o_pinfo + 3 * (size_t)p * sizeof(uint64_t), row, sizeof row);
+    }
+    // jobs in table order for the gathers (a stable counting sort), slots in
+    // candidate order for the sums
+    {
+        std::vector<uint32_t> cnt(tables.size() + 2, 0);
+        for (const DecidedJob& x : decided) ++cnt[x.table + 1];
+        for (size_t t = 1; t < cnt.size(); ++t) cnt[t] += cnt[t - 1];
+        for (size_t q = 0; q < decided.size(); ++q) {
+            DecidedJob x = decided[q];
+            x.slot = (uint32_t)q;
+            put(o_dcand + q * sizeof(uint32_t), &x.cand, sizeof(uint32_t));
+            put(o_dec + (size_t)cnt[x.table]++ * sizeof(DecidedJob), &x, sizeof x);
+        }
+    }
+    put(o_tab, tables.data(), tables.size() * sizeof(RunTable));
+    put(o_ks, table_ks.data(), table_ks.size() * sizeof(uint64_t));
+    put(o_pat, patterns.data(), patterns.size() * sizeof(PlruPattern));
     hipError_t e = np->dev.ensure(bytes);
     if (e != hipSuccess) return buf_fail(ws, e, "the inference scores");
     uint8_t* b = np->dev.as<uint8_t>();
-    np->d_m = reinterpret_cast<uint64_t*>(b);
-    np->d_n = np->d_m + n_cands;
-    np->d_zero = reinterpret_cast<uint32_t*>(np->d_n + n_cands);
+    np->d_m = reinterpret_cast<uint64_t*>(b + o_m);
+    np->d_n = reinterpret_cast<uint64_t*>(b + o_n);
+    np->d_zero = reinterpret_cast<uint32_t*>(b + o_zero);
     np->d_out = reinterpret_cast<ArgminOut*>(b + o_out);
     np->d_pinfo = reinterpret_cast<uint64_t*>(b + o_pinfo);
     np->d_zeros = reinterpret_cast<uint64_t*>(b + o_zeros);
@@ -1398,26 +1414,9 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->d_pat_bits = reinterpret_cast<uint32_t*>(b + o_pbits);
     np->n_tables = (uint32_t)tables.size();
     np->n_decided = (uint32_t)decided.size();
-    std::vector<uint64_t> pinfo(3 * (size_t)n_probes);
-    for (uint32_t p = 0; p < n_probes; ++p) {
-        pinfo[3 * (size_t)p] = bitoff[p];
-        pinfo[3 * (size_t)p + 1] = std::min(cf[p], len[p]);
-        pinfo[3 * (size_t)p + 2] = len[p];
-    }
-    PC_HIP(hipMemcpy(np->d_n, np->n_host.data(), n_cands * sizeof(uint64_t), hipMemcpyHostToDevice));
-    if (n_probes) PC_HIP(hipMemcpy(np->d_pinfo, pinfo.data(), pinfo.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    if (!decided.empty()) {
-        PC_HIP(hipMemcpy(np->d_decided, decided.data(), decided.size() * sizeof(DecidedJob), hipMemcpyHostToDevice));
-        PC_HIP(hipMemcpy(np->d_dec_cand, dec_cand.data(), dec_cand.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    }
-    if (!tables.empty())
-        PC_HIP(hipMemcpy(np->d_tables, tables.data(), tables.size() * sizeof(RunTable), hipMemcpyHostToDevice));
-    if (!table_ks.empty())
-        PC_HIP(hipMemcpy(np->d_table_ks, table_ks.data(), table_ks.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (o_img) PC_HIP(hipMemcpy(b, img.data(), o_img, hipMemcpyHostToDevice));
     if (!patterns.empty()) {
         // the patterns depend on the plan only: computed once, here
-        PC_HIP(hipMemcpy(np->d_patterns, patterns.data(), patterns.size() * sizeof(PlruPattern),
-                         hipMemcpyHostToDevice));
         PC_HIP(launch_plru_patterns(np->d_patterns, (uint32_t)patterns.size(), np->d_pat_bits,
                                     reinterpret_cast<uint32_t*>(b + o_pscr), nullptr));
         PC_HIP(hipStreamSynchronize(nullptr));

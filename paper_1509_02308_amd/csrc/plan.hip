@@ -245,15 +245,19 @@ int build_sweep_plan(SweepPlan* plan, const std::vector<DevModel>& models, const
     plan->d_plain = reinterpret_cast<SweepTask*>(base + o_plain);
     plan->d_queues = reinterpret_cast<uint32_t*>(base + o_queues);
     plan->d_clear = reinterpret_cast<uint64_t*>(base + o_clear);
-    auto up = [](void* dst, const void* src, size_t n) -> hipError_t {
-        return n ? hipMemcpy(dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
+    // one upload of the whole block from a host image of it (the queues are
+    // cleared by every run)
+    std::vector<uint8_t> img(off, 0);
+    auto put = [&](size_t at, const void* src, size_t n) {
+        if (n) std::memcpy(img.data() + at, src, n);
     };
-    PC_HIP(up(plan->d_models, models.data(), models.size() * sizeof(DevModel)));
-    PC_HIP(up(plan->d_probes, probes.data(), probes.size() * sizeof(DevProbe)));
-    PC_HIP(up(plan->d_jobs, jobs.data(), jobs.size() * sizeof(SweepJob)));
-    PC_HIP(up(plan->d_lpt, lpt.data(), lpt.size() * sizeof(SweepTask)));
-    PC_HIP(up(plan->d_plain, tasks.data(), tasks.size() * sizeof(SweepTask)));
-    PC_HIP(up(plan->d_clear, plan->clear.data(), plan->clear.size() * sizeof(uint64_t)));
+    put(o_models, models.data(), models.size() * sizeof(DevModel));
+    put(o_probes, probes.data(), probes.size() * sizeof(DevProbe));
+    put(o_jobs, jobs.data(), jobs.size() * sizeof(SweepJob));
+    put(o_lpt, lpt.data(), lpt.size() * sizeof(SweepTask));
+    put(o_plain, tasks.data(), tasks.size() * sizeof(SweepTask));
+    put(o_clear, plan->clear.data(), plan->clear.size() * sizeof(uint64_t));
+    PC_HIP(hipMemcpy(base, img.data(), off, hipMemcpyHostToDevice));
     return PCHASE_OK;
 }
 
