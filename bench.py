@@ -166,8 +166,8 @@ def closed_form(C: int, b: int, a: int, pol: int, N: int, s: int, L: int, passes
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -242,21 +242,23 @@ def main():
     cold_ms = (time.perf_counter() - t_cold0) * 1e3
     assert res.replayed_accesses == accesses, (res.replayed_accesses, accesses)
     assert res.closed_form_accesses == closed, (res.closed_form_accesses, closed)
-    warm_done = 1
     tune_ms = None
     if not args.no_autotune:
         # the second call on the same inputs times the branch strategies
         t_tune0 = time.perf_counter()
         res = step()
         tune_ms = (time.perf_counter() - t_tune0) * 1e3
-        warm_done = 2
         log(f"inference sweep: tuning step {tune_ms:.1f} ms")
     log(f"inference sweep: cold step {cold_ms:.1f} ms; {args.warmup} warm-up, {args.steps} timed steps")
-    for _ in range(max(0, args.warmup - warm_done)):
+    # W warm-up steps after the plan build and the tuning call
+    for _ in range(args.warmup):
         res = step()
 
     # timed region: K steps, HIP events on the launch stream around each step
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:   # the events exist before the timed region (created at their first record)
+        a.record(stream)
+        b.record(stream)
     lat_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -165,6 +165,20 @@ static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     return 2 * s == b || s == b || s == 2 * b;
 }
 
+// Pinned staging of a run's results (ws->host_res, 4 KB): the argmin at 0,
+// a plan's status word at kHostStatus, the zero-class bitmap from 256.
+constexpr size_t kHostStatus = 128;
+static_assert(sizeof(ArgminOut) <= kHostStatus, "the argmin result overlaps the status word");
+
+// Ends a plan's run: its status word (bit 0: aborted) comes back with the
+// stream's last copy, then the stream is synchronised (one round trip).
+static int finish_run(Workspace* ws, const SweepPlan& plan, hipStream_t stream) {
+    uint32_t* hs = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws->host_res) + kHostStatus);
+    PC_HIP(hipMemcpyAsync(hs, plan.d_queues + plan.batched.size(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    PC_HIP(hipStreamSynchronize(stream));
+    if (*hs & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
+    return PCHASE_OK;
+}
 
 // Replays `jobs` (grouped by model) with hit bits into `bits` (cleared
 // first) and synchronises; the counters go to workspace scratch.
@@ -184,11 +198,7 @@ int replay_jobs(Workspace* ws, const std::vector<DevModel>& dm, const std::vecto
     rc = run_sweep_plan(ws, &plan, false, ws->aux.as<uint64_t>(), 2 * jobs.size(), bits, true, PCHASE_BATCHED,
                         stream, {});
     if (rc) return rc;
-    PC_HIP(hipStreamSynchronize(stream));
-    uint32_t status = 0;
-    PC_HIP(hipMemcpy(&status, plan.d_queues + plan.batched.size(), sizeof status, hipMemcpyDeviceToHost));
-    if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
-    return PCHASE_OK;
+    return finish_run(ws, plan, stream);
 }
 
 }  // namespace pc
@@ -407,11 +417,7 @@ extern "C" int cache_replay_probes(const pchase_model* models, uint32_t n_models
     rc = run_sweep_plan(ws, &plan, false, misses_dev, 2 * n_pairs, hitbits_dev, hitbits_dev != nullptr, mode,
                         stream, {});
     if (rc) return rc;
-    PC_HIP(hipStreamSynchronize(stream));
-    uint32_t status = 0;
-    PC_HIP(hipMemcpy(&status, plan.d_queues + plan.batched.size(), sizeof status, hipMemcpyDeviceToHost));
-    if (status & 1u) return set_error(PCHASE_EABORTED, "replay aborted by pchase_abort");
-    return PCHASE_OK;
+    return finish_run(ws, plan, stream);
 }
 
 // -------------------------------------------------- trace-array replay ---
@@ -1447,6 +1453,26 @@ static std::string infer_key(const pchase_observation* obs, const pchase_model* 
     return k;
 }
 
+// Whether `k` (an infer_key) holds exactly these inputs, compared in place
+// (no key is built: the repeated call's lookup reads the inputs once).
+static bool infer_key_equals(const std::string& k, const pchase_observation* obs, const pchase_model* cands,
+                             uint32_t n_cands, int probe_select, const uint64_t* bitoff, bool closed) {
+    size_t at = 0;
+    auto eq = [&](const void* p, size_t n) {
+        if (at + n > k.size() || std::memcmp(k.data() + at, p, n) != 0) return false;
+        at += n;
+        return true;
+    };
+    const char tag = closed ? 'c' : 'r';
+    const uint8_t has_cf = obs->count_from != nullptr, has_allow = 0;
+    const size_t np = obs->n_probes;
+    return eq(&tag, 1) && eq(&n_cands, sizeof n_cands) && eq(&obs->n_probes, sizeof obs->n_probes) &&
+           eq(&probe_select, sizeof probe_select) && eq(&has_cf, 1) && eq(&has_allow, 1) &&
+           eq(cands, n_cands * sizeof(pchase_model)) && eq(obs->probes, np * sizeof(pchase_probe)) &&
+           (!has_cf || eq(obs->count_from, np * sizeof(uint64_t))) && eq(bitoff, np * sizeof(uint64_t)) &&
+           at == k.size();
+}
+
 static std::string digest_of(const std::string& blob) {
     Digest dg;
     dg.add(blob.data(), blob.size());
@@ -1533,10 +1559,11 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
         PC_HIP(hipMemcpy2DAsync(mn_dev, 16, ip->d_m, 8, 8, n_cands, hipMemcpyDeviceToDevice, stream));
         PC_HIP(hipMemcpy2DAsync(mn_dev + 1, 16, ip->d_n, 8, 8, n_cands, hipMemcpyDeviceToDevice, stream));
     }
+    uint32_t* hs = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws->host_res) + kHostStatus);
+    PC_HIP(hipMemcpyAsync(hs, ip->sweep.d_queues + ip->sweep.batched.size(), sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          stream));
     PC_HIP(hipStreamSynchronize(stream));
-    uint32_t status = 0;
-    PC_HIP(hipMemcpy(&status, ip->sweep.d_queues + ip->sweep.batched.size(), sizeof status, hipMemcpyDeviceToHost));
-    if (status & 1u) return set_error(PCHASE_EABORTED, "inference aborted by pchase_abort");
+    if (*hs & 1u) return set_error(PCHASE_EABORTED, "inference aborted by pchase_abort");
     out->best = hr->best;
     out->best_m = hr->m;
     out->best_n = hr->n;
@@ -1659,13 +1686,12 @@ extern "C" int infer_cache_params(const pchase_observation* obs, const pchase_mo
         std::unique_lock<std::mutex> lk;
         int rc = workspace_for(plan, &ws, &lk);
         if (rc) return rc;
-        const std::string blob = infer_key(obs, cands, n_cands, probe_select, obs->bitoff, nullptr, closed);
-        auto it = ws->plans.find(digest_of(blob));
-        if (it != ws->plans.end() && it->second->key == blob) {
+        for (auto& kv : ws->plans) {
+            if (!infer_key_equals(kv.second->key, obs, cands, n_cands, probe_select, obs->bitoff, closed)) continue;
             out->threshold_used = 0xFFFFFFFFu;
             out->fallback = 0;
             uint64_t replayed = 0;
-            rc = run_infer_plan(ws, it->second.get(), obs->bits_dev, out, mn_dev, zero_host, stream, &replayed, sched,
+            rc = run_infer_plan(ws, kv.second.get(), obs->bits_dev, out, mn_dev, zero_host, stream, &replayed, sched,
                                 tune);
             out->replayed_accesses = replayed;
             return rc;
