@@ -325,6 +325,56 @@ def test_inference_all_probes_mode():
     assert res.best == best
 
 
+def test_inference_repeat_calls_see_changed_inputs():
+    """A repeat call runs the cached plan only when every input that shaped
+    it is unchanged: a candidate edited in place (same array), a different
+    bitmap layout and a different count_from must each give the oracle's
+    scores for the new inputs (Sec. 4.2's search on the small grid)."""
+    torch, capi = need_gpu()
+    cands = W.candidate_grid(Cs=(4096, 6144, 8192), bs=(32, 64), As=(1, 2, 4, 8), policies=(0, 1, 2))
+    crows = [tuple(int(x) for x in c) for c in cands]
+    probes = W.sweep_union(cands)
+    prows = [(int(p["N"]), int(p["s"]), int(p["passes"])) for p in probes]
+    k = next(i for i, r in enumerate(crows) if r[:4] == (8192, 32, 4, W.LRU))
+    hits_all, off, cfs = _obs_from_oracle(crows[k], prows)
+    obs = np.concatenate(hits_all)
+    oprobes = [orc_probe(r) for r in prows]
+    carr, parr = capi.models(crows), capi.probes(prows)
+    packed, bitoff = _bits_layout(hits_all)
+    bits = torch.from_numpy(packed.view(np.int32)).cuda()
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+
+    def check(rows, cf, bits_t, bo, count_from=None, what=""):
+        best, m, n = orc.infer([orc_model(r) for r in rows], oprobes, obs, off, cf, probe_select=1)
+        say(f"infer_cache_params repeat call: {what}")
+        res, _ = capi.infer_cache_params(parr, carr, bits=bits_t, bitoff=bo, count_from=count_from,
+                                         probe_select=1, mn=mn)
+        got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        assert np.array_equal(got[:, 0], m) and np.array_equal(got[:, 1], n), what
+        assert res.best == best and res.best_m == m[best], what
+        return m, n
+
+    m0, _ = check(crows, cfs, bits, bitoff, what="first call")
+    check(crows, cfs, bits, bitoff, what="same inputs")
+    # candidate k edited in place: 2 ways, twice the sets
+    rows2 = list(crows)
+    rows2[k] = (8192, 32, 2, W.LRU)
+    carr[k].ways, carr[k].sets = 2, 8192 // (2 * 32)
+    m1, n1 = check(rows2, cfs, bits, bitoff, what="candidate edited in place")
+    assert m1[k] != m0[k]
+    # the same bits at other word offsets: one empty word after probe 0
+    words = [(len(h) + 31) // 32 for h in hits_all]
+    bitoff2 = bitoff + np.array([0] + [1] * (len(words) - 1), np.uint64)
+    packed2 = np.concatenate([packed[:words[0]], np.zeros(1, np.uint32), packed[words[0]:]])
+    bits2 = torch.from_numpy(packed2.view(np.int32)).cuda()
+    m2, n2 = check(rows2, cfs, bits2, bitoff2, what="bitmap moved")
+    assert np.array_equal(m2, m1) and np.array_equal(n2, n1)
+    # every access compared
+    cf0 = np.zeros_like(cfs)
+    _, n3 = check(rows2, cf0, bits2, bitoff2, count_from=cf0, what="count_from 0")
+    assert n3[k] > n1[k]
+
+
 def test_inference_scores_any_observation_and_count_from():
     """Every scoring path against the oracle on an arbitrary (random)
     observation: every way class and policy, set_shift mappings, probes of
