@@ -1,8 +1,12 @@
 // capi.hip -- C-ABI entry points: trace generation, replay of probes and of
 // materialised traces, exhaustive and learned inference.
+#include <sys/mman.h>
+
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <new>
 
 #include "plan.h"
 #include "tile.h"
@@ -540,6 +544,45 @@ extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t
                                pair_trace, count_from, n_pairs, misses_dev, hitbits_dev, bitoff, mode, plan, stream);
 }
 
+// Host memory for the large arrays of a plan or schedule build (work
+// items, decided jobs, descriptor images): from 4 MB on, 2 MB-aligned and
+// advised as transparent huge pages, so that first touch costs a few dozen
+// page faults instead of thousands; not initialised.
+static void* huge_alloc(size_t bytes) {
+    if (bytes < (4u << 20)) return std::malloc(bytes ? bytes : 1);
+    const size_t al = 2u << 20, sz = (bytes + al - 1) / al * al;
+    void* p = std::aligned_alloc(al, sz);
+    if (p) (void)madvise(p, sz, MADV_HUGEPAGE);
+    return p;
+}
+template <class T>
+struct HugeAlloc {
+    using value_type = T;
+    HugeAlloc() = default;
+    template <class U>
+    HugeAlloc(const HugeAlloc<U>&) {}
+    T* allocate(size_t n) {
+        void* p = huge_alloc(n * sizeof(T));
+        if (!p) throw std::bad_alloc();
+        return static_cast<T*>(p);
+    }
+    void deallocate(T* p, size_t) { std::free(p); }
+    template <class U>
+    bool operator==(const HugeAlloc<U>&) const { return true; }
+    template <class U>
+    bool operator!=(const HugeAlloc<U>&) const { return false; }
+};
+struct HostImage {
+    uint8_t* p = nullptr;
+    explicit HostImage(size_t n) : p(static_cast<uint8_t*>(huge_alloc(n))) {}
+    ~HostImage() { std::free(p); }
+    HostImage(const HostImage&) = delete;
+    HostImage& operator=(const HostImage&) = delete;
+};
+
+template <class T>
+using HugeVec = std::vector<T, HugeAlloc<T>>;
+
 // Standard models: the set-partitioned tile replay.  Every pair becomes
 // one or more (pair, part) items: the fewest parts P (a power of two, at
 // most T) for which one part's sets fit a wave's LDS state of at most
@@ -547,9 +590,9 @@ extern "C" int cache_replay_general(const pchase_general_model* models, uint32_t
 // class: the state rows rounded up to a power of two, at least 16), each
 // group one launch whose LDS fits its class, longest items first.
 struct TileSchedule {
-    std::vector<TileItem> items;     // grouped, longest first in a group
-    std::vector<uint32_t> key;       // group key of each item
-    std::vector<float> cost;         // estimated cost of each item
+    HugeVec<TileItem> items;     // grouped, longest first in a group
+    HugeVec<uint32_t> key;       // group key of each item
+    HugeVec<float> cost;         // estimated cost of each item
     std::vector<uint64_t> zero_cnt;  // (word, count) ranges that split pairs merge into
     std::vector<uint64_t> zero_bits;
 };
@@ -559,10 +602,10 @@ static int build_tile_schedule(const std::vector<DevModel>& dm, uint32_t n_model
                                const uint32_t* pair_trace, const uint64_t* count_from, uint64_t n_pairs,
                                bool want_bits, const uint64_t* bitoff, TileSchedule* ts) {
     const uint32_t row_cap = 256;
-    std::vector<TileItem> items;
+    HugeVec<TileItem> items;
     items.reserve(n_pairs);
-    std::vector<uint32_t> key;   // group key | cost bucket << 8 of each item
-    std::vector<float> cost;
+    HugeVec<uint32_t> key;   // group key | cost bucket << 8 of each item
+    HugeVec<float> cost;
     key.reserve(n_pairs);
     cost.reserve(n_pairs);
     ts->zero_cnt.clear();
@@ -1171,6 +1214,7 @@ static int replay_materialised(const std::vector<DevModel>& dm, const GeneralDes
     return PCHASE_OK;
 }
 
+
 // ----------------------------------------------------------- inference ---
 static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const pchase_model* cands,
                             uint32_t n_cands, const std::vector<DevModel>& dm, const std::vector<DevProbe>& dp,
@@ -1191,7 +1235,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->n_cands = n_cands;
     np->n_host.assign(n_cands, 0);
     std::vector<SweepJob> jobs;
-    std::vector<DecidedJob> decided;
+    HugeVec<DecidedJob> decided;
     std::vector<RunTable> tables;
     std::vector<uint64_t> table_ks;   // first access of each sweep of the multi-sweep tables
     uint64_t entries = 0;
@@ -1219,16 +1263,14 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
         if (ls_slot[dm[c].line_shift] < 0) ls_slot[dm[c].line_shift] = (int32_t)n_ls++;
     std::vector<Geo> geo;
     std::vector<uint64_t> geo_ks;
-    std::vector<uint32_t> mine;
+    // the (candidate, probe) pairs first, so that the job arrays are sized once
+    std::vector<uint64_t> pair_off(n_cands + 1, 0);
+    std::vector<uint32_t> pairs;
     for (uint32_t c = 0; c < n_cands; ++c) {
+        pair_off[c] = pairs.size();
         if (allow && !(*allow)[c]) continue;
-        const DevModel& md = dm[c];
-        // the closed forms hold for LRU and FIFO; with one way every policy
-        // replaces as LRU does, and two-way tree-PLRU is LRU
-        const bool lru_fifo = md.policy == PCHASE_LRU || md.policy == PCHASE_FIFO || md.ways == 1 ||
-                              (md.ways == 2 && md.policy == PCHASE_PLRU);
-        mine.clear();
         if (probe_select == PCHASE_PROBES_OWN_SWEEP) {
+            const size_t first = pairs.size();
             const uint64_t C = cands[c].capacity_bytes, b = cands[c].line_bytes;
             const uint64_t strides[3] = {b / 2, b, 2 * b};
             for (int si = 0; si < 3; ++si) {
@@ -1238,13 +1280,24 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                 const auto& v = it->second;
                 auto lo = std::lower_bound(v.begin(), v.end(), std::make_pair((C + 1) / 2, 0u));
                 for (; lo != v.end() && lo->first <= 2 * C; ++lo)
-                    if (own_sweep(cands[c], obs->probes[lo->second])) mine.push_back(lo->second);
+                    if (own_sweep(cands[c], obs->probes[lo->second])) pairs.push_back(lo->second);
             }
-            std::sort(mine.begin(), mine.end());
+            std::sort(pairs.begin() + first, pairs.end());
         } else {
-            for (uint32_t p = 0; p < obs->n_probes; ++p) mine.push_back(p);
+            for (uint32_t p = 0; p < obs->n_probes; ++p) pairs.push_back(p);
         }
-        for (uint32_t p : mine) {
+    }
+    pair_off[n_cands] = pairs.size();
+    if (closed) decided.reserve(pairs.size());
+    else jobs.reserve(pairs.size());
+    for (uint32_t c = 0; c < n_cands; ++c) {
+        const DevModel& md = dm[c];
+        // the closed forms hold for LRU and FIFO; with one way every policy
+        // replaces as LRU does, and two-way tree-PLRU is LRU
+        const bool lru_fifo = md.policy == PCHASE_LRU || md.policy == PCHASE_FIFO || md.ways == 1 ||
+                              (md.ways == 2 && md.policy == PCHASE_PLRU);
+        for (uint64_t pi = pair_off[c]; pi < pair_off[c + 1]; ++pi) {
+            const uint32_t p = pairs[pi];
             if (len[p] > cf[p]) np->n_host[c] += len[p] - cf[p];
             // no access evicts and nothing before the second pass is
             // compared: the only misses are first touches, all in the first
@@ -1373,10 +1426,24 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     const size_t o_pscr = up256(o_pbits + pat_bits / 8);
     const size_t o_pre = up256(o_pscr + pat_scratch * sizeof(uint32_t));
     const size_t bytes = o_pre + entries * sizeof(int32_t);
-    std::vector<uint8_t> img(o_img);
+    HostImage img(o_img);
+    if (o_img && !img.p) return set_error(PCHASE_ENOMEM, "host image of %zu bytes", o_img);
     auto put = [&](size_t at, const void* src, size_t n) {
-        if (n) std::memcpy(img.data() + at, src, n);
+        if (n) std::memcpy(img.p + at, src, n);
     };
+    // the alignment gaps between the regions (the regions are all written)
+    const size_t region[8][2] = {{o_n, n_cands * sizeof(uint64_t)},
+                                 {o_pinfo, 3 * (size_t)n_probes * sizeof(uint64_t)},
+                                 {o_dec, decided.size() * sizeof(DecidedJob)},
+                                 {o_dcand, decided.size() * sizeof(uint32_t)},
+                                 {o_tab, tables.size() * sizeof(RunTable)},
+                                 {o_ks, table_ks.size() * sizeof(uint64_t)},
+                                 {o_pat, patterns.size() * sizeof(PlruPattern)},
+                                 {o_img, 0}};
+    for (int r = 0; r < 7; ++r) {
+        const size_t end = region[r][0] + region[r][1];
+        if (region[r + 1][0] > end) std::memset(img.p + end, 0, region[r + 1][0] - end);
+    }
     put(o_n, np->n_host.data(), n_cands * sizeof(uint64_t));
     for (uint32_t p = 0; p < n_probes; ++p) {
         const uint64_t row[3] = {bitoff[p], std::min(cf[p], len[p]), len[p]};
@@ -1420,7 +1487,7 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     np->d_pat_bits = reinterpret_cast<uint32_t*>(b + o_pbits);
     np->n_tables = (uint32_t)tables.size();
     np->n_decided = (uint32_t)decided.size();
-    if (o_img) PC_HIP(hipMemcpy(b, img.data(), o_img, hipMemcpyHostToDevice));
+    if (o_img) PC_HIP(hipMemcpy(b, img.p, o_img, hipMemcpyHostToDevice));
     if (!patterns.empty()) {
         // the patterns depend on the plan only: computed once, here
         PC_HIP(launch_plru_patterns(np->d_patterns, (uint32_t)patterns.size(), np->d_pat_bits,
