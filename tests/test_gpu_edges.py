@@ -11,12 +11,7 @@ import oracle as orc
 from paper_1509_02308_amd import workloads as W
 from tests.gpu_common import need_gpu, orc_model, orc_probe, say, unpack_bits
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="a full GPU run that executed these tests first ended with a host segmentation fault "
-                            "in a later test (test_features_match_oracle, inside pchase_mlp_features); the cause "
-                            "is not found, so these tests stay off the GPU until it is"),
-]
+pytestmark = pytest.mark.gpu
 
 EDGE_PROBES = [
     (4, 4, 3), (4, 0, 2, 0, 12), (4096, 0, 2), (4096, 4096 * 3, 2),       # L = 1
