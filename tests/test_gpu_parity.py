@@ -375,6 +375,39 @@ def test_inference_repeat_calls_see_changed_inputs():
     assert n3[k] > n1[k]
 
 
+def test_inference_large_run_tables():
+    """Chases of a 1 MB array at the line size give run tables of 32,768
+    and 32,770 runs, beside a 256-access chase, with candidates of every
+    closed-form kind (no eviction, every set thrashing, two sets over their
+    ways, tree-PLRU patterns).  Every (m, n) against the oracle, closed
+    forms on and off."""
+    torch, capi = need_gpu()
+    prows = [(1 << 20, 32, 2), ((1 << 20) + 64, 32, 2), (4096, 32, 2)]
+    crows = [(1 << 20, 32, 8, W.LRU), (1 << 20, 32, 8, W.FIFO), (1 << 20, 32, 8, W.PLRU),
+             (8192, 32, 4, W.LRU), (4096, 32, 1, W.PLRU), (16384, 64, 2, W.PLRU), (16384, 32, 4, W.PLRU)]
+    rng = np.random.default_rng(77)
+    lens = [orc.trace_len(orc_probe(r)) for r in prows]
+    hits_all = [(rng.random(n) < 0.7).astype(np.uint8) for n in lens]
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    cfs = np.array([orc.cycle_len(orc_probe(r)) for r in prows], np.uint64)
+    best, m, n = orc.infer([orc_model(r) for r in crows], [orc_probe(r) for r in prows],
+                           np.concatenate(hits_all), off, cfs, probe_select=0)
+    packed, bitoff = _bits_layout(hits_all)
+    bits = torch.from_numpy(packed.view(np.int32)).cuda()
+    mn = torch.zeros(2 * len(crows), dtype=torch.int64, device="cuda")
+    closed = []
+    for sched in (0, capi.SCHED_FULL_REPLAY):
+        say(f"infer_cache_params, run tables of 32k runs, sched={sched:#x}")
+        res, _ = capi.infer_cache_params(capi.probes(prows), capi.models(crows), bits=bits, bitoff=bitoff,
+                                         probe_select=0, mn=mn, mode=sched)
+        got = mn.cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        bad = np.nonzero((got[:, 0] != m) | (got[:, 1] != n))[0]
+        assert len(bad) == 0, [(sched, crows[int(c)], tuple(got[c]), (int(m[c]), int(n[c]))) for c in bad]
+        assert res.best == best and res.best_m == m[best]
+        closed.append(res.closed_form_accesses)
+    assert closed[0] > 0 and closed[1] == 0
+
+
 def test_inference_scores_any_observation_and_count_from():
     """Every scoring path against the oracle on an arbitrary (random)
     observation: every way class and policy, set_shift mappings, probes of
