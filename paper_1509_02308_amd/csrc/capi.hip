@@ -161,6 +161,8 @@ static uint64_t gcd64(uint64_t x, uint64_t y) {
 constexpr uint64_t kMaxTableEntries = 1ull << 26;
 // Largest set (lines) a tree-PLRU pattern is tabulated for.
 constexpr uint64_t kMaxPatternLines = 4096;
+// Associativities whose pattern ids a plan build keeps in a flat table.
+constexpr uint64_t kPatternTableWays = 128;
 
 static bool own_sweep(const pchase_model& c, const pchase_probe& p) {
     const uint64_t C = c.capacity_bytes, b = c.line_bytes, N = p.n_bytes, s = p.s_bytes;
@@ -1240,7 +1242,8 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
     std::vector<uint64_t> table_ks;   // first access of each sweep of the multi-sweep tables
     uint64_t entries = 0;
     std::vector<PlruPattern> patterns;
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> pattern_of;   // (ways, lines) -> pattern
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> pattern_of;   // (ways, lines) -> pattern, > 128 ways
+    std::vector<int32_t> pattern_flat;                               // the same, up to 128 ways
     uint64_t pat_bits = 0, pat_scratch = 0;
     // own sweeps: probes indexed by stride, sorted by array size
     std::map<uint64_t, std::vector<std::pair<uint64_t, uint32_t>>> by_stride;
@@ -1353,14 +1356,23 @@ static int build_infer_plan(Workspace* ws, const pchase_observation* obs, const 
                 uint32_t tid = 0, pb = 0, ps = 0;
                 if (kind == 4) {
                     auto pattern = [&](uint32_t n) -> uint32_t {
-                        auto key = std::make_pair(md.ways, n);
-                        auto it = pattern_of.find(key);
-                        if (it != pattern_of.end()) return it->second;
+                        // ids of (ways, n) in a flat table for up to 128 ways
+                        int32_t* slot = nullptr;
+                        if (md.ways <= kPatternTableWays) {
+                            if (pattern_flat.empty())
+                                pattern_flat.assign((kPatternTableWays + 1) * (kMaxPatternLines + 2), -1);
+                            slot = &pattern_flat[(size_t)md.ways * (kMaxPatternLines + 2) + n];
+                            if (*slot >= 0) return (uint32_t)*slot;
+                        } else {
+                            auto it = pattern_of.find(std::make_pair(md.ways, n));
+                            if (it != pattern_of.end()) return it->second;
+                        }
                         const uint32_t id = (uint32_t)patterns.size();
                         patterns.push_back(PlruPattern{md.ways, md.log2_ways, n, (uint32_t)pat_scratch, pat_bits});
                         pat_scratch += n + md.ways;
                         pat_bits += (n + 31) / 32 * 32;
-                        pattern_of.emplace(key, id);
+                        if (slot) *slot = (int32_t)id;
+                        else pattern_of.emplace(std::make_pair(md.ways, n), id);
                         return id;
                     };
                     ps = pattern((uint32_t)q0);
