@@ -1606,9 +1606,7 @@ static int run_infer_plan(Workspace* ws, InferPlan* ip, const uint32_t* bits, pc
     const uint32_t n_cands = ip->n_cands;
     const size_t zw = (n_cands + 31) / 32;
     InferPlan* pp = ip;
-    auto tail = [pp, zw](hipStream_t s) -> hipError_t {
-        hipError_t e = launch_fill_u32(pp->d_zero, zw, 0, s);
-        if (e != hipSuccess) return e;
+    auto tail = [pp](hipStream_t s) -> hipError_t {
         return launch_argmin(pp->d_m, pp->d_n, pp->n_cands, pp->d_zero, pp->d_out, s);
     };
     // the jobs decided without a replay, beside the replay: their run
@@ -1925,7 +1923,6 @@ extern "C" int infer_cache_params_general(const pchase_observation* obs, const p
     PC_HIP(hipMemcpyAsync(d_len, len.data(), np * 8, hipMemcpyHostToDevice, stream));
     PC_HIP(hipMemcpyAsync(d_n, n_cmp.data(), (size_t)n_cands * 8, hipMemcpyHostToDevice, stream));
     PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(d_m), 2 * (uint64_t)n_cands, 0, stream));
-    PC_HIP(launch_fill_u32(d_zero, zw, 0, stream));
     PC_HIP(launch_mismatch(d_hits, cand_words, bits, d_hoff, d_obits, d_cf, d_len, np, n_pairs, d_m, stream));
     PC_HIP(launch_argmin(d_m, d_n, n_cands, d_zero, d_out, stream));
     PC_HIP(hipMemcpyAsync(hr, d_out, sizeof(ArgminOut), hipMemcpyDeviceToHost, stream));

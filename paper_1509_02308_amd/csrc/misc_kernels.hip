@@ -197,12 +197,15 @@ __device__ __forceinline__ bool better(uint64_t mi, uint64_t ni, uint32_t i, uin
     return i < j;
 }
 
+// One block; it clears the zero-class bitmap (nc bits) before setting it.
 __global__ void __launch_bounds__(1024) argmin_kernel(const uint64_t* m, const uint64_t* n, uint32_t nc,
                                                       uint32_t* zero_bits, ArgminOut* out) {
     __shared__ uint64_t sm[1024], sn[1024];
     __shared__ uint32_t si[1024];
     __shared__ unsigned long long zeros;
     if (threadIdx.x == 0) zeros = 0;
+    if (zero_bits)
+        for (uint32_t w = threadIdx.x; w < (nc + 31) / 32; w += blockDim.x) zero_bits[w] = 0;
     __syncthreads();
     uint64_t bm = 0, bn = 0;
     uint32_t bi = 0xFFFFFFFFu;
