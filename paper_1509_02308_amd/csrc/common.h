@@ -208,6 +208,7 @@ struct DevNuProbe {
 hipError_t launch_trace_nu(const DevNuProbe* probes, const DevNuSeg* segs, const uint64_t* off,
                            const ChunkRef* chunks, uint64_t n_chunks, int32_t* idx, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_fill2_u32(uint32_t* p, uint64_t n, uint32_t* q, uint64_t nq, uint32_t v, hipStream_t stream);
 hipError_t launch_argmin(const uint64_t* m, const uint64_t* n, uint32_t nc, uint32_t* zero_bits,
                          ArgminOut* out, hipStream_t stream);
 hipError_t launch_auto_threshold(const uint32_t* lat, uint64_t n, uint32_t* mm, uint32_t* present,

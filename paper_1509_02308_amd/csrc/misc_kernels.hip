@@ -182,6 +182,23 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stre
     return hipGetLastError();
 }
 
+// Two ranges in one launch: p[0 .. n) and q[0 .. nq) set to v.
+__global__ void fill2_u32_kernel(uint32_t* p, uint64_t n, uint32_t* q, uint64_t nq, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + nq;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < n) p[i] = v;
+        else q[i - n] = v;
+    }
+}
+
+hipError_t launch_fill2_u32(uint32_t* p, uint64_t n, uint32_t* q, uint64_t nq, uint32_t v, hipStream_t stream) {
+    if (n + nq == 0) return hipSuccess;
+    uint64_t blocks = (n + nq + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill2_u32_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, p, n, q, nq, v);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- argmin ---
 // best = argmin over candidates with n > 0 of m/n, compared exactly as
 // m_i * n_j < m_j * n_i in 128 bits, ties to the lower index.

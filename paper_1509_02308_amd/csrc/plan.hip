@@ -277,8 +277,7 @@ static int enqueue_batched(Workspace* ws, SweepPlan* plan, bool score, uint64_t*
                            const std::function<hipError_t(hipStream_t)>& tail,
                            const std::function<hipError_t(hipStream_t)>& side, int strategy = 0) {
     const uint32_t nq = (uint32_t)plan->batched.size() + 2;
-    PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, s));
-    PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
+    PC_HIP(launch_fill2_u32(plan->d_queues, nq, reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, s));
     if (clear_bits && bits)
         PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), s));
     const int want = strategy == 2 ? 2 : strategy == 3 ? 1 : kBranches;
@@ -348,8 +347,7 @@ int run_sweep_plan(Workspace* ws, SweepPlan* plan, bool score, uint64_t* counter
                    const std::function<hipError_t(hipStream_t)>& side) {
     if (mode == PCHASE_PLAIN) {
         const uint32_t nq = (uint32_t)plan->batched.size() + 2;
-        PC_HIP(launch_fill_u32(plan->d_queues, nq, 0, stream));
-        PC_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, stream));
+        PC_HIP(launch_fill2_u32(plan->d_queues, nq, reinterpret_cast<uint32_t*>(counters), 2 * n_counters, 0, stream));
         if (clear_bits && bits)
             PC_HIP(launch_clear_ranges(bits, plan->d_clear, (uint32_t)(plan->clear.size() / 2), stream));
         if (side) PC_HIP(side(stream));
